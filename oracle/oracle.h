@@ -1,0 +1,99 @@
+/*
+ * CB-GMRES CPU oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, FP64 implementation of compressed-basis GMRES as described in
+ * Aliaga, Anzt, Gruetzmacher, Quintana-Orti, Tomas, "Compressed Basis GMRES on
+ * High Performance GPUs" (arXiv 2009.12101): the restarted GMRES of Fig. 1
+ * (Section 3) whose Krylov basis is stored in a reduced format and widened to
+ * FP64 on every read (Section 4, "CB-GMRES"; Section 5.2, "Memory accessor").
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load this library. It shares no source, header, table or helper with
+ * the HIP library; the two meet only through the seeded input generators.
+ *
+ * All pointers are host pointers owned by the caller. Functions never
+ * allocate memory the caller must free.
+ */
+#ifndef CBG_ORACLE_H
+#define CBG_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Storage formats of the basis (Section 5.2 lists float64, float32, float16,
+ * int32, int16; bf16 and e4m3 are extensions defined the same way). */
+enum {
+    ORC_FP64 = 0, ORC_FP32 = 1, ORC_FP16 = 2, ORC_BF16 = 3,
+    ORC_E4M3 = 4, ORC_INT32 = 5, ORC_INT16 = 6
+};
+
+enum { ORC_PC_NONE = 0, ORC_PC_JACOBI = 1, ORC_PC_SPARSE = 2 };
+
+enum { ORC_OK = 0, ORC_NOT_CONVERGED = 1, ORC_E_ARG = -1, ORC_E_NONFINITE = -4 };
+
+/* bytes per stored entry, or 0 for an unknown format */
+int orc_format_bytes(int fmt);
+
+/* Encode n entries of v into q (orc_format_bytes(fmt)*n bytes) and the
+ * per-vector scale.  Scale meaning: fp64/fp32/fp16/bf16: 1; e4m3: 2^k; int:
+ * sigma = max|v| / max_int.  Returns 0, or ORC_E_ARG. */
+int orc_encode(int fmt, int64_t n, const double *v, void *q, double *scale);
+/* Widen n stored entries to FP64. */
+int orc_decode(int fmt, int64_t n, const void *q, double scale, double *out);
+
+/* y = A x for a CSR matrix (row_ptr n+1, 0-based). */
+void orc_spmv(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+              const double *val, const double *x, double *y);
+/* sum_i x_i y_i in fixed 1024-entry blocks (see the source). */
+double orc_dot(int64_t n, const double *x, const double *y);
+
+typedef struct {
+    int32_t restart;          /* m of Fig. 1 */
+    int32_t format;           /* ORC_FP64 ... ORC_INT16 */
+    double  tol;              /* tau: stop when ||b - A x||_2 <= tau ||b||_2 */
+    int64_t maxiter;          /* limit on Arnoldi steps over all cycles */
+    double  eta;              /* re-orthogonalisation threshold; <= 0 -> 1/sqrt(2) */
+    int32_t precond;          /* ORC_PC_* */
+    const float *p_val;       /* ORC_PC_SPARSE: values of P on A's pattern */
+    int32_t fallback;         /* ORC_PC_SPARSE: switch to M = I on stagnation */
+} orc_opts;
+
+typedef struct {
+    int64_t iterations;       /* Arnoldi steps taken */
+    int64_t restarts;         /* cycles started */
+    int64_t reorths;          /* steps that re-orthogonalised */
+    int32_t status;           /* ORC_OK / ORC_NOT_CONVERGED / error */
+    int32_t breakdowns;       /* cycles ended by the breakdown test */
+    int32_t fell_back;        /* 1 if the sparse preconditioner was dropped */
+    int32_t pad;
+    double  true_rel_res;     /* ||b - A x||_2 / ||b||_2 at exit */
+    double  recurrence_rel_res; /* last |g_{j+1}| / ||b||_2 */
+} orc_result;
+
+/* Restarted CB-GMRES (Fig. 1).  x is x0 on entry and the result on exit.
+ * hist (optional, maxiter entries): recurrence residual |g_{j+1}|/||b|| per
+ * Arnoldi step.  cycle_res (optional, maxiter+1 entries): explicit residual
+ * ||b - A x||/||b|| at the start of every cycle and at exit.  cycle_len
+ * (optional, maxiter entries): Arnoldi steps taken in each cycle.
+ * dbg_V (optional, n*(restart+1)): decoded basis vectors of the FIRST cycle,
+ * vector-major; dbg_H (optional, (restart+1)*restart, column-major): the
+ * Hessenberg matrix of the first cycle before any Givens rotation;
+ * dbg_steps[0..1] receive that cycle's step count and the number of basis
+ * vectors stored.  When dbg_V is given, the vector v_{j+1} after the
+ * cycle's last step j is also formed (if h_{j+1,j} > 0) so the Arnoldi
+ * relation can be checked; the solution is unaffected. */
+int orc_gmres(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+              const double *val, const double *b, double *x,
+              const orc_opts *opt, orc_result *res,
+              double *hist, double *cycle_res, int32_t *cycle_len,
+              double *dbg_V, double *dbg_H, int32_t *dbg_steps);
+
+void orc_set_threads(int nthreads);
+int  orc_get_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
