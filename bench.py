@@ -1,0 +1,161 @@
+"""Benchmark: time-to-solution and Arnoldi GB/s of CB-GMRES on one MI355X.
+
+Workload: the 3D 7-point upwind convection-diffusion system on a 128^3 grid
+(n = 2,097,152, nnz = 14,581,760, nonsymmetric, global Peclet 10 per axis),
+b ~ U[-1, 1] (seed 0), x0 = 0, restart m = 100, tol 1e-10 on the true
+relative residual.  One step = one complete solve with the basis stored in
+fp16 (the headline compressed format); solves with fp64 / fp32 / int16
+storage run after the timed region for the compressed-vs-fp64 comparison.
+
+Prints one JSON line.  `value` is the fp16-basis time to solution (seconds,
+lower is better).  `roofline` covers the multi-dot kernel h = V^T w (the
+dominant kernel): algorithmic bytes per launch (j * n * 2 + 8 n for j
+stored vectors) over its HIP-event-timed duration in the timed solves.
+`cpu_baseline` is the CPU oracle timed on one restart cycle of the same
+solve on the host cores, scaled to the GPU's iteration count.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "time-to-solution + Arnoldi GB/s at rel. residual 1e-10, CB vs fp64-basis"
+HBM_PEAK_GBPS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--grid", type=int, default=128)
+    ap.add_argument("--format", default="fp16")
+    ap.add_argument("--compare", default="fp64,fp32,int16")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-cycles", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
+                          "--gpus > 1 is not supported (single-GPU build)"}))
+        return 2
+
+    import numpy as np
+    import torch
+
+    import paper_2009_12101_amd as cbg
+    from paper_2009_12101_amd import problems as P
+
+    dev = torch.device("cuda:0")
+    m, tol, maxiter = 100, 1e-10, 20000
+    t0 = time.time()
+    A = P.convdiff7(args.grid)
+    b = P.rhs_uniform(A.n, 0)
+    log(f"generated {A.name}: n={A.n} nnz={A.nnz} in {time.time() - t0:.1f}s")
+    Ad = cbg.DeviceCSR.from_host(A, dev)
+    bd = torch.from_numpy(b).to(dev)
+    ws = torch.empty(cbg.workspace_bytes(A.n, m, "fp64"), dtype=torch.uint8, device=dev)
+
+    def one(fmt, profile):
+        return cbg.solve(Ad, bd, restart=m, fmt=fmt, tol=tol, maxiter=maxiter, profile=profile,
+                         workspace=ws)
+
+    for _ in range(args.warmup):
+        one(args.format, True)
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    results = []
+    torch.cuda.synchronize()
+    start = time.perf_counter()
+    for _ in range(args.steps):
+        results.append(one(args.format, True))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - start
+    r0 = results[-1]
+    ms_per_step = elapsed / args.steps * 1e3
+    value = elapsed / args.steps
+    dot_ms = sum(r.prof_dot_ms for r in results)
+    dot_bytes = sum(r.prof_dot_bytes for r in results)
+    dot_launch = sum(r.prof_dot_launches for r in results)
+    orth_ms = sum(r.prof_orth_ms for r in results)
+    orth_bytes = sum(r.prof_orth_bytes for r in results)
+    achieved = dot_bytes / (dot_ms * 1e-3) / 1e9 if dot_ms > 0 else 0.0
+    x = r0.x.cpu().numpy()
+    res_check = float(np.linalg.norm(b - A.to_scipy() @ x) / np.linalg.norm(b))
+    log(f"{args.format}: {ms_per_step:.1f} ms/solve it={r0.iterations} cycles={r0.restarts} "
+        f"res={res_check:.2e} multidot {achieved:.0f} GB/s")
+
+    formats = {args.format: dict(seconds=value, iterations=r0.iterations, restarts=r0.restarts,
+                                 reorths=r0.reorths, true_rel_res=res_check,
+                                 arnoldi_gbps=r0.model_bytes / r0.seconds / 1e9)}
+    for fmt in [f for f in args.compare.split(",") if f and f != args.format]:
+        one(fmt, False)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = one(fmt, False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        xr = r.x.cpu().numpy()
+        formats[fmt] = dict(seconds=dt, iterations=r.iterations, restarts=r.restarts,
+                            reorths=r.reorths,
+                            true_rel_res=float(np.linalg.norm(b - A.to_scipy() @ xr)
+                                               / np.linalg.norm(b)),
+                            arnoldi_gbps=r.model_bytes / r.seconds / 1e9)
+        log(f"{fmt}: {dt * 1e3:.1f} ms it={r.iterations}")
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        cyc = args.cpu_cycles
+        t = time.perf_counter()
+        o = oracle.gmres(A, b, restart=m, fmt=args.format, tol=tol, maxiter=cyc * m)
+        dt = time.perf_counter() - t
+        per_step = dt / max(o["iterations"], 1)
+        cpu = {"value": per_step * r0.iterations, "unit": "s", "cores": oracle.get_threads(),
+               "kind": "oracle",
+               "sample": f"{o['iterations']} Arnoldi steps ({cyc} restart cycle) of the same "
+                         f"{args.format}-basis solve on the host cores in {dt:.1f} s, scaled to "
+                         f"the GPU's {r0.iterations} steps"}
+        log(f"cpu oracle: {dt:.1f}s for {o['iterations']} steps")
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"3D 7-point upwind convection-diffusion {args.grid}^3 "
+                               f"(n={A.n}, nnz={A.nnz}), b~U[-1,1] seed 0, x0=0, "
+                               f"restart {m}, tol {tol}",
+                   "basis_format": args.format, "arithmetic": "fp64",
+                   "parallelism": "single GPU"},
+        "iterations": r0.iterations, "restarts": r0.restarts, "reorths": r0.reorths,
+        "true_rel_res": res_check,
+        "arnoldi_gbps": r0.model_bytes / r0.seconds / 1e9,
+        "orth_kernels_gbps": orth_bytes / (orth_ms * 1e-3) / 1e9 if orth_ms > 0 else None,
+        "formats": formats,
+        "speedup_vs_fp64_basis": (formats["fp64"]["seconds"] / value) if "fp64" in formats
+        else None,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "kernel": f"k_multidot<{args.format}>",
+                     "launches": dot_launch,
+                     "avg_launch_us": dot_ms * 1e3 / max(dot_launch, 1),
+                     "algorithmic_bytes_per_launch": dot_bytes / max(dot_launch, 1)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

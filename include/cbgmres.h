@@ -1,0 +1,194 @@
+/*
+ * cbgmres.h -- C ABI of the MI355X (gfx950) compressed-basis GMRES library.
+ *
+ * Solves A x = b (A sparse n x n in CSR form, b and x dense; the problem of
+ * the paper's Eq. (1)) with the restarted GMRES of Fig. 1 (Section 3), whose
+ * Krylov basis V is stored in a reduced format and widened to FP64 in
+ * registers on every read (Section 4, "CB-GMRES"; Section 5.2, "Memory
+ * accessor").  All arithmetic is FP64.
+ *
+ * Conventions for every entry point:
+ *  - Pointers marked [dev] are device pointers (HIP global memory) owned by
+ *    the caller; [host] pointers are host memory owned by the caller.  The
+ *    library never calls hipMalloc/hipFree: scratch space comes from a
+ *    caller-provided device workspace sized by the matching *_bytes query.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Kernel-level calls are asynchronous on that stream; cbgmres_solve
+ *    returns after the solve has finished.
+ *  - Vectors handed to kernel-level calls must be 16-byte aligned; basis
+ *    leading dimensions must be multiples of 16 elements.
+ *  - Return value: 0 on success, >0 "finished without meeting the
+ *    tolerance", <0 an error (cbg_strerror).  Argument errors are detected
+ *    on the host before any HIP call, and then no output is written.
+ *  - Calls sharing a workspace must not overlap; distinct workspaces may be
+ *    used concurrently on distinct streams.
+ */
+#ifndef CBGMRES_H
+#define CBGMRES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Storage format of the Krylov basis (Section 5.2 lists float64, float32,
+ * float16, int32 and int16; bf16 and fp8 e4m3 are extensions stored the same
+ * way).  Bytes per entry: 8, 4, 2, 2, 1, 4, 2.
+ *   CBG_FP32/FP16/BF16: one round-to-nearest-even conversion from FP64.
+ *   CBG_E4M3 (OCP E4M3FN): per-vector power-of-two scale 2^k chosen so that
+ *     max|v| * 2^-k lies in (224, 448]; entries RNE(v_i * 2^-k).
+ *   CBG_INT32/INT16: fixed point with per-vector scale
+ *     sigma = max|v| / max_int (the scale of Section 5.2 for a unit vector);
+ *     entries rint(v_i / sigma) clamped to [-max_int, max_int]. */
+typedef enum {
+    CBG_FP64 = 0, CBG_FP32 = 1, CBG_FP16 = 2, CBG_BF16 = 3,
+    CBG_E4M3 = 4, CBG_INT32 = 5, CBG_INT16 = 6
+} cbg_format;
+
+/* Right preconditioner M^{-1} of Fig. 1 steps 3 and 17. */
+typedef enum {
+    CBG_PC_NONE = 0,     /* M = I */
+    CBG_PC_JACOBI = 1,   /* M^{-1} = diag(1 / a_ii), the paper's default (Section 6) */
+    CBG_PC_SPARSE = 2    /* M^{-1} = P, single-precision values on A's pattern */
+} cbg_precond_kind;
+
+enum {
+    CBG_OK = 0,
+    CBG_NOT_CONVERGED = 1,   /* maxiter reached before ||b - A x|| <= tol ||b|| */
+    CBG_E_ARG = -1,          /* invalid argument (nothing was launched) */
+    CBG_E_WORKSPACE = -2,    /* workspace missing, misaligned or too small */
+    CBG_E_HIP = -3,          /* a HIP runtime call failed */
+    CBG_E_NONFINITE = -4,    /* NaN/Inf met (b, x0, A, or during the solve) */
+    CBG_E_UNSUPPORTED = -5   /* valid request this build does not support */
+};
+
+/* CSR matrix, 0-based, column indices sorted within each row.
+ * row_ptr [dev] n+1 int32; col_idx [dev] nnz int32; val [dev] nnz double. */
+typedef struct {
+    int32_t n;
+    int32_t reserved;
+    int64_t nnz;
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    const double *val;
+} cbg_csr;
+
+/* Solver options.  restart: m of Fig. 1 (1 .. CBG_MAX_RESTART).  tol: tau of
+ * the stop test ||b - A x||_2 <= tau ||b||_2 (Section 3).  maxiter: limit on
+ * Arnoldi steps over all cycles.  eta: re-orthogonalisation threshold of
+ * Fig. 1 step 7; <= 0 selects 1/sqrt(2).  p_val [dev]: CBG_PC_SPARSE values
+ * (nnz floats on A's pattern).  fallback: with CBG_PC_SPARSE, drop P and
+ * continue with M = I when the explicit residual fails to fall below 0.99x
+ * its previous value in two consecutive cycles or a non-finite value
+ * appears.  flags: CBG_FLAG_* bits. */
+typedef struct {
+    int32_t restart;
+    int32_t format;
+    double tol;
+    int64_t maxiter;
+    double eta;
+    int32_t precond;
+    int32_t fallback;
+    const float *p_val;
+    int32_t flags;
+    int32_t reserved;
+} cbg_opts;
+
+#define CBG_MAX_RESTART 512
+/* time the orthogonalisation kernels with HIP events (cbg_result.prof_*) */
+#define CBG_FLAG_PROFILE 1
+
+typedef struct {
+    int64_t iterations;        /* Arnoldi steps (SpMVs with A inside cycles) */
+    int64_t restarts;          /* cycles run */
+    int64_t reorths;           /* steps that re-orthogonalised (Fig. 1 step 7) */
+    int32_t status;            /* same value as returned */
+    int32_t breakdowns;        /* cycles ended by the breakdown test (step 12) */
+    int32_t fell_back;         /* 1 if CBG_PC_SPARSE was dropped */
+    int32_t reserved;
+    double true_rel_res;       /* ||b - A x||_2 / ||b||_2 of the returned x */
+    double recurrence_rel_res; /* last |g_{j+1}| / ||b||_2 of the least squares */
+    double seconds;            /* host wall time of the call */
+    double model_bytes;        /* algorithmic HBM bytes of the solve */
+    /* with CBG_FLAG_PROFILE: summed event-timed duration, algorithmic bytes
+     * and launch count of the basis-streaming kernels (multi-dot h = V^T w
+     * and update w -= V h, both passes).  Every launch is counted, also the
+     * ones that found their step skipped (no re-orthogonalisation, or the
+     * cycle already finished); those add time but no bytes. */
+    double prof_orth_ms;
+    double prof_orth_bytes;
+    int64_t prof_orth_launches;
+    double prof_dot_ms;        /* the multi-dot kernel alone */
+    double prof_dot_bytes;
+    int64_t prof_dot_launches;
+} cbg_result;
+
+/* Device workspace bytes cbgmres_solve needs for this problem shape
+ * (0 for invalid arguments).  The workspace must be 256-byte aligned. */
+size_t cbg_workspace_bytes(int32_t n, int32_t restart, int32_t format, int32_t precond);
+
+/* Restarted CB-GMRES (Fig. 1 of the paper).
+ * A [host struct, dev arrays]; b [dev] n doubles; x [dev] n doubles, x0 on
+ * entry, the solution on exit.  workspace [dev] ws_bytes >=
+ * cbg_workspace_bytes(...).  res [host] always filled (also on error).
+ * hist [host, optional] receives the recurrence residual |g_{j+1}|/||b|| of
+ * every Arnoldi step, up to hist_len entries.
+ * The residual is recomputed explicitly at every restart (Section 3) and
+ * whenever the recurrence residual signals convergence (Section 6.2: the
+ * solve continues from the explicit residual if it misses tol).
+ * If ||b|| = 0 the solution is x = 0.  The host synchronises with the
+ * stream once per restart cycle. */
+int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *opt,
+                  void *workspace, size_t ws_bytes, void *stream, cbg_result *res,
+                  double *hist, int64_t hist_len);
+
+/* Static description of a status code. */
+const char *cbg_strerror(int status);
+
+/* Padded leading dimension (elements) the solver uses for basis vectors of
+ * length n: a multiple of 256.  Kernel-level calls accept any ld >= n that
+ * is a multiple of 16. */
+int64_t cbg_basis_ld(int32_t n);
+
+/* Device workspace bytes the kernel-level reductions below need for
+ * vectors of length n and up to j basis vectors. */
+size_t cbg_kernel_workspace_bytes(int32_t n, int32_t j);
+
+/* ---------------- kernel-level entry points (asynchronous) -------------- */
+
+/* The accessor's store (Fig. 1 steps 13-14): q = enc_F(v), scale = the
+ * per-vector scale (1 for unscaled formats).  v [dev] n doubles; q [dev]
+ * n entries of the format; scale [dev] 1 double; ws [dev]. */
+int cbg_encode(int32_t format, const double *v, int32_t n, void *q, double *scale,
+               void *ws, size_t ws_bytes, void *stream);
+
+/* The accessor's load (steps 5, 8, 17): v = dec_F(q) * scale, exactly. */
+int cbg_decode(int32_t format, const void *q, const double *scale, int32_t n, double *v,
+               void *stream);
+
+/* y = A x (step 3); if norm2 [dev, nullable] is given, *norm2 = ||y||_2
+ * (step 4).  x [dev] n doubles, y [dev] n doubles. */
+int cbg_spmv(const cbg_csr *A, const double *x, double *y, double *norm2, void *ws,
+             size_t ws_bytes, void *stream);
+
+/* Multi-dot of step 5 through the accessor: h_k = sum_i dec(V_k)_i w_i for
+ * k < j.  V [dev] j vectors of ld entries (vector k at byte offset
+ * k*ld*bytes(format)); scales [dev] j doubles; w [dev] n doubles;
+ * h [dev] j doubles. */
+int cbg_multidot(int32_t format, const void *V, int64_t ld, const double *scales,
+                 int32_t n, int32_t j, const double *w, double *h, void *ws,
+                 size_t ws_bytes, void *stream);
+
+/* Update of step 5: w -= sum_k h_k dec(V_k), then norms[0] = ||w||_2 and
+ * norms[1] = ||w||_inf (Section 5.2: both norms in one pass).
+ * norms [dev, nullable] 2 doubles. */
+int cbg_update(int32_t format, const void *V, int64_t ld, const double *scales, int32_t n,
+               int32_t j, const double *h, double *w, double *norms, void *ws,
+               size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CBGMRES_H */

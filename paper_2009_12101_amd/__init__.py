@@ -1,0 +1,18 @@
+"""MI355X-native compressed-basis GMRES (CB-GMRES).
+
+Restarted GMRES (Fig. 1 of Aliaga et al., "Compressed Basis GMRES on High
+Performance GPUs") whose Krylov basis is stored in fp32 / fp16 / bf16 /
+fp8-e4m3 / int32 / int16 and widened to FP64 in registers on every read.
+The solver and every kernel of the hot path live in libcbgmres.so
+(hand-written HIP for gfx950, C ABI in include/cbgmres.h); this package is
+its ctypes binding plus seeded synthetic problem generators. torch supplies
+device memory and streams only.
+"""
+from . import problems
+from ._binding import (FORMATS, FORMAT_BYTES, PRECONDS, CbgError, DeviceCSR, SolveResult,
+                       basis_ld, decode, encode, kernel_workspace_bytes, lib, multidot, solve,
+                       spmv, strerror, update, workspace_bytes)
+
+__all__ = ["problems", "FORMATS", "FORMAT_BYTES", "PRECONDS", "CbgError", "DeviceCSR",
+           "SolveResult", "basis_ld", "decode", "encode", "kernel_workspace_bytes", "lib",
+           "multidot", "solve", "spmv", "strerror", "update", "workspace_bytes"]

@@ -1,0 +1,1033 @@
+// gfx950 kernels of the CB-GMRES hot path and their host launchers.
+//
+// One Arnoldi step of Fig. 1 (Section 3) runs as
+//   spmv       w = A M^-1 v; block partials of ||w||^2           (steps 3-4)
+//   multidot   block partials of h = V_j^T w                     (step 5)
+//   reduce     h, omega = ||A M^-1 v||
+//   update     w -= V_j h                                        (step 5)
+//   multidot   block partials of u = V_j^T w, ||w||^2, max|w_i|  (steps 6, 8)
+//   reduce     u, h_{j+1,j} = ||w||; re-orthogonalise iff
+//              h_{j+1,j} < eta * omega (step 7), else finish the step
+//   update     w -= V_j u, partials of ||w||^2, max|w_i|         (steps 8-10)
+//   reduce     h += u, h_{j+1,j}; breakdown test; Givens         (steps 11-12, 16-17)
+//   normalize  v = w / h_{j+1,j}; V_{j+1} = enc(v)               (steps 13-14)
+// The re-dot u = V_j^T w is computed with the norm of w in the same pass;
+// it is used only when step 7 asks for it.  Producers write block partials
+// with plain stores and a one-block reduce kernel folds them in fixed order,
+// so sums are bitwise reproducible and no block fences against another.
+// The host only enqueues kernels; it synchronises once per restart cycle.
+#include "cbg_device.hpp"
+#include "cbg_launch.hpp"
+
+#ifndef CBG_MD_ATTR
+#define CBG_MD_ATTR
+#endif
+
+namespace cbg {
+
+// ---------------------------------------------------------------------------
+// Vector chunk helpers.
+// ---------------------------------------------------------------------------
+
+template <int VW>
+__device__ __forceinline__ void load_w(const double *__restrict__ w, int64_t n, int64_t i0,
+                                       double *o)
+{
+    if (i0 + VW <= n) {
+#pragma unroll
+        for (int e = 0; e < VW; e += 2) {
+            f64x2 p = *(const f64x2 *)(w + i0 + e);
+            o[e] = p.x;
+            o[e + 1] = p.y;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < VW; ++e)
+            o[e] = (i0 + e < n) ? w[i0 + e] : 0.0;
+    }
+}
+
+template <int VW>
+__device__ __forceinline__ void store_w(double *__restrict__ w, int64_t n, int64_t i0,
+                                        const double *o)
+{
+    if (i0 + VW <= n) {
+#pragma unroll
+        for (int e = 0; e < VW; e += 2) {
+            f64x2 p = {o[e], o[e + 1]};
+            *(f64x2 *)(w + i0 + e) = p;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < VW; ++e)
+            if (i0 + e < n)
+                w[i0 + e] = o[e];
+    }
+}
+
+// Decode the chunk of stored vector Vk starting at entry i0 (entries >= n
+// read as 0).  A chunk that starts below n lies inside the vector's leading
+// dimension (a multiple of 16 >= n), so its 16-byte load is in bounds.
+template <int F>
+__device__ __forceinline__ void load_dec(const uint8_t *__restrict__ Vk, int64_t i0, int64_t n,
+                                         double s, double *d)
+{
+    using T = Fmt<F>;
+    constexpr int VW = T::VW;
+    if (i0 < n) {
+        u32x4 q = __builtin_nontemporal_load((const u32x4 *)(Vk + i0 * fmt_bytes(F)));
+        T::dec(q, s, d);
+        if (i0 + VW > n) {
+#pragma unroll
+            for (int e = 0; e < VW; ++e)
+                if (i0 + e >= n)
+                    d[e] = 0.0;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < VW; ++e)
+            d[e] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Scalar work of a step, done by the last block of a reduction.
+// ---------------------------------------------------------------------------
+
+struct StepArrays {
+    double *H;         // (m+1) x m, column-major, rotated in place
+    double *h, *u;     // m+1
+    double *cs, *sn;   // m
+    double *g;         // m+2
+    double *y;         // m
+    double *hist;      // m: recurrence residual of each step of the cycle
+    double *scales;    // m+1: per-vector scales of the stored basis
+    int32_t *flags;    // m: bit0 re-orthogonalised, bit1 breakdown
+};
+
+// Fig. 1 steps 9-12 and the column-by-column Givens update of step 17.
+// Reading of step 12 (the literal test would end every re-orthogonalised
+// cycle): breakdown iff h_{j+1,j} = 0, or the second pass again lost more
+// than a factor eta.
+__device__ void finish_step(DevState *st, const StepArrays &a, int j, bool reorth, double t2,
+                            double wmax2)
+{
+    const int m = st->m;
+    double t = st->t;
+    bool brk;
+    if (reorth) {
+        for (int k = 0; k < j; ++k)
+            a.h[k] += a.u[k];
+        brk = (t2 == 0.0) || (t2 < st->eta * t);
+        t = t2;
+        st->wmax = wmax2;
+        st->reorths += 1;
+    } else {
+        brk = (t == 0.0);
+    }
+    st->t = t;
+    const int jc = j - 1;
+    double *Hc = a.H + (size_t)jc * (m + 1);
+    for (int k = 0; k < j; ++k)
+        Hc[k] = a.h[k];
+    Hc[j] = t;
+    for (int i = 0; i < jc; ++i) {
+        double a0 = Hc[i], a1 = Hc[i + 1];
+        Hc[i] = a.cs[i] * a0 + a.sn[i] * a1;
+        Hc[i + 1] = -a.sn[i] * a0 + a.cs[i] * a1;
+    }
+    double x0 = Hc[jc], x1 = Hc[j];
+    double rr = sqrt(x0 * x0 + x1 * x1);
+    double c = 1.0, s = 0.0;
+    if (rr > 0.0) {
+        c = x0 / rr;
+        s = x1 / rr;
+    }
+    a.cs[jc] = c;
+    a.sn[jc] = s;
+    Hc[jc] = rr;
+    Hc[j] = 0.0;
+    a.g[j] = -s * a.g[jc];
+    a.g[jc] = c * a.g[jc];
+    st->it += 1;
+    double rec = fabs(a.g[j]) / st->nb;
+    a.hist[jc] = rec;
+    st->last_rec = rec;
+    bool finite = isfinite(st->omega) && isfinite(t) && isfinite(a.g[j]);
+    bool conv = fabs(a.g[j]) <= st->tau_nb;
+    if (brk)
+        st->breakdowns += 1;
+    a.flags[jc] = (reorth ? 1 : 0) | (brk ? 2 : 0);
+    st->jeff = j;
+    if (!finite)
+        st->nonfinite = 1;
+    if (brk || conv || st->it >= st->maxiter || !finite || j == m) {
+        st->done = 1;
+        st->conv = conv ? 1 : 0;
+    } else {
+        a.scales[j] = make_param(st->fmt, st->wmax / t).scale;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Utility kernels.
+// ---------------------------------------------------------------------------
+
+__global__ void k_init_state(DevState *st, int n, int m, int fmt, double tol, double eta,
+                             int64_t maxiter)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        DevState s{};
+        s.n = n;
+        s.m = m;
+        s.fmt = fmt;
+        s.eta = eta;
+        s.maxiter = maxiter;
+        s.tau_nb = tol;       // scaled by ||b|| once it is known
+        *st = s;
+    }
+}
+
+// dinv_i = 1 / a_ii (Jacobi); rows >= n get 0.  bad != 0 if a diagonal entry
+// is missing, zero or not finite.
+__global__ void k_jacobi_setup(int n, int64_t ld, const int32_t *__restrict__ rp,
+                               const int32_t *__restrict__ ci, const double *__restrict__ val,
+                               double *__restrict__ dinv, unsigned *bad)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ld;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (i >= n) {
+            dinv[i] = 0.0;
+            continue;
+        }
+        double d = 0.0;
+        for (int p = rp[i]; p < rp[i + 1]; ++p)
+            if (ci[p] == i)
+                d = val[p];
+        if (d == 0.0 || !isfinite(d))
+            atomicOr(bad, 1u);
+        dinv[i] = 1.0 / d;
+    }
+}
+
+// Block partials of ||x||_2^2 and ||x||_inf of a length-n vector (two
+// values, in the SpMV partial region).
+__global__ __launch_bounds__(BLK) void k_norm(const double *__restrict__ x, int64_t n, RedArgs ra)
+{
+    double s = 0.0, m = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)BLK + threadIdx.x; i < n; i += (int64_t)gridDim.x * BLK) {
+        double v = x[i];
+        s += v * v;
+        m = fmax(m, fabs(v));
+    }
+    block_sum_max(s, m);
+    if (threadIdx.x == 0) {
+        ra.part[blockIdx.x] = s;
+        ra.part[(size_t)ra.stride + blockIdx.x] = m;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// CSR SpMV, CSR-stream style (after Greathouse and Daga, SC'14): a block owns
+// RPB consecutive rows.  Phase 1 walks the block's nonzeros with unit stride
+// across the threads (coalesced val/col loads, x gathered through the
+// caches) and stages the products a_p * x_col(p) in LDS; phase 2 sums each
+// row from LDS with 256/RPB threads per row.  A block whose rows hold more
+// than CAP nonzeros sums them straight from memory instead.  Rows in
+// [n, ldy) are written as 0 (padding of the solver's work vectors).
+// ---------------------------------------------------------------------------
+
+enum {
+    SP_PLAIN = 0,      // y = A x
+    SP_JACOBI = 1,     // y = A (dinv .* x)
+    SP_RESID = 2,      // y = b - A x
+    SP_FLOATVAL = 3,   // y = P x, P with float values on A's pattern
+    SP_ACCUM = 4       // y += P x (P float values), y of length n
+};
+// roles: SR_NONE no partials (skipped once the cycle is done); SR_STEP
+// partials of ||y||^2 and max|y_i| (skipped once done); SR_FREE partials,
+// never skipped (explicit residual, kernel-level calls).
+enum { SR_NONE = 0, SR_STEP = 1, SR_FREE = 2 };
+
+template <int MODE>
+__device__ __forceinline__ double spmv_term(int p, const int32_t *__restrict__ ci,
+                                            const double *__restrict__ val,
+                                            const float *__restrict__ fval,
+                                            const double *__restrict__ x,
+                                            const double *__restrict__ dinv)
+{
+    const int c = ci[p];
+    double a;
+    if constexpr (MODE == SP_FLOATVAL || MODE == SP_ACCUM)
+        a = (double)fval[p];
+    else
+        a = val[p];
+    double xv = x[c];
+    if constexpr (MODE == SP_JACOBI)
+        xv = dinv[c] * xv;
+    return a * xv;
+}
+
+template <int RPB, int CAP, int MODE>
+__global__ __launch_bounds__(BLK) void k_spmv(int n, int64_t ldy, const int32_t *__restrict__ rp,
+                                              const int32_t *__restrict__ ci,
+                                              const double *__restrict__ val,
+                                              const float *__restrict__ fval,
+                                              const double *__restrict__ x,
+                                              const double *__restrict__ dinv,
+                                              const double *__restrict__ b,
+                                              double *__restrict__ y, RedArgs ra, int role,
+                                              const DevState *st)
+{
+    if (st && role != SR_FREE && st->done)
+        return;
+    constexpr int TPR = BLK / RPB;          // threads per row in the sum phase
+    constexpr int UNR = 4;                  // products per thread per batch
+    __shared__ double prod[CAP];
+    __shared__ int lrp[RPB + 1];
+    const int tid = threadIdx.x;
+    double ssq = 0.0, mx = 0.0;
+    const int64_t nblk = (ldy + RPB - 1) / RPB;
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const int64_t r0 = blk * RPB;
+        const int nr = r0 < n ? (int)min((int64_t)RPB, (int64_t)n - r0) : 0;   // rows with entries
+        __syncthreads();                    // LDS reuse across iterations
+        for (int t = tid; t <= nr && nr > 0; t += BLK)
+            lrp[t] = rp[r0 + t];
+        __syncthreads();
+        const int p0 = nr > 0 ? lrp[0] : 0;
+        const int cnt = nr > 0 ? lrp[nr] - p0 : 0;
+        const bool staged = cnt <= CAP;
+        if (staged && cnt > 0) {
+            for (int q = tid; q < cnt; q += BLK * UNR) {
+                double v[UNR];
+#pragma unroll
+                for (int u = 0; u < UNR; ++u) {
+                    const int qq = min(q + u * BLK, cnt - 1);      // clamped: loads stay in bounds
+                    v[u] = spmv_term<MODE>(p0 + qq, ci, val, fval, x, dinv);
+                }
+#pragma unroll
+                for (int u = 0; u < UNR; ++u)
+                    if (q + u * BLK < cnt)
+                        prod[q + u * BLK] = v[u];
+            }
+        }
+        __syncthreads();
+        const int lr = tid / TPR, part = tid % TPR;
+        const int64_t row = r0 + lr;
+        double s = 0.0;
+        if (lr < nr) {
+            const int a0 = lrp[lr] - p0, a1 = lrp[lr + 1] - p0;
+            if (staged) {
+                for (int q = a0 + part; q < a1; q += TPR)
+                    s += prod[q];
+            } else {
+                for (int q = a0 + part; q < a1; q += TPR)
+                    s += spmv_term<MODE>(p0 + q, ci, val, fval, x, dinv);
+            }
+        }
+#pragma unroll
+        for (int d = TPR / 2; d >= 1; d >>= 1)
+            s += __shfl_xor(s, d);
+        if (part == 0 && row < ldy) {
+            double yv;
+            if constexpr (MODE == SP_RESID)
+                yv = row < n ? b[row] - s : 0.0;
+            else if constexpr (MODE == SP_ACCUM)
+                yv = y[row] + s;
+            else
+                yv = row < n ? s : 0.0;
+            y[row] = yv;
+            ssq += yv * yv;
+            mx = fmax(mx, fabs(yv));
+        }
+    }
+    if (role == SR_NONE)
+        return;
+    block_sum_max(ssq, mx);
+    if (threadIdx.x == 0) {
+        ra.part[blockIdx.x] = ssq;
+        ra.part[(size_t)ra.stride + blockIdx.x] = mx;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Multi-dot through the accessor: h_k = sum_i dec(V_k)_i w_i, k < j.
+// Each block keeps a tile of w in registers and streams the stored vectors
+// KC at a time.  In full tiles every load of a batch is issued before any
+// is used (no bounds test between them); only the ragged last tile takes
+// the guarded path.  Per-lane partials are reduced across the wave by a
+// transposing butterfly, across waves in LDS, across tiles in LDS, and
+// across blocks by the fixed-order grid reduction.
+// ---------------------------------------------------------------------------
+
+
+template <int F>
+__device__ __forceinline__ u32x4 ld_chunk(const uint8_t *__restrict__ V, int64_t ldb, int k,
+                                          int64_t i0)
+{
+    return __builtin_nontemporal_load(
+        (const u32x4 *)(V + (int64_t)k * ldb + i0 * fmt_bytes(F)));
+}
+
+template <int F>
+__global__ __launch_bounds__(BLK) CBG_MD_ATTR void k_multidot(const uint8_t *__restrict__ V, int64_t ld,
+                                                  const double *__restrict__ scales, int n, int j,
+                                                  const double *__restrict__ w, RedArgs ra,
+                                                  const DevState *st, int gated, int with_norms)
+{
+    if (gated && st->done)
+        return;
+    using T = Fmt<F>;
+    constexpr int VW = T::VW, CH = T::CH, KC = T::KC;
+    constexpr int TILE = BLK * VW * CH;
+    const int64_t ldb = ld * fmt_bytes(F);
+    // per-wave running sums over the block's tiles: no barrier until the end
+    __shared__ double wacc[NWAVE][MAX_RESTART + 1];
+    for (int k = threadIdx.x; k < NWAVE * (MAX_RESTART + 1); k += BLK)
+        (&wacc[0][0])[k] = 0.0;
+    __syncthreads();
+    const int64_t ntiles = ((int64_t)n + TILE - 1) / TILE;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double ssq = 0.0, mx = 0.0;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const bool full = (tile + 1) * TILE <= n;
+        double wr[CH * VW];
+        int64_t i0[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            i0[c] = tile * TILE + ((int64_t)c * BLK + threadIdx.x) * VW;
+            load_w<VW>(w, n, i0[c], wr + c * VW);
+        }
+        if (with_norms) {
+#pragma unroll
+            for (int e = 0; e < CH * VW; ++e) {
+                ssq += wr[e] * wr[e];
+                mx = fmax(mx, fabs(wr[e]));
+            }
+        }
+        for (int kc = 0; kc < j; kc += KC) {
+            double acc[KC];
+            if (full) {
+                u32x4 raw[KC][CH];
+#pragma unroll
+                for (int kk = 0; kk < KC; ++kk)
+#pragma unroll
+                    for (int c = 0; c < CH; ++c)
+                        raw[kk][c] = ld_chunk<F>(V, ldb, min(kc + kk, j - 1), i0[c]);
+#pragma unroll
+                for (int kk = 0; kk < KC; ++kk) {
+                    const double s = T::SCALED ? scales[min(kc + kk, j - 1)] : 1.0;
+                    double a = 0.0;
+#pragma unroll
+                    for (int c = 0; c < CH; ++c) {
+                        double d[VW];
+                        T::dec(raw[kk][c], s, d);
+#pragma unroll
+                        for (int e = 0; e < VW; ++e)
+                            a = fma(d[e], wr[c * VW + e], a);
+                    }
+                    acc[kk] = a;
+                }
+            } else {
+#pragma unroll
+                for (int kk = 0; kk < KC; ++kk) {
+                    const int k = min(kc + kk, j - 1);
+                    const double s = T::SCALED ? scales[k] : 1.0;
+                    const uint8_t *Vk = V + (int64_t)k * ldb;
+                    double a = 0.0;
+#pragma unroll
+                    for (int c = 0; c < CH; ++c) {
+                        double d[VW];
+                        load_dec<F>(Vk, i0[c], n, s, d);
+#pragma unroll
+                        for (int e = 0; e < VW; ++e)
+                            a = fma(d[e], wr[c * VW + e], a);
+                    }
+                    acc[kk] = a;
+                }
+            }
+            wave_transpose_sum<KC>(acc);
+            if (lane < KC) {
+                const int k = kc + bitrev<KC>(lane);
+                if (k < j)
+                    wacc[wave][k] += acc[0];
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < j; k += BLK) {
+        double t = wacc[0][k];
+#pragma unroll
+        for (int q = 1; q < NWAVE; ++q)
+            t += wacc[q][k];
+        ra.part[(size_t)k * ra.stride + blockIdx.x] = t;
+    }
+    if (with_norms) {
+        block_sum_max(ssq, mx);
+        if (threadIdx.x == 0) {
+            ra.part[(size_t)j * ra.stride + blockIdx.x] = ssq;
+            ra.part[(size_t)(j + 1) * ra.stride + blockIdx.x] = mx;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Basis combination through the accessor: s = sum_k c_k dec(V_k), k < j.
+//   U_PLAIN / U_STEP1 / U_STEP2: w -= s, with ||w||_2 and ||w||_inf;
+//   U_SOLUTION: x += dinv .* s (Jacobi) or x += s;  U_COMBINE: out = s.
+// Full tiles stream the vectors UNR at a time with the next batch's loads
+// in flight while the current batch is decoded and accumulated.
+// ---------------------------------------------------------------------------
+
+enum { U_PLAIN = 0, U_STEP1 = 1, U_STEP2 = 2, U_SOLUTION = 3, U_COMBINE = 4 };
+
+template <int F, int ROLE>
+__global__ __launch_bounds__(BLK) void k_update(const uint8_t *__restrict__ V, int64_t ld,
+                                                const double *__restrict__ scales, int n, int j_arg,
+                                                const double *__restrict__ coef,
+                                                double *__restrict__ w,
+                                                const double *__restrict__ dinv, RedArgs ra,
+                                                const DevState *st)
+{
+    int j = j_arg;
+    if constexpr (ROLE == U_STEP1 || ROLE == U_STEP2) {
+        if (st->done)
+            return;
+        if (ROLE == U_STEP2 && !st->reorth)
+            return;
+    }
+    if constexpr (ROLE == U_SOLUTION || ROLE == U_COMBINE)
+        j = st->jeff;
+    using T = Fmt<F>;
+    constexpr int VW = T::VW, CH = T::CH, UNR = T::UNR;
+    constexpr int TILE = BLK * VW * CH;
+    const int64_t ldb = ld * fmt_bytes(F);
+    const int64_t ntiles = ((int64_t)n + TILE - 1) / TILE;
+    double ssq = 0.0, mx = 0.0;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const bool full = (tile + 1) * TILE <= n;
+        double s[CH * VW];
+        int64_t i0[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            i0[c] = tile * TILE + ((int64_t)c * BLK + threadIdx.x) * VW;
+#pragma unroll
+            for (int e = 0; e < VW; ++e)
+                s[c * VW + e] = 0.0;
+        }
+        if (full && j > 0) {
+            u32x4 cur[UNR][CH];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u)
+#pragma unroll
+                for (int c = 0; c < CH; ++c)
+                    cur[u][c] = ld_chunk<F>(V, ldb, min(u, j - 1), i0[c]);
+            for (int kg = 0; kg < j; kg += UNR) {
+                u32x4 nxt[UNR][CH];
+#pragma unroll
+                for (int u = 0; u < UNR; ++u)
+#pragma unroll
+                    for (int c = 0; c < CH; ++c)
+                        nxt[u][c] = ld_chunk<F>(V, ldb, min(kg + UNR + u, j - 1), i0[c]);
+#pragma unroll
+                for (int u = 0; u < UNR; ++u) {
+                    const int k = min(kg + u, j - 1);
+                    const double ck = (kg + u < j) ? coef[k] : 0.0;
+                    const double sk = T::SCALED ? scales[k] : 1.0;
+#pragma unroll
+                    for (int c = 0; c < CH; ++c) {
+                        double d[VW];
+                        T::dec(cur[u][c], sk, d);
+#pragma unroll
+                        for (int e = 0; e < VW; ++e)
+                            s[c * VW + e] = fma(ck, d[e], s[c * VW + e]);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < UNR; ++u)
+#pragma unroll
+                    for (int c = 0; c < CH; ++c)
+                        cur[u][c] = nxt[u][c];
+            }
+        } else {
+            for (int k = 0; k < j; ++k) {
+                const double ck = coef[k];
+                const double sk = T::SCALED ? scales[k] : 1.0;
+                const uint8_t *Vk = V + (int64_t)k * ldb;
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    double d[VW];
+                    load_dec<F>(Vk, i0[c], n, sk, d);
+#pragma unroll
+                    for (int e = 0; e < VW; ++e)
+                        s[c * VW + e] = fma(ck, d[e], s[c * VW + e]);
+                }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            double o[VW];
+            if constexpr (ROLE == U_COMBINE) {
+#pragma unroll
+                for (int e = 0; e < VW; ++e)
+                    o[e] = s[c * VW + e];
+            } else if constexpr (ROLE == U_SOLUTION) {
+                load_w<VW>(w, n, i0[c], o);
+                if (dinv) {
+                    double dv[VW];
+                    load_w<VW>(dinv, n, i0[c], dv);
+#pragma unroll
+                    for (int e = 0; e < VW; ++e)
+                        o[e] = o[e] + dv[e] * s[c * VW + e];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VW; ++e)
+                        o[e] = o[e] + s[c * VW + e];
+                }
+            } else {
+                load_w<VW>(w, n, i0[c], o);
+#pragma unroll
+                for (int e = 0; e < VW; ++e) {
+                    o[e] = o[e] - s[c * VW + e];
+                    ssq += o[e] * o[e];
+                    mx = fmax(mx, fabs(o[e]));
+                }
+            }
+            store_w<VW>(w, n, i0[c], o);
+        }
+    }
+    if constexpr (ROLE == U_SOLUTION || ROLE == U_COMBINE || ROLE == U_STEP1)
+        return;
+    block_sum_max(ssq, mx);
+    if (threadIdx.x == 0) {
+        ra.part[blockIdx.x] = ssq;
+        ra.part[(size_t)ra.stride + blockIdx.x] = mx;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One-block reductions of the producers' partials (fixed order: lane l sums
+// blocks l, l+64, ... in turn, then a butterfly across the wave), followed
+// by the scalar work that needs the totals.
+// ---------------------------------------------------------------------------
+
+// Roles (RR_* in the launch header):
+//   RR_NB      ||b||: solve set-up
+//   RR_SCALE   kernel-level encode: scale of a vector from max|v|
+//   RR_NORM2   kernel-level SpMV: ||y||_2
+//   RR_RESID   explicit residual: start of a restart cycle (Fig. 1 step 1)
+//   RR_H       h = V^T w and omega (steps 4-5)
+//   RR_U       u = V^T w, h_{j+1,j}, max|w|, and the test of step 7
+//   RR_T2      after the re-orthogonalisation pass (steps 9-12)
+//   RR_VALUES  kernel-level multi-dot
+//   RR_NORMS   kernel-level update: ||w||_2, ||w||_inf
+
+constexpr int RBLK = 1024;
+
+__global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth, int nb_spmv,
+                                                 int j, DevState *st, StepArrays sa,
+                                                 double *out, int fmt)
+{
+    if (role == RR_H || role == RR_U || role == RR_T2) {
+        if (st->done)
+            return;
+        if (role == RR_T2 && !st->reorth)
+            return;
+    }
+    __shared__ double val[MAX_RESTART + 4];
+    // output v: source region (0 orth, 1 spmv), row in that region, block
+    // count, and whether it is a maximum
+    int nv;
+    switch (role) {
+    case RR_H: nv = j + 1; break;
+    case RR_U: nv = j + 2; break;
+    case RR_VALUES: nv = j; break;
+    default: nv = 2; break;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int v = wave; v < nv; v += RBLK / 64) {
+        const double *src;
+        int nb;
+        bool is_max;
+        if (role == RR_NB || role == RR_SCALE || role == RR_NORM2 || role == RR_RESID) {
+            src = ws.spmv + (size_t)v * ws.stride;
+            nb = nb_spmv;
+            is_max = v == 1;
+        } else if (role == RR_H && v == j) {
+            src = ws.spmv;
+            nb = nb_spmv;
+            is_max = false;
+        } else if (role == RR_T2 || role == RR_NORMS) {
+            src = ws.orth + (size_t)v * ws.stride;
+            nb = nb_orth;
+            is_max = v == 1;
+        } else {
+            src = ws.orth + (size_t)v * ws.stride;
+            nb = nb_orth;
+            is_max = (role == RR_U && v == j + 1);
+        }
+        double a = 0.0;
+        for (int b = lane; b < nb; b += 64)
+            a = is_max ? fmax(a, src[b]) : a + src[b];
+        a = is_max ? wave_max(a) : wave_sum(a);
+        if (lane == 0)
+            val[v] = a;
+    }
+    __syncthreads();
+    const int tid = threadIdx.x;
+    switch (role) {
+    case RR_NB:
+        if (tid == 0) {
+            const double nb = sqrt(val[0]);
+            st->nb = nb;
+            st->tau_nb = st->tau_nb * nb;
+            if (!isfinite(nb))
+                st->nonfinite = 1;
+        }
+        break;
+    case RR_SCALE:
+        if (tid == 0)
+            *out = make_param(fmt, val[1]).scale;
+        break;
+    case RR_NORM2:
+        if (tid == 0)
+            *out = sqrt(val[0]);
+        break;
+    case RR_NORMS:
+        if (tid == 0 && out) {
+            out[0] = sqrt(val[0]);
+            out[1] = val[1];
+        }
+        break;
+    case RR_VALUES:
+        for (int k = tid; k < j; k += RBLK)
+            out[k] = val[k];
+        break;
+    case RR_RESID: {
+        const double beta = sqrt(val[0]);
+        const int m = st->m;
+        for (int i = tid; i < m + 2; i += RBLK)
+            sa.g[i] = 0.0;
+        __syncthreads();
+        if (tid == 0) {
+            st->jprev = st->jeff;
+            st->beta = beta;
+            st->rmax = val[1];
+            st->t = beta;
+            st->done = 0;
+            st->jeff = 0;
+            st->reorth = 0;
+            st->conv = 0;
+            sa.g[0] = beta;
+            if (!isfinite(beta))
+                st->nonfinite = 1;
+            sa.scales[0] = beta > 0.0 ? make_param(st->fmt, val[1] / beta).scale : 1.0;
+        }
+        break;
+    }
+    case RR_H:
+        for (int k = tid; k < j; k += RBLK)
+            sa.h[k] = val[k];
+        if (tid == 0)
+            st->omega = sqrt(val[j]);
+        break;
+    case RR_U: {
+        for (int k = tid; k < j; k += RBLK)
+            sa.u[k] = val[k];
+        __syncthreads();
+        if (tid == 0) {
+            // Fig. 1 steps 6-7
+            const double t = sqrt(val[j]);
+            st->t = t;
+            st->wmax = val[j + 1];
+            const bool ro = t < st->eta * st->omega;
+            st->reorth = ro ? 1 : 0;
+            if (!ro)
+                finish_step(st, sa, j, false, 0.0, 0.0);
+        }
+        break;
+    }
+    case RR_T2:
+        if (tid == 0)
+            finish_step(st, sa, j, true, sqrt(val[0]), val[1]);
+        break;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Normalise and store through the accessor (Fig. 1 steps 13-14):
+// v = w / t (IEEE division), v_out = v (FP64, the next SpMV input) and
+// Q = enc(v) with the slot's scale.  Entries in [n, nst) are stored as 0.
+// ---------------------------------------------------------------------------
+
+template <int F>
+__global__ __launch_bounds__(BLK) void k_normalize(const double *__restrict__ w, int n,
+                                                   int64_t nst, double *__restrict__ v_out,
+                                                   uint8_t *__restrict__ Q,
+                                                   const double *__restrict__ scale_slot,
+                                                   const double *__restrict__ tptr, double tval,
+                                                   const DevState *st, int check_done, int fmt)
+{
+    if (check_done && st->done)
+        return;
+    using T = Fmt<F>;
+    constexpr int VW = T::VW;
+    const double t = tptr ? *tptr : tval;
+    const EncParam p = param_from_scale(fmt, *scale_slot);
+    const int64_t nchunks = (nst + VW - 1) / VW;
+    for (int64_t c = blockIdx.x * (int64_t)BLK + threadIdx.x; c < nchunks;
+         c += (int64_t)gridDim.x * BLK) {
+        const int64_t i0 = c * VW;
+        double v[VW];
+        load_w<VW>(w, n, i0, v);
+#pragma unroll
+        for (int e = 0; e < VW; ++e)
+            v[e] = v[e] / t;
+        if (v_out)
+            store_w<VW>(v_out, nst, i0, v);
+        u32x4 q = T::enc(v, p);
+        if (i0 + VW <= nst) {
+            *(u32x4 *)(Q + i0 * fmt_bytes(F)) = q;
+        } else {
+            const uint8_t *qb = (const uint8_t *)&q;
+            for (int64_t b = 0; b < (nst - i0) * fmt_bytes(F); ++b)
+                Q[i0 * fmt_bytes(F) + b] = qb[b];
+        }
+    }
+}
+
+// The accessor's load for the kernel-level API: v = dec(q) exactly.
+template <int F>
+__global__ __launch_bounds__(BLK) void k_decode(const uint8_t *__restrict__ Q, int n,
+                                                const double *__restrict__ scale,
+                                                double *__restrict__ v)
+{
+    using T = Fmt<F>;
+    constexpr int VW = T::VW;
+    const double s = T::SCALED ? *scale : 1.0;
+    const int64_t nchunks = ((int64_t)n + VW - 1) / VW;
+    for (int64_t c = blockIdx.x * (int64_t)BLK + threadIdx.x; c < nchunks;
+         c += (int64_t)gridDim.x * BLK) {
+        const int64_t i0 = c * VW;
+        double d[VW];
+        if (i0 + VW <= n) {
+            u32x4 q = *(const u32x4 *)(Q + i0 * fmt_bytes(F));
+            T::dec(q, s, d);
+        } else {
+            u32x4 q = {0u, 0u, 0u, 0u};
+            uint8_t *qb = (uint8_t *)&q;
+            for (int64_t b = 0; b < (n - i0) * fmt_bytes(F); ++b)
+                qb[b] = Q[i0 * fmt_bytes(F) + b];
+            T::dec(q, s, d);
+        }
+        store_w<VW>(v, n, i0, d);
+    }
+}
+
+// Back substitution R y = g for the cycle's least-squares problem (Fig. 1
+// step 17); R is the rotated Hessenberg matrix.  One wavefront, column
+// oriented: y_i = g_i / R_ii, then g_k -= R_ki y_i for k < i in parallel.
+__global__ __launch_bounds__(64) void k_backsolve(const DevState *st, StepArrays sa)
+{
+    __shared__ double gl[MAX_RESTART + 2];
+    __shared__ double yi;
+    const int jeff = st->jeff, m = st->m;
+    for (int i = threadIdx.x; i < jeff; i += 64)
+        gl[i] = sa.g[i];
+    __syncthreads();
+    for (int i = jeff - 1; i >= 0; --i) {
+        if (threadIdx.x == 0) {
+            yi = gl[i] / sa.H[(size_t)i * (m + 1) + i];
+            sa.y[i] = yi;
+        }
+        __syncthreads();
+        const double* Hi = sa.H + (size_t)i * (m + 1);
+        for (int k = threadIdx.x; k < i; k += 64)
+            gl[k] -= Hi[k] * yi;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+
+static int grid_for(int64_t work_items, int per_block)
+{
+    int64_t g = (work_items + per_block - 1) / per_block;
+    if (g < 1)
+        g = 1;
+    if (g > MAX_GRID)
+        g = MAX_GRID;
+    return (int)g;
+}
+
+// Rows per block of the CSR-stream SpMV, from the mean row length.
+int spmv_lanes(int n, int64_t nnz)
+{
+    double avg = n > 0 ? (double)nnz / n : 1.0;
+    if (avg <= 7.5) return 256;
+    if (avg <= 30.0) return 128;
+    if (avg <= 60.0) return 64;
+    return 32;
+}
+
+template <int RPB, int CAP>
+static int spmv_shape(const SpmvArgs &a, hipStream_t s)
+{
+    int g = grid_for((a.ldy + RPB - 1) / RPB, 1);
+    RedArgs ra{a.ws.spmv, a.ws.stride};
+#define CBG_SPMV_CASE(M)                                                                      \
+    case M:                                                                                   \
+        k_spmv<RPB, CAP, M><<<g, BLK, 0, s>>>(a.n, a.ldy, a.rp, a.ci, a.val, a.fval, a.x,     \
+                                               a.dinv, a.b, a.y, ra, a.role, a.st);           \
+        break;
+    switch (a.mode) {
+        CBG_SPMV_CASE(SP_PLAIN)
+        CBG_SPMV_CASE(SP_JACOBI)
+        CBG_SPMV_CASE(SP_RESID)
+        CBG_SPMV_CASE(SP_FLOATVAL)
+        CBG_SPMV_CASE(SP_ACCUM)
+    }
+#undef CBG_SPMV_CASE
+    return g;
+}
+
+int launch_spmv(const SpmvArgs &a, hipStream_t s)
+{
+    switch (a.sg) {
+    case 256: return spmv_shape<256, 2048>(a, s);
+    case 128: return spmv_shape<128, 4096>(a, s);
+    case 64: return spmv_shape<64, 4096>(a, s);
+    default: return spmv_shape<32, 4096>(a, s);
+    }
+}
+
+int spmv_grid(int sg, int64_t ldy) { return grid_for((ldy + sg - 1) / sg, 1); }
+
+template <int F>
+static int tile_elems() { return BLK * Fmt<F>::VW * Fmt<F>::CH; }
+
+#define CBG_FMT_SWITCH(fmt, CALL)                  \
+    switch (fmt) {                                 \
+    case F_FP64: { constexpr int F = F_FP64; CALL; } break; \
+    case F_FP32: { constexpr int F = F_FP32; CALL; } break; \
+    case F_FP16: { constexpr int F = F_FP16; CALL; } break; \
+    case F_BF16: { constexpr int F = F_BF16; CALL; } break; \
+    case F_E4M3: { constexpr int F = F_E4M3; CALL; } break; \
+    case F_INT32: { constexpr int F = F_INT32; CALL; } break; \
+    default: { constexpr int F = F_INT16; CALL; } break;    \
+    }
+
+int orth_grid(int fmt, int64_t n)
+{
+    int tile = 0;
+    CBG_FMT_SWITCH(fmt, (tile = tile_elems<F>()))
+    return grid_for(n, tile);
+}
+
+void launch_multidot(const OrthArgs &a, hipStream_t s)
+{
+    int g = orth_grid(a.fmt, a.n);
+    RedArgs ra{a.ws.orth, a.ws.stride};
+    CBG_FMT_SWITCH(a.fmt, (k_multidot<F><<<g, BLK, 0, s>>>((const uint8_t *)a.V, a.ld, a.scales,
+                                                            a.n, a.j, a.w, ra, a.st, a.gated,
+                                                            a.with_norms)))
+}
+
+void launch_update(const OrthArgs &a, hipStream_t s)
+{
+    int g = orth_grid(a.fmt, a.n);
+    RedArgs ra{a.ws.orth, a.ws.stride};
+    const uint8_t *V = (const uint8_t *)a.V;
+#define CBG_UPD(R)                                                                            \
+    CBG_FMT_SWITCH(a.fmt, (k_update<F, R><<<g, BLK, 0, s>>>(V, a.ld, a.scales, a.n, a.j,       \
+                                                             a.coef, a.wio, a.dinv, ra, a.st)))
+    switch (a.role) {
+    case U_PLAIN: CBG_UPD(U_PLAIN) break;
+    case U_STEP1: CBG_UPD(U_STEP1) break;
+    case U_STEP2: CBG_UPD(U_STEP2) break;
+    case U_SOLUTION: CBG_UPD(U_SOLUTION) break;
+    default: CBG_UPD(U_COMBINE) break;
+    }
+#undef CBG_UPD
+}
+
+void launch_reduce(const RedWs &ws, int role, int nb_orth, int nb_spmv, int j, DevState *st,
+                   const void *sa, double *out, int fmt, hipStream_t s)
+{
+    StepArrays a{};
+    if (sa)
+        a = *(const StepArrays *)sa;
+    k_reduce<<<1, RBLK, 0, s>>>(ws, role, nb_orth, nb_spmv, j, st, a, out, fmt);
+}
+
+void launch_normalize(int fmt, const double *w, int n, int64_t nst, double *v_out, void *Q,
+                      const double *scale_slot, const double *tptr, double tval,
+                      const DevState *st, int check_done, hipStream_t s)
+{
+    int vw = fmt == F_FP64 ? 2 : (fmt == F_FP32 || fmt == F_INT32) ? 4 : fmt == F_E4M3 ? 16 : 8;
+    int g = grid_for((nst + vw - 1) / vw, BLK);
+    CBG_FMT_SWITCH(fmt, (k_normalize<F><<<g, BLK, 0, s>>>(w, n, nst, v_out, (uint8_t *)Q,
+                                                           scale_slot, tptr, tval, st,
+                                                           check_done, fmt)))
+}
+
+void launch_decode(int fmt, const void *Q, int n, const double *scale, double *v, hipStream_t s)
+{
+    int vw = fmt == F_FP64 ? 2 : (fmt == F_FP32 || fmt == F_INT32) ? 4 : fmt == F_E4M3 ? 16 : 8;
+    int g = grid_for(((int64_t)n + vw - 1) / vw, BLK);
+    CBG_FMT_SWITCH(fmt, (k_decode<F><<<g, BLK, 0, s>>>((const uint8_t *)Q, n, scale, v)))
+}
+
+int launch_norm(const double *x, int64_t n, const RedWs &ws, hipStream_t s)
+{
+    int g = grid_for(n, BLK * 4);
+    k_norm<<<g, BLK, 0, s>>>(x, n, RedArgs{ws.spmv, ws.stride});
+    return g;
+}
+
+void launch_init_state(DevState *st, int n, int m, int fmt, double tol, double eta,
+                       int64_t maxiter, hipStream_t s)
+{
+    k_init_state<<<1, 64, 0, s>>>(st, n, m, fmt, tol, eta, maxiter);
+}
+
+void launch_jacobi_setup(int n, int64_t ld, const int32_t *rp, const int32_t *ci,
+                         const double *val, double *dinv, unsigned *bad, hipStream_t s)
+{
+    k_jacobi_setup<<<grid_for(ld, BLK), BLK, 0, s>>>(n, ld, rp, ci, val, dinv, bad);
+}
+
+__global__ void k_clear_flags(DevState *st, unsigned *bad)
+{
+    if (threadIdx.x == 0) {
+        if (st)
+            st->nonfinite = 0;
+        if (bad)
+            *bad = 0u;
+    }
+}
+
+void launch_clear_flags(DevState *st, unsigned *bad, hipStream_t s)
+{
+    k_clear_flags<<<1, 64, 0, s>>>(st, bad);
+}
+
+void launch_backsolve(const DevState *st, const void *sa, hipStream_t s)
+{
+    k_backsolve<<<1, 64, 0, s>>>(st, *(const StepArrays *)sa);
+}
+
+size_t step_arrays_size() { return sizeof(StepArrays); }
+
+void make_step_arrays(void *out, double *H, double *h, double *u, double *cs, double *sn,
+                      double *g, double *y, double *hist, double *scales, int32_t *flags)
+{
+    StepArrays *a = (StepArrays *)out;
+    a->H = H; a->h = h; a->u = u; a->cs = cs; a->sn = sn; a->g = g; a->y = y;
+    a->hist = hist; a->scales = scales; a->flags = flags;
+}
+
+}  // namespace cbg

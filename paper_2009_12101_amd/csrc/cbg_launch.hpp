@@ -1,0 +1,77 @@
+// Host-side launch interface between the C ABI / solver loop and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cbg {
+
+struct DevState;
+
+// Block-partial scratch carved from a workspace (value-major, see RedArgs).
+struct RedWs {
+    double *orth;     // multi-dot / update partials: (max j + 2) rows of `stride`
+    double *spmv;     // SpMV / norm partials: 2 rows of `stride`
+    int stride;       // >= the grid of every producer
+};
+
+struct SpmvArgs {
+    int n;
+    int64_t ldy;          // rows written (>= n; [n, ldy) written as 0)
+    const int32_t *rp, *ci;
+    const double *val;
+    const float *fval;
+    const double *x, *dinv, *b;
+    double *y;
+    RedWs ws;
+    int mode;             // SP_* of the kernels
+    int role;             // SR_*: 0 none, 1 step (partials, skipped when done), 2 free
+    int sg;               // rows per block (spmv_lanes)
+    const DevState *st;
+};
+
+struct OrthArgs {
+    int fmt;
+    const void *V;
+    int64_t ld;
+    const double *scales;
+    int n, j;
+    const double *w;      // multi-dot input
+    int gated;            // multi-dot: skipped once the cycle is done
+    int with_norms;       // multi-dot: also partials of ||w||^2 and max|w_i|
+    const double *coef;   // update coefficients
+    double *wio;          // update: the vector updated in place (or written)
+    const double *dinv;
+    int role;             // update U_*
+    RedWs ws;
+    const DevState *st;
+};
+
+// reduce roles (k_reduce)
+enum { RR_NB = 0, RR_SCALE = 1, RR_NORM2 = 2, RR_RESID = 3, RR_H = 4, RR_U = 5, RR_T2 = 6,
+       RR_VALUES = 7, RR_NORMS = 8 };
+
+int spmv_lanes(int n, int64_t nnz);
+int spmv_grid(int sg, int64_t ldy);
+int orth_grid(int fmt, int64_t n);
+int launch_spmv(const SpmvArgs &a, hipStream_t s);
+void launch_multidot(const OrthArgs &a, hipStream_t s);
+void launch_update(const OrthArgs &a, hipStream_t s);
+void launch_reduce(const RedWs &ws, int role, int nb_orth, int nb_spmv, int j, DevState *st,
+                   const void *sa, double *out, int fmt, hipStream_t s);
+void launch_normalize(int fmt, const double *w, int n, int64_t nst, double *v_out, void *Q,
+                      const double *scale_slot, const double *tptr, double tval,
+                      const DevState *st, int check_done, hipStream_t s);
+void launch_decode(int fmt, const void *Q, int n, const double *scale, double *v, hipStream_t s);
+int launch_norm(const double *x, int64_t n, const RedWs &ws, hipStream_t s);
+void launch_init_state(DevState *st, int n, int m, int fmt, double tol, double eta,
+                       int64_t maxiter, hipStream_t s);
+void launch_jacobi_setup(int n, int64_t ld, const int32_t *rp, const int32_t *ci,
+                         const double *val, double *dinv, unsigned *bad, hipStream_t s);
+void launch_clear_flags(DevState *st, unsigned *bad, hipStream_t s);
+void launch_backsolve(const DevState *st, const void *sa, hipStream_t s);
+size_t step_arrays_size();
+void make_step_arrays(void *out, double *H, double *h, double *u, double *cs, double *sn,
+                      double *g, double *y, double *hist, double *scales, int32_t *flags);
+
+}  // namespace cbg

@@ -1,0 +1,594 @@
+// C ABI of the library: argument checks, workspace carving and the restart
+// loop of Fig. 1 (Section 3).  Every step of the loop runs in the kernels of
+// cbg_kernels.hip; this file only enqueues them, reads the device state once
+// per restart cycle, and applies the host-side decisions (stop, restart,
+// preconditioner fallback).
+#include <math.h>
+#include <string.h>
+
+#include <chrono>
+#include <vector>
+
+#include "../../include/cbgmres.h"
+#include "cbg_device.hpp"
+#include "cbg_launch.hpp"
+
+using namespace cbg;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr double ETA_DEFAULT = 0.70710678118654752440;   // 1/sqrt(2), nearest double
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+bool valid_format(int f) { return f >= CBG_FP64 && f <= CBG_INT16; }
+
+int64_t basis_ld(int32_t n) { return ((int64_t)n + 255) / 256 * 256; }
+
+size_t red_bytes(int jmax)
+{
+    return align_up((size_t)(jmax + 2) * MAX_GRID * sizeof(double)) +
+           align_up((size_t)2 * MAX_GRID * sizeof(double));
+}
+
+// Carves a workspace front to back; records the total size.
+struct Carver {
+    uint8_t *base;
+    size_t off = 0;
+    explicit Carver(void *p) : base((uint8_t *)p) {}
+    template <class T> T *take(size_t count)
+    {
+        T *p = base ? (T *)(base + off) : nullptr;
+        off = align_up(off + count * sizeof(T));
+        return p;
+    }
+};
+
+RedWs carve_red(Carver &c, int jmax)
+{
+    RedWs r;
+    r.stride = MAX_GRID;
+    r.orth = c.take<double>((size_t)(jmax + 2) * MAX_GRID);
+    r.spmv = c.take<double>((size_t)2 * MAX_GRID);
+    return r;
+}
+
+struct SolveWs {
+    DevState *st;
+    uint8_t *V;
+    double *scales, *v, *w, *z, *dinv, *xprev;
+    double *H, *h, *u, *cs, *sn, *g, *y, *hist;
+    int32_t *flags;
+    unsigned *bad;
+    RedWs red;
+};
+
+SolveWs carve_solve(void *ws, int32_t n, int32_t m, int fmt, int pc, size_t *total)
+{
+    Carver c(ws);
+    SolveWs s;
+    const int64_t ld = basis_ld(n);
+    s.st = c.take<DevState>(1);
+    s.V = c.take<uint8_t>((size_t)(m + 1) * ld * fmt_bytes(fmt));
+    s.scales = c.take<double>(m + 1);
+    s.v = c.take<double>(ld);
+    s.w = c.take<double>(ld);
+    s.z = c.take<double>(pc == CBG_PC_SPARSE ? ld : 1);
+    s.dinv = c.take<double>(pc == CBG_PC_JACOBI ? ld : 1);
+    s.xprev = c.take<double>(pc == CBG_PC_SPARSE ? ld : 1);
+    s.H = c.take<double>((size_t)(m + 1) * m);
+    s.h = c.take<double>(m + 1);
+    s.u = c.take<double>(m + 1);
+    s.cs = c.take<double>(m + 1);
+    s.sn = c.take<double>(m + 1);
+    s.g = c.take<double>(m + 2);
+    s.y = c.take<double>(m + 1);
+    s.hist = c.take<double>(m);
+    s.flags = c.take<int32_t>(m);
+    s.bad = c.take<unsigned>(1);
+    s.red = carve_red(c, m + 1);
+    if (total)
+        *total = c.off;
+    return s;
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+#define HIP_TRY(x)                          \
+    do {                                    \
+        if ((x) != hipSuccess) {            \
+            (void)hipGetLastError();        \
+            return CBG_E_HIP;               \
+        }                                   \
+    } while (0)
+
+// Algorithmic HBM bytes (what each kernel must move at least).
+struct ByteModel {
+    double n, nnz, bs;
+    double spmv() const { return 12.0 * nnz + 4.0 * (n + 1) + 16.0 * n; }
+    double dot(int j) const { return j * n * bs + 8.0 * n; }
+    double upd(int j) const { return j * n * bs + 16.0 * n; }
+    double normalize() const { return 16.0 * n + n * bs; }
+};
+
+// Profiling events of one cycle: per step, start/end of the four
+// basis-streaming launches (dot, update, re-dot, re-update).
+struct CycleEvents {
+    std::vector<hipEvent_t> ev;
+    int m = 0;
+    bool ok = false;
+    int create(int mm)
+    {
+        m = mm;
+        ev.assign((size_t)m * 8, nullptr);
+        for (auto &e : ev)
+            if (hipEventCreate(&e) != hipSuccess)
+                return CBG_E_HIP;
+        ok = true;
+        return 0;
+    }
+    hipEvent_t at(int j, int k, int edge) { return ev[((size_t)(j - 1) * 4 + k) * 2 + edge]; }
+    ~CycleEvents()
+    {
+        for (auto &e : ev)
+            if (e)
+                (void)hipEventDestroy(e);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char *cbg_strerror(int status)
+{
+    switch (status) {
+    case CBG_OK: return "converged";
+    case CBG_NOT_CONVERGED: return "iteration limit reached before the tolerance";
+    case CBG_E_ARG: return "invalid argument";
+    case CBG_E_WORKSPACE: return "workspace missing, misaligned or too small";
+    case CBG_E_HIP: return "HIP runtime error";
+    case CBG_E_NONFINITE: return "non-finite value in the input or during the solve";
+    case CBG_E_UNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+    }
+}
+
+int64_t cbg_basis_ld(int32_t n) { return n < 0 ? 0 : basis_ld(n); }
+
+size_t cbg_workspace_bytes(int32_t n, int32_t restart, int32_t format, int32_t precond)
+{
+    if (n < 0 || restart < 1 || restart > CBG_MAX_RESTART || !valid_format(format) ||
+        precond < CBG_PC_NONE || precond > CBG_PC_SPARSE)
+        return 0;
+    size_t total = 0;
+    carve_solve(nullptr, n, restart, format, precond, &total);
+    return total;
+}
+
+size_t cbg_kernel_workspace_bytes(int32_t n, int32_t j)
+{
+    if (n < 0 || j < 0 || j > CBG_MAX_RESTART + 1)
+        return 0;
+    return red_bytes(j);
+}
+
+int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *opt,
+                  void *workspace, size_t ws_bytes, void *stream, cbg_result *res,
+                  double *hist_out, int64_t hist_len)
+{
+    const double t_start = now_s();
+    if (!res)
+        return CBG_E_ARG;
+    memset(res, 0, sizeof(*res));
+    auto fail = [&](int code) {
+        res->status = code;
+        res->seconds = now_s() - t_start;
+        return code;
+    };
+    if (!A || !opt)
+        return fail(CBG_E_ARG);
+    const int32_t n = A->n, m = opt->restart;
+    const int fmt = opt->format, pc0 = opt->precond;
+    if (n < 0 || A->nnz < 0 || m < 1 || m > CBG_MAX_RESTART || !valid_format(fmt) ||
+        !(opt->tol >= 0.0) || !isfinite(opt->tol) || opt->maxiter < 0 || pc0 < CBG_PC_NONE ||
+        pc0 > CBG_PC_SPARSE || (hist_len > 0 && !hist_out) || hist_len < 0)
+        return fail(CBG_E_ARG);
+    if (n > 0 && (!A->row_ptr || !A->col_idx || !A->val || !b || !x || !aligned16(b) ||
+                  !aligned16(x) || (A->nnz > 0 && (!A->col_idx || !A->val))))
+        return fail(CBG_E_ARG);
+    if (pc0 == CBG_PC_SPARSE && n > 0 && !opt->p_val)
+        return fail(CBG_E_ARG);
+    if (n == 0)
+        return fail(CBG_OK);
+    size_t need = 0;
+    carve_solve(nullptr, n, m, fmt, pc0, &need);
+    if (!workspace || ((uintptr_t)workspace & (ALIGN - 1)) || ws_bytes < need)
+        return fail(CBG_E_WORKSPACE);
+
+    hipStream_t s = (hipStream_t)stream;
+    SolveWs W = carve_solve(workspace, n, m, fmt, pc0, nullptr);
+    const int64_t ld = basis_ld(n);
+    const size_t vbytes = (size_t)ld * fmt_bytes(fmt);
+    const double eta = opt->eta > 0.0 ? opt->eta : ETA_DEFAULT;
+    const int sg = spmv_lanes(n, A->nnz);
+    const bool prof = (opt->flags & CBG_FLAG_PROFILE) != 0;
+    ByteModel bm{(double)n, (double)A->nnz, (double)fmt_bytes(fmt)};
+
+    std::vector<unsigned char> sa_buf(step_arrays_size());
+    void *sa = sa_buf.data();
+    make_step_arrays(sa, W.H, W.h, W.u, W.cs, W.sn, W.g, W.y, W.hist, W.scales, W.flags);
+
+    // set-up: initialise the state, ||b||
+    const int nb_orth = orth_grid(fmt, n);
+    launch_clear_flags(nullptr, W.bad, s);
+    launch_init_state(W.st, n, m, fmt, opt->tol, eta, opt->maxiter, s);
+    {
+        const int g = launch_norm(b, n, W.red, s);
+        launch_reduce(W.red, RR_NB, 0, g, 0, W.st, sa, nullptr, fmt, s);
+    }
+    int pc = pc0;
+    if (pc == CBG_PC_JACOBI)
+        launch_jacobi_setup(n, ld, A->row_ptr, A->col_idx, A->val, W.dinv, W.bad, s);
+    HIP_TRY(hipGetLastError());
+
+    DevState hs;
+    unsigned bad = 0;
+    HIP_TRY(hipMemcpyAsync(&hs, W.st, sizeof(hs), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&bad, W.bad, sizeof(bad), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (bad)
+        return fail(CBG_E_ARG);
+    if (!isfinite(hs.nb))
+        return fail(CBG_E_NONFINITE);
+    if (hs.nb == 0.0) {                       // b = 0: the solution is x = 0
+        HIP_TRY(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return fail(CBG_OK);
+    }
+    const double nb = hs.nb;
+
+    CycleEvents evs;
+    if (prof && evs.create(m) != 0)
+        return fail(CBG_E_HIP);
+
+    std::vector<double> cyc_hist(m);
+    std::vector<int32_t> cyc_flags(m);
+    int64_t hist_n = 0;
+    int status = CBG_NOT_CONVERGED;
+    double rho_prev = INFINITY, rho = NAN;
+    int stagnant = 0;
+    int64_t cycles = 0;
+    double model_bytes = 0.0;
+    bool prev_cycle = false;
+    int prev_pc = pc;
+
+    for (;;) {
+        // Fig. 1 step 1 / step 18: explicit residual r = b - A x into w,
+        // ||r|| and max|r_i|; resets the cycle state.
+        {
+            SpmvArgs a{};
+            a.n = n; a.ldy = ld; a.rp = A->row_ptr; a.ci = A->col_idx; a.val = A->val;
+            a.x = x; a.b = b; a.y = W.w; a.ws = W.red; a.mode = 2 /*SP_RESID*/;
+            a.role = 2 /*SR_FREE*/; a.sg = sg; a.st = W.st;
+            const int g = launch_spmv(a, s);
+            launch_reduce(W.red, RR_RESID, 0, g, 0, W.st, sa, nullptr, fmt, s);
+            model_bytes += bm.spmv() + 8.0 * n;
+        }
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(&hs, W.st, sizeof(hs), hipMemcpyDeviceToHost, s));
+        if (prev_cycle) {
+            HIP_TRY(hipMemcpyAsync(cyc_hist.data(), W.hist, sizeof(double) * m,
+                                   hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipMemcpyAsync(cyc_flags.data(), W.flags, sizeof(int32_t) * m,
+                                   hipMemcpyDeviceToHost, s));
+        }
+        HIP_TRY(hipStreamSynchronize(s));
+
+        if (prev_cycle) {
+            // account for the cycle that just ended
+            const int jeff = hs.jprev;
+            if (prof) {
+                // every launch of the cycle is timed, including the ones that
+                // found the cycle finished (they move no bytes)
+                for (int j = 1; j <= m; ++j) {
+                    const bool ro = j <= jeff && (cyc_flags[j - 1] & 1);
+                    for (int k = 0; k < 4; ++k) {
+                        float ms;
+                        HIP_TRY(hipEventElapsedTime(&ms, evs.at(j, k, 0), evs.at(j, k, 1)));
+                        const bool work = j <= jeff && (k < 3 || ro);
+                        const double by = !work ? 0.0 : (k % 2 == 0) ? bm.dot(j) : bm.upd(j);
+                        res->prof_orth_ms += ms;
+                        res->prof_orth_bytes += by;
+                        res->prof_orth_launches += 1;
+                        if (k % 2 == 0) {
+                            res->prof_dot_ms += ms;
+                            res->prof_dot_bytes += by;
+                            res->prof_dot_launches += 1;
+                        }
+                    }
+                }
+            }
+            for (int j = 1; j <= jeff; ++j) {
+                const bool ro = cyc_flags[j - 1] & 1;
+                if (hist_n < hist_len)
+                    hist_out[hist_n] = cyc_hist[j - 1];
+                ++hist_n;
+                double b_step = bm.spmv() + bm.dot(j) + bm.upd(j);
+                if (prev_pc == CBG_PC_JACOBI) b_step += 8.0 * n;
+                if (prev_pc == CBG_PC_SPARSE) b_step += 8.0 * A->nnz + 4.0 * (n + 1) + 16.0 * n;
+                b_step += bm.dot(j);                 // the re-dot pass runs every step
+                if (ro) b_step += bm.upd(j);
+                if (j < jeff) b_step += bm.normalize();
+                model_bytes += b_step;
+            }
+            model_bytes += bm.normalize() + jeff * n * bm.bs + 16.0 * n;
+        }
+
+        rho = hs.beta;
+        if (hs.nonfinite || !isfinite(rho)) {
+            if (pc == CBG_PC_SPARSE && opt->fallback && cycles > 0) {
+                // plain CB-GMRES takes over from the last finite iterate
+                HIP_TRY(hipMemcpyAsync(x, W.xprev, (size_t)n * sizeof(double),
+                                       hipMemcpyDeviceToDevice, s));
+                pc = CBG_PC_NONE;
+                res->fell_back = 1;
+                stagnant = 0;
+                rho_prev = INFINITY;
+                prev_cycle = false;
+                launch_clear_flags(W.st, nullptr, s);
+                continue;
+            }
+            status = CBG_E_NONFINITE;
+            break;
+        }
+        if (rho <= hs.tau_nb) {
+            status = CBG_OK;
+            break;
+        }
+        if (hs.it >= opt->maxiter) {
+            status = CBG_NOT_CONVERGED;
+            break;
+        }
+        if (pc == CBG_PC_SPARSE && opt->fallback) {
+            stagnant = rho > 0.99 * rho_prev ? stagnant + 1 : 0;
+            if (stagnant >= 2) {
+                pc = CBG_PC_NONE;
+                res->fell_back = 1;
+                stagnant = 0;
+            }
+        }
+        rho_prev = rho;
+        if (pc == CBG_PC_SPARSE && opt->fallback)
+            HIP_TRY(hipMemcpyAsync(W.xprev, x, (size_t)n * sizeof(double),
+                                   hipMemcpyDeviceToDevice, s));
+        cycles += 1;
+        prev_cycle = true;
+        prev_pc = pc;
+
+        // v_1 = r / beta, stored through the accessor.
+        launch_normalize(fmt, W.w, n, ld, W.v, W.V, W.scales, &W.st->t, 0.0, W.st, 0, s);
+
+        for (int j = 1; j <= m; ++j) {
+            const double *src = W.v;
+            if (pc == CBG_PC_SPARSE) {
+                SpmvArgs a{};
+                a.n = n; a.ldy = ld; a.rp = A->row_ptr; a.ci = A->col_idx; a.fval = opt->p_val;
+                a.x = W.v; a.y = W.z; a.ws = W.red; a.mode = 3 /*SP_FLOATVAL*/;
+                a.role = 0 /*SR_NONE*/; a.sg = sg; a.st = W.st;
+                launch_spmv(a, s);
+                src = W.z;
+            }
+            int nb_spmv;
+            {   // steps 3-4
+                SpmvArgs a{};
+                a.n = n; a.ldy = ld; a.rp = A->row_ptr; a.ci = A->col_idx; a.val = A->val;
+                a.x = src; a.dinv = W.dinv; a.y = W.w; a.ws = W.red;
+                a.mode = pc == CBG_PC_JACOBI ? 1 : 0; a.role = 1 /*SR_STEP*/; a.sg = sg;
+                a.st = W.st;
+                nb_spmv = launch_spmv(a, s);
+            }
+            OrthArgs o{};
+            o.fmt = fmt; o.V = W.V; o.ld = ld; o.scales = W.scales; o.n = n; o.j = j;
+            o.w = W.w; o.wio = W.w; o.ws = W.red; o.st = W.st; o.gated = 1;
+            // step 5: h = V^T w ; w -= V h
+            if (prof) HIP_TRY(hipEventRecord(evs.at(j, 0, 0), s));
+            launch_multidot(o, s);
+            if (prof) HIP_TRY(hipEventRecord(evs.at(j, 0, 1), s));
+            launch_reduce(W.red, RR_H, nb_orth, nb_spmv, j, W.st, sa, nullptr, fmt, s);
+            o.coef = W.h; o.role = 1 /*U_STEP1*/;
+            if (prof) HIP_TRY(hipEventRecord(evs.at(j, 1, 0), s));
+            launch_update(o, s);
+            if (prof) HIP_TRY(hipEventRecord(evs.at(j, 1, 1), s));
+            // steps 6-8: ||w||, the test of step 7, and u = V^T w in one pass
+            o.with_norms = 1;
+            if (prof) HIP_TRY(hipEventRecord(evs.at(j, 2, 0), s));
+            launch_multidot(o, s);
+            if (prof) HIP_TRY(hipEventRecord(evs.at(j, 2, 1), s));
+            launch_reduce(W.red, RR_U, nb_orth, 0, j, W.st, sa, nullptr, fmt, s);
+            // steps 8-12 (no work unless step 7 asked for it)
+            o.coef = W.u; o.role = 2 /*U_STEP2*/;
+            if (prof) HIP_TRY(hipEventRecord(evs.at(j, 3, 0), s));
+            launch_update(o, s);
+            if (prof) HIP_TRY(hipEventRecord(evs.at(j, 3, 1), s));
+            launch_reduce(W.red, RR_T2, nb_orth, 0, j, W.st, sa, nullptr, fmt, s);
+            // steps 13-14
+            if (j < m)
+                launch_normalize(fmt, W.w, n, ld, W.v, W.V + (size_t)j * vbytes, W.scales + j,
+                                 &W.st->t, 0.0, W.st, 1, s);
+        }
+        HIP_TRY(hipGetLastError());
+        // step 17: y = R^-1 g ; x += M^-1 V y
+        launch_backsolve(W.st, sa, s);
+        {
+            OrthArgs o{};
+            o.fmt = fmt; o.V = W.V; o.ld = ld; o.scales = W.scales; o.n = n; o.j = 0;
+            o.coef = W.y; o.ws = W.red; o.st = W.st;
+            if (pc == CBG_PC_SPARSE) {
+                o.role = 4 /*U_COMBINE*/;       // z = V y
+                o.wio = W.z;
+                launch_update(o, s);
+                SpmvArgs a{};                   // x += P z
+                a.n = n; a.ldy = n; a.rp = A->row_ptr; a.ci = A->col_idx; a.fval = opt->p_val;
+                a.x = W.z; a.y = x; a.ws = W.red; a.mode = 4 /*SP_ACCUM*/; a.role = 0;
+                a.sg = sg; a.st = nullptr;
+                launch_spmv(a, s);
+            } else {
+                o.role = 3 /*U_SOLUTION*/;      // x += dinv .* (V y)  or  x += V y
+                o.dinv = pc == CBG_PC_JACOBI ? W.dinv : nullptr;
+                o.wio = x;
+                launch_update(o, s);
+            }
+        }
+        HIP_TRY(hipGetLastError());
+    }
+
+    res->status = status;
+    res->iterations = hs.it;
+    res->restarts = cycles;
+    res->reorths = hs.reorths;
+    res->breakdowns = hs.breakdowns;
+    res->true_rel_res = rho / nb;
+    res->recurrence_rel_res = hs.last_rec;
+    res->model_bytes = model_bytes;
+    res->seconds = now_s() - t_start;
+    return status;
+}
+
+// ------------------------------------------------------------------------
+// Kernel-level entry points.
+// ------------------------------------------------------------------------
+
+static bool kernel_ws_ok(void *ws, size_t ws_bytes, int j)
+{
+    return ws && ((uintptr_t)ws & (ALIGN - 1)) == 0 && ws_bytes >= red_bytes(j);
+}
+
+static RedWs kernel_red(void *ws, int j)
+{
+    Carver c(ws);
+    return carve_red(c, j);
+}
+
+int cbg_encode(int32_t format, const double *v, int32_t n, void *q, double *scale, void *ws,
+               size_t ws_bytes, void *stream)
+{
+    if (!valid_format(format) || n < 0 || !scale || (n > 0 && (!v || !q)) || !aligned16(v) ||
+        !aligned16(q))
+        return CBG_E_ARG;
+    if (!kernel_ws_ok(ws, ws_bytes, 0))
+        return CBG_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    RedWs r = kernel_red(ws, 0);
+    const int g = launch_norm(v, n, r, s);
+    launch_reduce(r, RR_SCALE, 0, g, 0, nullptr, nullptr, scale, format, s);
+    if (n > 0)
+        launch_normalize(format, v, n, n, nullptr, q, scale, nullptr, 1.0, nullptr, 0, s);
+    HIP_TRY(hipGetLastError());
+    return CBG_OK;
+}
+
+int cbg_decode(int32_t format, const void *q, const double *scale, int32_t n, double *v,
+               void *stream)
+{
+    if (!valid_format(format) || n < 0 || !scale || (n > 0 && (!v || !q)) || !aligned16(v) ||
+        !aligned16(q))
+        return CBG_E_ARG;
+    if (n > 0)
+        launch_decode(format, q, n, scale, v, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return CBG_OK;
+}
+
+int cbg_spmv(const cbg_csr *A, const double *x, double *y, double *norm2, void *ws,
+             size_t ws_bytes, void *stream)
+{
+    if (!A || A->n < 0 || A->nnz < 0 ||
+        (A->n > 0 && (!A->row_ptr || !x || !y || (A->nnz > 0 && (!A->col_idx || !A->val)))))
+        return CBG_E_ARG;
+    if (norm2 && !kernel_ws_ok(ws, ws_bytes, 0))
+        return CBG_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    if (A->n == 0) {
+        if (norm2)
+            HIP_TRY(hipMemsetAsync(norm2, 0, sizeof(double), s));
+        return CBG_OK;
+    }
+    SpmvArgs a{};
+    a.n = A->n; a.ldy = A->n; a.rp = A->row_ptr; a.ci = A->col_idx; a.val = A->val; a.x = x;
+    a.y = y; a.mode = 0; a.sg = spmv_lanes(A->n, A->nnz);
+    a.role = norm2 ? 2 /*SR_FREE*/ : 0;
+    if (norm2)
+        a.ws = kernel_red(ws, 0);
+    const int g = launch_spmv(a, s);
+    if (norm2)
+        launch_reduce(a.ws, RR_NORM2, 0, g, 0, nullptr, nullptr, norm2, 0, s);
+    HIP_TRY(hipGetLastError());
+    return CBG_OK;
+}
+
+static bool basis_args_ok(int32_t format, const void *V, int64_t ld, const double *scales,
+                          int32_t n, int32_t j)
+{
+    return valid_format(format) && n >= 0 && j >= 0 && j <= CBG_MAX_RESTART + 1 && ld >= n &&
+           ld % 16 == 0 && (j == 0 || n == 0 || (V && scales && aligned16(V)));
+}
+
+int cbg_multidot(int32_t format, const void *V, int64_t ld, const double *scales, int32_t n,
+                 int32_t j, const double *w, double *h, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!basis_args_ok(format, V, ld, scales, n, j) || (j > 0 && !h) ||
+        (n > 0 && (!w || !aligned16(w))))
+        return CBG_E_ARG;
+    if (!kernel_ws_ok(ws, ws_bytes, j))
+        return CBG_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    if (j == 0)
+        return CBG_OK;
+    if (n == 0) {
+        HIP_TRY(hipMemsetAsync(h, 0, sizeof(double) * j, s));
+        return CBG_OK;
+    }
+    OrthArgs o{};
+    o.fmt = format; o.V = V; o.ld = ld; o.scales = scales; o.n = n; o.j = j; o.w = w;
+    o.ws = kernel_red(ws, j);
+    launch_multidot(o, s);
+    launch_reduce(o.ws, RR_VALUES, orth_grid(format, n), 0, j, nullptr, nullptr, h, format, s);
+    HIP_TRY(hipGetLastError());
+    return CBG_OK;
+}
+
+int cbg_update(int32_t format, const void *V, int64_t ld, const double *scales, int32_t n,
+               int32_t j, const double *h, double *w, double *norms, void *ws, size_t ws_bytes,
+               void *stream)
+{
+    if (!basis_args_ok(format, V, ld, scales, n, j) || (j > 0 && !h) ||
+        (n > 0 && (!w || !aligned16(w))))
+        return CBG_E_ARG;
+    if (!kernel_ws_ok(ws, ws_bytes, 0))
+        return CBG_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) {
+        if (norms)
+            HIP_TRY(hipMemsetAsync(norms, 0, 2 * sizeof(double), s));
+        return CBG_OK;
+    }
+    OrthArgs o{};
+    o.fmt = format; o.V = V; o.ld = ld; o.scales = scales; o.n = n; o.j = j; o.coef = h;
+    o.wio = w; o.role = 0 /*U_PLAIN*/; o.ws = kernel_red(ws, 0);
+    launch_update(o, s);
+    if (norms)
+        launch_reduce(o.ws, RR_NORMS, orth_grid(format, n), 0, 0, nullptr, nullptr, norms, format,
+                      s);
+    HIP_TRY(hipGetLastError());
+    return CBG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+"""The C-ABI library loads, exports every symbol its header declares, and
+rejects invalid arguments on the host before any HIP call (no GPU needed)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cbgmres.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(cbg\w*|cbgmres\w*)\s*\(", src)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2009_12101_amd import _binding
+    return _binding.lib()
+
+
+def test_header_functions_are_exported(L):
+    names = declared_functions()
+    assert "cbgmres_solve" in names and len(names) >= 10
+    for nm in names:
+        assert hasattr(L, nm), nm
+    from paper_2009_12101_amd import _binding
+    assert sorted(_binding.EXPORTS) == names
+
+
+def test_strerror_and_sizes(L):
+    from paper_2009_12101_amd import _binding as B
+    for code in (0, 1, -1, -2, -3, -4, -5, 42):
+        assert isinstance(B.strerror(code), str) and B.strerror(code)
+    assert B.basis_ld(1) == 256 and B.basis_ld(256) == 256 and B.basis_ld(257) == 512
+    assert B.workspace_bytes(1000, 0, "fp16") == 0           # restart < 1
+    assert B.workspace_bytes(1000, 513, "fp16") == 0         # restart > max
+    small = B.workspace_bytes(1000, 10, "fp16")
+    big = B.workspace_bytes(1000, 10, "fp64")
+    assert 0 < small < big
+    # the basis dominates: (m+1) * ld * bytes
+    d = B.workspace_bytes(10 ** 6, 100, "fp64") - B.workspace_bytes(10 ** 6, 100, "fp16")
+    assert d == 101 * B.basis_ld(10 ** 6) * 6
+    assert B.kernel_workspace_bytes(100, 10) > 0
+    assert B.kernel_workspace_bytes(100, 10 ** 6) == 0
+
+
+def test_solve_rejects_bad_arguments_on_host(L):
+    from paper_2009_12101_amd import _binding as B
+    res = B.CbgResult()
+    csr = B.CbgCsr(4, 0, 4, 16, 32, 48)          # fake but 16-aligned device pointers
+    good = dict(restart=10, format=2, tol=1e-10, maxiter=100, eta=0.0, precond=0, fallback=0,
+                p_val=None, flags=0, reserved=0)
+
+    def call(A=csr, b=64, x=128, ws=None, wsb=0, **over):
+        o = dict(good)
+        o.update(over)
+        opts = B.CbgOpts(**o)
+        return L.cbgmres_solve(C.byref(A) if A is not None else None, C.c_void_p(b),
+                               C.c_void_p(x), C.byref(opts), C.c_void_p(ws), wsb, None,
+                               C.byref(res), None, 0)
+
+    assert call(restart=0) == B.E_ARG and res.status == B.E_ARG
+    assert call(restart=513) == B.E_ARG
+    assert call(format=9) == B.E_ARG
+    assert call(tol=-1.0) == B.E_ARG
+    assert call(tol=float("nan")) == B.E_ARG
+    assert call(maxiter=-5) == B.E_ARG
+    assert call(precond=7) == B.E_ARG
+    assert call(precond=2) == B.E_ARG              # sparse P without values
+    assert call(b=0) == B.E_ARG                   # null b
+    assert call(x=8) == B.E_ARG                   # misaligned x
+    assert call(A=None) == B.E_ARG
+    assert call(ws=None) == B.E_WORKSPACE          # missing workspace
+    assert call(ws=4096 + 8, wsb=1 << 40) == B.E_WORKSPACE   # misaligned workspace
+    assert call(ws=4096, wsb=10) == B.E_WORKSPACE            # too small
+    empty = B.CbgCsr(0, 0, 0, None, None, None)
+    assert call(A=empty, b=0, x=0) == B.OK                   # n = 0: nothing to do
+    assert L.cbgmres_solve(C.byref(csr), None, None, None, None, 0, None, C.byref(res),
+                           None, 0) == B.E_ARG
+
+
+def test_kernel_calls_reject_bad_arguments_on_host(L):
+    from paper_2009_12101_amd import _binding as B
+    vp = C.c_void_p
+    assert L.cbg_encode(9, vp(16), 10, vp(32), vp(48), vp(256), 1 << 20, None) == B.E_ARG
+    assert L.cbg_encode(2, vp(16), -1, vp(32), vp(48), vp(256), 1 << 20, None) == B.E_ARG
+    assert L.cbg_encode(2, vp(16), 10, vp(32), vp(48), None, 0, None) == B.E_WORKSPACE
+    assert L.cbg_decode(2, vp(16), None, 10, vp(32), None) == B.E_ARG
+    # ld must be >= n and a multiple of 16
+    assert L.cbg_multidot(2, vp(16), 10, vp(32), 20, 3, vp(48), vp(64), vp(256), 1 << 20,
+                          None) == B.E_ARG
+    assert L.cbg_multidot(2, vp(16), 24, vp(32), 20, 3, vp(48), vp(64), vp(256), 1 << 20,
+                          None) == B.E_ARG
+    assert L.cbg_update(2, vp(16), 32, vp(32), 20, 600, vp(48), vp(64), vp(80), vp(256),
+                        1 << 20, None) == B.E_ARG
+    bad = B.CbgCsr(-1, 0, 0, None, None, None)
+    assert L.cbg_spmv(C.byref(bad), vp(16), vp(32), None, None, 0, None) == B.E_ARG

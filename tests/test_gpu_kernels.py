@@ -1,0 +1,179 @@
+"""GPU parity of the hot-path kernels against the CPU oracle, through the C ABI.
+
+Codec: bit-exact (the compressed representation is integer/byte work).
+SpMV, multi-dot, update: FP64 with a different summation order; compared
+element by element within a bound derived from the arithmetic,
+|err| <= c * n_terms * 2^-53 * sum|terms|.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FORMATS = ["fp64", "fp32", "fp16", "bf16", "e4m3", "int32", "int16"]
+STORE = {"fp64": np.float64, "fp32": np.float32, "fp16": np.uint16, "bf16": np.uint16,
+         "e4m3": np.uint8, "int32": np.int32, "int16": np.int16}
+U = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def cbg():
+    import paper_2009_12101_amd as cbg
+    cbg.lib()
+    return cbg
+
+
+def unit_vectors(n, seed, kind="normal"):
+    rng = np.random.default_rng(seed)
+    if kind == "normal":
+        v = rng.standard_normal(n)
+    else:   # wide dynamic range, down into the fp16/bf16 subnormals
+        v = rng.standard_normal(n) * 10.0 ** rng.uniform(-12, 0, n)
+    return v / np.linalg.norm(v)
+
+
+def gpu_codes(q, fmt):
+    a = q.cpu().numpy()
+    return a.view(STORE[fmt]) if a.dtype.itemsize == np.dtype(STORE[fmt]).itemsize else a
+
+
+@pytest.mark.parametrize("fmt", FORMATS)
+@pytest.mark.parametrize("n,kind", [(1, "normal"), (7, "normal"), (1000, "wide"),
+                                    (100003, "normal"), (262147, "wide")])
+def test_encode_bit_exact(cbg, orc, dev, fmt, n, kind):
+    print(f"encode {fmt} n={n} {kind}", flush=True)
+    v = unit_vectors(n, n + 11, kind)
+    q, sc = cbg.encode(fmt, torch.from_numpy(v).to(dev))
+    torch.cuda.synchronize()
+    qo, so = orc.encode(fmt, v)
+    assert sc.item() == so
+    assert np.array_equal(gpu_codes(q, fmt).view(np.uint8), qo.view(np.uint8))
+    d = cbg.decode(fmt, q, sc, n).cpu().numpy()
+    assert np.array_equal(d.view(np.uint64), orc.decode(fmt, qo, so).view(np.uint64))
+
+
+@pytest.mark.parametrize("fmt", ["fp16", "bf16"])
+def test_encode_midpoints_bit_exact(cbg, orc, dev, fmt):
+    """Every tie between neighbouring representable values in [0, 1], and
+    the values one fp64 ulp either side of it."""
+    if fmt == "fp16":
+        c = np.arange(0, 0x3C01, dtype=np.uint16)
+        vals = c.view(np.float16).astype(np.float64)
+    else:
+        c = np.arange(0, 0x3F81, dtype=np.uint32)
+        vals = (c << 16).view(np.float32).astype(np.float64)
+    mid = (vals[:-1] + vals[1:]) / 2
+    x = np.concatenate([mid, np.nextafter(mid, 2.0), np.nextafter(mid, -1.0), -mid, vals])
+    x[0] = 1.0       # keeps max|x| = 1 (irrelevant for unscaled formats)
+    q, _ = cbg.encode(fmt, torch.from_numpy(x).to(dev))
+    qo, _ = orc.encode(fmt, x)
+    assert np.array_equal(gpu_codes(q, fmt).view(np.uint16), qo.view(np.uint16))
+
+
+def test_e4m3_all_codes_and_ties(cbg, orc, dev):
+    # every code as a scaled value, plus ties and near-ties between codes
+    codes = np.arange(0, 0x7F, dtype=np.uint8)
+    vals = orc.decode("e4m3", codes, 1.0)
+    pos = np.unique(vals)
+    mid = (pos[:-1] + pos[1:]) / 2
+    x = np.concatenate([[448.0], pos, mid, np.nextafter(mid, 1e9), np.nextafter(mid, -1), -mid])
+    x = x * 2.0 ** -9             # scale 2^-9: the scaled values are the codes' values
+    q, sc = cbg.encode("e4m3", torch.from_numpy(x).to(dev))
+    qo, so = orc.encode("e4m3", x)
+    assert sc.item() == so
+    assert np.array_equal(gpu_codes(q, "e4m3"), qo)
+
+
+@pytest.mark.parametrize("fmt", ["int16", "int32"])
+def test_fixed_point_ties(cbg, orc, dev, fmt):
+    M = 32767 if fmt == "int16" else 2147483647
+    k = np.arange(-2000, 2000)
+    x = np.concatenate([[M], k + 0.5, k]) * 2.0 ** -20     # sigma = 2^-20 exactly
+    q, sc = cbg.encode(fmt, torch.from_numpy(x).to(dev))
+    qo, so = orc.encode(fmt, x)
+    assert sc.item() == so == 2.0 ** -20
+    assert np.array_equal(gpu_codes(q, fmt), qo)
+
+
+def _spmv_bound(A, x):
+    S = A.to_scipy()
+    absx = np.abs(x)
+    mag = abs(S) @ absx
+    return 4 * (np.diff(A.row_ptr).max() + 2) * U * mag
+
+
+@pytest.mark.parametrize("name", ["poisson2d_64", "convdiff7_33", "lognormal27_21"])
+def test_spmv_parity(cbg, orc, dev, name):
+    from paper_2009_12101_amd import problems as P
+    A, _, _ = P.workload(name)
+    x = np.random.default_rng(1).standard_normal(A.n)
+    y, nrm = cbg.spmv(cbg.DeviceCSR.from_host(A, dev), torch.from_numpy(x).to(dev),
+                      want_norm=True)
+    y = y.cpu().numpy()
+    yo = orc.spmv(A, x)
+    assert np.all(np.abs(y - yo) <= _spmv_bound(A, x))
+    assert abs(nrm.item() - np.sqrt(orc.dot(yo, yo))) <= 1e-13 * np.linalg.norm(yo)
+
+
+def _basis(orc, fmt, n, j, ld, seed):
+    """j encoded unit vectors, laid out vector-major with leading dimension ld."""
+    rng = np.random.default_rng(seed)
+    raw = np.zeros((j, ld), dtype=STORE[fmt])
+    dec = np.zeros((j, n))
+    scales = np.zeros(j)
+    for k in range(j):
+        v = rng.standard_normal(n)
+        v /= np.linalg.norm(v)
+        q, s = orc.encode(fmt, v)
+        raw[k, :n] = q
+        scales[k] = s
+        dec[k] = orc.decode(fmt, q, s)
+    return raw, dec, scales
+
+
+@pytest.mark.parametrize("fmt", FORMATS)
+@pytest.mark.parametrize("n,j", [(1, 1), (33, 3), (5000, 17), (70001, 40), (300000, 100)])
+def test_multidot_and_update_parity(cbg, orc, dev, fmt, n, j):
+    print(f"orth {fmt} n={n} j={j}", flush=True)
+    ld = cbg.basis_ld(n)
+    raw, dec, scales = _basis(orc, fmt, n, j, ld, seed=n + j)
+    w = np.random.default_rng(7).standard_normal(n)
+    Vd = torch.from_numpy(raw.view(np.uint8).reshape(-1)).to(dev)
+    sd = torch.from_numpy(scales).to(dev)
+    wd = torch.from_numpy(w).to(dev)
+    h = cbg.multidot(fmt, Vd, ld, sd, n, j, wd).cpu().numpy()
+    ho = np.array([orc.dot(dec[k], w) for k in range(j)])
+    bound = 4 * n * U * (np.abs(dec) @ np.abs(w)) + 1e-300
+    assert np.all(np.abs(h - ho) <= bound), np.max(np.abs(h - ho) / bound)
+    # update with the oracle's coefficients: w' = w - V^T h
+    norms = cbg.update(fmt, Vd, ld, sd, n, j, torch.from_numpy(ho).to(dev), wd)
+    w2 = wd.cpu().numpy()
+    s = np.zeros(n)
+    for k in range(j):
+        s = s + ho[k] * dec[k]
+    wo = w - s
+    ebound = 4 * (j + 1) * U * (np.abs(w) + np.abs(ho) @ np.abs(dec))
+    assert np.all(np.abs(w2 - wo) <= ebound)
+    nv = norms.cpu().numpy()
+    assert abs(nv[0] - np.sqrt(orc.dot(w2, w2))) <= 1e-13 * nv[0] + 1e-300
+    assert nv[1] == np.abs(w2).max()
+
+
+def test_multidot_is_deterministic(cbg, orc, dev):
+    n, j, fmt = 400000, 60, "fp16"
+    ld = cbg.basis_ld(n)
+    raw, dec, scales = _basis(orc, fmt, n, j, ld, seed=3)
+    Vd = torch.from_numpy(raw.view(np.uint8).reshape(-1)).to(dev)
+    sd = torch.from_numpy(scales).to(dev)
+    wd = torch.from_numpy(np.random.default_rng(2).standard_normal(n)).to(dev)
+    h1 = cbg.multidot(fmt, Vd, ld, sd, n, j, wd).cpu().numpy()
+    h2 = cbg.multidot(fmt, Vd, ld, sd, n, j, wd).cpu().numpy()
+    assert np.array_equal(h1.view(np.uint64), h2.view(np.uint64))

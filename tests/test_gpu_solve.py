@@ -1,0 +1,233 @@
+"""GPU CB-GMRES solves against the CPU oracle, through the C ABI.
+
+fp64 basis: the GPU and the oracle follow the same iteration up to rounding,
+so in iteration-matched mode (both capped at the oracle's step count) the
+iterates agree to 1e-8 relative (observed: 1e-14 to 4e-11) and the counts
+to within one step.
+
+Compressed bases: which way a stored entry rounds is decided by its last
+fp64 bits, so two correct implementations whose fp64 arithmetic differs in
+summation order drift apart at the storage precision after a few steps
+(the first steps still agree to rounding).  The iteration count is then a
+random variable of the problem: a 1e-15 relative change of b moves it by up
+to +-8% on these systems (measured on the oracle).  Parity is therefore
+stated over 11 seeded rounding-level perturbations of b run on both sides:
+median counts within 5% (plus half the oracle's 10-90% spread), every GPU
+solve at true residual <= tol, and every GPU solution within
+2 tol ||b|| / sigma_min(A) of the oracle's (the bound two solves that both
+meet the tolerance can differ by).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FORMATS = ["fp64", "fp32", "fp16", "bf16", "e4m3", "int32", "int16"]
+PROBLEMS = [("poisson2d_64", 100), ("convdiff7_20", 30), ("lognormal27_12", 40)]
+TOL = 1e-10
+NPERT = 11
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def cbg():
+    import paper_2009_12101_amd as cbg
+    cbg.lib()
+    return cbg
+
+
+def run_pair(cbg, orc, dev, A, b, **kw):
+    ref = orc.gmres(A, b, **kw)
+    Ad = cbg.DeviceCSR.from_host(A, dev)
+    bd = torch.from_numpy(b).to(dev)
+    kw2 = dict(kw)
+    kw2["fmt"] = kw2.pop("fmt", "fp64")
+    r = cbg.solve(Ad, bd, **kw2)
+    torch.cuda.synchronize()
+    return ref, r, Ad, bd
+
+
+def true_res(orc, A, b, x):
+    return np.linalg.norm(b - orc.spmv(A, x)) / np.linalg.norm(b)
+
+
+def sigma_min(A):
+    import scipy.sparse.linalg as spla
+    S = A.to_scipy().tocsc()
+    lam = spla.eigsh((S.T @ S).tocsc(), k=1, sigma=0, which="LM", return_eigenvectors=False)
+    return float(np.sqrt(lam[0]))
+
+
+def perturbed(b, seed):
+    return b * (1.0 + 1e-15 * np.random.default_rng(1000 + seed).standard_normal(b.size))
+
+
+@pytest.mark.parametrize("name,m", PROBLEMS)
+def test_solve_parity_fp64(cbg, orc, dev, name, m):
+    from paper_2009_12101_amd import problems as P
+    print(f"solve {name} fp64 m={m}", flush=True)
+    A, b, _ = P.workload(name)
+    ref, r, Ad, bd = run_pair(cbg, orc, dev, A, b, restart=m, fmt="fp64", tol=TOL, maxiter=20000)
+    assert ref["status"] == 0 and r.status == 0
+    assert abs(r.iterations - ref["iterations"]) <= 1
+    x = r.x.cpu().numpy()
+    assert true_res(orc, A, b, x) <= TOL
+    assert abs(r.true_rel_res - true_res(orc, A, b, x)) <= 1e-3 * TOL
+    it = ref["iterations"]
+    rm = cbg.solve(Ad, bd, restart=m, fmt="fp64", tol=0.0, maxiter=it)
+    refm = orc.gmres(A, b, restart=m, fmt="fp64", tol=0.0, maxiter=it)
+    assert rm.iterations == refm["iterations"] == it
+    xm = rm.x.cpu().numpy()
+    # same iteration, different rounding: the gap grows like kappa * steps * u
+    # (4e-11 on the lognormal system); 1e-8 is the stated bar
+    assert np.linalg.norm(xm - refm["x"]) <= 1e-8 * np.linalg.norm(refm["x"])
+    # within the first cycle the recurrence residuals coincide to rounding
+    k = min(m, len(rm.hist), len(refm["hist"]))
+    assert np.allclose(rm.hist[:k], refm["hist"][:k], rtol=1e-9, atol=1e-15)
+
+
+@pytest.mark.parametrize("fmt", FORMATS[1:])
+@pytest.mark.parametrize("name,m", PROBLEMS)
+def test_solve_parity_compressed(cbg, orc, dev, fmt, name, m):
+    from paper_2009_12101_amd import problems as P
+    print(f"solve {name} {fmt} m={m}", flush=True)
+    A, b, _ = P.workload(name)
+    Ad = cbg.DeviceCSR.from_host(A, dev)
+    smin = sigma_min(A)
+    it_g, it_o = [], []
+    for s in range(NPERT):
+        bp = perturbed(b, s)
+        o = orc.gmres(A, bp, restart=m, fmt=fmt, tol=TOL, maxiter=20000)
+        r = cbg.solve(Ad, torch.from_numpy(bp).to(dev), restart=m, fmt=fmt, tol=TOL,
+                      maxiter=20000)
+        assert o["status"] == 0 and r.status == 0
+        x = r.x.cpu().numpy()
+        assert true_res(orc, A, bp, x) <= TOL
+        assert np.linalg.norm(x - o["x"]) <= 2.05 * TOL * np.linalg.norm(bp) / smin
+        it_g.append(r.iterations)
+        it_o.append(o["iterations"])
+    mo, mg = np.median(it_o), np.median(it_g)
+    spread = np.percentile(it_o, 90) - np.percentile(it_o, 10)
+    assert abs(mg - mo) <= 0.05 * mo + 0.5 * spread + 2, (sorted(it_g), sorted(it_o))
+    # before the stored entries can round differently, the runs coincide
+    r = cbg.solve(Ad, torch.from_numpy(b).to(dev), restart=m, fmt=fmt, tol=0.0, maxiter=3)
+    o = orc.gmres(A, b, restart=m, fmt=fmt, tol=0.0, maxiter=3)
+    xg = r.x.cpu().numpy()
+    assert np.linalg.norm(xg - o["x"]) <= 1e-12 * np.linalg.norm(o["x"])
+    assert np.allclose(r.hist, o["hist"], rtol=1e-12, atol=0)
+
+
+def test_solve_is_bitwise_reproducible(cbg, orc, dev):
+    from paper_2009_12101_amd import problems as P
+    A = P.convdiff7(24)
+    b = P.rhs_uniform(A.n, 0)
+    Ad = cbg.DeviceCSR.from_host(A, dev)
+    bd = torch.from_numpy(b).to(dev)
+    x1 = cbg.solve(Ad, bd, restart=50, fmt="fp16", tol=1e-10).x.cpu().numpy()
+    x2 = cbg.solve(Ad, bd, restart=50, fmt="fp16", tol=1e-10).x.cpu().numpy()
+    assert np.array_equal(x1.view(np.uint64), x2.view(np.uint64))
+
+
+def test_jacobi_parity(cbg, orc, dev):
+    from paper_2009_12101_amd import problems as P
+    A = P.lognormal27(12, 4)
+    b = P.rhs_uniform(A.n, 4)
+    ref, r, _, _ = run_pair(cbg, orc, dev, A, b, restart=40, fmt="fp32", tol=1e-10,
+                            maxiter=20000, precond="jacobi")
+    assert ref["status"] == 0 and r.status == 0
+    assert abs(r.iterations - ref["iterations"]) <= 0.05 * ref["iterations"] + 2
+    assert true_res(orc, A, b, r.x.cpu().numpy()) <= 1e-10
+
+
+def test_sparse_preconditioner_equal_to_jacobi(cbg, orc, dev):
+    from paper_2009_12101_amd import problems as P
+    A = P.lognormal27(10, 5)
+    b = P.rhs_uniform(A.n, 5)
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    diag = A.col_idx == rows
+    pv = np.zeros(A.nnz, np.float32)
+    pv[diag] = (1.0 / A.val[diag]).astype(np.float32)
+    ref = orc.gmres(A, b, restart=30, fmt="fp16", tol=1e-10, maxiter=5000, precond="sparse",
+                    p_val=pv)
+    Ad = cbg.DeviceCSR.from_host(A, dev)
+    r = cbg.solve(Ad, torch.from_numpy(b).to(dev), restart=30, fmt="fp16", tol=1e-10,
+                  maxiter=5000, precond="sparse", p_val=torch.from_numpy(pv).to(dev))
+    assert r.status == 0 and ref["status"] == 0
+    assert abs(r.iterations - ref["iterations"]) <= 0.05 * ref["iterations"] + 2
+    assert true_res(orc, A, b, r.x.cpu().numpy()) <= 1e-10
+
+
+def test_sparse_fallback_on_nonfinite(cbg, orc, dev):
+    from paper_2009_12101_amd import problems as P
+    A = P.convdiff7(6)
+    b = P.rhs_uniform(A.n, 4)
+    Ad = cbg.DeviceCSR.from_host(A, dev)
+    pz = torch.zeros(A.nnz, dtype=torch.float32, device=dev)
+    r = cbg.solve(Ad, torch.from_numpy(b).to(dev), restart=20, fmt="fp64", tol=1e-10,
+                  maxiter=2000, precond="sparse", p_val=pz, fallback=True)
+    assert r.status == 0 and r.fell_back == 1
+    assert true_res(orc, A, b, r.x.cpu().numpy()) <= 1e-10
+    with pytest.raises(cbg.CbgError) as e:
+        cbg.solve(Ad, torch.from_numpy(b).to(dev), restart=20, fmt="fp64", tol=1e-10,
+                  maxiter=2000, precond="sparse", p_val=pz, fallback=False)
+    assert e.value.status == -4
+
+
+def test_edge_cases(cbg, orc, dev):
+    from paper_2009_12101_amd import problems as P
+    from _helpers import csr_from_dense
+    # A = I: one step, breakdown, x = b
+    A = csr_from_dense(np.eye(50))
+    b = P.rhs_uniform(50, 2)
+    ref, r, Ad, bd = run_pair(cbg, orc, dev, A, b, restart=10, fmt="fp64", tol=1e-12,
+                              maxiter=100)
+    assert r.status == 0 and r.iterations == 1 and r.breakdowns == 1
+    assert np.max(np.abs(r.x.cpu().numpy() - b)) <= 4e-16 * np.abs(b).max()
+    # 5 distinct eigenvalues: breakdown at step 5
+    d = np.tile(np.arange(1.0, 6.0), 8)
+    A = csr_from_dense(np.diag(d))
+    ref, r, _, _ = run_pair(cbg, orc, dev, A, np.ones(40), restart=20, fmt="fp64", tol=1e-12,
+                            maxiter=100)
+    assert r.status == 0 and r.iterations == 5 and r.breakdowns == 1
+    # b = 0 -> x = 0 ; x0 = solution -> 0 iterations ; maxiter = 1
+    A = P.poisson2d(4)
+    Ad = cbg.DeviceCSR.from_host(A, dev)
+    r = cbg.solve(Ad, torch.zeros(A.n, dtype=torch.float64, device=dev),
+                  x0=torch.ones(A.n, dtype=torch.float64, device=dev), restart=5)
+    assert r.status == 0 and float(r.x.abs().max()) == 0.0
+    b = P.rhs_row_sums(A)
+    bd = torch.from_numpy(b).to(dev)
+    r = cbg.solve(Ad, bd, x0=torch.ones(A.n, dtype=torch.float64, device=dev), restart=5)
+    assert r.status == 0 and r.iterations == 0
+    r = cbg.solve(Ad, bd, restart=5, maxiter=1)
+    assert r.status == 1 and r.iterations == 1
+    # cyclic shift with m < n: stagnation, |g| exactly 1
+    n = 8
+    A = csr_from_dense(np.roll(np.eye(n), 1, axis=0))
+    e1 = np.zeros(n)
+    e1[0] = 1
+    r = cbg.solve(cbg.DeviceCSR.from_host(A, dev), torch.from_numpy(e1).to(dev), restart=n - 1,
+                  tol=1e-12, maxiter=3 * (n - 1))
+    assert r.status == 1 and np.all(r.hist == 1.0) and r.reorths == 0
+    # non-finite right-hand side
+    bn = b.copy()
+    bn[3] = np.nan
+    with pytest.raises(cbg.CbgError):
+        cbg.solve(Ad, torch.from_numpy(bn).to(dev), restart=5)
+    # ragged tiny systems in every format
+    for n in (1, 2, 3, 17):
+        M = np.diag(np.arange(1.0, n + 1)) + np.diag(np.full(n - 1, 0.3), 1) if n > 1 else np.eye(1)
+        A = csr_from_dense(M)
+        b = np.ones(n)
+        for fmt in FORMATS:
+            r = cbg.solve(cbg.DeviceCSR.from_host(A, dev), torch.from_numpy(b).to(dev),
+                          restart=min(n, 5), fmt=fmt, tol=1e-12, maxiter=500)
+            assert r.status == 0, (n, fmt)
+            assert true_res(orc, A, b, r.x.cpu().numpy()) <= 1e-12

@@ -13,22 +13,9 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from paper_2009_12101_amd import problems as P
+from _helpers import csr_from_dense, csr_from_scipy
 
 FORMATS = ["fp64", "fp32", "fp16", "bf16", "e4m3", "int32", "int16"]
-
-
-def csr_from_dense(M, name="dense"):
-    S = sp.csr_matrix(M)
-    S.sort_indices()
-    return P.CSR(M.shape[0], S.indptr.astype(np.int32), S.indices.astype(np.int32),
-                 S.data.astype(np.float64), name=name)
-
-
-def csr_from_scipy(S, name="scipy"):
-    S = sp.csr_matrix(S)
-    S.sort_indices()
-    return P.CSR(S.shape[0], S.indptr.astype(np.int32), S.indices.astype(np.int32),
-                 S.data.astype(np.float64), name=name)
 
 
 def random_wellcond(n, seed):
