@@ -28,6 +28,58 @@ if ROOT not in sys.path:
 
 METRIC = "time-to-solution + Arnoldi GB/s at rel. residual 1e-10, CB vs fp64-basis"
 HBM_PEAK_GBPS = 8000.0
+KERNEL_SOURCES = ["paper_2009_12101_amd/csrc/cbg_kernels.hip",
+                  "paper_2009_12101_amd/csrc/cbg_device.hpp"]
+COPY_CALIB_BYTES = 256 * 2 ** 20
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_file(fmt: str, grid: int) -> str:
+    return os.path.join(ROOT, "profiles", f"traffic_k_multidot_{fmt}_convdiff7_{grid}.json")
+
+
+def pmc_summary(fetch_csv: str, write_csv: str, fmt: str, grid: int) -> dict:
+    """HBM bytes per launch of the multi-dot kernel from two rocprofv3 --pmc
+    runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch), each scaled by what the
+    same counter reads for the plain 256 MiB elementwise pass (torch.neg)
+    that `bench.py --calib-copy` runs first."""
+    import csv
+    fmt_id = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "e4m3": 4, "int32": 5, "int16": 6}[fmt]
+    kname = f"k_multidot<{fmt_id}>"
+
+    def read(path, counter):
+        rows = list(csv.DictReader(open(path)))
+        by_kernel = {}
+        for r in rows:
+            if r.get("Counter_Name") != counter:
+                continue
+            by_kernel.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        copy = [v for k, vals in by_kernel.items() if "neg_kernel" in k for v in vals]
+        md = [v for k, vals in by_kernel.items() if kname in k for v in vals]
+        if not copy or not md:
+            raise SystemExit(f"{path}: no copy-kernel or {kname} rows for {counter}")
+        copy_kib = max(copy)                 # the 256 MiB calibration copy
+        return sum(md) / len(md), copy_kib, len(md)
+
+    f_kib, f_copy, nf = read(fetch_csv, "FETCH_SIZE")
+    w_kib, w_copy, nw = read(write_csv, "WRITE_SIZE")
+    f_scale = COPY_CALIB_BYTES / (f_copy * 1024.0)
+    w_scale = COPY_CALIB_BYTES / (w_copy * 1024.0)
+    out = {"kernel": kname, "format": fmt, "grid": grid,
+           "fetch_bytes_per_launch": f_kib * 1024.0 * f_scale,
+           "write_bytes_per_launch": w_kib * 1024.0 * w_scale,
+           "fetch_scale": f_scale, "write_scale": w_scale, "launches": [nf, nw],
+           "kernel_source_sha256": kernel_source_hash()}
+    out["traffic_bytes_per_launch"] = out["fetch_bytes_per_launch"] + out["write_bytes_per_launch"]
+    return out
 
 
 def log(*a):
@@ -44,7 +96,17 @@ def main() -> int:
     ap.add_argument("--compare", default="fp64,fp32,int16")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-cycles", type=int, default=1)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run a plain 256 MiB device copy first (counter calibration)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the multi-dot traffic record from two counter runs and exit")
     args = ap.parse_args()
+    if args.pmc_summary:
+        rec = pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.format, args.grid)
+        with open(traffic_file(args.format, args.grid), "w") as f:
+            json.dump(rec, f, indent=1)
+        print(json.dumps(rec))
+        return 0
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
                           "--gpus > 1 is not supported (single-GPU build)"}))
@@ -57,6 +119,14 @@ def main() -> int:
     from paper_2009_12101_amd import problems as P
 
     dev = torch.device("cuda:0")
+    if args.calib_copy:
+        # a plain elementwise pass of known size (reads and writes 256 MiB):
+        # the counter runs scale FETCH_SIZE / WRITE_SIZE by what it reads
+        src = torch.ones(COPY_CALIB_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     m, tol, maxiter = 100, 1e-10, 20000
     t0 = time.time()
     A = P.convdiff7(args.grid)
@@ -129,6 +199,13 @@ def main() -> int:
                          f"the GPU's {r0.iterations} steps"}
         log(f"cpu oracle: {dt:.1f}s for {o['iterations']} steps")
 
+    traffic = None
+    tf = traffic_file(args.format, args.grid)
+    if os.path.exists(tf):
+        rec = json.load(open(tf))
+        if rec.get("kernel_source_sha256") == kernel_source_hash():
+            traffic = rec["traffic_bytes_per_launch"]
+
     line = {
         "metric": METRIC, "value": value, "unit": "s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": False,
@@ -146,7 +223,7 @@ def main() -> int:
         "speedup_vs_fp64_basis": (formats["fp64"]["seconds"] / value) if "fp64" in formats
         else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                      "kernel": f"k_multidot<{args.format}>",
                      "launches": dot_launch,
                      "avg_launch_us": dot_ms * 1e3 / max(dot_launch, 1),

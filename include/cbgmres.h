@@ -116,7 +116,8 @@ typedef struct {
      * and launch count of the basis-streaming kernels (multi-dot h = V^T w
      * and update w -= V h, both passes).  Every launch is counted, also the
      * ones that found their step skipped (no re-orthogonalisation, or the
-     * cycle already finished); those add time but no bytes. */
+     * cycle already finished); those add time but no bytes.  The events are
+     * recorded at each kernel's own start and end (hipExtLaunchKernelGGL). */
     double prof_orth_ms;
     double prof_orth_bytes;
     int64_t prof_orth_launches;

@@ -16,6 +16,8 @@
 // with plain stores and a one-block reduce kernel folds them in fixed order,
 // so sums are bitwise reproducible and no block fences against another.
 // The host only enqueues kernels; it synchronises once per restart cycle.
+#include <hip/hip_ext.h>
+
 #include "cbg_device.hpp"
 #include "cbg_launch.hpp"
 
@@ -105,19 +107,31 @@ struct StepArrays {
     int32_t *flags;    // m: bit0 re-orthogonalised, bit1 breakdown
 };
 
-// Fig. 1 steps 9-12 and the column-by-column Givens update of step 17.
-// Reading of step 12 (the literal test would end every re-orthogonalised
-// cycle): breakdown iff h_{j+1,j} = 0, or the second pass again lost more
-// than a factor eta.
+// Fig. 1 steps 9-12 and the column-by-column Givens update of step 17, run
+// by every thread of a one-block kernel.  Reading of step 12 (the literal
+// test would end every re-orthogonalised cycle): breakdown iff
+// h_{j+1,j} = 0, or the second pass again lost more than a factor eta.
+// The column (h, plus u after a re-orthogonalisation) and the stored
+// rotations are staged in LDS; one thread then runs the rotation chain with
+// the carried entry in a register.
 __device__ void finish_step(DevState *st, const StepArrays &a, int j, bool reorth, double t2,
                             double wmax2)
 {
+    __shared__ double lh[MAX_RESTART + 1], lc[MAX_RESTART], ls[MAX_RESTART];
+    const int tid = threadIdx.x, nth = blockDim.x;
+    for (int k = tid; k < j; k += nth)
+        lh[k] = reorth ? a.h[k] + a.u[k] : a.h[k];
+    for (int k = tid; k < j - 1; k += nth) {
+        lc[k] = a.cs[k];
+        ls[k] = a.sn[k];
+    }
+    __syncthreads();
+    if (tid != 0)
+        return;
     const int m = st->m;
     double t = st->t;
     bool brk;
     if (reorth) {
-        for (int k = 0; k < j; ++k)
-            a.h[k] += a.u[k];
         brk = (t2 == 0.0) || (t2 < st->eta * t);
         t = t2;
         st->wmax = wmax2;
@@ -128,33 +142,32 @@ __device__ void finish_step(DevState *st, const StepArrays &a, int j, bool reort
     st->t = t;
     const int jc = j - 1;
     double *Hc = a.H + (size_t)jc * (m + 1);
-    for (int k = 0; k < j; ++k)
-        Hc[k] = a.h[k];
-    Hc[j] = t;
+    double carry = lh[0];
     for (int i = 0; i < jc; ++i) {
-        double a0 = Hc[i], a1 = Hc[i + 1];
-        Hc[i] = a.cs[i] * a0 + a.sn[i] * a1;
-        Hc[i + 1] = -a.sn[i] * a0 + a.cs[i] * a1;
+        const double a1 = lh[i + 1];
+        Hc[i] = lc[i] * carry + ls[i] * a1;
+        carry = -ls[i] * carry + lc[i] * a1;
     }
-    double x0 = Hc[jc], x1 = Hc[j];
-    double rr = sqrt(x0 * x0 + x1 * x1);
-    double c = 1.0, s = 0.0;
+    const double rr = sqrt(carry * carry + t * t);
+    double c = 1.0, sn = 0.0;
     if (rr > 0.0) {
-        c = x0 / rr;
-        s = x1 / rr;
+        c = carry / rr;
+        sn = t / rr;
     }
     a.cs[jc] = c;
-    a.sn[jc] = s;
+    a.sn[jc] = sn;
     Hc[jc] = rr;
     Hc[j] = 0.0;
-    a.g[j] = -s * a.g[jc];
-    a.g[jc] = c * a.g[jc];
+    const double gj = a.g[jc];
+    const double gnew = -sn * gj;
+    a.g[j] = gnew;
+    a.g[jc] = c * gj;
     st->it += 1;
-    double rec = fabs(a.g[j]) / st->nb;
+    const double rec = fabs(gnew) / st->nb;
     a.hist[jc] = rec;
     st->last_rec = rec;
-    bool finite = isfinite(st->omega) && isfinite(t) && isfinite(a.g[j]);
-    bool conv = fabs(a.g[j]) <= st->tau_nb;
+    const bool finite = isfinite(st->omega) && isfinite(t) && isfinite(gnew);
+    const bool conv = fabs(gnew) <= st->tau_nb;
     if (brk)
         st->breakdowns += 1;
     a.flags[jc] = (reorth ? 1 : 0) | (brk ? 2 : 0);
@@ -242,30 +255,58 @@ enum {
     SP_JACOBI = 1,     // y = A (dinv .* x)
     SP_RESID = 2,      // y = b - A x
     SP_FLOATVAL = 3,   // y = P x, P with float values on A's pattern
-    SP_ACCUM = 4       // y += P x (P float values), y of length n
+    SP_ACCUM = 4,      // y += P x (P float values), y of length n
+    // Arnoldi-step variants: the input is the previous step's orthogonalised
+    // w and t = h_{j+1,j}; the kernel gathers v = w / t (IEEE division, the
+    // same bits as Fig. 1 step 13 produces) and stores v's compressed form
+    // for its own rows (step 14) while it computes A M^-1 v (step 3)
+    SP_STEP_PLAIN = 8 | SP_PLAIN,
+    SP_STEP_JACOBI = 8 | SP_JACOBI,
+    SP_STEP_FLOATVAL = 8 | SP_FLOATVAL
 };
 // roles: SR_NONE no partials (skipped once the cycle is done); SR_STEP
 // partials of ||y||^2 and max|y_i| (skipped once done); SR_FREE partials,
 // never skipped (explicit residual, kernel-level calls).
 enum { SR_NONE = 0, SR_STEP = 1, SR_FREE = 2 };
 
+constexpr bool sp_step(int mode) { return (mode & 8) != 0; }
+
 template <int MODE>
 __device__ __forceinline__ double spmv_term(int p, const int32_t *__restrict__ ci,
                                             const double *__restrict__ val,
                                             const float *__restrict__ fval,
                                             const double *__restrict__ x,
-                                            const double *__restrict__ dinv)
+                                            const double *__restrict__ dinv, double tdiv)
 {
+    constexpr int BASE = MODE & 7;
     const int c = ci[p];
     double a;
-    if constexpr (MODE == SP_FLOATVAL || MODE == SP_ACCUM)
+    if constexpr (BASE == SP_FLOATVAL || BASE == SP_ACCUM)
         a = (double)fval[p];
     else
         a = val[p];
     double xv = x[c];
-    if constexpr (MODE == SP_JACOBI)
+    if constexpr (sp_step(MODE))
+        xv = xv / tdiv;
+    if constexpr (BASE == SP_JACOBI)
         xv = dinv[c] * xv;
     return a * xv;
+}
+
+// Store entry i of a vector through the accessor (one entry; the vector's
+// scale parameters in p).
+__device__ __forceinline__ void store_entry(int fmt, uint8_t *__restrict__ Q, int64_t i, double v,
+                                            EncParam p)
+{
+    switch (fmt) {
+    case F_FP64: ((double *)Q)[i] = v; break;
+    case F_FP32: ((float *)Q)[i] = (float)v; break;
+    case F_FP16: ((uint16_t *)Q)[i] = (uint16_t)Fmt<F_FP16>::code(v, p); break;
+    case F_BF16: ((uint16_t *)Q)[i] = (uint16_t)Fmt<F_BF16>::code(v, p); break;
+    case F_E4M3: Q[i] = (uint8_t)Fmt<F_E4M3>::code(v, p); break;
+    case F_INT32: ((uint32_t *)Q)[i] = Fmt<F_INT32>::code(v, p); break;
+    default: ((uint16_t *)Q)[i] = (uint16_t)Fmt<F_INT16>::code(v, p); break;
+    }
 }
 
 template <int RPB, int CAP, int MODE>
@@ -277,10 +318,17 @@ __global__ __launch_bounds__(BLK) void k_spmv(int n, int64_t ldy, const int32_t 
                                               const double *__restrict__ dinv,
                                               const double *__restrict__ b,
                                               double *__restrict__ y, RedArgs ra, int role,
-                                              const DevState *st)
+                                              const DevState *st, uint8_t *__restrict__ Q,
+                                              const double *__restrict__ qscale, int fmt)
 {
     if (st && role != SR_FREE && st->done)
         return;
+    double tdiv = 1.0;
+    EncParam ep{1.0, 0};
+    if constexpr (sp_step(MODE)) {
+        tdiv = st->t;
+        ep = param_from_scale(fmt, *qscale);
+    }
     constexpr int TPR = BLK / RPB;          // threads per row in the sum phase
     constexpr int UNR = 4;                  // products per thread per batch
     __shared__ double prod[CAP];
@@ -304,7 +352,7 @@ __global__ __launch_bounds__(BLK) void k_spmv(int n, int64_t ldy, const int32_t 
 #pragma unroll
                 for (int u = 0; u < UNR; ++u) {
                     const int qq = min(q + u * BLK, cnt - 1);      // clamped: loads stay in bounds
-                    v[u] = spmv_term<MODE>(p0 + qq, ci, val, fval, x, dinv);
+                    v[u] = spmv_term<MODE>(p0 + qq, ci, val, fval, x, dinv, tdiv);
                 }
 #pragma unroll
                 for (int u = 0; u < UNR; ++u)
@@ -323,17 +371,23 @@ __global__ __launch_bounds__(BLK) void k_spmv(int n, int64_t ldy, const int32_t 
                     s += prod[q];
             } else {
                 for (int q = a0 + part; q < a1; q += TPR)
-                    s += spmv_term<MODE>(p0 + q, ci, val, fval, x, dinv);
+                    s += spmv_term<MODE>(p0 + q, ci, val, fval, x, dinv, tdiv);
             }
         }
 #pragma unroll
         for (int d = TPR / 2; d >= 1; d >>= 1)
             s += __shfl_xor(s, d);
+        if constexpr (sp_step(MODE)) {
+            // steps 13-14 for this block's rows: v = w / t, stored through
+            // the accessor (rows in [n, ldy) hold w = 0 and store 0)
+            if (part == 0 && row < ldy)
+                store_entry(fmt, Q, row, x[row] / tdiv, ep);
+        }
         if (part == 0 && row < ldy) {
             double yv;
-            if constexpr (MODE == SP_RESID)
+            if constexpr ((MODE & 7) == SP_RESID)
                 yv = row < n ? b[row] - s : 0.0;
-            else if constexpr (MODE == SP_ACCUM)
+            else if constexpr ((MODE & 7) == SP_ACCUM)
                 yv = y[row] + s;
             else
                 yv = row < n ? s : 0.0;
@@ -623,7 +677,46 @@ __global__ __launch_bounds__(BLK) void k_update(const uint8_t *__restrict__ V, i
 //   RR_VALUES  kernel-level multi-dot
 //   RR_NORMS   kernel-level update: ||w||_2, ||w||_inf
 
-constexpr int RBLK = 1024;
+constexpr int RBLK = 256;
+constexpr int RWAVES = RBLK / 64;
+
+// One wave folds block partials src[0 .. nb) (8 independent loads in flight
+// per lane, fixed order); every lane returns the total.
+__device__ __forceinline__ double wave_fold(const double *__restrict__ src, int nb, bool is_max)
+{
+    const int lane = threadIdx.x & 63;
+    double acc[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+        acc[u] = 0.0;
+    for (int b0 = lane; b0 < nb; b0 += 64 * 8) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            x[u] = src[min(b0 + 64 * u, nb - 1)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double xv = (b0 + 64 * u < nb) ? x[u] : 0.0;
+            acc[u] = is_max ? fmax(acc[u], xv) : acc[u] + xv;
+        }
+    }
+    double a = acc[0];
+#pragma unroll
+    for (int u = 1; u < 8; ++u)
+        a = is_max ? fmax(a, acc[u]) : a + acc[u];
+    return is_max ? wave_max(a) : wave_sum(a);
+}
+
+// Number of blocks k_reduce runs with: the j independent coefficients (h or
+// u) are spread one per wave over the grid.
+int reduce_grid(int role, int j)
+{
+    if (role == RR_H || role == RR_U || role == RR_VALUES) {
+        int g = (j + RWAVES - 1) / RWAVES;
+        return g < 1 ? 1 : (g > 64 ? 64 : g);
+    }
+    return 1;
+}
 
 __global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth, int nb_spmv,
                                                  int j, DevState *st, StepArrays sa,
@@ -635,77 +728,71 @@ __global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth
         if (role == RR_T2 && !st->reorth)
             return;
     }
-    __shared__ double val[MAX_RESTART + 4];
-    // output v: source region (0 orth, 1 spmv), row in that region, block
-    // count, and whether it is a maximum
-    int nv;
-    switch (role) {
-    case RR_H: nv = j + 1; break;
-    case RR_U: nv = j + 2; break;
-    case RR_VALUES: nv = j; break;
-    default: nv = 2; break;
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int v = wave; v < nv; v += RBLK / 64) {
-        const double *src;
-        int nb;
-        bool is_max;
-        if (role == RR_NB || role == RR_SCALE || role == RR_NORM2 || role == RR_RESID) {
-            src = ws.spmv + (size_t)v * ws.stride;
-            nb = nb_spmv;
-            is_max = v == 1;
-        } else if (role == RR_H && v == j) {
-            src = ws.spmv;
-            nb = nb_spmv;
-            is_max = false;
-        } else if (role == RR_T2 || role == RR_NORMS) {
-            src = ws.orth + (size_t)v * ws.stride;
-            nb = nb_orth;
-            is_max = v == 1;
-        } else {
-            src = ws.orth + (size_t)v * ws.stride;
-            nb = nb_orth;
-            is_max = (role == RR_U && v == j + 1);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, tid = threadIdx.x;
+    // coefficients h_k / u_k / kernel-level values: one wave each, all blocks
+    if (role == RR_H || role == RR_U || role == RR_VALUES) {
+        double *dst = role == RR_H ? sa.h : role == RR_U ? sa.u : out;
+        for (int k = blockIdx.x * RWAVES + wave; k < j; k += gridDim.x * RWAVES) {
+            const double a = wave_fold(ws.orth + (size_t)k * ws.stride, nb_orth, false);
+            if (lane == 0)
+                dst[k] = a;
         }
-        double a = 0.0;
-        for (int b = lane; b < nb; b += 64)
-            a = is_max ? fmax(a, src[b]) : a + src[b];
-        a = is_max ? wave_max(a) : wave_sum(a);
+    }
+    if (blockIdx.x != 0 || role == RR_VALUES)
+        return;
+    // the scalars (block 0): sum and max of a partial pair
+    __shared__ double sv[2];
+    const double *s0, *s1;
+    int nb;
+    if (role == RR_H) {
+        s0 = ws.spmv;                                   // omega^2
+        s1 = ws.spmv + ws.stride;
+        nb = nb_spmv;
+    } else if (role == RR_U) {
+        s0 = ws.orth + (size_t)j * ws.stride;           // ||w||^2, max|w_i|
+        s1 = ws.orth + (size_t)(j + 1) * ws.stride;
+        nb = nb_orth;
+    } else if (role == RR_T2 || role == RR_NORMS) {
+        s0 = ws.orth;
+        s1 = ws.orth + ws.stride;
+        nb = nb_orth;
+    } else {
+        s0 = ws.spmv;
+        s1 = ws.spmv + ws.stride;
+        nb = nb_spmv;
+    }
+    if (wave < 2) {
+        const double a = wave_fold(wave == 0 ? s0 : s1, nb, wave == 1);
         if (lane == 0)
-            val[v] = a;
+            sv[wave] = a;
     }
     __syncthreads();
-    const int tid = threadIdx.x;
     switch (role) {
     case RR_NB:
         if (tid == 0) {
-            const double nb = sqrt(val[0]);
-            st->nb = nb;
-            st->tau_nb = st->tau_nb * nb;
-            if (!isfinite(nb))
+            const double nbv = sqrt(sv[0]);
+            st->nb = nbv;
+            st->tau_nb = st->tau_nb * nbv;
+            if (!isfinite(nbv))
                 st->nonfinite = 1;
         }
         break;
     case RR_SCALE:
         if (tid == 0)
-            *out = make_param(fmt, val[1]).scale;
+            *out = make_param(fmt, sv[1]).scale;
         break;
     case RR_NORM2:
         if (tid == 0)
-            *out = sqrt(val[0]);
+            *out = sqrt(sv[0]);
         break;
     case RR_NORMS:
         if (tid == 0 && out) {
-            out[0] = sqrt(val[0]);
-            out[1] = val[1];
+            out[0] = sqrt(sv[0]);
+            out[1] = sv[1];
         }
         break;
-    case RR_VALUES:
-        for (int k = tid; k < j; k += RBLK)
-            out[k] = val[k];
-        break;
     case RR_RESID: {
-        const double beta = sqrt(val[0]);
+        const double beta = sqrt(sv[0]);
         const int m = st->m;
         for (int i = tid; i < m + 2; i += RBLK)
             sa.g[i] = 0.0;
@@ -713,7 +800,7 @@ __global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth
         if (tid == 0) {
             st->jprev = st->jeff;
             st->beta = beta;
-            st->rmax = val[1];
+            st->rmax = sv[1];
             st->t = beta;
             st->done = 0;
             st->jeff = 0;
@@ -722,35 +809,32 @@ __global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth
             sa.g[0] = beta;
             if (!isfinite(beta))
                 st->nonfinite = 1;
-            sa.scales[0] = beta > 0.0 ? make_param(st->fmt, val[1] / beta).scale : 1.0;
+            sa.scales[0] = beta > 0.0 ? make_param(st->fmt, sv[1] / beta).scale : 1.0;
         }
         break;
     }
     case RR_H:
-        for (int k = tid; k < j; k += RBLK)
-            sa.h[k] = val[k];
         if (tid == 0)
-            st->omega = sqrt(val[j]);
+            st->omega = sqrt(sv[0]);
         break;
     case RR_U: {
-        for (int k = tid; k < j; k += RBLK)
-            sa.u[k] = val[k];
+        // Fig. 1 steps 6-7; without re-orthogonalisation the step ends here
+        // (finish_step needs h, which the previous kernel stored, not u)
+        const double t = sqrt(sv[0]);
+        const bool ro = t < st->eta * st->omega;
         __syncthreads();
         if (tid == 0) {
-            // Fig. 1 steps 6-7
-            const double t = sqrt(val[j]);
             st->t = t;
-            st->wmax = val[j + 1];
-            const bool ro = t < st->eta * st->omega;
+            st->wmax = sv[1];
             st->reorth = ro ? 1 : 0;
-            if (!ro)
-                finish_step(st, sa, j, false, 0.0, 0.0);
         }
+        __syncthreads();
+        if (!ro)
+            finish_step(st, sa, j, false, 0.0, 0.0);
         break;
     }
     case RR_T2:
-        if (tid == 0)
-            finish_step(st, sa, j, true, sqrt(val[0]), val[1]);
+        finish_step(st, sa, j, true, sqrt(sv[0]), sv[1]);
         break;
     }
 }
@@ -881,7 +965,8 @@ static int spmv_shape(const SpmvArgs &a, hipStream_t s)
 #define CBG_SPMV_CASE(M)                                                                      \
     case M:                                                                                   \
         k_spmv<RPB, CAP, M><<<g, BLK, 0, s>>>(a.n, a.ldy, a.rp, a.ci, a.val, a.fval, a.x,     \
-                                               a.dinv, a.b, a.y, ra, a.role, a.st);           \
+                                               a.dinv, a.b, a.y, ra, a.role, a.st,            \
+                                               (uint8_t *)a.Q, a.qscale, a.fmt);              \
         break;
     switch (a.mode) {
         CBG_SPMV_CASE(SP_PLAIN)
@@ -889,6 +974,9 @@ static int spmv_shape(const SpmvArgs &a, hipStream_t s)
         CBG_SPMV_CASE(SP_RESID)
         CBG_SPMV_CASE(SP_FLOATVAL)
         CBG_SPMV_CASE(SP_ACCUM)
+        CBG_SPMV_CASE(SP_STEP_PLAIN)
+        CBG_SPMV_CASE(SP_STEP_JACOBI)
+        CBG_SPMV_CASE(SP_STEP_FLOATVAL)
     }
 #undef CBG_SPMV_CASE
     return g;
@@ -927,13 +1015,23 @@ int orth_grid(int fmt, int64_t n)
     return grid_for(n, tile);
 }
 
+// With events, the launch goes through hipExtLaunchKernelGGL, which records
+// them at the kernel's own start and end (the interval a profiler reports).
 void launch_multidot(const OrthArgs &a, hipStream_t s)
 {
     int g = orth_grid(a.fmt, a.n);
     RedArgs ra{a.ws.orth, a.ws.stride};
-    CBG_FMT_SWITCH(a.fmt, (k_multidot<F><<<g, BLK, 0, s>>>((const uint8_t *)a.V, a.ld, a.scales,
-                                                            a.n, a.j, a.w, ra, a.st, a.gated,
-                                                            a.with_norms)))
+    const uint8_t *V = (const uint8_t *)a.V;
+    if (a.ev0) {
+        CBG_FMT_SWITCH(a.fmt, (hipExtLaunchKernelGGL(k_multidot<F>, dim3(g), dim3(BLK), 0, s,
+                                                     a.ev0, a.ev1, 0, V, a.ld, a.scales, a.n,
+                                                     a.j, a.w, ra, a.st, a.gated,
+                                                     a.with_norms)))
+    } else {
+        CBG_FMT_SWITCH(a.fmt, (k_multidot<F><<<g, BLK, 0, s>>>(V, a.ld, a.scales, a.n, a.j, a.w,
+                                                                ra, a.st, a.gated,
+                                                                a.with_norms)))
+    }
 }
 
 void launch_update(const OrthArgs &a, hipStream_t s)
@@ -942,8 +1040,15 @@ void launch_update(const OrthArgs &a, hipStream_t s)
     RedArgs ra{a.ws.orth, a.ws.stride};
     const uint8_t *V = (const uint8_t *)a.V;
 #define CBG_UPD(R)                                                                            \
-    CBG_FMT_SWITCH(a.fmt, (k_update<F, R><<<g, BLK, 0, s>>>(V, a.ld, a.scales, a.n, a.j,       \
-                                                             a.coef, a.wio, a.dinv, ra, a.st)))
+    if (a.ev0) {                                                                              \
+        CBG_FMT_SWITCH(a.fmt, (hipExtLaunchKernelGGL(k_update<F, R>, dim3(g), dim3(BLK), 0, s, \
+                                                     a.ev0, a.ev1, 0, V, a.ld, a.scales, a.n, \
+                                                     a.j, a.coef, a.wio, a.dinv, ra, a.st)))  \
+    } else {                                                                                  \
+        CBG_FMT_SWITCH(a.fmt, (k_update<F, R><<<g, BLK, 0, s>>>(V, a.ld, a.scales, a.n, a.j,   \
+                                                                 a.coef, a.wio, a.dinv, ra,   \
+                                                                 a.st)))                      \
+    }
     switch (a.role) {
     case U_PLAIN: CBG_UPD(U_PLAIN) break;
     case U_STEP1: CBG_UPD(U_STEP1) break;
@@ -960,7 +1065,8 @@ void launch_reduce(const RedWs &ws, int role, int nb_orth, int nb_spmv, int j, D
     StepArrays a{};
     if (sa)
         a = *(const StepArrays *)sa;
-    k_reduce<<<1, RBLK, 0, s>>>(ws, role, nb_orth, nb_spmv, j, st, a, out, fmt);
+    k_reduce<<<reduce_grid(role, j), RBLK, 0, s>>>(ws, role, nb_orth, nb_spmv, j, st, a, out,
+                                                   fmt);
 }
 
 void launch_normalize(int fmt, const double *w, int n, int64_t nst, double *v_out, void *Q,

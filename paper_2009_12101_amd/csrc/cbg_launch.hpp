@@ -24,10 +24,13 @@ struct SpmvArgs {
     const double *x, *dinv, *b;
     double *y;
     RedWs ws;
-    int mode;             // SP_* of the kernels
+    int mode;             // SP_* of the kernels (8 | base: Arnoldi-step variant)
     int role;             // SR_*: 0 none, 1 step (partials, skipped when done), 2 free
     int sg;               // rows per block (spmv_lanes)
     const DevState *st;
+    void *Q;              // step variants: basis slot receiving enc(x / t)
+    const double *qscale; // step variants: that slot's scale
+    int fmt;              // step variants: storage format
 };
 
 struct OrthArgs {
@@ -45,6 +48,7 @@ struct OrthArgs {
     int role;             // update U_*
     RedWs ws;
     const DevState *st;
+    hipEvent_t ev0, ev1;  // optional: recorded at the kernel's own start and end
 };
 
 // reduce roles (k_reduce)

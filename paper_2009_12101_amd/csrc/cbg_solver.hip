@@ -57,7 +57,7 @@ RedWs carve_red(Carver &c, int jmax)
 struct SolveWs {
     DevState *st;
     uint8_t *V;
-    double *scales, *v, *w, *z, *dinv, *xprev;
+    double *scales, *w0, *w1, *z, *dinv, *xprev;
     double *H, *h, *u, *cs, *sn, *g, *y, *hist;
     int32_t *flags;
     unsigned *bad;
@@ -72,8 +72,8 @@ SolveWs carve_solve(void *ws, int32_t n, int32_t m, int fmt, int pc, size_t *tot
     s.st = c.take<DevState>(1);
     s.V = c.take<uint8_t>((size_t)(m + 1) * ld * fmt_bytes(fmt));
     s.scales = c.take<double>(m + 1);
-    s.v = c.take<double>(ld);
-    s.w = c.take<double>(ld);
+    s.w0 = c.take<double>(ld);   // the step's w and the previous step's w
+    s.w1 = c.take<double>(ld);   // alternate between these two buffers
     s.z = c.take<double>(pc == CBG_PC_SPARSE ? ld : 1);
     s.dinv = c.take<double>(pc == CBG_PC_JACOBI ? ld : 1);
     s.xprev = c.take<double>(pc == CBG_PC_SPARSE ? ld : 1);
@@ -112,14 +112,18 @@ double now_s()
 // Algorithmic HBM bytes (what each kernel must move at least).
 struct ByteModel {
     double n, nnz, bs;
+    // CSR (values, column indices, row pointers), the gathered input and the
+    // output vector
     double spmv() const { return 12.0 * nnz + 4.0 * (n + 1) + 16.0 * n; }
+    // the Arnoldi-step SpMV also stores the previous basis vector
+    double spmv_step() const { return spmv() + n * bs; }
     double dot(int j) const { return j * n * bs + 8.0 * n; }
     double upd(int j) const { return j * n * bs + 16.0 * n; }
-    double normalize() const { return 16.0 * n + n * bs; }
 };
 
 // Profiling events of one cycle: per step, start/end of the four
-// basis-streaming launches (dot, update, re-dot, re-update).
+// basis-streaming launches (dot, update, re-dot, re-update), recorded by
+// hipExtLaunchKernelGGL at each kernel's own start and end.
 struct CycleEvents {
     std::vector<hipEvent_t> ev;
     int m = 0;
@@ -276,7 +280,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
         {
             SpmvArgs a{};
             a.n = n; a.ldy = ld; a.rp = A->row_ptr; a.ci = A->col_idx; a.val = A->val;
-            a.x = x; a.b = b; a.y = W.w; a.ws = W.red; a.mode = 2 /*SP_RESID*/;
+            a.x = x; a.b = b; a.y = W.w0; a.ws = W.red; a.mode = 2 /*SP_RESID*/;
             a.role = 2 /*SR_FREE*/; a.sg = sg; a.st = W.st;
             const int g = launch_spmv(a, s);
             launch_reduce(W.red, RR_RESID, 0, g, 0, W.st, sa, nullptr, fmt, s);
@@ -321,15 +325,14 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                 if (hist_n < hist_len)
                     hist_out[hist_n] = cyc_hist[j - 1];
                 ++hist_n;
-                double b_step = bm.spmv() + bm.dot(j) + bm.upd(j);
+                double b_step = bm.spmv_step() + bm.dot(j) + bm.upd(j);
                 if (prev_pc == CBG_PC_JACOBI) b_step += 8.0 * n;
                 if (prev_pc == CBG_PC_SPARSE) b_step += 8.0 * A->nnz + 4.0 * (n + 1) + 16.0 * n;
                 b_step += bm.dot(j);                 // the re-dot pass runs every step
                 if (ro) b_step += bm.upd(j);
-                if (j < jeff) b_step += bm.normalize();
                 model_bytes += b_step;
             }
-            model_bytes += bm.normalize() + jeff * n * bm.bs + 16.0 * n;
+            model_bytes += jeff * n * bm.bs + 16.0 * n;     // solution update
         }
 
         rho = hs.beta;
@@ -373,56 +376,61 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
         prev_cycle = true;
         prev_pc = pc;
 
-        // v_1 = r / beta, stored through the accessor.
-        launch_normalize(fmt, W.w, n, ld, W.v, W.V, W.scales, &W.st->t, 0.0, W.st, 0, s);
-
+        // The residual r sits in w0 with t = beta; step 1's SpMV forms
+        // v_1 = r / beta and stores it as basis vector 1.
+        double *cur = W.w0, *nxt = W.w1;
         for (int j = 1; j <= m; ++j) {
-            const double *src = W.v;
+            // steps 13-14 of the previous step (v_j = w / t, stored as basis
+            // vector j) fused with steps 3-4: w = A M^-1 v_j, omega
+            void *slot = W.V + (size_t)(j - 1) * vbytes;
+            int nb_spmv;
             if (pc == CBG_PC_SPARSE) {
                 SpmvArgs a{};
                 a.n = n; a.ldy = ld; a.rp = A->row_ptr; a.ci = A->col_idx; a.fval = opt->p_val;
-                a.x = W.v; a.y = W.z; a.ws = W.red; a.mode = 3 /*SP_FLOATVAL*/;
+                a.x = cur; a.y = W.z; a.ws = W.red; a.mode = 8 | 3 /*SP_STEP_FLOATVAL*/;
                 a.role = 0 /*SR_NONE*/; a.sg = sg; a.st = W.st;
+                a.Q = slot; a.qscale = W.scales + (j - 1); a.fmt = fmt;
                 launch_spmv(a, s);
-                src = W.z;
-            }
-            int nb_spmv;
-            {   // steps 3-4
+                SpmvArgs b2{};
+                b2.n = n; b2.ldy = ld; b2.rp = A->row_ptr; b2.ci = A->col_idx; b2.val = A->val;
+                b2.x = W.z; b2.y = nxt; b2.ws = W.red; b2.mode = 0 /*SP_PLAIN*/;
+                b2.role = 1 /*SR_STEP*/; b2.sg = sg; b2.st = W.st;
+                nb_spmv = launch_spmv(b2, s);
+            } else {
                 SpmvArgs a{};
                 a.n = n; a.ldy = ld; a.rp = A->row_ptr; a.ci = A->col_idx; a.val = A->val;
-                a.x = src; a.dinv = W.dinv; a.y = W.w; a.ws = W.red;
-                a.mode = pc == CBG_PC_JACOBI ? 1 : 0; a.role = 1 /*SR_STEP*/; a.sg = sg;
-                a.st = W.st;
+                a.x = cur; a.dinv = W.dinv; a.y = nxt; a.ws = W.red;
+                a.mode = pc == CBG_PC_JACOBI ? (8 | 1) : (8 | 0); a.role = 1 /*SR_STEP*/;
+                a.sg = sg; a.st = W.st; a.Q = slot; a.qscale = W.scales + (j - 1); a.fmt = fmt;
                 nb_spmv = launch_spmv(a, s);
             }
             OrthArgs o{};
             o.fmt = fmt; o.V = W.V; o.ld = ld; o.scales = W.scales; o.n = n; o.j = j;
-            o.w = W.w; o.wio = W.w; o.ws = W.red; o.st = W.st; o.gated = 1;
+            o.w = nxt; o.wio = nxt; o.ws = W.red; o.st = W.st; o.gated = 1;
+            auto timed = [&](int k) {
+                o.ev0 = prof ? evs.at(j, k, 0) : nullptr;
+                o.ev1 = prof ? evs.at(j, k, 1) : nullptr;
+            };
             // step 5: h = V^T w ; w -= V h
-            if (prof) HIP_TRY(hipEventRecord(evs.at(j, 0, 0), s));
+            timed(0);
             launch_multidot(o, s);
-            if (prof) HIP_TRY(hipEventRecord(evs.at(j, 0, 1), s));
             launch_reduce(W.red, RR_H, nb_orth, nb_spmv, j, W.st, sa, nullptr, fmt, s);
             o.coef = W.h; o.role = 1 /*U_STEP1*/;
-            if (prof) HIP_TRY(hipEventRecord(evs.at(j, 1, 0), s));
+            timed(1);
             launch_update(o, s);
-            if (prof) HIP_TRY(hipEventRecord(evs.at(j, 1, 1), s));
             // steps 6-8: ||w||, the test of step 7, and u = V^T w in one pass
             o.with_norms = 1;
-            if (prof) HIP_TRY(hipEventRecord(evs.at(j, 2, 0), s));
+            timed(2);
             launch_multidot(o, s);
-            if (prof) HIP_TRY(hipEventRecord(evs.at(j, 2, 1), s));
             launch_reduce(W.red, RR_U, nb_orth, 0, j, W.st, sa, nullptr, fmt, s);
             // steps 8-12 (no work unless step 7 asked for it)
             o.coef = W.u; o.role = 2 /*U_STEP2*/;
-            if (prof) HIP_TRY(hipEventRecord(evs.at(j, 3, 0), s));
+            timed(3);
             launch_update(o, s);
-            if (prof) HIP_TRY(hipEventRecord(evs.at(j, 3, 1), s));
             launch_reduce(W.red, RR_T2, nb_orth, 0, j, W.st, sa, nullptr, fmt, s);
-            // steps 13-14
-            if (j < m)
-                launch_normalize(fmt, W.w, n, ld, W.v, W.V + (size_t)j * vbytes, W.scales + j,
-                                 &W.st->t, 0.0, W.st, 1, s);
+            double *t = cur;
+            cur = nxt;
+            nxt = t;
         }
         HIP_TRY(hipGetLastError());
         // step 17: y = R^-1 g ; x += M^-1 V y
