@@ -95,6 +95,8 @@ def main() -> int:
     ap.add_argument("--format", default="fp16")
     ap.add_argument("--compare", default="fp64,fp32,int16")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fuse", action="store_true",
+                    help="ablation: update and re-dot as two basis passes")
     ap.add_argument("--cpu-cycles", type=int, default=1)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain 256 MiB device copy first (counter calibration)")
@@ -138,7 +140,7 @@ def main() -> int:
 
     def one(fmt, profile):
         return cbg.solve(Ad, bd, restart=m, fmt=fmt, tol=tol, maxiter=maxiter, profile=profile,
-                         workspace=ws)
+                         workspace=ws, fuse=not args.no_fuse)
 
     for _ in range(args.warmup):
         one(args.format, True)
@@ -158,6 +160,9 @@ def main() -> int:
     dot_ms = sum(r.prof_dot_ms for r in results)
     dot_bytes = sum(r.prof_dot_bytes for r in results)
     dot_launch = sum(r.prof_dot_launches for r in results)
+    fz_ms = sum(r.prof_fused_ms for r in results)
+    fz_bytes = sum(r.prof_fused_bytes for r in results)
+    fz_launch = sum(r.prof_fused_launches for r in results)
     orth_ms = sum(r.prof_orth_ms for r in results)
     orth_bytes = sum(r.prof_orth_bytes for r in results)
     achieved = dot_bytes / (dot_ms * 1e-3) / 1e9 if dot_ms > 0 else 0.0
@@ -219,6 +224,9 @@ def main() -> int:
         "true_rel_res": res_check,
         "arnoldi_gbps": r0.model_bytes / r0.seconds / 1e9,
         "orth_kernels_gbps": orth_bytes / (orth_ms * 1e-3) / 1e9 if orth_ms > 0 else None,
+        "fused_update_redot": None if fz_launch == 0 else {
+            "gbps": fz_bytes / (fz_ms * 1e-3) / 1e9, "launches": fz_launch,
+            "avg_launch_us": fz_ms * 1e3 / fz_launch},
         "formats": formats,
         "speedup_vs_fp64_basis": (formats["fp64"]["seconds"] / value) if "fp64" in formats
         else None,

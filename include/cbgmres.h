@@ -99,6 +99,10 @@ typedef struct {
 #define CBG_MAX_RESTART 512
 /* time the orthogonalisation kernels with HIP events (cbg_result.prof_*) */
 #define CBG_FLAG_PROFILE 1
+/* run the update of step 5 and the re-dot of step 8 as two basis passes
+ * (by default they share one pass while j fits the fused kernel's register
+ * tile; the arithmetic is the same, the summation order of u differs) */
+#define CBG_FLAG_NO_FUSE 2
 
 typedef struct {
     int64_t iterations;        /* Arnoldi steps (SpMVs with A inside cycles) */
@@ -113,17 +117,22 @@ typedef struct {
     double seconds;            /* host wall time of the call */
     double model_bytes;        /* algorithmic HBM bytes of the solve */
     /* with CBG_FLAG_PROFILE: summed event-timed duration, algorithmic bytes
-     * and launch count of the basis-streaming kernels (multi-dot h = V^T w
-     * and update w -= V h, both passes).  Every launch is counted, also the
-     * ones that found their step skipped (no re-orthogonalisation, or the
-     * cycle already finished); those add time but no bytes.  The events are
-     * recorded at each kernel's own start and end (hipExtLaunchKernelGGL). */
+     * and launch count of the basis-streaming kernels of the Arnoldi steps
+     * (multi-dot h = V^T w; update w -= V h fused with the re-dot, or the
+     * update and the re-dot as two passes; the re-orthogonalising update).
+     * Every launch is counted, also the ones that found their step skipped
+     * (no re-orthogonalisation, or the cycle already finished); those add
+     * time but no bytes.  The events are recorded at each kernel's own start
+     * and end (hipExtLaunchKernelGGL). */
     double prof_orth_ms;
     double prof_orth_bytes;
     int64_t prof_orth_launches;
-    double prof_dot_ms;        /* the multi-dot kernel alone */
+    double prof_dot_ms;        /* the multi-dot kernel alone (both passes) */
     double prof_dot_bytes;
     int64_t prof_dot_launches;
+    double prof_fused_ms;      /* the fused update + re-dot kernel alone */
+    double prof_fused_bytes;
+    int64_t prof_fused_launches;
 } cbg_result;
 
 /* Device workspace bytes cbgmres_solve needs for this problem shape
@@ -144,6 +153,17 @@ size_t cbg_workspace_bytes(int32_t n, int32_t restart, int32_t format, int32_t p
 int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *opt,
                   void *workspace, size_t ws_bytes, void *stream, cbg_result *res,
                   double *hist, int64_t hist_len);
+
+/* Where a cbgmres_solve workspace of this shape keeps the Krylov basis:
+ * after a solve, basis vector k (0-based) of the last cycle is stored at
+ * byte workspace + basis_offset + k * cbg_basis_ld(n) * bytes(format) in
+ * the chosen format (FP64 values for CBG_FP64), with its scale (double) at
+ * workspace + scales_offset + 8k, for k below that cycle's step count (the
+ * vector formed after a cycle's last step is not stored).  A solve that
+ * stops on maxiter leaves the basis of its last cycle in place.  Returns
+ * CBG_OK or CBG_E_ARG. */
+int cbg_workspace_basis(int32_t n, int32_t restart, int32_t format, int32_t precond,
+                        size_t *basis_offset, size_t *scales_offset);
 
 /* Static description of a status code. */
 const char *cbg_strerror(int status);
@@ -188,6 +208,128 @@ int cbg_multidot(int32_t format, const void *V, int64_t ld, const double *scales
 int cbg_update(int32_t format, const void *V, int64_t ld, const double *scales, int32_t n,
                int32_t j, const double *h, double *w, double *norms, void *ws,
                size_t ws_bytes, void *stream);
+
+
+/* Steps 5-8 in one basis pass: w -= sum_k h_k dec(V_k), then
+ * u_k = sum_i dec(V_k)_i w_i (the re-dot of step 8) for k < j, norms[0] =
+ * ||w||_2 and norms[1] = ||w||_inf of the updated w.  While j fits the
+ * kernel's register tile (j <= 104; 64 for e4m3) each lane keeps the bytes
+ * it loaded of every stored vector and the basis is read once; beyond it,
+ * the same arithmetic runs as an update and a multi-dot.  u [dev] j
+ * doubles; norms [dev] 2 doubles; other arguments as cbg_update. */
+int cbg_update_redot(int32_t format, const void *V, int64_t ld, const double *scales, int32_t n,
+                     int32_t j, const double *h, double *w, double *u, double *norms, void *ws,
+                     size_t ws_bytes, void *stream);
+
+/* ---------------- learned sparse approximate inverse ------------------- */
+/* An extension of the paper (which uses scalar Jacobi, Section 6): a per-row
+ * network proposes the values of a right preconditioner P on A's pattern, for
+ * matrices on an nx*ny*nz grid (x fastest, row = x + nx*(y + ny*z), n =
+ * nx*ny*nz) whose pattern lies within the 27-point stencil.
+ *
+ * Slots: entry (i, c) has slot p = (dz+1)*9 + (dy+1)*3 + (dx+1), the grid
+ * offset from row i to column c; slot 13 is the diagonal; entries outside the
+ * 27-point stencil have no slot.
+ * Features (n x 32 bf16, row-major): f_p = bf16(fl32(a_ic / a_ii)) for the
+ * row's slots, f_27 = bf16(fl32((a_ii - sum_{c != i} |a_ic|) / a_ii)) with the
+ * sum in CSR order, all else 0.
+ * Network: H1 = bf16(ReLU(F W1 + b1)), H2 = bf16(ReLU(H1 W2 + b2)),
+ * O = H2 W3 + b3 (32 outputs, slots 0..26 used); bf16 weights, fp32 biases,
+ * fp32 accumulation on the matrix cores.
+ * P: P_ic = fl32((delta_{p,13} + O_ip) / a_ii) on A's pattern (0 where the
+ * entry has no slot); W3 = 0 and b3 = 0 give P = D^-1 (Jacobi).
+ * Loss over K unit vectors v_k: L = scale * sum_k ||A P v_k - v_k||_2^2.
+ *
+ * Parameters: `params` [dev] CBG_SPAI_NPARAM fp32 masters in the order W1
+ * (32x64, row-major: [in][out]), b1 (64), W2 (64x64), b2 (64), W3 (64x32),
+ * b3 (32); `weights` [dev] CBG_SPAI_NWEIGHT bf16 (uint16 bit patterns) of W1,
+ * W2, W3 in the same layout.  Vectors for the loss: `V` [dev] n x K fp16 bit
+ * patterns, row-major (entry (i, k) at i*K + k), K <= CBG_SPAI_MAX_K.
+ * All [dev] arrays 16-byte aligned; workspaces 256-byte aligned and sized by
+ * cbg_spai_workspace_bytes(n, nnz, K) (K = 0 where no vectors are used). */
+#define CBG_SPAI_NFEAT 32
+#define CBG_SPAI_NHID 64
+#define CBG_SPAI_NOUT 32
+#define CBG_SPAI_NPARAM 8352
+#define CBG_SPAI_NWEIGHT 8192
+#define CBG_SPAI_MAX_K 32
+
+size_t cbg_spai_workspace_bytes(int32_t n, int64_t nnz, int32_t K);
+
+/* Features of every row (see above).  grid [host] {nx, ny, nz}; feat [dev]
+ * n x 32 bf16.  Synchronises with the stream; returns CBG_E_NONFINITE if a
+ * row has a zero (or missing) diagonal or a non-finite feature. */
+int cbg_spai_features(const cbg_csr *A, const int32_t grid[3], uint16_t *feat, void *ws,
+                      size_t ws_bytes, void *stream);
+
+/* Network forward pass on n feature rows.  out [dev] n x 32 fp32; h1, h2
+ * [dev, nullable together] n x 64 bf16 activations kept for the backward
+ * pass. */
+int cbg_mlp_forward(int32_t n, const uint16_t *feat, const uint16_t *weights, const float *params,
+                    float *out, uint16_t *h1, uint16_t *h2, void *stream);
+
+/* P values on A's pattern from the network output.  out [dev] n x 32 fp32;
+ * p_val [dev] nnz fp32 (the CBG_PC_SPARSE values of cbg_opts). */
+int cbg_spai_assemble(const cbg_csr *A, const int32_t grid[3], const float *out, float *p_val,
+                      void *stream);
+
+/* Inference: features, forward pass and assembly of P in one call (once
+ * per matrix, before cbgmres_solve with CBG_PC_SPARSE).  Synchronises;
+ * CBG_E_NONFINITE as cbg_spai_features. */
+int cbg_learned_build(const cbg_csr *A, const int32_t grid[3], const uint16_t *weights,
+                      const float *params, float *p_val, void *ws, size_t ws_bytes, void *stream);
+
+/* Values of A^T on A's pattern: t_val[p] = a_ci for entry p = (i, c).  A
+ * must be structurally symmetric; synchronises and returns
+ * CBG_E_UNSUPPORTED if some (c, i) is missing. */
+int cbg_csr_transpose_values(const cbg_csr *A, double *t_val, void *ws, size_t ws_bytes,
+                             void *stream);
+
+/* Training vectors: out (n x K fp16, row-major, one round-to-nearest-even)
+ * from the FP64 vectors V + (first + k*stride)*ld, k < K (e.g. a cycle's
+ * basis in a cbgmres_solve workspace, see cbg_workspace_basis_offset). */
+int cbg_spai_pack(const double *V, int64_t ld, int32_t n, int32_t K, int32_t first,
+                  int32_t stride, uint16_t *out, void *stream);
+
+/* Loss and its gradient with respect to P's values: R = A P V - V,
+ * *loss (+)= scale * ||R||_F^2, G = 2 scale A^T R, dP_e = sum_k G[i][k]
+ * V[c][k] for entry e = (i, c).  t_val [dev] from cbg_csr_transpose_values;
+ * p_val [dev] nnz fp32; loss [dev] 1 double; dP [dev] nnz doubles.
+ * accumulate = 0 overwrites *loss, 1 adds to it. */
+int cbg_spai_grad_p(const cbg_csr *A, const double *t_val, const float *p_val, int32_t K,
+                    const uint16_t *V, double scale, double *loss, int32_t accumulate,
+                    double *dP, void *ws, size_t ws_bytes, void *stream);
+
+/* dL/dO (n x 32 bf16, one rounding from FP64): dO_ip = dP_e / a_ii for the
+ * entry e of slot p in row i, 0 elsewhere. */
+int cbg_spai_grad_o(const cbg_csr *A, const int32_t grid[3], const double *dP, uint16_t *dO,
+                    void *stream);
+
+/* Network backward pass: grad [dev] CBG_SPAI_NPARAM doubles (+)= dL/dparams
+ * (params order) for the activations h1, h2 of cbg_mlp_forward and dL/dO
+ * (bf16); dH2 and dH1 are rounded to bf16 before their products. */
+int cbg_mlp_backward(int32_t n, const uint16_t *feat, const uint16_t *h1, const uint16_t *h2,
+                     const uint16_t *dO, const uint16_t *weights, double *grad,
+                     int32_t accumulate, void *ws, size_t ws_bytes, void *stream);
+
+/* One training evaluation on one matrix: forward, assembly, grad_p, grad_o
+ * and backward; *loss and grad (+)= the loss and its parameter gradient. */
+int cbg_spai_loss_grad(const cbg_csr *A, const double *t_val, const int32_t grid[3],
+                       const uint16_t *feat, const uint16_t *weights, const float *params,
+                       int32_t K, const uint16_t *V, double scale, double *loss, double *grad,
+                       int32_t accumulate, void *ws, size_t ws_bytes, void *stream);
+
+/* weights [dev] = the bf16 rounding (nearest even) of the W1, W2, W3 parts
+ * of params [dev]: sets the bf16 copy after the masters are initialised or
+ * loaded. */
+int cbg_spai_round_weights(const float *params, uint16_t *weights, void *stream);
+
+/* Adam step t >= 1 (Kingma and Ba, 2015, with bias correction) on the fp32
+ * masters; m1, m2 [dev] NPARAM fp32 moments (zero before step 1); moments and
+ * parameters are formed in FP64 and stored as fp32; weights is refreshed
+ * with their bf16 rounding. */
+int cbg_adam_step(float *params, float *m1, float *m2, uint16_t *weights, const double *grad,
+                  int64_t t, double lr, double beta1, double beta2, double eps, void *stream);
 
 #ifdef __cplusplus
 }

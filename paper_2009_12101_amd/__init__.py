@@ -10,9 +10,15 @@ device memory and streams only.
 """
 from . import problems
 from ._binding import (FORMATS, FORMAT_BYTES, PRECONDS, CbgError, DeviceCSR, SolveResult,
-                       basis_ld, decode, encode, kernel_workspace_bytes, lib, multidot, solve,
-                       spmv, strerror, update, workspace_bytes)
+                       adam_step, basis_ld, csr_transpose_values, decode, encode,
+                       kernel_workspace_bytes, learned_build, lib, mlp_backward, mlp_forward,
+                       multidot, solve, spai_assemble, spai_features, spai_grad_o, spai_grad_p,
+                       spai_loss_grad, spai_pack, spai_round_weights, spai_workspace_bytes, spmv,
+                       strerror, update, update_redot, workspace_basis, workspace_bytes)
 
 __all__ = ["problems", "FORMATS", "FORMAT_BYTES", "PRECONDS", "CbgError", "DeviceCSR",
-           "SolveResult", "basis_ld", "decode", "encode", "kernel_workspace_bytes", "lib",
-           "multidot", "solve", "spmv", "strerror", "update", "workspace_bytes"]
+           "SolveResult", "adam_step", "basis_ld", "csr_transpose_values", "decode", "encode",
+           "kernel_workspace_bytes", "learned_build", "lib", "mlp_backward", "mlp_forward",
+           "multidot", "solve", "spai_assemble", "spai_features", "spai_grad_o", "spai_grad_p",
+           "spai_loss_grad", "spai_pack", "spai_round_weights", "spai_workspace_bytes", "spmv",
+           "strerror", "update", "update_redot", "workspace_basis", "workspace_bytes"]

@@ -21,11 +21,19 @@ PRECONDS = {"none": 0, "jacobi": 1, "sparse": 2}
 OK, NOT_CONVERGED = 0, 1
 E_ARG, E_WORKSPACE, E_HIP, E_NONFINITE, E_UNSUPPORTED = -1, -2, -3, -4, -5
 FLAG_PROFILE = 1
+FLAG_NO_FUSE = 2
 MAX_RESTART = 512
 
 EXPORTS = ["cbg_strerror", "cbg_basis_ld", "cbg_workspace_bytes", "cbg_kernel_workspace_bytes",
-           "cbgmres_solve", "cbg_encode", "cbg_decode", "cbg_spmv", "cbg_multidot",
-           "cbg_update"]
+           "cbg_workspace_basis", "cbgmres_solve", "cbg_encode", "cbg_decode", "cbg_spmv",
+           "cbg_multidot", "cbg_update", "cbg_update_redot",
+           "cbg_spai_workspace_bytes", "cbg_spai_features", "cbg_mlp_forward",
+           "cbg_spai_assemble", "cbg_learned_build", "cbg_csr_transpose_values",
+           "cbg_spai_pack", "cbg_spai_grad_p", "cbg_spai_grad_o", "cbg_mlp_backward",
+           "cbg_spai_loss_grad", "cbg_spai_round_weights", "cbg_adam_step"]
+
+SPAI_NFEAT, SPAI_NHID, SPAI_NOUT = 32, 64, 32
+SPAI_NPARAM, SPAI_NWEIGHT, SPAI_MAX_K = 8352, 8192, 32
 
 
 class CbgCsr(C.Structure):
@@ -48,7 +56,8 @@ class CbgResult(C.Structure):
                 ("model_bytes", C.c_double), ("prof_orth_ms", C.c_double),
                 ("prof_orth_bytes", C.c_double), ("prof_orth_launches", C.c_int64),
                 ("prof_dot_ms", C.c_double), ("prof_dot_bytes", C.c_double),
-                ("prof_dot_launches", C.c_int64)]
+                ("prof_dot_launches", C.c_int64), ("prof_fused_ms", C.c_double),
+                ("prof_fused_bytes", C.c_double), ("prof_fused_launches", C.c_int64)]
 
 
 class CbgError(RuntimeError):
@@ -84,8 +93,29 @@ def lib():
         L.cbg_spmv.argtypes = [C.POINTER(CbgCsr), vp, vp, vp, vp, sz, vp]
         L.cbg_multidot.argtypes = [i32, vp, i64, vp, i32, i32, vp, vp, vp, sz, vp]
         L.cbg_update.argtypes = [i32, vp, i64, vp, i32, i32, vp, vp, vp, vp, sz, vp]
+        L.cbg_update_redot.argtypes = [i32, vp, i64, vp, i32, i32, vp, vp, vp, vp, vp, sz, vp]
+        L.cbg_workspace_basis.argtypes = [i32, i32, i32, i32, C.POINTER(sz), C.POINTER(sz)]
+        pcsr, f64 = C.POINTER(CbgCsr), C.c_double
+        L.cbg_spai_workspace_bytes.argtypes = [i32, i64, i32]
+        L.cbg_spai_workspace_bytes.restype = sz
+        L.cbg_spai_features.argtypes = [pcsr, vp, vp, vp, sz, vp]
+        L.cbg_mlp_forward.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp]
+        L.cbg_spai_assemble.argtypes = [pcsr, vp, vp, vp, vp]
+        L.cbg_learned_build.argtypes = [pcsr, vp, vp, vp, vp, vp, sz, vp]
+        L.cbg_csr_transpose_values.argtypes = [pcsr, vp, vp, sz, vp]
+        L.cbg_spai_pack.argtypes = [vp, i64, i32, i32, i32, i32, vp, vp]
+        L.cbg_spai_grad_p.argtypes = [pcsr, vp, vp, i32, vp, f64, vp, i32, vp, vp, sz, vp]
+        L.cbg_spai_grad_o.argtypes = [pcsr, vp, vp, vp, vp]
+        L.cbg_mlp_backward.argtypes = [i32, vp, vp, vp, vp, vp, vp, i32, vp, sz, vp]
+        L.cbg_spai_loss_grad.argtypes = [pcsr, vp, vp, vp, vp, vp, i32, vp, f64, vp, vp, i32,
+                                         vp, sz, vp]
+        L.cbg_spai_round_weights.argtypes = [vp, vp, vp]
+        L.cbg_adam_step.argtypes = [vp, vp, vp, vp, vp, i64, f64, f64, f64, f64, vp]
         for f in ("cbgmres_solve", "cbg_encode", "cbg_decode", "cbg_spmv", "cbg_multidot",
-                  "cbg_update"):
+                  "cbg_update", "cbg_update_redot", "cbg_workspace_basis", "cbg_spai_features", "cbg_mlp_forward",
+                  "cbg_spai_assemble", "cbg_learned_build", "cbg_csr_transpose_values",
+                  "cbg_spai_pack", "cbg_spai_grad_p", "cbg_spai_grad_o", "cbg_mlp_backward",
+                  "cbg_spai_loss_grad", "cbg_spai_round_weights", "cbg_adam_step"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -105,6 +135,18 @@ def workspace_bytes(n: int, restart: int, fmt: str, precond: str = "none") -> in
 
 def kernel_workspace_bytes(n: int, j: int) -> int:
     return int(lib().cbg_kernel_workspace_bytes(int(n), int(j)))
+
+
+def workspace_basis(n: int, restart: int, fmt: str, precond: str = "none"):
+    """(basis_offset, scales_offset) in bytes inside a solve workspace."""
+    bo, so = C.c_size_t(), C.c_size_t()
+    _check(lib().cbg_workspace_basis(int(n), int(restart), FORMATS[fmt], PRECONDS[precond],
+                                     C.byref(bo), C.byref(so)), "cbg_workspace_basis")
+    return int(bo.value), int(so.value)
+
+
+def spai_workspace_bytes(n: int, nnz: int, K: int = 0) -> int:
+    return int(lib().cbg_spai_workspace_bytes(int(n), int(nnz), int(K)))
 
 
 # ---------------------------------------------------------------- torch glue
@@ -171,11 +213,14 @@ class SolveResult:
     prof_dot_ms: float = 0.0
     prof_dot_bytes: float = 0.0
     prof_dot_launches: int = 0
+    prof_fused_ms: float = 0.0
+    prof_fused_bytes: float = 0.0
+    prof_fused_launches: int = 0
 
 
 def solve(A: DeviceCSR, b, x0=None, restart=100, fmt="fp64", tol=1e-10, maxiter=10000,
           eta=0.0, precond="none", p_val=None, fallback=False, profile=False, workspace=None,
-          hist=True) -> SolveResult:
+          hist=True, fuse=True) -> SolveResult:
     """cbgmres_solve on device tensors; returns the solution and counters.
     Raises CbgError on a negative status."""
     torch = _torch()
@@ -187,7 +232,7 @@ def solve(A: DeviceCSR, b, x0=None, restart=100, fmt="fp64", tol=1e-10, maxiter=
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=b.device)
     opts = CbgOpts(restart, FORMATS[fmt], tol, maxiter, eta, PRECONDS[precond],
                    int(bool(fallback)), None if p_val is None else p_val.data_ptr(),
-                   FLAG_PROFILE if profile else 0, 0)
+                   (FLAG_PROFILE if profile else 0) | (0 if fuse else FLAG_NO_FUSE), 0)
     res = CbgResult()
     hl = int(maxiter) if hist else 0
     h = np.zeros(max(hl, 1))
@@ -204,7 +249,9 @@ def solve(A: DeviceCSR, b, x0=None, restart=100, fmt="fp64", tol=1e-10, maxiter=
                        prof_orth_ms=res.prof_orth_ms, prof_orth_bytes=res.prof_orth_bytes,
                        prof_orth_launches=res.prof_orth_launches, prof_dot_ms=res.prof_dot_ms,
                        prof_dot_bytes=res.prof_dot_bytes,
-                       prof_dot_launches=res.prof_dot_launches)
+                       prof_dot_launches=res.prof_dot_launches,
+                       prof_fused_ms=res.prof_fused_ms, prof_fused_bytes=res.prof_fused_bytes,
+                       prof_fused_launches=res.prof_fused_launches)
 
 
 def _kws(n, j, device):
@@ -262,3 +309,155 @@ def update(fmt: str, V, ld: int, scales, n: int, j: int, h, w, norms=None, ws=No
     _check(lib().cbg_update(FORMATS[fmt], _ptr(V), ld, _ptr(scales), n, j, _ptr(h), _ptr(w),
                             _ptr(norms), _ptr(ws), ws.numel(), _stream()), "cbg_update")
     return norms
+
+
+def update_redot(fmt: str, V, ld: int, scales, n: int, j: int, h, w, ws=None):
+    """w -= V h, then (u = V^T w, norms = [||w||_2, ||w||_inf]) in one pass."""
+    torch = _torch()
+    u = torch.empty(max(j, 1), dtype=torch.float64, device=w.device)
+    norms = torch.empty(2, dtype=torch.float64, device=w.device)
+    ws = _kws(n, j, w.device) if ws is None else ws
+    _check(lib().cbg_update_redot(FORMATS[fmt], _ptr(V), ld, _ptr(scales), n, j, _ptr(h),
+                                  _ptr(w), _ptr(u), _ptr(norms), _ptr(ws), ws.numel(),
+                                  _stream()), "cbg_update_redot")
+    return u[:j], norms
+
+
+# ------------------------------------------------ learned preconditioner
+
+def _grid3(grid):
+    return (C.c_int32 * 3)(*[int(g) for g in grid])
+
+
+def _sws(n, nnz, K, device):
+    torch = _torch()
+    return torch.empty(max(spai_workspace_bytes(n, nnz, K), 256), dtype=torch.uint8,
+                       device=device)
+
+
+def spai_features(A: DeviceCSR, grid, feat=None, ws=None):
+    """(n, 32) int16 tensor of bf16 feature bit patterns."""
+    torch = _torch()
+    dev = A.val.device
+    feat = torch.empty((A.n, SPAI_NFEAT), dtype=torch.int16, device=dev) if feat is None else feat
+    ws = _sws(A.n, A.nnz, 0, dev) if ws is None else ws
+    csr = A.cstruct()
+    _check(lib().cbg_spai_features(C.byref(csr), _grid3(grid), _ptr(feat), _ptr(ws), ws.numel(),
+                                   _stream()), "cbg_spai_features")
+    return feat
+
+
+def mlp_forward(feat, weights, params, keep_activations=False):
+    """Returns O (n, 32) fp32, and (H1, H2) bf16 bit patterns if asked."""
+    torch = _torch()
+    n, dev = feat.shape[0], feat.device
+    O = torch.empty((n, SPAI_NOUT), dtype=torch.float32, device=dev)
+    h1 = h2 = None
+    if keep_activations:
+        h1 = torch.empty((n, SPAI_NHID), dtype=torch.int16, device=dev)
+        h2 = torch.empty((n, SPAI_NHID), dtype=torch.int16, device=dev)
+    _check(lib().cbg_mlp_forward(n, _ptr(feat), _ptr(weights), _ptr(params), _ptr(O), _ptr(h1),
+                                 _ptr(h2), _stream()), "cbg_mlp_forward")
+    return (O, h1, h2) if keep_activations else O
+
+
+def spai_assemble(A: DeviceCSR, grid, O, p_val=None):
+    torch = _torch()
+    p_val = torch.empty(A.nnz, dtype=torch.float32, device=O.device) if p_val is None else p_val
+    csr = A.cstruct()
+    _check(lib().cbg_spai_assemble(C.byref(csr), _grid3(grid), _ptr(O), _ptr(p_val), _stream()),
+           "cbg_spai_assemble")
+    return p_val
+
+
+def learned_build(A: DeviceCSR, grid, weights, params, p_val=None, ws=None):
+    """P values (nnz fp32) on A's pattern: features, forward pass, assembly."""
+    torch = _torch()
+    dev = A.val.device
+    p_val = torch.empty(A.nnz, dtype=torch.float32, device=dev) if p_val is None else p_val
+    ws = _sws(A.n, A.nnz, 0, dev) if ws is None else ws
+    csr = A.cstruct()
+    _check(lib().cbg_learned_build(C.byref(csr), _grid3(grid), _ptr(weights), _ptr(params),
+                                   _ptr(p_val), _ptr(ws), ws.numel(), _stream()),
+           "cbg_learned_build")
+    return p_val
+
+
+def csr_transpose_values(A: DeviceCSR, ws=None):
+    torch = _torch()
+    dev = A.val.device
+    t = torch.empty(A.nnz, dtype=torch.float64, device=dev)
+    ws = _sws(A.n, A.nnz, 0, dev) if ws is None else ws
+    csr = A.cstruct()
+    _check(lib().cbg_csr_transpose_values(C.byref(csr), _ptr(t), _ptr(ws), ws.numel(),
+                                          _stream()), "cbg_csr_transpose_values")
+    return t
+
+
+def spai_pack(V, ld: int, n: int, K: int, first: int = 0, stride: int = 1, out=None):
+    """(n, K) int16 tensor of fp16 bit patterns from K FP64 vectors in V."""
+    torch = _torch()
+    out = torch.empty((n, K), dtype=torch.int16, device=V.device) if out is None else out
+    _check(lib().cbg_spai_pack(_ptr(V), int(ld), int(n), int(K), int(first), int(stride),
+                               _ptr(out), _stream()), "cbg_spai_pack")
+    return out
+
+
+def spai_grad_p(A: DeviceCSR, t_val, p_val, V, scale, ws=None):
+    """(loss tensor[1], dP tensor[nnz]) for V (n, K) fp16 bit patterns."""
+    torch = _torch()
+    dev = A.val.device
+    K = V.shape[1]
+    loss = torch.empty(1, dtype=torch.float64, device=dev)
+    dP = torch.empty(A.nnz, dtype=torch.float64, device=dev)
+    ws = _sws(A.n, A.nnz, K, dev) if ws is None else ws
+    csr = A.cstruct()
+    _check(lib().cbg_spai_grad_p(C.byref(csr), _ptr(t_val), _ptr(p_val), K, _ptr(V),
+                                 float(scale), _ptr(loss), 0, _ptr(dP), _ptr(ws), ws.numel(),
+                                 _stream()), "cbg_spai_grad_p")
+    return loss, dP
+
+
+def spai_grad_o(A: DeviceCSR, grid, dP):
+    torch = _torch()
+    dO = torch.empty((A.n, SPAI_NOUT), dtype=torch.int16, device=dP.device)
+    csr = A.cstruct()
+    _check(lib().cbg_spai_grad_o(C.byref(csr), _grid3(grid), _ptr(dP), _ptr(dO), _stream()),
+           "cbg_spai_grad_o")
+    return dO
+
+
+def mlp_backward(feat, h1, h2, dO, weights, grad=None, accumulate=False, ws=None):
+    torch = _torch()
+    n, dev = feat.shape[0], feat.device
+    grad = torch.empty(SPAI_NPARAM, dtype=torch.float64, device=dev) if grad is None else grad
+    ws = _sws(n, 0, 0, dev) if ws is None else ws
+    _check(lib().cbg_mlp_backward(n, _ptr(feat), _ptr(h1), _ptr(h2), _ptr(dO), _ptr(weights),
+                                  _ptr(grad), int(bool(accumulate)), _ptr(ws), ws.numel(),
+                                  _stream()), "cbg_mlp_backward")
+    return grad
+
+
+def spai_loss_grad(A: DeviceCSR, t_val, grid, feat, weights, params, V, scale, loss, grad,
+                   accumulate=False, ws=None):
+    """loss[1], grad[NPARAM] (+)= one matrix's loss and parameter gradient."""
+    dev = A.val.device
+    K = V.shape[1]
+    ws = _sws(A.n, A.nnz, K, dev) if ws is None else ws
+    csr = A.cstruct()
+    _check(lib().cbg_spai_loss_grad(C.byref(csr), _ptr(t_val), _grid3(grid), _ptr(feat),
+                                    _ptr(weights), _ptr(params), K, _ptr(V), float(scale),
+                                    _ptr(loss), _ptr(grad), int(bool(accumulate)), _ptr(ws),
+                                    ws.numel(), _stream()), "cbg_spai_loss_grad")
+
+
+def spai_round_weights(params, weights):
+    _check(lib().cbg_spai_round_weights(_ptr(params), _ptr(weights), _stream()),
+           "cbg_spai_round_weights")
+    return weights
+
+
+def adam_step(params, m1, m2, weights, grad, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(lib().cbg_adam_step(_ptr(params), _ptr(m1), _ptr(m2), _ptr(weights), _ptr(grad),
+                               int(t), float(lr), float(beta1), float(beta2), float(eps),
+                               _stream()), "cbg_adam_step")

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcbgmres.so")
-SOURCES = ["cbg_kernels.hip", "cbg_solver.hip"]
+SOURCES = ["cbg_kernels.hip", "cbg_solver.hip", "cbg_spai.hip"]
 ARCH = os.environ.get("CBG_OFFLOAD_ARCH", "gfx950")
 
 

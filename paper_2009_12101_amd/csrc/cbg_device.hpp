@@ -18,6 +18,7 @@ constexpr int MAX_RESTART = 512;
 constexpr int MAX_GRID = 4096;           // upper bound on blocks of reducing kernels
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
 // ---------------------------------------------------------------------------

@@ -661,6 +661,210 @@ __global__ __launch_bounds__(BLK) void k_update(const uint8_t *__restrict__ V, i
 }
 
 // ---------------------------------------------------------------------------
+// Fused update and re-dot (Fig. 1 steps 5-8 for one basis pass):
+//   w' = w - sum_k h_k dec(V_k);  u_k = sum_i dec(V_k)_i w'_i;  ||w'||, max|w'|.
+// The re-dot needs every entry of w' of its rows, and w'_i needs every
+// stored vector at row i, so each lane keeps the 8 bytes it loaded from
+// each of the j vectors in registers (2 VGPRs per vector, j <= JM) and
+// decodes them twice: once for the update, once for the dot.  The basis is
+// read from HBM once instead of twice.  Partials as k_multidot with norms.
+// ---------------------------------------------------------------------------
+
+template <int F> struct Lane8;     // 8 bytes of a stored vector: LW entries
+template <> struct Lane8<F_FP64> {
+    static constexpr int LW = 1;
+    __device__ static void dec(u32x2 q, double, double *d)
+    {
+        d[0] = __hiloint2double((int)q.y, (int)q.x);
+    }
+};
+template <> struct Lane8<F_FP32> {
+    static constexpr int LW = 2;
+    __device__ static void dec(u32x2 q, double, double *d)
+    {
+        d[0] = (double)__uint_as_float(q.x);
+        d[1] = (double)__uint_as_float(q.y);
+    }
+};
+template <> struct Lane8<F_INT32> {
+    static constexpr int LW = 2;
+    __device__ static void dec(u32x2 q, double s, double *d)
+    {
+        d[0] = s * (double)(int32_t)q.x;
+        d[1] = s * (double)(int32_t)q.y;
+    }
+};
+template <int F> struct Lane8_16 {
+    static constexpr int LW = 4;
+    __device__ static void dec(u32x2 q, double s, double *d)
+    {
+        d[0] = Fmt16<F>::one(q.x & 0xFFFFu, s);
+        d[1] = Fmt16<F>::one(q.x >> 16, s);
+        d[2] = Fmt16<F>::one(q.y & 0xFFFFu, s);
+        d[3] = Fmt16<F>::one(q.y >> 16, s);
+    }
+};
+template <> struct Lane8<F_FP16> : Lane8_16<F_FP16> {};
+template <> struct Lane8<F_BF16> : Lane8_16<F_BF16> {};
+template <> struct Lane8<F_INT16> : Lane8_16<F_INT16> {};
+template <> struct Lane8<F_E4M3> {
+    static constexpr int LW = 8;
+    __device__ static void dec(u32x2 q, double s, double *d)
+    {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            d[b] = dec_e4m3((q.x >> (8 * b)) & 0xFFu) * s;
+            d[4 + b] = dec_e4m3((q.y >> (8 * b)) & 0xFFu) * s;
+        }
+    }
+};
+
+// Loads LW entries of w from i0 (entries >= n read as 0).
+template <int LW>
+__device__ __forceinline__ void load_wn(const double *__restrict__ w, int64_t n, int64_t i0,
+                                        double *o)
+{
+    if constexpr (LW == 1) {
+        o[0] = i0 < n ? w[i0] : 0.0;
+    } else {
+        load_w<LW>(w, n, i0, o);
+    }
+}
+template <int LW>
+__device__ __forceinline__ void store_wn(double *__restrict__ w, int64_t n, int64_t i0,
+                                         const double *o)
+{
+    if constexpr (LW == 1) {
+        if (i0 < n)
+            w[i0] = o[0];
+    } else {
+        store_w<LW>(w, n, i0, o);
+    }
+}
+
+constexpr int FUSED_JMAX = 104;     // largest j the fused pass takes
+
+template <int F, int JM>
+__global__ __launch_bounds__(BLK) void k_update_redot(const uint8_t *__restrict__ V, int64_t ld,
+                                                      const double *__restrict__ scales, int n,
+                                                      int j, const double *__restrict__ coef,
+                                                      double *__restrict__ w, RedArgs ra,
+                                                      const DevState *st)
+{
+    if (st && st->done)
+        return;
+    using L = Lane8<F>;
+    constexpr int LW = L::LW, KC = 8;
+    constexpr int TILE = BLK * LW;
+    constexpr bool SCALED = Fmt<F>::SCALED;
+    const int64_t ldb = ld * fmt_bytes(F);
+    __shared__ double wacc[NWAVE][JM];
+    __shared__ double lh[JM], ls[JM];     // coefficients and scales, read per use
+    for (int k = threadIdx.x; k < NWAVE * JM; k += BLK)
+        (&wacc[0][0])[k] = 0.0;
+    for (int k = threadIdx.x; k < JM; k += BLK) {
+        lh[k] = k < j ? coef[k] : 0.0;
+        ls[k] = (SCALED && k < j) ? scales[k] : 1.0;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t ntiles = ((int64_t)n + TILE - 1) / TILE;
+    double ssq = 0.0, mx = 0.0;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t i0 = tile * TILE + (int64_t)threadIdx.x * LW;
+        // an 8-byte chunk that starts below n lies inside the padded vector
+        const bool live = i0 < n;
+        // entries at or beyond n (the tail of a ragged chunk) read as code 0
+        uint64_t keep = ~0ull;
+        if (live && i0 + LW > n)
+            keep = (1ull << (8 * fmt_bytes(F) * (n - i0))) - 1ull;
+        u32x2 raw[JM];
+        const uint8_t *vp = V + (live ? i0 : 0) * fmt_bytes(F);
+#pragma unroll
+        for (int k = 0; k < JM; ++k) {
+            if (k < j) {
+                u32x2 q = {0u, 0u};
+                if (live)
+                    q = __builtin_nontemporal_load((const u32x2 *)vp);
+                vp += ldb;
+                asm volatile("" : "+v"(vp));   // one running address, not j bases
+                q.x &= (uint32_t)keep;
+                q.y &= (uint32_t)(keep >> 32);
+                raw[k] = q;
+            }
+        }
+        double wv[LW], sacc[LW];
+        load_wn<LW>(w, n, i0, wv);
+#pragma unroll
+        for (int e = 0; e < LW; ++e)
+            sacc[e] = 0.0;
+        // update: s = sum_k h_k dec(V_k)
+#pragma unroll
+        for (int k = 0; k < JM; ++k) {
+            if (k < j) {
+                const double hk = lh[k];
+                double d[LW];
+                L::dec(raw[k], ls[k], d);
+#pragma unroll
+                for (int e = 0; e < LW; ++e)
+                    sacc[e] = fma(hk, d[e], sacc[e]);
+            }
+        }
+        // keep only the raw bytes live into the re-dot (decode again there)
+#pragma unroll
+        for (int k = 0; k < JM; ++k)
+            if (k < j)
+                asm volatile("" : "+v"(raw[k]));
+#pragma unroll
+        for (int e = 0; e < LW; ++e) {
+            wv[e] = (i0 + e < n) ? wv[e] - sacc[e] : 0.0;
+            ssq += wv[e] * wv[e];
+            mx = fmax(mx, fabs(wv[e]));
+        }
+        store_wn<LW>(w, n, i0, wv);
+        // re-dot of the updated rows, KC vectors per transposing reduction
+#pragma unroll
+        for (int kc = 0; kc < JM; kc += KC) {
+            if (kc < j) {
+                double acc[KC];
+#pragma unroll
+                for (int kk = 0; kk < KC; ++kk) {
+                    const int k = kc + kk;
+                    double a = 0.0;
+                    if (k < j) {
+                        double d[LW];
+                        L::dec(raw[k], ls[k], d);
+#pragma unroll
+                        for (int e = 0; e < LW; ++e)
+                            a = fma(d[e], wv[e], a);
+                    }
+                    acc[kk] = a;
+                }
+                wave_transpose_sum<KC>(acc);
+                if (lane < KC) {
+                    const int k = kc + bitrev<KC>(lane);
+                    if (k < j)
+                        wacc[wave][k] += acc[0];
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < j; k += BLK) {
+        double t = wacc[0][k];
+#pragma unroll
+        for (int q = 1; q < NWAVE; ++q)
+            t += wacc[q][k];
+        ra.part[(size_t)k * ra.stride + blockIdx.x] = t;
+    }
+    block_sum_max(ssq, mx);
+    if (threadIdx.x == 0) {
+        ra.part[(size_t)j * ra.stride + blockIdx.x] = ssq;
+        ra.part[(size_t)(j + 1) * ra.stride + blockIdx.x] = mx;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // One-block reductions of the producers' partials (fixed order: lane l sums
 // blocks l, l+64, ... in turn, then a butterfly across the wave), followed
 // by the scalar work that needs the totals.
@@ -1057,6 +1261,39 @@ void launch_update(const OrthArgs &a, hipStream_t s)
     default: CBG_UPD(U_COMBINE) break;
     }
 #undef CBG_UPD
+}
+
+int fused_jmax(int fmt) { return fmt == F_E4M3 ? 64 : FUSED_JMAX; }
+
+int launch_update_redot(const OrthArgs &a, hipStream_t s)
+{
+    if (a.j < 1 || a.j > fused_jmax(a.fmt))
+        return 0;
+    int lw = a.fmt == F_FP64 ? 1 : (a.fmt == F_FP32 || a.fmt == F_INT32) ? 2
+             : a.fmt == F_E4M3 ? 8 : 4;
+    const int g = grid_for(a.n, BLK * lw);
+    RedArgs ra{a.ws.orth, a.ws.stride};
+    const uint8_t *V = (const uint8_t *)a.V;
+#define CBG_FUSED(JM)                                                                         \
+    if (a.ev0) {                                                                              \
+        CBG_FMT_SWITCH(a.fmt, (hipExtLaunchKernelGGL(k_update_redot<F, JM>, dim3(g),          \
+                                                     dim3(BLK), 0, s, a.ev0, a.ev1, 0, V,     \
+                                                     a.ld, a.scales, a.n, a.j, a.coef, a.wio, \
+                                                     ra, a.st)))                              \
+    } else {                                                                                  \
+        CBG_FMT_SWITCH(a.fmt, (k_update_redot<F, JM><<<g, BLK, 0, s>>>(V, a.ld, a.scales,     \
+                                                                        a.n, a.j, a.coef,     \
+                                                                        a.wio, ra, a.st)))    \
+    }
+    if (a.j <= 32) {
+        CBG_FUSED(32)
+    } else if (a.j <= 64) {
+        CBG_FUSED(64)
+    } else {
+        CBG_FUSED(FUSED_JMAX)
+    }
+#undef CBG_FUSED
+    return g;
 }
 
 void launch_reduce(const RedWs &ws, int role, int nb_orth, int nb_spmv, int j, DevState *st,

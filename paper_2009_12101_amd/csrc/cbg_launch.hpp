@@ -61,6 +61,12 @@ int orth_grid(int fmt, int64_t n);
 int launch_spmv(const SpmvArgs &a, hipStream_t s);
 void launch_multidot(const OrthArgs &a, hipStream_t s);
 void launch_update(const OrthArgs &a, hipStream_t s);
+// Fused update + re-dot with norms (w -= V coef; partials of V^T w, ||w||^2,
+// max|w| as the multi-dot with norms).  Returns the grid size (the number of
+// partials per value), or 0 if j is beyond the fused kernel's register tile
+// (then nothing is launched).
+int launch_update_redot(const OrthArgs &a, hipStream_t s);
+int fused_jmax(int fmt);   // largest j launch_update_redot takes
 void launch_reduce(const RedWs &ws, int role, int nb_orth, int nb_spmv, int j, DevState *st,
                    const void *sa, double *out, int fmt, hipStream_t s);
 void launch_normalize(int fmt, const double *w, int n, int64_t nst, double *v_out, void *Q,

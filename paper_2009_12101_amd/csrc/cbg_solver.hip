@@ -55,6 +55,7 @@ RedWs carve_red(Carver &c, int jmax)
 }
 
 struct SolveWs {
+    size_t v_off, scales_off;   // byte offsets of V and scales in the workspace
     DevState *st;
     uint8_t *V;
     double *scales, *w0, *w1, *z, *dinv, *xprev;
@@ -70,7 +71,9 @@ SolveWs carve_solve(void *ws, int32_t n, int32_t m, int fmt, int pc, size_t *tot
     SolveWs s;
     const int64_t ld = basis_ld(n);
     s.st = c.take<DevState>(1);
+    s.v_off = c.off;
     s.V = c.take<uint8_t>((size_t)(m + 1) * ld * fmt_bytes(fmt));
+    s.scales_off = c.off;
     s.scales = c.take<double>(m + 1);
     s.w0 = c.take<double>(ld);   // the step's w and the previous step's w
     s.w1 = c.take<double>(ld);   // alternate between these two buffers
@@ -177,6 +180,18 @@ size_t cbg_workspace_bytes(int32_t n, int32_t restart, int32_t format, int32_t p
     return total;
 }
 
+int cbg_workspace_basis(int32_t n, int32_t restart, int32_t format, int32_t precond,
+                        size_t *basis_offset, size_t *scales_offset)
+{
+    if (n < 0 || restart < 1 || restart > CBG_MAX_RESTART || !valid_format(format) ||
+        precond < CBG_PC_NONE || precond > CBG_PC_SPARSE || !basis_offset || !scales_offset)
+        return CBG_E_ARG;
+    const SolveWs w = carve_solve(nullptr, n, restart, format, precond, nullptr);
+    *basis_offset = w.v_off;
+    *scales_offset = w.scales_off;
+    return CBG_OK;
+}
+
 size_t cbg_kernel_workspace_bytes(int32_t n, int32_t j)
 {
     if (n < 0 || j < 0 || j > CBG_MAX_RESTART + 1)
@@ -224,6 +239,9 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
     const double eta = opt->eta > 0.0 ? opt->eta : ETA_DEFAULT;
     const int sg = spmv_lanes(n, A->nnz);
     const bool prof = (opt->flags & CBG_FLAG_PROFILE) != 0;
+    const bool fuse = (opt->flags & CBG_FLAG_NO_FUSE) == 0;
+    // steps whose update and re-dot share one basis pass
+    auto fused = [&](int j) { return fuse && j <= fused_jmax(fmt); };
     ByteModel bm{(double)n, (double)A->nnz, (double)fmt_bytes(fmt)};
 
     std::vector<unsigned char> sa_buf(step_arrays_size());
@@ -305,6 +323,8 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                 for (int j = 1; j <= m; ++j) {
                     const bool ro = j <= jeff && (cyc_flags[j - 1] & 1);
                     for (int k = 0; k < 4; ++k) {
+                        if (k == 2 && fused(j))
+                            continue;            // no separate re-dot launch
                         float ms;
                         HIP_TRY(hipEventElapsedTime(&ms, evs.at(j, k, 0), evs.at(j, k, 1)));
                         const bool work = j <= jeff && (k < 3 || ro);
@@ -316,6 +336,10 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                             res->prof_dot_ms += ms;
                             res->prof_dot_bytes += by;
                             res->prof_dot_launches += 1;
+                        } else if (k == 1 && fused(j)) {
+                            res->prof_fused_ms += ms;
+                            res->prof_fused_bytes += by;
+                            res->prof_fused_launches += 1;
                         }
                     }
                 }
@@ -328,7 +352,8 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                 double b_step = bm.spmv_step() + bm.dot(j) + bm.upd(j);
                 if (prev_pc == CBG_PC_JACOBI) b_step += 8.0 * n;
                 if (prev_pc == CBG_PC_SPARSE) b_step += 8.0 * A->nnz + 4.0 * (n + 1) + 16.0 * n;
-                b_step += bm.dot(j);                 // the re-dot pass runs every step
+                if (!fused(j))
+                    b_step += bm.dot(j);             // the separate re-dot pass
                 if (ro) b_step += bm.upd(j);
                 model_bytes += b_step;
             }
@@ -417,12 +442,19 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
             launch_reduce(W.red, RR_H, nb_orth, nb_spmv, j, W.st, sa, nullptr, fmt, s);
             o.coef = W.h; o.role = 1 /*U_STEP1*/;
             timed(1);
-            launch_update(o, s);
-            // steps 6-8: ||w||, the test of step 7, and u = V^T w in one pass
-            o.with_norms = 1;
-            timed(2);
-            launch_multidot(o, s);
-            launch_reduce(W.red, RR_U, nb_orth, 0, j, W.st, sa, nullptr, fmt, s);
+            if (fused(j)) {
+                // steps 5-8 in one basis pass: w -= V h, then ||w||, max|w|
+                // and u = V^T w of the updated rows
+                const int nb_u = launch_update_redot(o, s);
+                launch_reduce(W.red, RR_U, nb_u, 0, j, W.st, sa, nullptr, fmt, s);
+            } else {
+                launch_update(o, s);
+                // steps 6-8: ||w||, the test of step 7, and u = V^T w in one pass
+                o.with_norms = 1;
+                timed(2);
+                launch_multidot(o, s);
+                launch_reduce(W.red, RR_U, nb_orth, 0, j, W.st, sa, nullptr, fmt, s);
+            }
             // steps 8-12 (no work unless step 7 asked for it)
             o.coef = W.u; o.role = 2 /*U_STEP2*/;
             timed(3);
@@ -595,6 +627,41 @@ int cbg_update(int32_t format, const void *V, int64_t ld, const double *scales, 
     if (norms)
         launch_reduce(o.ws, RR_NORMS, orth_grid(format, n), 0, 0, nullptr, nullptr, norms, format,
                       s);
+    HIP_TRY(hipGetLastError());
+    return CBG_OK;
+}
+
+int cbg_update_redot(int32_t format, const void *V, int64_t ld, const double *scales, int32_t n,
+                     int32_t j, const double *h, double *w, double *u, double *norms, void *ws,
+                     size_t ws_bytes, void *stream)
+{
+    if (!basis_args_ok(format, V, ld, scales, n, j) || j < 1 || !h || !u || !norms ||
+        (n > 0 && (!w || !aligned16(w))))
+        return CBG_E_ARG;
+    if (!kernel_ws_ok(ws, ws_bytes, j))
+        return CBG_E_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) {
+        HIP_TRY(hipMemsetAsync(u, 0, sizeof(double) * j, s));
+        HIP_TRY(hipMemsetAsync(norms, 0, 2 * sizeof(double), s));
+        return CBG_OK;
+    }
+    OrthArgs o{};
+    o.fmt = format; o.V = V; o.ld = ld; o.scales = scales; o.n = n; o.j = j; o.coef = h;
+    o.wio = w; o.w = w; o.ws = kernel_red(ws, j);
+    int nb = launch_update_redot(o, s);
+    if (nb == 0) {
+        // beyond the register tile: the same arithmetic in two passes
+        o.role = 0 /*U_PLAIN*/;
+        launch_update(o, s);
+        o.with_norms = 1;
+        launch_multidot(o, s);
+        nb = orth_grid(format, n);
+    }
+    launch_reduce(o.ws, RR_VALUES, nb, 0, j, nullptr, nullptr, u, format, s);
+    RedWs tail = o.ws;                  // ||w||^2 and max|w| follow the j values
+    tail.orth += (size_t)j * tail.stride;
+    launch_reduce(tail, RR_NORMS, nb, 0, 0, nullptr, nullptr, norms, format, s);
     HIP_TRY(hipGetLastError());
     return CBG_OK;
 }

@@ -1,0 +1,86 @@
+"""Parity on the large 27-point workloads, one restart cycle each.
+
+* 27-point lognormal diffusion on 128^3 (n = 2,097,152, nnz = 55,742,968),
+  restart 100, bases bf16 and fp8-e4m3 with per-vector scale.
+* The same generator on 160^3 (n = 4,096,000, nnz = 109,215,352), restart
+  200, bases fp16 and int16.
+
+b ~ U[-1, 1] seed 0, x0 = 0.  Both sides run one full cycle (maxiter = m).
+The first steps agree to rounding; after that the stored bases drift apart
+at storage precision, so the recurrence residual at the end of the cycle
+is compared to 1e-2 relative.  The first stored basis vector, read from
+the solver workspace, is enc(r0 / ||r0||) on both sides; ||r0|| is summed
+in different orders, so a code may differ by one step where r0_i / ||r0||
+lies within an ulp of a rounding boundary (a tiny fraction of entries).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2009_12101_amd import problems as P
+
+CASES = [(128, 100, "bf16"), (128, 100, "e4m3"), (160, 200, "fp16"), (160, 200, "int16")]
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def cbg():
+    import paper_2009_12101_amd as cbg
+    cbg.lib()
+    return cbg
+
+
+_cache = {}
+
+
+def system(cbg, dev, N):
+    if N not in _cache:
+        _cache.clear()
+        torch.cuda.empty_cache()
+        A = P.lognormal27(N, 0)
+        b = P.rhs_uniform(A.n, 0)
+        _cache[N] = (A, b, cbg.DeviceCSR.from_host(A, dev), torch.from_numpy(b).to(dev))
+    return _cache[N]
+
+
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("N,m,fmt", CASES)
+def test_one_cycle(cbg, orc, dev, N, m, fmt):
+    A, b, Ad, bd = system(cbg, dev, N)
+    ref = orc.gmres(A, b, restart=m, fmt=fmt, tol=1e-10, maxiter=m)
+    ws = torch.empty(cbg.workspace_bytes(A.n, m, fmt), dtype=torch.uint8, device=dev)
+    r = cbg.solve(Ad, bd, restart=m, fmt=fmt, tol=1e-10, maxiter=m, workspace=ws)
+    assert r.iterations == ref["iterations"] == m
+    assert np.allclose(r.hist[:3], ref["hist"][:3], rtol=1e-12, atol=0)
+    assert abs(r.hist[m - 1] / ref["hist"][m - 1] - 1.0) <= 1e-2
+    # the first stored basis vector: enc(r0 / ||r0||)
+    off, soff = cbg.workspace_basis(A.n, m, fmt)
+    dt = {"fp16": np.uint16, "bf16": np.uint16, "e4m3": np.uint8, "int16": np.int16}[fmt]
+    nbytes = np.dtype(dt).itemsize
+    q0 = ws[off:off + A.n * nbytes].cpu().numpy().view(dt)
+    s0 = ws[soff:soff + 8].view(torch.float64).item()
+    qr, sr = orc.encode(fmt, b / np.linalg.norm(b))        # x0 = 0: r0 = b
+    differ = q0 != qr
+    assert differ.mean() <= 1e-4
+    if differ.any():
+        d = orc.decode(fmt, q0, s0)[differ]
+        e = orc.decode(fmt, qr, sr)[differ]
+        assert np.all(np.abs(d - e) <= one_step(fmt, np.maximum(np.abs(d), np.abs(e)),
+                                                max(s0, sr)))
+
+
+def one_step(fmt, mag, scale):
+    """Spacing of the format's codes at magnitude `mag` (a bound, x1.01)."""
+    if fmt == "int16":
+        return 1.01 * scale
+    mb, emin = {"fp16": (10, -14), "bf16": (7, -126), "e4m3": (3, -6)}[fmt]
+    e = np.maximum(np.floor(np.log2(np.maximum(mag / scale, 2.0 ** emin))), emin)
+    return 1.01 * scale * 2.0 ** (e - mb)

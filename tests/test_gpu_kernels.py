@@ -167,6 +167,37 @@ def test_multidot_and_update_parity(cbg, orc, dev, fmt, n, j):
     assert nv[1] == np.abs(w2).max()
 
 
+@pytest.mark.parametrize("fmt", FORMATS)
+@pytest.mark.parametrize("n,j", [(1, 1), (33, 3), (5001, 32), (70001, 33), (70001, 64),
+                                 (70003, 65), (300000, 100), (300001, 104), (20000, 105),
+                                 (20000, 130)])
+def test_update_redot_parity(cbg, orc, dev, fmt, n, j):
+    """Fused update + re-dot (one basis pass while j fits the register tile,
+    two passes beyond it) against the oracle's update and dots."""
+    print(f"update_redot {fmt} n={n} j={j}", flush=True)
+    ld = cbg.basis_ld(n)
+    raw, dec, scales = _basis(orc, fmt, n, j, ld, seed=n + 3 * j)
+    w = np.random.default_rng(9).standard_normal(n)
+    h = np.random.default_rng(10).standard_normal(j) * 0.3
+    Vd = torch.from_numpy(raw.view(np.uint8).reshape(-1)).to(dev)
+    wd = torch.from_numpy(w).to(dev)
+    u, norms = cbg.update_redot(fmt, Vd, ld, torch.from_numpy(scales).to(dev), n, j,
+                                torch.from_numpy(h).to(dev), wd)
+    w2 = wd.cpu().numpy()
+    wo = w.copy()
+    for k in range(j):
+        wo = wo - h[k] * dec[k]
+    ebound = 4 * (j + 1) * U * (np.abs(w) + np.abs(h) @ np.abs(dec))
+    assert np.all(np.abs(w2 - wo) <= ebound)
+    # u from the GPU's own w' (the update is checked above): FP64 dot bound
+    uo = np.array([orc.dot(dec[k], w2) for k in range(j)])
+    bound = 4 * n * U * (np.abs(dec) @ np.abs(w2)) + 1e-300
+    assert np.all(np.abs(u.cpu().numpy() - uo) <= bound)
+    nv = norms.cpu().numpy()
+    assert abs(nv[0] - np.sqrt(orc.dot(w2, w2))) <= 1e-13 * nv[0] + 1e-300
+    assert nv[1] == np.abs(w2).max()
+
+
 def test_multidot_is_deterministic(cbg, orc, dev):
     n, j, fmt = 400000, 60, "fp16"
     ld = cbg.basis_ld(n)
