@@ -277,8 +277,13 @@ __device__ __forceinline__ void wave_transpose_sum(double (&a)[N])
         const bool up = lane & d;
 #pragma unroll
         for (int i = 0; i < cnt / 2; ++i) {
-            double send = up ? a[i] : a[i + cnt / 2];
-            double keep = up ? a[i + cnt / 2] : a[i];
+            // both candidates as register values: a select between two array
+            // loads would otherwise become a load at a lane-dependent index,
+            // which the backend emulates with compare/select chains
+            double lo = a[i], hi = a[i + cnt / 2];
+            asm volatile("" : "+v"(lo), "+v"(hi));
+            const double send = up ? lo : hi;
+            const double keep = up ? hi : lo;
             a[i] = keep + __shfl_xor(send, d);
         }
     }

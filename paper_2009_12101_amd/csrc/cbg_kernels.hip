@@ -744,6 +744,9 @@ __device__ __forceinline__ void store_wn(double *__restrict__ w, int64_t n, int6
 
 constexpr int FUSED_JMAX = 104;     // largest j the fused pass takes
 
+// Buffer resource word 3 for raw 32-bit accesses on gfx9-family parts.
+constexpr int BUF_RSRC_W3 = 0x00020000;
+
 template <int F, int JM>
 __global__ __launch_bounds__(BLK) void k_update_redot(const uint8_t *__restrict__ V, int64_t ld,
                                                       const double *__restrict__ scales, int n,
@@ -757,9 +760,10 @@ __global__ __launch_bounds__(BLK) void k_update_redot(const uint8_t *__restrict_
     constexpr int LW = L::LW, KC = 8;
     constexpr int TILE = BLK * LW;
     constexpr bool SCALED = Fmt<F>::SCALED;
-    const int64_t ldb = ld * fmt_bytes(F);
+    constexpr uint32_t EB = fmt_bytes(F);
+    const uint32_t ldb = (uint32_t)(ld * EB);
     __shared__ double wacc[NWAVE][JM];
-    __shared__ double lh[JM], ls[JM];     // coefficients and scales, read per use
+    __shared__ double lh[JM], ls[JM];     // coefficients (0 beyond j) and scales
     for (int k = threadIdx.x; k < NWAVE * JM; k += BLK)
         (&wacc[0][0])[k] = 0.0;
     for (int k = threadIdx.x; k < JM; k += BLK) {
@@ -767,54 +771,58 @@ __global__ __launch_bounds__(BLK) void k_update_redot(const uint8_t *__restrict_
         ls[k] = (SCALED && k < j) ? scales[k] : 1.0;
     }
     __syncthreads();
+    // The j stored vectors as one buffer of j*ldb bytes (the host checks that
+    // JM*ldb fits in 32 bits): a load at or past the end returns 0, so the
+    // vectors k >= j of the template's tile read as zero without a branch.
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)V, 0, (int)(j * ldb), BUF_RSRC_W3);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t ntiles = ((int64_t)n + TILE - 1) / TILE;
     double ssq = 0.0, mx = 0.0;
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t i0 = tile * TILE + (int64_t)threadIdx.x * LW;
-        // an 8-byte chunk that starts below n lies inside the padded vector
-        const bool live = i0 < n;
-        // entries at or beyond n (the tail of a ragged chunk) read as code 0
-        uint64_t keep = ~0ull;
-        if (live && i0 + LW > n)
-            keep = (1ull << (8 * fmt_bytes(F) * (n - i0))) - 1ull;
+        // an opaque zero offset per tile: the JM coefficient and scale reads
+        // stay inside the loop instead of being hoisted into 2*JM registers
+        int z;
+        asm volatile("s_mov_b32 %0, 0" : "=s"(z));
+        const double *vh = lh + z, *vs = ls + z;
+        // entries at or beyond n read as code 0: a chunk past n entirely, and
+        // the tail of the chunk that straddles n
+        uint64_t keep = 0ull;
+        if (i0 < n)
+            keep = i0 + LW <= n ? ~0ull : (1ull << (8 * EB * (n - i0))) - 1ull;
+        const uint32_t voff = (uint32_t)((i0 < n ? i0 : 0) * EB);
+        const uint32_t klo = (uint32_t)keep, khi = (uint32_t)(keep >> 32);
         u32x2 raw[JM];
-        const uint8_t *vp = V + (live ? i0 : 0) * fmt_bytes(F);
 #pragma unroll
         for (int k = 0; k < JM; ++k) {
-            if (k < j) {
-                u32x2 q = {0u, 0u};
-                if (live)
-                    q = __builtin_nontemporal_load((const u32x2 *)vp);
-                vp += ldb;
-                asm volatile("" : "+v"(vp));   // one running address, not j bases
-                q.x &= (uint32_t)keep;
-                q.y &= (uint32_t)(keep >> 32);
-                raw[k] = q;
-            }
+            u32x2 q = __builtin_amdgcn_raw_buffer_load_b64(rs, voff + (uint32_t)k * ldb, 0, 0);
+            q.x &= klo;
+            q.y &= khi;
+            raw[k] = q;
         }
         double wv[LW], sacc[LW];
         load_wn<LW>(w, n, i0, wv);
 #pragma unroll
         for (int e = 0; e < LW; ++e)
             sacc[e] = 0.0;
-        // update: s = sum_k h_k dec(V_k)
+        // update: s = sum_k h_k dec(V_k)   (h_k = 0 and V_k = 0 for k >= j)
 #pragma unroll
         for (int k = 0; k < JM; ++k) {
-            if (k < j) {
-                const double hk = lh[k];
-                double d[LW];
-                L::dec(raw[k], ls[k], d);
+            const double hk = vh[k];
+            double d[LW];
+            L::dec(raw[k], SCALED ? vs[k] : 1.0, d);
 #pragma unroll
-                for (int e = 0; e < LW; ++e)
-                    sacc[e] = fma(hk, d[e], sacc[e]);
-            }
+            for (int e = 0; e < LW; ++e)
+                sacc[e] = fma(hk, d[e], sacc[e]);
+            // decode in groups of 8: keeps decoded values from piling up
+            if ((k & 7) == 7)
+                __builtin_amdgcn_sched_barrier(0);
         }
-        // keep only the raw bytes live into the re-dot (decode again there)
+        // only the raw bytes stay live into the re-dot (decoded again there)
 #pragma unroll
         for (int k = 0; k < JM; ++k)
-            if (k < j)
-                asm volatile("" : "+v"(raw[k]));
+            asm volatile("" : "+v"(raw[k]));
 #pragma unroll
         for (int e = 0; e < LW; ++e) {
             wv[e] = (i0 + e < n) ? wv[e] - sacc[e] : 0.0;
@@ -829,15 +837,12 @@ __global__ __launch_bounds__(BLK) void k_update_redot(const uint8_t *__restrict_
                 double acc[KC];
 #pragma unroll
                 for (int kk = 0; kk < KC; ++kk) {
-                    const int k = kc + kk;
+                    double d[LW];
+                    L::dec(raw[kc + kk], SCALED ? vs[kc + kk] : 1.0, d);
                     double a = 0.0;
-                    if (k < j) {
-                        double d[LW];
-                        L::dec(raw[k], ls[k], d);
 #pragma unroll
-                        for (int e = 0; e < LW; ++e)
-                            a = fma(d[e], wv[e], a);
-                    }
+                    for (int e = 0; e < LW; ++e)
+                        a = fma(d[e], wv[e], a);
                     acc[kk] = a;
                 }
                 wave_transpose_sum<KC>(acc);
@@ -847,6 +852,7 @@ __global__ __launch_bounds__(BLK) void k_update_redot(const uint8_t *__restrict_
                         wacc[wave][k] += acc[0];
                 }
             }
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
     __syncthreads();
@@ -1263,36 +1269,54 @@ void launch_update(const OrthArgs &a, hipStream_t s)
 #undef CBG_UPD
 }
 
-int fused_jmax(int fmt) { return fmt == F_E4M3 ? 64 : FUSED_JMAX; }
+template <int F, int JM>
+static void fused_launch(const OrthArgs &a, int g, const RedArgs &ra, const uint8_t *V,
+                         hipStream_t s)
+{
+    if constexpr (F == F_E4M3 && JM > 16) {
+        return;              // not instantiated: e4m3 fuses only up to j = 16
+    } else if (a.ev0) {
+        hipExtLaunchKernelGGL(k_update_redot<F, JM>, dim3(g), dim3(BLK), 0, s, a.ev0, a.ev1, 0,
+                              V, a.ld, a.scales, a.n, a.j, a.coef, a.wio, ra, a.st);
+    } else {
+        k_update_redot<F, JM><<<g, BLK, 0, s>>>(V, a.ld, a.scales, a.n, a.j, a.coef, a.wio, ra,
+                                                a.st);
+    }
+}
+
+template <int JM>
+static void fused_shape(const OrthArgs &a, int g, const RedArgs &ra, const uint8_t *V,
+                        hipStream_t s)
+{
+    CBG_FMT_SWITCH(a.fmt, (fused_launch<F, JM>(a, g, ra, V, s)))
+}
+
+int fused_jmax(int fmt) { return fmt == F_E4M3 ? 16 : FUSED_JMAX; }
 
 int launch_update_redot(const OrthArgs &a, hipStream_t s)
 {
     if (a.j < 1 || a.j > fused_jmax(a.fmt))
+        return 0;
+    // the vectors are addressed with 32-bit buffer offsets
+    if ((double)FUSED_JMAX * (double)a.ld * fmt_bytes(a.fmt) >= 2147483648.0)
         return 0;
     int lw = a.fmt == F_FP64 ? 1 : (a.fmt == F_FP32 || a.fmt == F_INT32) ? 2
              : a.fmt == F_E4M3 ? 8 : 4;
     const int g = grid_for(a.n, BLK * lw);
     RedArgs ra{a.ws.orth, a.ws.stride};
     const uint8_t *V = (const uint8_t *)a.V;
-#define CBG_FUSED(JM)                                                                         \
-    if (a.ev0) {                                                                              \
-        CBG_FMT_SWITCH(a.fmt, (hipExtLaunchKernelGGL(k_update_redot<F, JM>, dim3(g),          \
-                                                     dim3(BLK), 0, s, a.ev0, a.ev1, 0, V,     \
-                                                     a.ld, a.scales, a.n, a.j, a.coef, a.wio, \
-                                                     ra, a.st)))                              \
-    } else {                                                                                  \
-        CBG_FMT_SWITCH(a.fmt, (k_update_redot<F, JM><<<g, BLK, 0, s>>>(V, a.ld, a.scales,     \
-                                                                        a.n, a.j, a.coef,     \
-                                                                        a.wio, ra, a.st)))    \
-    }
-    if (a.j <= 32) {
-        CBG_FUSED(32)
-    } else if (a.j <= 64) {
-        CBG_FUSED(64)
-    } else {
-        CBG_FUSED(FUSED_JMAX)
-    }
-#undef CBG_FUSED
+    if (a.j <= 16)
+        fused_shape<16>(a, g, ra, V, s);
+    else if (a.j <= 32)
+        fused_shape<32>(a, g, ra, V, s);
+    else if (a.j <= 48)
+        fused_shape<48>(a, g, ra, V, s);
+    else if (a.j <= 64)
+        fused_shape<64>(a, g, ra, V, s);
+    else if (a.j <= 80)
+        fused_shape<80>(a, g, ra, V, s);
+    else
+        fused_shape<FUSED_JMAX>(a, g, ra, V, s);
     return g;
 }
 

@@ -146,37 +146,37 @@ def _generate(args):
     return A, P.rhs_uniform(A.n, seed)
 
 
-def make_instances(seeds, N: int, device, workers: int = 8, log=None):
+def make_instances(seeds, N: int, device, pool=None, log=None):
     """Training matrices (27-point lognormal diffusion on N^3, one per seed):
-    generated on the host, then on the device one fp64-basis GMRES cycle
-    (m = 100, M = I, b ~ U[-1, 1] of the same seed) whose basis vectors
-    v_1, v_4, ..., v_94 are kept as fp16."""
+    generated on the host (in `pool`, a multiprocessing pool forked before
+    the GPU was touched, or serially), then on the device one fp64-basis
+    GMRES cycle (m = 100, M = I, b ~ U[-1, 1] of the same seed) whose basis
+    vectors v_1, v_4, ..., v_94 are kept as fp16."""
     torch = _torch()
-    from concurrent.futures import ProcessPoolExecutor
     out = []
     ws = None
     t0 = time.time()
     jobs = [(N, int(s)) for s in seeds]
-    with ProcessPoolExecutor(max_workers=max(1, workers)) as ex:
-        for A, b in ex.map(_generate, jobs, chunksize=1):
-            Ad = B.DeviceCSR.from_host(A, device)
-            need = B.workspace_bytes(A.n, CYCLE, "fp64")
-            if ws is None or ws.numel() < need:
-                ws = torch.empty(need, dtype=torch.uint8, device=device)
-            r = B.solve(Ad, torch.from_numpy(b).to(device), restart=CYCLE, fmt="fp64",
-                        tol=0.0, maxiter=CYCLE, workspace=ws, hist=False)
-            if r.iterations != CYCLE:
-                raise RuntimeError(f"{A.name}: the cycle ended after {r.iterations} steps")
-            off, _ = B.workspace_basis(A.n, CYCLE, "fp64")
-            ld = B.basis_ld(A.n)
-            Vws = ws[off:off + CYCLE * ld * 8].view(torch.float64)
-            V = B.spai_pack(Vws, ld, A.n, VECTORS_PER_INSTANCE, 0, VECTOR_STRIDE)
-            sws = torch.empty(B.spai_workspace_bytes(A.n, A.nnz, 0), dtype=torch.uint8,
-                              device=device)
-            out.append(Instance(Ad, A.grid, B.csr_transpose_values(Ad, ws=sws),
-                                B.spai_features(Ad, A.grid, ws=sws), V))
-            if log and len(out) % 32 == 0:
-                log(f"{len(out)}/{len(jobs)} training instances ({time.time() - t0:.1f}s)")
+    gen = pool.imap(_generate, jobs) if pool is not None else map(_generate, jobs)
+    for A, b in gen:
+        Ad = B.DeviceCSR.from_host(A, device)
+        need = B.workspace_bytes(A.n, CYCLE, "fp64")
+        if ws is None or ws.numel() < need:
+            ws = torch.empty(need, dtype=torch.uint8, device=device)
+        r = B.solve(Ad, torch.from_numpy(b).to(device), restart=CYCLE, fmt="fp64",
+                    tol=0.0, maxiter=CYCLE, workspace=ws, hist=False)
+        if r.iterations != CYCLE:
+            raise RuntimeError(f"{A.name}: the cycle ended after {r.iterations} steps")
+        off, _ = B.workspace_basis(A.n, CYCLE, "fp64")
+        ld = B.basis_ld(A.n)
+        Vws = ws[off:off + CYCLE * ld * 8].view(torch.float64)
+        V = B.spai_pack(Vws, ld, A.n, VECTORS_PER_INSTANCE, 0, VECTOR_STRIDE)
+        sws = torch.empty(B.spai_workspace_bytes(A.n, A.nnz, 0), dtype=torch.uint8,
+                          device=device)
+        out.append(Instance(Ad, A.grid, B.csr_transpose_values(Ad, ws=sws),
+                            B.spai_features(Ad, A.grid, ws=sws), V))
+        if log and len(out) % 32 == 0:
+            log(f"{len(out)}/{len(jobs)} training instances ({time.time() - t0:.1f}s)")
     torch.cuda.synchronize()
     return out
 
@@ -227,11 +227,17 @@ def main(argv=None) -> int:
     ap.add_argument("--test-seed", type=int, default=0)
     ap.add_argument("--format", default="fp16")
     ap.add_argument("--repeats", type=int, default=1)
-    ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--workers", type=int, default=8,
+                    help="host processes generating the training matrices")
     ap.add_argument("--out", default=None, help="save the trained parameters (.npz)")
     ap.add_argument("--load", default=None, help="skip training; load parameters (.npz)")
     ap.add_argument("--json", default=None, help="write the report here")
     a = ap.parse_args(argv)
+    # the generator processes are forked before anything touches the GPU
+    pool = None
+    if not a.load and a.workers > 1:
+        import multiprocessing
+        pool = multiprocessing.get_context("fork").Pool(a.workers)
     torch = _torch()
     dev = torch.device("cuda:0")
 
@@ -246,7 +252,10 @@ def main(argv=None) -> int:
     else:
         t0 = time.time()
         data = make_instances(range(a.first_seed, a.first_seed + a.train_count), a.train_grid,
-                              dev, a.workers, log)
+                              dev, pool, log)
+        if pool is not None:
+            pool.close()
+            pool.join()
         report["data_seconds"] = time.time() - t0
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -87,9 +87,18 @@ def random_params(S, seed, scale3=0.05):
     return prm
 
 
+def rne_bits_bf16(x):
+    """bf16 bit patterns of the round-to-nearest-even of fp32 values (the
+    bf16 copy of fp32 master weights)."""
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+    return torch.from_numpy(r.view(np.int16).copy())
+
+
 def to_device(prm, dev):
     params = torch.from_numpy(flat_params(prm)).to(dev)
-    weights = torch.cat([bits_bf16(prm[k]).reshape(-1) for k in ("W1", "W2", "W3")]).to(dev)
+    weights = torch.cat([rne_bits_bf16(prm[k]).reshape(-1)
+                         for k in ("W1", "W2", "W3")]).to(dev)
     return params, weights
 
 
@@ -346,3 +355,25 @@ def test_solver_basis_in_workspace(cbg, orc, dev):
     G = V @ V.T
     assert np.linalg.norm(G - np.eye(m)) <= 1e-12
     assert np.linalg.norm(V[:5] - ref["V"][:5]) <= 1e-10
+
+
+@pytest.mark.timeout(300)
+def test_trained_network_gain(cbg, dev):
+    """Train on Arnoldi vectors of 12 instances (27-point lognormal, 20^3)
+    with the project's kernels, then solve a held-out 28^3 system with an
+    fp16 basis: the learned P must reach the tolerance in fewer steps than
+    M = I.  Its gain over Jacobi (the network's starting point) is printed;
+    it is measured, not pinned."""
+    from paper_2009_12101_amd.spai import LearnedSPAI, compare, make_instances
+    data = make_instances(range(101, 113), 20, dev)
+    model = LearnedSPAI(dev, seed=0)
+    hist = model.train(data, epochs=15, batch=4, lr=3e-3)
+    assert hist[-1] < hist[0]
+    A = P.lognormal27(28, 7)
+    b = P.rhs_uniform(A.n, 7)
+    rows = compare(model, A, b, fmt="fp16", restart=50, tol=1e-10, maxiter=20000, device=dev)
+    print({k: (v["iterations"], round(v["seconds"] * 1e3, 2)) for k, v in rows.items()},
+          f"loss {hist[0]:.4e} -> {hist[-1]:.4e}", flush=True)
+    for v in rows.values():
+        assert v["status"] == 0 and v["true_rel_res"] <= 1e-10
+    assert rows["learned"]["iterations"] < rows["none"]["iterations"]
