@@ -213,9 +213,10 @@ int cbg_update(int32_t format, const void *V, int64_t ld, const double *scales, 
 /* Steps 5-8 in one basis pass: w -= sum_k h_k dec(V_k), then
  * u_k = sum_i dec(V_k)_i w_i (the re-dot of step 8) for k < j, norms[0] =
  * ||w||_2 and norms[1] = ||w||_inf of the updated w.  While j fits the
- * kernel's register tile (j <= 104; 64 for e4m3) each lane keeps the bytes
- * it loaded of every stored vector and the basis is read once; beyond it,
- * the same arithmetic runs as an update and a multi-dot.  u [dev] j
+ * kernel's register tile (j <= 104 for fp64, fp32, fp16, int32; 80 for
+ * int16; 48 for bf16; e4m3 never) each lane keeps the bytes it loaded of
+ * every stored vector and the basis is read once; beyond it, the same
+ * arithmetic runs as an update and a multi-dot.  u [dev] j
  * doubles; norms [dev] 2 doubles; other arguments as cbg_update. */
 int cbg_update_redot(int32_t format, const void *V, int64_t ld, const double *scales, int32_t n,
                      int32_t j, const double *h, double *w, double *u, double *norms, void *ws,
@@ -230,9 +231,10 @@ int cbg_update_redot(int32_t format, const void *V, int64_t ld, const double *sc
  * Slots: entry (i, c) has slot p = (dz+1)*9 + (dy+1)*3 + (dx+1), the grid
  * offset from row i to column c; slot 13 is the diagonal; entries outside the
  * 27-point stencil have no slot.
- * Features (n x 32 bf16, row-major): f_p = bf16(fl32(a_ic / a_ii)) for the
- * row's slots, f_27 = bf16(fl32((a_ii - sum_{c != i} |a_ic|) / a_ii)) with the
- * sum in CSR order, all else 0.
+ * Features (n x 64 bf16, row-major): f_p = bf16(fl32(a_ic / a_ii)) and
+ * f_{32+p} = bf16(fl32(a_cc / a_ii)) (the neighbour's diagonal) for the row's
+ * slots p (column c), f_27 = bf16(fl32((a_ii - sum_{c != i} |a_ic|) / a_ii))
+ * with the sum in CSR order, all else 0.
  * Network: H1 = bf16(ReLU(F W1 + b1)), H2 = bf16(ReLU(H1 W2 + b2)),
  * O = H2 W3 + b3 (32 outputs, slots 0..26 used); bf16 weights, fp32 biases,
  * fp32 accumulation on the matrix cores.
@@ -241,23 +243,23 @@ int cbg_update_redot(int32_t format, const void *V, int64_t ld, const double *sc
  * Loss over K unit vectors v_k: L = scale * sum_k ||A P v_k - v_k||_2^2.
  *
  * Parameters: `params` [dev] CBG_SPAI_NPARAM fp32 masters in the order W1
- * (32x64, row-major: [in][out]), b1 (64), W2 (64x64), b2 (64), W3 (64x32),
+ * (64x64, row-major: [in][out]), b1 (64), W2 (64x64), b2 (64), W3 (64x32),
  * b3 (32); `weights` [dev] CBG_SPAI_NWEIGHT bf16 (uint16 bit patterns) of W1,
  * W2, W3 in the same layout.  Vectors for the loss: `V` [dev] n x K fp16 bit
  * patterns, row-major (entry (i, k) at i*K + k), K <= CBG_SPAI_MAX_K.
  * All [dev] arrays 16-byte aligned; workspaces 256-byte aligned and sized by
  * cbg_spai_workspace_bytes(n, nnz, K) (K = 0 where no vectors are used). */
-#define CBG_SPAI_NFEAT 32
+#define CBG_SPAI_NFEAT 64
 #define CBG_SPAI_NHID 64
 #define CBG_SPAI_NOUT 32
-#define CBG_SPAI_NPARAM 8352
-#define CBG_SPAI_NWEIGHT 8192
+#define CBG_SPAI_NPARAM 10400
+#define CBG_SPAI_NWEIGHT 10240
 #define CBG_SPAI_MAX_K 32
 
 size_t cbg_spai_workspace_bytes(int32_t n, int64_t nnz, int32_t K);
 
 /* Features of every row (see above).  grid [host] {nx, ny, nz}; feat [dev]
- * n x 32 bf16.  Synchronises with the stream; returns CBG_E_NONFINITE if a
+ * n x 64 bf16.  Synchronises with the stream; returns CBG_E_NONFINITE if a
  * row has a zero (or missing) diagonal or a non-finite feature. */
 int cbg_spai_features(const cbg_csr *A, const int32_t grid[3], uint16_t *feat, void *ws,
                       size_t ws_bytes, void *stream);

@@ -14,11 +14,15 @@ rounding points.
   offset (dz, dy, dx) = (p//9 - 1, (p//3)%3 - 1, p%3 - 1); slot 13 is the
   diagonal. The entry (i, c) of A has the slot of the grid offset from row i
   to column c.
-* Features of row i (32 values): f_p = fl32(a_{i,c(p)} / a_ii) for slots
+* Features of row i (64 values): f_p = fl32(a_{i,c(p)} / a_ii) for slots
   present in row i (0 otherwise); f_27 = fl32((a_ii - sum_{c != i} |a_ic|)
-  / a_ii), the sum taken in CSR order; f_28..31 = 0. Each is then rounded
-  to bf16 (round to nearest even).
-* Network, 32 -> 64 -> 64 -> 32: H1 = bf16(ReLU(F W1 + b1)),
+  / a_ii), the sum taken in CSR order; f_28..31 = 0; f_{32+p} =
+  fl32(a_{c(p),c(p)} / a_ii), the neighbour's diagonal relative to the
+  row's, for slots present in row i (0 otherwise); f_59..63 = 0. Each is
+  then rounded to bf16 (round to nearest even). The neighbour diagonals
+  carry what row i alone cannot: an entry of a good approximate inverse
+  near (i, c) depends on the size of a_cc as well as on row i.
+* Network, 64 -> 64 -> 64 -> 32: H1 = bf16(ReLU(F W1 + b1)),
   H2 = bf16(ReLU(H1 W2 + b2)), O = H2 W3 + b3. Weights are bf16 and biases
   fp32. The oracle accumulates in FP64 and rounds at the bf16 points.
 * P values: P_{i,c} = fl32((delta_{p,13} + O_{i,p}) / a_ii) on A's
@@ -39,7 +43,8 @@ import numpy as np
 
 from . import decode, encode
 
-NFEAT, NHID, NOUT, NSLOT, CENTER = 32, 64, 32, 27, 13
+NFEAT, NHID, NOUT, NSLOT, CENTER = 64, 64, 32, 27, 13
+NBR = 32                     # first neighbour-diagonal feature
 
 
 def bf16(x: np.ndarray) -> np.ndarray:
@@ -74,7 +79,7 @@ def diagonal(A) -> np.ndarray:
 
 
 def features(A, grid) -> np.ndarray:
-    """(n, 32) features, bf16-representable float64 values."""
+    """(n, 64) features, bf16-representable float64 values."""
     n = A.n
     slots = entry_slots(A, grid)
     d = diagonal(A)
@@ -82,6 +87,7 @@ def features(A, grid) -> np.ndarray:
     F = np.zeros((n, NFEAT))
     good = slots >= 0
     F[rows[good], slots[good]] = fl32(A.val[good] / d[rows[good]])
+    F[rows[good], NBR + slots[good]] = fl32(d[A.col_idx[good]] / d[rows[good]])
     # off-diagonal absolute sum of each row, accumulated in CSR order
     off = np.where(A.col_idx == rows, 0.0, np.abs(A.val))
     lens = np.diff(A.row_ptr)

@@ -32,8 +32,8 @@ EXPORTS = ["cbg_strerror", "cbg_basis_ld", "cbg_workspace_bytes", "cbg_kernel_wo
            "cbg_spai_pack", "cbg_spai_grad_p", "cbg_spai_grad_o", "cbg_mlp_backward",
            "cbg_spai_loss_grad", "cbg_spai_round_weights", "cbg_adam_step"]
 
-SPAI_NFEAT, SPAI_NHID, SPAI_NOUT = 32, 64, 32
-SPAI_NPARAM, SPAI_NWEIGHT, SPAI_MAX_K = 8352, 8192, 32
+SPAI_NFEAT, SPAI_NHID, SPAI_NOUT = 64, 64, 32
+SPAI_NPARAM, SPAI_NWEIGHT, SPAI_MAX_K = 10400, 10240, 32
 
 
 class CbgCsr(C.Structure):
@@ -336,7 +336,7 @@ def _sws(n, nnz, K, device):
 
 
 def spai_features(A: DeviceCSR, grid, feat=None, ws=None):
-    """(n, 32) int16 tensor of bf16 feature bit patterns."""
+    """(n, 64) int16 tensor of bf16 feature bit patterns."""
     torch = _torch()
     dev = A.val.device
     feat = torch.empty((A.n, SPAI_NFEAT), dtype=torch.int16, device=dev) if feat is None else feat

@@ -1273,8 +1273,8 @@ template <int F, int JM>
 static void fused_launch(const OrthArgs &a, int g, const RedArgs &ra, const uint8_t *V,
                          hipStream_t s)
 {
-    if constexpr (F == F_E4M3 && JM > 16) {
-        return;              // not instantiated: e4m3 fuses only up to j = 16
+    if constexpr (F == F_E4M3 || (F == F_BF16 && JM > 48) || (F == F_INT16 && JM > 80)) {
+        return;              // not instantiated: beyond the format's fused range
     } else if (a.ev0) {
         hipExtLaunchKernelGGL(k_update_redot<F, JM>, dim3(g), dim3(BLK), 0, s, a.ev0, a.ev1, 0,
                               V, a.ld, a.scales, a.n, a.j, a.coef, a.wio, ra, a.st);
@@ -1291,7 +1291,18 @@ static void fused_shape(const OrthArgs &a, int g, const RedArgs &ra, const uint8
     CBG_FMT_SWITCH(a.fmt, (fused_launch<F, JM>(a, g, ra, V, s)))
 }
 
-int fused_jmax(int fmt) { return fmt == F_E4M3 ? 16 : FUSED_JMAX; }
+// Largest j each format fuses at, from per-bucket timings on 128^3 (the
+// fused pass against an update plus a multi-dot): beyond these the
+// register tile drops the kernel to one wave per SIMD and two passes win.
+int fused_jmax(int fmt)
+{
+    switch (fmt) {
+    case F_BF16: return 48;
+    case F_INT16: return 80;
+    case F_E4M3: return 0;
+    default: return FUSED_JMAX;
+    }
+}
 
 int launch_update_redot(const OrthArgs &a, hipStream_t s)
 {

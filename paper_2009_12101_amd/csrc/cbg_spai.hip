@@ -1,6 +1,6 @@
 // gfx950 kernels of the learned sparse-approximate-inverse preconditioner
 // (an extension of the paper, which preconditions with scalar Jacobi,
-// Section 6).  A per-row network 32 -> 64 -> 64 -> 32 (ReLU, bf16 weights,
+// Section 6).  A per-row network 64 -> 64 -> 64 -> 32 (ReLU, bf16 weights,
 // fp32 biases and accumulation on the MFMA units) maps features of row i of A
 // to corrections of the Jacobi row: P_{i,c} = fl32((delta_{p,13} + O_{i,p}) /
 // a_ii) on A's pattern, p the 27-point slot of (i, c).  Training minimises
@@ -25,8 +25,9 @@ namespace spai {
 typedef short s16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int NF = 32, NH = 64, NO = 32, NSLOT = 27, CENTER = 13;
-// parameter vector: W1 (32x64) b1 (64) W2 (64x64) b2 (64) W3 (64x32) b3 (32)
+constexpr int NF = 64, NH = 64, NO = 32, NSLOT = 27, CENTER = 13;
+constexpr int NBR = 32;     // first neighbour-diagonal feature
+// parameter vector: W1 (64x64) b1 (64) W2 (64x64) b2 (64) W3 (64x32) b3 (32)
 constexpr int OW1 = 0, OB1 = OW1 + NF * NH, OW2 = OB1 + NH, OB2 = OW2 + NH * NH,
               OW3 = OB2 + NH, OB3 = OW3 + NH * NO, NPARAM = OB3 + NO;
 // bf16 weights: W1, W2, W3 back to back
@@ -73,18 +74,31 @@ __device__ __forceinline__ double row_diag(int64_t i, const int32_t *rp, const i
     return d;
 }
 
-// Features of each row: f_p = fl32(a_{i,c(p)} / a_ii) on present slots,
-// f_27 = fl32((a_ii - sum_{c != i} |a_ic|) / a_ii) with the sum in CSR order,
-// the rest 0; all rounded to bf16.
+// The diagonal of A (0 where a row stores none).
+__global__ __launch_bounds__(256) void k_diag(int n, const int32_t *__restrict__ rp,
+                                              const int32_t *__restrict__ ci,
+                                              const double *__restrict__ val,
+                                              double *__restrict__ diag)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        diag[i] = row_diag(i, rp, ci, val);
+}
+
+// Features of each row: f_p = fl32(a_{i,c(p)} / a_ii) and f_{32+p} =
+// fl32(a_{c(p),c(p)} / a_ii) on present slots, f_27 = fl32((a_ii -
+// sum_{c != i} |a_ic|) / a_ii) with the sum in CSR order, the rest 0; all
+// rounded to bf16.
 __global__ __launch_bounds__(256) void k_features(int n, const int32_t *__restrict__ rp,
                                                   const int32_t *__restrict__ ci,
                                                   const double *__restrict__ val, int nx, int ny,
+                                                  const double *__restrict__ diag,
                                                   uint16_t *__restrict__ feat,
                                                   unsigned *__restrict__ bad)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
-        const double d = row_diag(i, rp, ci, val);
+        const double d = diag[i];
         uint16_t f[NF];
 #pragma unroll
         for (int k = 0; k < NF; ++k)
@@ -97,12 +111,16 @@ __global__ __launch_bounds__(256) void k_features(int n, const int32_t *__restri
                 off += fabs(a);
             const int s = slot_of(i, c, nx, ny);
             if (s >= 0) {
+                const uint16_t fa = bf16_of((float)(a / d));
+                const uint16_t fd = bf16_of((float)(diag[c] / d));
                 // slot index is data-dependent: write through a switch-free
                 // select so f stays in registers
 #pragma unroll
                 for (int k = 0; k < NSLOT; ++k)
-                    if (k == s)
-                        f[k] = bf16_of((float)(a / d));
+                    if (k == s) {
+                        f[k] = fa;
+                        f[NBR + k] = fd;
+                    }
             }
         }
         const double margin = (d - off) / d;
@@ -115,7 +133,7 @@ __global__ __launch_bounds__(256) void k_features(int n, const int32_t *__restri
             w[k] = (uint32_t)f[2 * k] | ((uint32_t)f[2 * k + 1] << 16);
         u32x4 *dst = (u32x4 *)(feat + i * NF);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < NF / 8; ++q) {
             u32x4 v = {w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]};
             dst[q] = v;
         }
@@ -125,7 +143,7 @@ __global__ __launch_bounds__(256) void k_features(int n, const int32_t *__restri
 // Weights staged in LDS transposed (out-major) so that an A operand
 // (4 consecutive k of one output row) is one 8-byte read.
 struct WeightsLds {
-    uint16_t w1t[NH * NF];   // [out 64][in 32]
+    uint16_t w1t[NH * NF];   // [out 64][in 64]
     uint16_t w2t[NH * NH];   // [out 64][in 64]
     uint16_t w3t[NO * NH];   // [out 32][in 64]
     float b1[NH], b2[NH], b3[NO];
@@ -192,10 +210,10 @@ __global__ __launch_bounds__(256) void k_forward(int n, const uint16_t *__restri
          tile += (int64_t)gridDim.x * nw) {
         const int64_t row = tile * 16 + col;              // this lane's row in the B layout
         const bool live = row < n;
-        // layer 1: H1^T (64 x 16) = W1^T (64 x 32) F^T (32 x 16)
-        s16x4 fb[2];
+        // layer 1: H1^T (64 x 16) = W1^T (64 x 64) F^T (64 x 16)
+        s16x4 fb[NF / 16];
 #pragma unroll
-        for (int ks = 0; ks < 2; ++ks) {
+        for (int ks = 0; ks < NF / 16; ++ks) {
             if (live) {
                 const uint2 v = *(const uint2 *)(feat + row * NF + ks * 16 + kq);
                 fb[ks][0] = (short)(v.x & 0xFFFF);
@@ -214,7 +232,7 @@ __global__ __launch_bounds__(256) void k_forward(int n, const uint16_t *__restri
             for (int q = 0; q < 4; ++q)
                 c[q] = L.b1[ot * 16 + kq + q];
 #pragma unroll
-            for (int ks = 0; ks < 2; ++ks)
+            for (int ks = 0; ks < NF / 16; ++ks)
                 c = mfma(lds4(&L.w1t[(ot * 16 + col) * NF + ks * 16 + kq]), fb[ks], c);
             h1[ot] = relu_bf16(c);
         }
@@ -447,7 +465,7 @@ __global__ __launch_bounds__(256) void k_backward(int n, const uint16_t *__restr
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int col = lane & 15, kq = (lane >> 4) * 4;
     TileLds &t = T[wave];
-    f32x4 gw3[4][2], gw2[4][4], gw1[2][4];     // [row tile of W][col tile of W]
+    f32x4 gw3[4][2], gw2[4][4], gw1[NF / 16][4];   // [row tile of W][col tile of W]
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -459,7 +477,7 @@ __global__ __launch_bounds__(256) void k_backward(int n, const uint16_t *__restr
         for (int b = 0; b < 4; ++b)
             gw2[a][b] = f32x4{0, 0, 0, 0};
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < NF / 16; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b)
             gw1[a][b] = f32x4{0, 0, 0, 0};
@@ -472,6 +490,9 @@ __global__ __launch_bounds__(256) void k_backward(int n, const uint16_t *__restr
         for (int e = lane; e < 16 * NF; e += 64) {
             const int64_t r = r0 + e / NF;
             t.f[e] = r < n ? feat[r * NF + e % NF] : 0;
+        }
+        for (int e = lane; e < 16 * NO; e += 64) {
+            const int64_t r = r0 + e / NO;
             t.dO[e] = r < n ? dO[r * NO + e % NO] : 0;
         }
         for (int e = lane; e < 16 * NH; e += 64) {
@@ -531,7 +552,7 @@ __global__ __launch_bounds__(256) void k_backward(int n, const uint16_t *__restr
                 gw2[a][b] = mfma(col4(t.h1, NH, kq, a * 16 + col),
                                  col4(t.dh2, NH, kq, b * 16 + col), gw2[a][b]);
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < NF / 16; ++a)
 #pragma unroll
             for (int b = 0; b < 4; ++b)
                 gw1[a][b] = mfma(col4(t.f, NF, kq, a * 16 + col),
@@ -574,7 +595,7 @@ __global__ __launch_bounds__(256) void k_backward(int n, const uint16_t *__restr
                         mine[e - q0] = gw2[a][b][r];
                 }
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int a = 0; a < NF / 16; ++a)
 #pragma unroll
             for (int b = 0; b < 4; ++b)
 #pragma unroll
@@ -734,6 +755,7 @@ size_t salign(size_t x) { return (x + SALIGN - 1) / SALIGN * SALIGN; }
 
 struct SpaiWs {
     unsigned *bad;
+    double *diag;
     double *lpart;
     float *gpart;
     uint16_t *feat, *h1, *h2, *dO;
@@ -752,6 +774,7 @@ SpaiWs carve_spai(void *ws, int64_t n, int64_t nnz, int64_t K, size_t *total)
     };
     SpaiWs s;
     s.bad = (unsigned *)take(sizeof(unsigned));
+    s.diag = (double *)take(8 * (size_t)n);
     s.lpart = (double *)take(sizeof(double) * MAXB_ROW);
     s.gpart = (float *)take(sizeof(float) * (size_t)MAXB_BACK * NPARAM);
     s.feat = (uint16_t *)take(2 * (size_t)n * NF);
@@ -881,8 +904,11 @@ int cbg_spai_features(const cbg_csr *A, const int32_t grid[3], uint16_t *feat, v
     hipStream_t s = (hipStream_t)stream;
     SpaiWs W = carve_spai(ws, A->n, A->nnz, 0, nullptr);
     SP_TRY(hipMemsetAsync(W.bad, 0, sizeof(unsigned), s));
+    hipLaunchKernelGGL(k_diag, dim3(row_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
+                       A->col_idx, A->val, W.diag);
     hipLaunchKernelGGL(k_features, dim3(row_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
-                       A->col_idx, A->val, grid[0], grid[1], feat, W.bad);
+                       A->col_idx, A->val, grid[0], grid[1], (const double *)W.diag, feat,
+                       W.bad);
     SP_TRY(hipGetLastError());
     unsigned bad = 0;
     if ((e = read_flag(W.bad, s, &bad)))
@@ -931,8 +957,11 @@ int cbg_learned_build(const cbg_csr *A, const int32_t grid[3], const uint16_t *w
     hipStream_t s = (hipStream_t)stream;
     SpaiWs W = carve_spai(ws, A->n, A->nnz, 0, nullptr);
     SP_TRY(hipMemsetAsync(W.bad, 0, sizeof(unsigned), s));
+    hipLaunchKernelGGL(k_diag, dim3(row_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
+                       A->col_idx, A->val, W.diag);
     hipLaunchKernelGGL(k_features, dim3(row_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
-                       A->col_idx, A->val, grid[0], grid[1], W.feat, W.bad);
+                       A->col_idx, A->val, grid[0], grid[1], (const double *)W.diag, W.feat,
+                       W.bad);
     enqueue_forward(A->n, W.feat, weights, params, W.O, nullptr, nullptr, s);
     hipLaunchKernelGGL(k_assemble, dim3(row_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
                        A->col_idx, A->val, grid[0], grid[1], (const float *)W.O, p_val);

@@ -1,7 +1,7 @@
 """Learned sparse-approximate-inverse preconditioner: training and inference.
 
 An extension of the paper, which preconditions with scalar Jacobi (Section
-6).  A per-row network (32 -> 64 -> 64 -> 32, ReLU, bf16 weights, fp32
+6).  A per-row network (64 -> 64 -> 64 -> 32, ReLU, bf16 weights, fp32
 biases, matrix-core products) maps features of row i of A to the values of
 a right preconditioner P on A's pattern; the untrained network (last layer
 zero) is exactly fp32 Jacobi.  Training minimises the mean of
@@ -48,7 +48,7 @@ class Instance:
     A: "B.DeviceCSR"
     grid: tuple
     t_val: object          # values of A^T on A's pattern
-    feat: object           # (n, 32) bf16 features
+    feat: object           # (n, 64) bf16 features
     V: object              # (n, K) fp16 Arnoldi vectors
 
 

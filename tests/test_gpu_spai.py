@@ -21,6 +21,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from paper_2009_12101_amd import problems as P
+from paper_2009_12101_amd._binding import SPAI_NPARAM as NPARAM
 
 
 @pytest.fixture(scope="module")
@@ -248,7 +249,7 @@ def test_backward_matches_oracle(cbg, S, dev):
 
 def split_grad(g):
     out, o = {}, 0
-    for k, shape in (("W1", (32, 64)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)),
+    for k, shape in (("W1", (64, 64)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)),
                      ("W3", (64, 32)), ("b3", (32,))):
         size = int(np.prod(shape))
         out[k] = g[o:o + size].reshape(shape)
@@ -263,7 +264,7 @@ def test_loss_grad_end_to_end(cbg, S, dev):
     prm = random_params(S, 12)
     params, weights = to_device(prm, dev)
     loss = torch.zeros(1, dtype=torch.float64, device=dev)
-    grad = torch.zeros(8352, dtype=torch.float64, device=dev)
+    grad = torch.zeros(NPARAM, dtype=torch.float64, device=dev)
     Lref, gref = 0.0, None
     scale = 1.0 / (K * len(insts))
     for i, A in enumerate(insts):
@@ -293,7 +294,7 @@ def test_loss_grad_end_to_end(cbg, S, dev):
 def test_adam_matches_oracle(cbg, S, dev):
     prm = random_params(S, 13)
     params, weights = to_device(prm, dev)
-    m1 = torch.zeros(8352, dtype=torch.float32, device=dev)
+    m1 = torch.zeros(NPARAM, dtype=torch.float32, device=dev)
     m2 = torch.zeros_like(m1)
     state = {}
     ref = {k: v.copy() for k, v in prm.items()}
@@ -316,7 +317,7 @@ def test_training_steps_reduce_loss(cbg, S, dev):
     insts = [P.lognormal27(10, s) for s in (31, 32)]
     prm = S.init_params(5)
     params, weights = to_device(prm, dev)
-    m1 = torch.zeros(8352, dtype=torch.float32, device=dev)
+    m1 = torch.zeros(NPARAM, dtype=torch.float32, device=dev)
     m2 = torch.zeros_like(m1)
     data = []
     for i, A in enumerate(insts):
@@ -325,7 +326,7 @@ def test_training_steps_reduce_loss(cbg, S, dev):
         data.append((A, Ad, cbg.csr_transpose_values(Ad), cbg.spai_features(Ad, A.grid),
                      torch.from_numpy(V.T.copy().view(np.int16)).to(dev)))
     loss = torch.zeros(1, dtype=torch.float64, device=dev)
-    grad = torch.zeros(8352, dtype=torch.float64, device=dev)
+    grad = torch.zeros(NPARAM, dtype=torch.float64, device=dev)
     hist = []
     for t in range(1, 31):
         for i, (A, Ad, tv, feat, Vd) in enumerate(data):

@@ -48,22 +48,30 @@ def test_features_of_constant_coefficient_stencil(S):
     assert np.all(F[i, :27][np.arange(27) != 13] == f_off)
     assert F[i, 13] == 1.0
     assert F[i, 27] == S.bf16(np.array([b((26.01 - 26.0) / 26.01)]))[0]
-    assert np.all(F[i, 28:] == 0.0)
+    assert np.all(F[i, 28:32] == 0.0)
+    # neighbour diagonals: every in-grid neighbour of (1,1,1) on a 4^3 grid
+    # has 26 weights of 1 plus the shift, so each ratio is exactly 1
+    assert np.all(F[i, 32:59] == 1.0)
+    assert np.all(F[i, 59:] == 0.0)
     # the corner row 0: 7 off-diagonal neighbours, all others absent
     present = [13, 14, 16, 17, 22, 23, 25, 26]
     for p in range(27):
         assert F[0, p] == (1.0 if p == 13 else f_off if p in present else 0.0)
+        assert F[0, 32 + p] == (1.0 if p in present else 0.0)
     assert F[0, 27] == S.bf16(np.array([b((26.01 - 7.0) / 26.01)]))[0]
 
 
 def test_identity_network_returns_relu_of_features(S):
     A = P.lognormal27(4, 3)
     F = S.features(A, A.grid)
-    W1 = np.zeros((32, 64)); W1[:32, :32] = np.eye(32)
+    W1 = np.eye(64)
     W2 = np.eye(64)
     W3 = np.zeros((64, 32)); W3[:32, :32] = np.eye(32)
     _, _, O = S.forward(F, W1, np.zeros(64), W2, np.zeros(64), W3, np.zeros(32))
-    assert np.array_equal(O, np.maximum(F, 0.0))
+    assert np.array_equal(O, np.maximum(F[:, :32], 0.0))
+    W3 = np.zeros((64, 32)); W3[32:, :] = np.eye(32)
+    _, _, O = S.forward(F, W1, np.zeros(64), W2, np.zeros(64), W3, np.zeros(32))
+    assert np.array_equal(O, np.maximum(F[:, 32:], 0.0))
 
 
 def test_loss_closed_forms(S):
@@ -91,7 +99,7 @@ def test_gradients_match_central_differences(S):
     F = S.features(A, A.grid)
     V = unit_vectors(A.n, 2, 3)
     rng = np.random.default_rng(11)
-    prm = dict(W1=rng.standard_normal((32, 64)) * 0.3, b1=rng.standard_normal(64) * 0.1,
+    prm = dict(W1=rng.standard_normal((64, 64)) * 0.3, b1=rng.standard_normal(64) * 0.1,
                W2=rng.standard_normal((64, 64)) * 0.2, b2=rng.standard_normal(64) * 0.1,
                W3=rng.standard_normal((64, 32)) * 0.05, b3=rng.standard_normal(32) * 0.01)
     H1, H2, O = S.forward(F, prm["W1"], prm["b1"], prm["W2"], prm["b2"], prm["W3"], prm["b3"],
@@ -122,7 +130,7 @@ def test_gradients_match_central_differences(S):
 
 def test_adam_first_step_is_lr_sign(S):
     rng = np.random.default_rng(0)
-    prm = dict(W1=np.zeros((32, 64)), b1=np.zeros(64), W2=np.zeros((64, 64)), b2=np.zeros(64),
+    prm = dict(W1=np.zeros((64, 64)), b1=np.zeros(64), W2=np.zeros((64, 64)), b2=np.zeros(64),
                W3=np.zeros((64, 32)), b3=np.zeros(32))
     g = {k: rng.standard_normal(v.shape) for k, v in prm.items()}
     S.adam_step(prm, g, {}, 1, lr=1e-3)

@@ -18,10 +18,10 @@ def header_defines():
 def test_layout_constants_match_header():
     from paper_2009_12101_amd import _binding as B
     d = header_defines()
-    assert d["CBG_SPAI_NFEAT"] == B.SPAI_NFEAT == 32
+    assert d["CBG_SPAI_NFEAT"] == B.SPAI_NFEAT == 64
     assert d["CBG_SPAI_NHID"] == B.SPAI_NHID == 64
     assert d["CBG_SPAI_NOUT"] == B.SPAI_NOUT == 32
-    nf, nh, no = 32, 64, 32
+    nf, nh, no = 64, 64, 32
     assert d["CBG_SPAI_NPARAM"] == B.SPAI_NPARAM == nf * nh + nh + nh * nh + nh + nh * no + no
     assert d["CBG_SPAI_NWEIGHT"] == B.SPAI_NWEIGHT == nf * nh + nh * nh + nh * no
     assert d["CBG_SPAI_MAX_K"] == B.SPAI_MAX_K
