@@ -122,10 +122,13 @@ template <> struct Fmt<F_FP32> {
 #define CBG_KC16 4
 #endif
 #ifndef CBG_UNR16
-#define CBG_UNR16 4
+#define CBG_UNR16 2
+#endif
+#ifndef CBG_CH16
+#define CBG_CH16 2
 #endif
 template <int F> struct Fmt16 {
-    static constexpr int VW = 8, CH = 1, KC = CBG_KC16, UNR = CBG_UNR16;
+    static constexpr int VW = 8, CH = CBG_CH16, KC = CBG_KC16, UNR = CBG_UNR16;
     static constexpr bool SCALED = (F == F_INT16);
     __device__ static double one(uint32_t c, double s)
     {
