@@ -103,6 +103,9 @@ typedef struct {
  * (by default they share one pass while j fits the fused kernel's register
  * tile; the arithmetic is the same, the summation order of u differs) */
 #define CBG_FLAG_NO_FUSE 2
+/* time only the multi-dot launches with HIP events (cbg_result.prof_dot_*;
+ * one event pair per launch instead of four per step) */
+#define CBG_FLAG_PROFILE_DOT 4
 
 typedef struct {
     int64_t iterations;        /* Arnoldi steps (SpMVs with A inside cycles) */

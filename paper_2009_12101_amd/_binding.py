@@ -22,6 +22,7 @@ OK, NOT_CONVERGED = 0, 1
 E_ARG, E_WORKSPACE, E_HIP, E_NONFINITE, E_UNSUPPORTED = -1, -2, -3, -4, -5
 FLAG_PROFILE = 1
 FLAG_NO_FUSE = 2
+FLAG_PROFILE_DOT = 4
 MAX_RESTART = 512
 
 EXPORTS = ["cbg_strerror", "cbg_basis_ld", "cbg_workspace_bytes", "cbg_kernel_workspace_bytes",
@@ -222,7 +223,8 @@ def solve(A: DeviceCSR, b, x0=None, restart=100, fmt="fp64", tol=1e-10, maxiter=
           eta=0.0, precond="none", p_val=None, fallback=False, profile=False, workspace=None,
           hist=True, fuse=True) -> SolveResult:
     """cbgmres_solve on device tensors; returns the solution and counters.
-    Raises CbgError on a negative status."""
+    profile: False, True (event-time every basis-streaming launch) or "dot"
+    (only the multi-dot launches).  Raises CbgError on a negative status."""
     torch = _torch()
     x = torch.zeros(A.n, dtype=torch.float64, device=b.device) if x0 is None else x0.clone()
     need = workspace_bytes(A.n, restart, fmt, precond)
@@ -232,7 +234,8 @@ def solve(A: DeviceCSR, b, x0=None, restart=100, fmt="fp64", tol=1e-10, maxiter=
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=b.device)
     opts = CbgOpts(restart, FORMATS[fmt], tol, maxiter, eta, PRECONDS[precond],
                    int(bool(fallback)), None if p_val is None else p_val.data_ptr(),
-                   (FLAG_PROFILE if profile else 0) | (0 if fuse else FLAG_NO_FUSE), 0)
+                   {False: 0, True: FLAG_PROFILE, "dot": FLAG_PROFILE_DOT}[profile]
+                   | (0 if fuse else FLAG_NO_FUSE), 0)
     res = CbgResult()
     hl = int(maxiter) if hist else 0
     h = np.zeros(max(hl, 1))

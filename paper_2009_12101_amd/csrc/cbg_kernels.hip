@@ -890,41 +890,62 @@ __global__ __launch_bounds__(BLK) void k_update_redot(const uint8_t *__restrict_
 constexpr int RBLK = 256;
 constexpr int RWAVES = RBLK / 64;
 
-// One wave folds block partials src[0 .. nb) (8 independent loads in flight
-// per lane, fixed order); every lane returns the total.
+// One wave folds block partials src[0 .. nb) (16 independent loads in flight
+// per lane, fixed order); every lane returns the total.  nb = 0 gives 0.
 __device__ __forceinline__ double wave_fold(const double *__restrict__ src, int nb, bool is_max)
 {
+    constexpr int U = 16;
     const int lane = threadIdx.x & 63;
-    double acc[8];
+    double acc[U];
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < U; ++u)
         acc[u] = 0.0;
-    for (int b0 = lane; b0 < nb; b0 += 64 * 8) {
-        double x[8];
+    for (int b0 = lane; b0 < nb; b0 += 64 * U) {
+        double x[U];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < U; ++u)
             x[u] = src[min(b0 + 64 * u, nb - 1)];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < U; ++u) {
             const double xv = (b0 + 64 * u < nb) ? x[u] : 0.0;
             acc[u] = is_max ? fmax(acc[u], xv) : acc[u] + xv;
         }
     }
     double a = acc[0];
 #pragma unroll
-    for (int u = 1; u < 8; ++u)
+    for (int u = 1; u < U; ++u)
         a = is_max ? fmax(a, acc[u]) : a + acc[u];
     return is_max ? wave_max(a) : wave_sum(a);
 }
 
-// Number of blocks k_reduce runs with: the j independent coefficients (h or
-// u) are spread one per wave over the grid.
+// The whole block folds src[0 .. nb): wave w takes the contiguous quarter
+// starting at w * ceil(nb / 4), and the four wave totals are combined in
+// wave order (so the result depends on nb only, not on timing).  Every
+// thread returns the total; block-uniform call.
+__device__ double block_fold(const double *__restrict__ src, int nb, bool is_max)
+{
+    __shared__ double part[RWAVES];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = (nb + RWAVES - 1) / RWAVES;
+    const int lo = min(wave * q, nb), hi = min(lo + q, nb);
+    const double a = wave_fold(src + lo, hi - lo, is_max);
+    if (lane == 0)
+        part[wave] = a;
+    __syncthreads();
+    double t = part[0];
+#pragma unroll
+    for (int w = 1; w < RWAVES; ++w)
+        t = is_max ? fmax(t, part[w]) : t + part[w];
+    __syncthreads();
+    return t;
+}
+
+// Block 0 does the scalars; block 1 + k folds value k (h_k, u_k or a
+// kernel-level multi-dot value).
 int reduce_grid(int role, int j)
 {
-    if (role == RR_H || role == RR_U || role == RR_VALUES) {
-        int g = (j + RWAVES - 1) / RWAVES;
-        return g < 1 ? 1 : (g > 64 ? 64 : g);
-    }
+    if (role == RR_H || role == RR_U || role == RR_VALUES)
+        return 1 + (j > 0 ? j : 0);
     return 1;
 }
 
@@ -938,17 +959,17 @@ __global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth
         if (role == RR_T2 && !st->reorth)
             return;
     }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, tid = threadIdx.x;
-    // coefficients h_k / u_k / kernel-level values: one wave each, all blocks
-    if (role == RR_H || role == RR_U || role == RR_VALUES) {
+    const int tid = threadIdx.x;
+    // coefficients h_k / u_k / kernel-level values: block 1 + k folds value k
+    if (blockIdx.x > 0) {
+        const int k = blockIdx.x - 1;
         double *dst = role == RR_H ? sa.h : role == RR_U ? sa.u : out;
-        for (int k = blockIdx.x * RWAVES + wave; k < j; k += gridDim.x * RWAVES) {
-            const double a = wave_fold(ws.orth + (size_t)k * ws.stride, nb_orth, false);
-            if (lane == 0)
-                dst[k] = a;
-        }
+        const double a = block_fold(ws.orth + (size_t)k * ws.stride, nb_orth, false);
+        if (tid == 0)
+            dst[k] = a;
+        return;
     }
-    if (blockIdx.x != 0 || role == RR_VALUES)
+    if (role == RR_VALUES)
         return;
     // the scalars (block 0): sum and max of a partial pair
     __shared__ double sv[2];
@@ -971,10 +992,13 @@ __global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth
         s1 = ws.spmv + ws.stride;
         nb = nb_spmv;
     }
-    if (wave < 2) {
-        const double a = wave_fold(wave == 0 ? s0 : s1, nb, wave == 1);
-        if (lane == 0)
-            sv[wave] = a;
+    {
+        const double a0 = block_fold(s0, nb, false);
+        const double a1 = block_fold(s1, nb, true);
+        if (tid == 0) {
+            sv[0] = a0;
+            sv[1] = a1;
+        }
     }
     __syncthreads();
     switch (role) {

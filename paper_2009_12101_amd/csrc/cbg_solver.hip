@@ -238,7 +238,11 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
     const size_t vbytes = (size_t)ld * fmt_bytes(fmt);
     const double eta = opt->eta > 0.0 ? opt->eta : ETA_DEFAULT;
     const int sg = spmv_lanes(n, A->nnz);
-    const bool prof = (opt->flags & CBG_FLAG_PROFILE) != 0;
+    const bool prof_all = (opt->flags & CBG_FLAG_PROFILE) != 0;
+    const bool prof = prof_all || (opt->flags & CBG_FLAG_PROFILE_DOT) != 0;
+    // launch slots k of a step: 0 multi-dot, 1 update (or fused update +
+    // re-dot), 2 re-dot multi-dot, 3 re-orthogonalising update
+    auto profiled = [&](int k) { return prof_all || k % 2 == 0; };
     const bool fuse = (opt->flags & CBG_FLAG_NO_FUSE) == 0;
     // steps whose update and re-dot share one basis pass
     auto fused = [&](int j) { return fuse && j <= fused_jmax(fmt); };
@@ -323,8 +327,8 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                 for (int j = 1; j <= m; ++j) {
                     const bool ro = j <= jeff && (cyc_flags[j - 1] & 1);
                     for (int k = 0; k < 4; ++k) {
-                        if (k == 2 && fused(j))
-                            continue;            // no separate re-dot launch
+                        if ((k == 2 && fused(j)) || !profiled(k))
+                            continue;            // no separate re-dot launch, or not timed
                         float ms;
                         HIP_TRY(hipEventElapsedTime(&ms, evs.at(j, k, 0), evs.at(j, k, 1)));
                         const bool work = j <= jeff && (k < 3 || ro);
@@ -433,8 +437,9 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
             o.fmt = fmt; o.V = W.V; o.ld = ld; o.scales = W.scales; o.n = n; o.j = j;
             o.w = nxt; o.wio = nxt; o.ws = W.red; o.st = W.st; o.gated = 1;
             auto timed = [&](int k) {
-                o.ev0 = prof ? evs.at(j, k, 0) : nullptr;
-                o.ev1 = prof ? evs.at(j, k, 1) : nullptr;
+                const bool on = prof && profiled(k);
+                o.ev0 = on ? evs.at(j, k, 0) : nullptr;
+                o.ev1 = on ? evs.at(j, k, 1) : nullptr;
             };
             // step 5: h = V^T w ; w -= V h
             timed(0);
