@@ -1328,12 +1328,17 @@ int fused_jmax(int fmt)
     }
 }
 
+// Whether launch_update_redot takes step j: within the format's fused range,
+// and the template's vectors addressable with 32-bit buffer offsets.
+bool fused_takes(int fmt, int64_t ld, int j)
+{
+    return j >= 1 && j <= fused_jmax(fmt) &&
+           (double)FUSED_JMAX * (double)ld * fmt_bytes(fmt) < 2147483648.0;
+}
+
 int launch_update_redot(const OrthArgs &a, hipStream_t s)
 {
-    if (a.j < 1 || a.j > fused_jmax(a.fmt))
-        return 0;
-    // the vectors are addressed with 32-bit buffer offsets
-    if ((double)FUSED_JMAX * (double)a.ld * fmt_bytes(a.fmt) >= 2147483648.0)
+    if (!fused_takes(a.fmt, a.ld, a.j))
         return 0;
     int lw = a.fmt == F_FP64 ? 1 : (a.fmt == F_FP32 || a.fmt == F_INT32) ? 2
              : a.fmt == F_E4M3 ? 8 : 4;

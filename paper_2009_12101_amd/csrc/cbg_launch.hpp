@@ -67,6 +67,9 @@ void launch_update(const OrthArgs &a, hipStream_t s);
 // (then nothing is launched).
 int launch_update_redot(const OrthArgs &a, hipStream_t s);
 int fused_jmax(int fmt);   // largest j launch_update_redot takes
+// Whether launch_update_redot takes step j for basis vectors of leading
+// dimension ld (the one predicate the solver and the launcher share).
+bool fused_takes(int fmt, int64_t ld, int j);
 void launch_reduce(const RedWs &ws, int role, int nb_orth, int nb_spmv, int j, DevState *st,
                    const void *sa, double *out, int fmt, hipStream_t s);
 void launch_normalize(int fmt, const double *w, int n, int64_t nst, double *v_out, void *Q,

@@ -245,7 +245,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
     auto profiled = [&](int k) { return prof_all || k % 2 == 0; };
     const bool fuse = (opt->flags & CBG_FLAG_NO_FUSE) == 0;
     // steps whose update and re-dot share one basis pass
-    auto fused = [&](int j) { return fuse && j <= fused_jmax(fmt); };
+    auto fused = [&](int j) { return fuse && fused_takes(fmt, basis_ld(n), j); };
     ByteModel bm{(double)n, (double)A->nnz, (double)fmt_bytes(fmt)};
 
     std::vector<unsigned char> sa_buf(step_arrays_size());

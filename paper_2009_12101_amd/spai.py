@@ -182,17 +182,20 @@ def make_instances(seeds, N: int, device, pool=None, log=None):
 
 
 def compare(model: LearnedSPAI, A, b, fmt="fp16", restart=100, tol=1e-10, maxiter=20000,
-            repeats=1, device="cuda"):
+            repeats=1, device="cuda", plain_fp64=False):
     """Time to solution of CB-GMRES with M = I, Jacobi and the learned P
-    (its build, features to P values, included in the time)."""
+    (its build, features to P values, included in the time), all with the
+    `fmt` basis; with plain_fp64 also plain GMRES (fp64 basis, M = I)."""
     torch = _torch()
     Ad = B.DeviceCSR.from_host(A, device)
     bd = torch.from_numpy(b).to(device)
-    ws = torch.empty(B.workspace_bytes(A.n, restart, fmt, "sparse"), dtype=torch.uint8,
-                     device=device)
+    need = max(B.workspace_bytes(A.n, restart, fmt, "sparse"),
+               B.workspace_bytes(A.n, restart, "fp64", "none") if plain_fp64 else 0)
+    ws = torch.empty(need, dtype=torch.uint8, device=device)
     sws = torch.empty(B.spai_workspace_bytes(A.n, A.nnz, 0), dtype=torch.uint8, device=device)
     rows = {}
-    for kind in ("none", "jacobi", "learned"):
+    kinds = ["none", "jacobi", "learned"] + (["plain_fp64"] if plain_fp64 else [])
+    for kind in kinds:
         best = None
         for _ in range(repeats + 1):            # the first run warms up
             torch.cuda.synchronize()
@@ -202,6 +205,9 @@ def compare(model: LearnedSPAI, A, b, fmt="fp16", restart=100, tol=1e-10, maxite
                 r = B.solve(Ad, bd, restart=restart, fmt=fmt, tol=tol, maxiter=maxiter,
                             precond="sparse", p_val=pv, fallback=True, workspace=ws,
                             hist=False)
+            elif kind == "plain_fp64":
+                r = B.solve(Ad, bd, restart=restart, fmt="fp64", tol=tol, maxiter=maxiter,
+                            precond="none", workspace=ws, hist=False)
             else:
                 r = B.solve(Ad, bd, restart=restart, fmt=fmt, tol=tol, maxiter=maxiter,
                             precond=kind, workspace=ws, hist=False)
@@ -225,7 +231,11 @@ def main(argv=None) -> int:
     ap.add_argument("--init-seed", type=int, default=0)
     ap.add_argument("--test-grid", type=int, default=128)
     ap.add_argument("--test-seed", type=int, default=0)
-    ap.add_argument("--format", default="fp16")
+    ap.add_argument("--format", default="fp16",
+                    help="basis storage of the test solves (comma list allowed)")
+    ap.add_argument("--restart", type=int, default=100)
+    ap.add_argument("--plain-fp64", action="store_true",
+                    help="also time plain GMRES (fp64 basis, M = I) on the test system")
     ap.add_argument("--repeats", type=int, default=1)
     ap.add_argument("--workers", type=int, default=8,
                     help="host processes generating the training matrices")
@@ -268,11 +278,15 @@ def main(argv=None) -> int:
     if a.test_grid > 0:
         A = P.lognormal27(a.test_grid, a.test_seed)
         b = P.rhs_uniform(A.n, a.test_seed)
-        rows = compare(model, A, b, fmt=a.format, repeats=a.repeats, device=dev)
-        report["test"] = dict(system=A.name, n=A.n, nnz=A.nnz, format=a.format, **rows)
-        for k, v in rows.items():
-            log(f"{k:8s}: {v['seconds'] * 1e3:9.1f} ms  it={v['iterations']}  "
-                f"res={v['true_rel_res']:.2e}  status={v['status']}")
+        report["test"] = []
+        for i, fmt in enumerate(a.format.split(",")):
+            rows = compare(model, A, b, fmt=fmt, restart=a.restart, repeats=a.repeats,
+                           device=dev, plain_fp64=a.plain_fp64 and i == 0)
+            report["test"].append(dict(system=A.name, n=A.n, nnz=A.nnz, format=fmt,
+                                       restart=a.restart, **rows))
+            for k, v in rows.items():
+                log(f"{fmt} {k:10s}: {v['seconds'] * 1e3:9.1f} ms  it={v['iterations']}  "
+                    f"res={v['true_rel_res']:.2e}  status={v['status']}")
     line = json.dumps(report)
     if a.json:
         with open(a.json, "w") as f:
