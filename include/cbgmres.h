@@ -51,7 +51,9 @@ typedef enum {
 typedef enum {
     CBG_PC_NONE = 0,     /* M = I */
     CBG_PC_JACOBI = 1,   /* M^{-1} = diag(1 / a_ii), the paper's default (Section 6) */
-    CBG_PC_SPARSE = 2    /* M^{-1} = P, single-precision values on A's pattern */
+    CBG_PC_SPARSE = 2,   /* M^{-1} = P, single-precision values on A's pattern */
+    CBG_PC_BLOCK_JACOBI = 3 /* M^{-1} = blockdiag(D_b^{-1}), adaptive-precision storage
+                               (cbg_block_jacobi_setup; Section 6 discusses block-Jacobi) */
 } cbg_precond_kind;
 
 enum {
@@ -82,7 +84,9 @@ typedef struct {
  * (nnz floats on A's pattern).  fallback: with CBG_PC_SPARSE, drop P and
  * continue with M = I when the explicit residual fails to fall below 0.99x
  * its previous value in two consecutive cycles or a non-finite value
- * appears.  flags: CBG_FLAG_* bits. */
+ * appears.  flags: CBG_FLAG_* bits.  A singular diagonal block with
+ * CBG_PC_BLOCK_JACOBI (or a zero diagonal with CBG_PC_JACOBI) returns
+ * CBG_E_ARG. */
 typedef struct {
     int32_t restart;
     int32_t format;
@@ -94,6 +98,9 @@ typedef struct {
     const float *p_val;
     int32_t flags;
     int32_t reserved;
+    int32_t pc_block;    /* CBG_PC_BLOCK_JACOBI: block size 1..8 (0 selects 4) */
+    int32_t pc_prec;     /* CBG_PC_BLOCK_JACOBI: lowest storage precision of the
+                            inverted blocks, 16, 32 or 64 bits (0 selects 16) */
 } cbg_opts;
 
 #define CBG_MAX_RESTART 512
@@ -139,7 +146,8 @@ typedef struct {
 } cbg_result;
 
 /* Device workspace bytes cbgmres_solve needs for this problem shape
- * (0 for invalid arguments).  The workspace must be 256-byte aligned. */
+ * (0 for invalid arguments).  The workspace must be 256-byte aligned.
+ * For CBG_PC_BLOCK_JACOBI it is sized for any block size up to 8. */
 size_t cbg_workspace_bytes(int32_t n, int32_t restart, int32_t format, int32_t precond);
 
 /* Restarted CB-GMRES (Fig. 1 of the paper).
@@ -224,6 +232,30 @@ int cbg_update(int32_t format, const void *V, int64_t ld, const double *scales, 
 int cbg_update_redot(int32_t format, const void *V, int64_t ld, const double *scales, int32_t n,
                      int32_t j, const double *h, double *w, double *u, double *norms, void *ws,
                      size_t ws_bytes, void *stream);
+
+/* ---------------- block-Jacobi preconditioner ------------------------- */
+/* An extension: the paper's Section 6 discusses block-Jacobi
+ * preconditioners, and its references store the inverted blocks at a
+ * precision chosen per block; the rule here is this project's own.  Block b
+ * covers rows and columns [b*bs, min((b+1)*bs, n)); D_b is A restricted to
+ * it, inverted by Gauss-Jordan elimination with partial pivoting in FP64
+ * (first row with the largest |entry| as pivot; no fused operations).  With
+ * kappa_b = ||D_b||_1 ||D_b^-1||_1, the inverse is stored in the lowest of
+ * fp16 (u = 2^-11) and fp32 (u = 2^-24), not below prec_min bits, with
+ * kappa_b u <= 1/100 and the block's largest entry in the format's normal
+ * range, else in fp64 (round to nearest even).
+ * tags [dev] ceil(n/bs) int8: 16, 32 or 64 per block; x64/x32/x16 [dev]
+ * ceil(n/bs)*bs*bs entries each: block b's inverse at b*bs*bs, row-major,
+ * row stride bs, zeros beyond the block, in the array of its precision.
+ * Synchronises; CBG_E_ARG for a singular block (or bad arguments). */
+int cbg_block_jacobi_setup(const cbg_csr *A, int32_t bs, int32_t prec_min, int8_t *tags,
+                           double *x64, float *x32, uint16_t *x16, void *ws, size_t ws_bytes,
+                           void *stream);
+
+/* z = M^-1 v (n doubles each [dev]) with the blocks of cbg_block_jacobi_setup. */
+int cbg_block_jacobi_apply(int32_t n, int32_t bs, const int8_t *tags, const double *x64,
+                           const float *x32, const uint16_t *x16, const double *v, double *z,
+                           void *stream);
 
 /* ---------------- learned sparse approximate inverse ------------------- */
 /* An extension of the paper (which uses scalar Jacobi, Section 6): a per-row

@@ -24,7 +24,7 @@ FORMATS = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "e4m3": 4, "int32": 5, "i
 FORMAT_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2, "e4m3": 1, "int32": 4, "int16": 2}
 STORAGE_DTYPE = {"fp64": np.float64, "fp32": np.float32, "fp16": np.uint16, "bf16": np.uint16,
                  "e4m3": np.uint8, "int32": np.int32, "int16": np.int16}
-PRECONDS = {"none": 0, "jacobi": 1, "sparse": 2}
+PRECONDS = {"none": 0, "jacobi": 1, "sparse": 2, "block_jacobi": 3}
 OK, NOT_CONVERGED, E_ARG, E_NONFINITE = 0, 1, -1, -4
 
 
@@ -42,7 +42,8 @@ def build(verbose: bool = False) -> str:
 class _Opts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("format", C.c_int32), ("tol", C.c_double),
                 ("maxiter", C.c_int64), ("eta", C.c_double), ("precond", C.c_int32),
-                ("p_val", C.c_void_p), ("fallback", C.c_int32)]
+                ("p_val", C.c_void_p), ("fallback", C.c_int32), ("pc_block", C.c_int32),
+                ("pc_prec", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -71,6 +72,8 @@ def lib():
         L.orc_dot.restype = dbl
         L.orc_gmres.argtypes = [i32, vp, vp, vp, vp, vp, C.POINTER(_Opts), C.POINTER(_Result),
                                 vp, vp, vp, vp, vp, C.POINTER(i32)]
+        L.orc_block_jacobi.argtypes = [i32, vp, vp, vp, i32, i32, vp, vp]
+        L.orc_block_jacobi.restype = C.c_int
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_set_threads.restype = None
         L.orc_get_threads.argtypes = []
@@ -126,8 +129,22 @@ def dot(x, y) -> float:
     return float(lib().orc_dot(x.shape[0], _p(x), _p(y)))
 
 
+def block_jacobi(A, bs=4, prec_min=16):
+    """The block-Jacobi preconditioner's stored inverse blocks: (vals, prec)
+    with vals (n_blocks, bs, bs) float64 (the stored values) and prec
+    (n_blocks,) int8 in {16, 32, 64}.  Raises ValueError for a singular block."""
+    nblk = (A.n + bs - 1) // bs
+    vals = np.zeros(nblk * bs * bs)
+    prec = np.zeros(nblk, dtype=np.int8)
+    rc = lib().orc_block_jacobi(A.n, _p(A.row_ptr), _p(A.col_idx), _p(A.val), bs, prec_min,
+                                _p(vals), _p(prec))
+    if rc != 0:
+        raise ValueError(f"orc_block_jacobi: {rc}")
+    return vals.reshape(nblk, bs, bs), prec
+
+
 def gmres(A, b, x0=None, restart=100, fmt="fp64", tol=1e-10, maxiter=10000, eta=0.0,
-          precond="none", p_val=None, fallback=False, debug=False):
+          precond="none", p_val=None, fallback=False, debug=False, pc_block=0, pc_prec=0):
     """Run the oracle solver. Returns a dict with x, status, counts, the
     recurrence-residual history and the explicit residual per cycle; with
     ``debug`` also the first cycle's decoded basis V (k x n) and its
@@ -139,7 +156,7 @@ def gmres(A, b, x0=None, restart=100, fmt="fp64", tol=1e-10, maxiter=10000, eta=
     if precond == "sparse":
         pv = np.ascontiguousarray(p_val, dtype=np.float32)
     opts = _Opts(restart, FORMATS[fmt], tol, maxiter, eta, PRECONDS[precond],
-                 None if pv is None else pv.ctypes.data, int(bool(fallback)))
+                 None if pv is None else pv.ctypes.data, int(bool(fallback)), pc_block, pc_prec)
     res = _Result()
     hist = np.full(max(maxiter, 1), np.nan)
     cyc = np.full(max(maxiter, 1) + 2, np.nan)

@@ -353,10 +353,128 @@ static void basis_combine(int fmt, int32_t j, void *const *Q, const double *sc, 
 /* Restarted CB-GMRES (Fig. 1).                                              */
 /* ------------------------------------------------------------------------- */
 
+/* ------------------------------------------------------------------------- */
+/* Block-Jacobi with adaptive-precision storage (definition in oracle.h).     */
+/* ------------------------------------------------------------------------- */
+
+#define BJ_MAXB 8
+
+/* X = D^-1 for the bs x bs row-major D (overwritten) by Gauss-Jordan
+ * elimination with partial pivoting; every operation is a separate IEEE
+ * multiply, subtract or divide in the order written.  -1 if a pivot is 0. */
+static int gj_invert(int bs, double *D, double *X)
+{
+    for (int i = 0; i < bs; ++i)
+        for (int k = 0; k < bs; ++k)
+            X[i * bs + k] = (i == k) ? 1.0 : 0.0;
+    for (int c = 0; c < bs; ++c) {
+        int r = c;
+        double best = fabs(D[c * bs + c]);
+        for (int i = c + 1; i < bs; ++i)
+            if (fabs(D[i * bs + c]) > best) {
+                best = fabs(D[i * bs + c]);
+                r = i;
+            }
+        if (best == 0.0)
+            return -1;
+        if (r != c)
+            for (int k = 0; k < bs; ++k) {
+                double t = D[c * bs + k]; D[c * bs + k] = D[r * bs + k]; D[r * bs + k] = t;
+                t = X[c * bs + k]; X[c * bs + k] = X[r * bs + k]; X[r * bs + k] = t;
+            }
+        const double p = D[c * bs + c];
+        for (int k = 0; k < bs; ++k) {
+            D[c * bs + k] = D[c * bs + k] / p;
+            X[c * bs + k] = X[c * bs + k] / p;
+        }
+        for (int i = 0; i < bs; ++i) {
+            if (i == c)
+                continue;
+            const double f = D[i * bs + c];
+            for (int k = 0; k < bs; ++k) {
+                const double pd = f * D[c * bs + k];
+                D[i * bs + k] = D[i * bs + k] - pd;
+                const double px = f * X[c * bs + k];
+                X[i * bs + k] = X[i * bs + k] - px;
+            }
+        }
+    }
+    return 0;
+}
+
+/* max over columns of the column's absolute sum (rows summed in order). */
+static double norm1(int bs, const double *M)
+{
+    double best = 0.0;
+    for (int k = 0; k < bs; ++k) {
+        double s = 0.0;
+        for (int i = 0; i < bs; ++i)
+            s = s + fabs(M[i * bs + k]);
+        if (s > best)
+            best = s;
+    }
+    return best;
+}
+
+int orc_block_jacobi(int32_t n, const int32_t *rp, const int32_t *ci, const double *val,
+                     int32_t bs, int32_t prec_min, double *vals, int8_t *prec)
+{
+    if (n < 0 || bs < 1 || bs > BJ_MAXB || (prec_min != 16 && prec_min != 32 && prec_min != 64) ||
+        (n > 0 && (!rp || !ci || !val || !vals || !prec)))
+        return ORC_E_ARG;
+    fesetround(FE_TONEAREST);
+    const int32_t nblk = (n + bs - 1) / bs;
+    int bad = 0;
+    for (int32_t b = 0; b < nblk; ++b) {
+        const int32_t i0 = b * bs;
+        const int sz = (n - i0 < bs) ? (int)(n - i0) : bs;
+        double D[BJ_MAXB * BJ_MAXB], A0[BJ_MAXB * BJ_MAXB], X[BJ_MAXB * BJ_MAXB];
+        for (int t = 0; t < sz * sz; ++t)
+            D[t] = 0.0;
+        for (int i = 0; i < sz; ++i)
+            for (int32_t p = rp[i0 + i]; p < rp[i0 + i + 1]; ++p) {
+                const int32_t c = ci[p];
+                if (c >= i0 && c < i0 + sz)
+                    D[i * sz + (c - i0)] = val[p];
+            }
+        memcpy(A0, D, sizeof(double) * (size_t)(sz * sz));
+        double *out = vals + (size_t)b * bs * bs;
+        for (int t = 0; t < bs * bs; ++t)
+            out[t] = 0.0;
+        if (gj_invert(sz, D, X) != 0) {
+            bad = 1;
+            prec[b] = 64;
+            continue;
+        }
+        const double kappa = norm1(sz, A0) * norm1(sz, X);
+        double mx = 0.0;
+        for (int t = 0; t < sz * sz; ++t)
+            if (fabs(X[t]) > mx)
+                mx = fabs(X[t]);
+        int pr = 64;
+        if (prec_min <= 16 && kappa * ldexp(1.0, -11) <= 0.01 && mx <= 65504.0 &&
+            mx >= ldexp(1.0, -14))
+            pr = 16;
+        else if (prec_min <= 32 && kappa * ldexp(1.0, -24) <= 0.01 &&
+                 mx <= 3.40282346638528859811704183484516925e38 && mx >= ldexp(1.0, -126))
+            pr = 32;
+        prec[b] = (int8_t)pr;
+        for (int i = 0; i < sz; ++i)
+            for (int k = 0; k < sz; ++k) {
+                const double x = X[i * sz + k];
+                out[i * bs + k] = pr == 16 ? round_to_p(x, 11, -14)
+                                : pr == 32 ? round_to_p(x, 24, -126) : x;
+            }
+    }
+    return bad ? ORC_E_ARG : 0;
+}
+
 typedef struct {
     int kind;                 /* ORC_PC_* currently in force */
     double *dinv;             /* Jacobi: 1 / a_ii */
     const float *pv;          /* sparse: P values on A's pattern */
+    int bs;                   /* block-Jacobi: block size */
+    double *bj;               /* block-Jacobi: stored inverse values */
 } precond;
 
 /* z = M^{-1} v (Fig. 1 step 3 and step 17). */
@@ -369,6 +487,18 @@ static void apply_precond(const precond *M, int32_t n, const int32_t *rp, const 
             z[i] = M->dinv[i] * v[i];
     } else if (M->kind == ORC_PC_SPARSE) {
         spmv_f32vals(n, rp, ci, M->pv, v, z);
+    } else if (M->kind == ORC_PC_BLOCK_JACOBI) {
+        const int bs = M->bs;
+#pragma omp parallel for schedule(static)
+        for (int32_t i = 0; i < n; ++i) {
+            const int32_t i0 = i / bs * bs;
+            const int sz = (n - i0 < bs) ? (int)(n - i0) : bs;
+            const double *row = M->bj + (size_t)(i0 / bs) * bs * bs + (size_t)(i - i0) * bs;
+            double s = 0.0;
+            for (int l = 0; l < sz; ++l)
+                s = s + row[l] * v[i0 + l];
+            z[i] = s;
+        }
     } else {
         memcpy(z, v, (size_t)n * sizeof(double));
     }
@@ -395,7 +525,7 @@ int orc_gmres(int32_t n, const int32_t *rp, const int32_t *ci, const double *val
     const int fmt = opt->format;
     const int bs = orc_format_bytes(fmt);
     if (n < 0 || m < 1 || bs == 0 || !(opt->tol >= 0.0) || opt->maxiter < 0 ||
-        opt->precond < ORC_PC_NONE || opt->precond > ORC_PC_SPARSE ||
+        opt->precond < ORC_PC_NONE || opt->precond > ORC_PC_BLOCK_JACOBI ||
         (opt->precond == ORC_PC_SPARSE && !opt->p_val) ||
         (n > 0 && (!rp || !ci || !val || !b || !x))) {
         res->status = ORC_E_ARG;
@@ -423,7 +553,21 @@ int orc_gmres(int32_t n, const int32_t *rp, const int32_t *ci, const double *val
         return ORC_OK;
     }
 
-    precond M = {opt->precond, NULL, opt->p_val};
+    precond M = {opt->precond, NULL, opt->p_val, 0, NULL};
+    if (M.kind == ORC_PC_BLOCK_JACOBI) {
+        M.bs = opt->pc_block > 0 ? opt->pc_block : 4;
+        const int pmin = opt->pc_prec > 0 ? opt->pc_prec : 16;
+        const int32_t nblk = (n + M.bs - 1) / M.bs;
+        M.bj = (double *)malloc(sizeof(double) * (size_t)nblk * M.bs * M.bs);
+        int8_t *pr = (int8_t *)malloc((size_t)nblk);
+        const int rc = orc_block_jacobi(n, rp, ci, val, M.bs, pmin, M.bj, pr);
+        free(pr);
+        if (rc != 0) {
+            free(M.bj);
+            res->status = ORC_E_ARG;
+            return ORC_E_ARG;
+        }
+    }
     if (M.kind == ORC_PC_JACOBI) {
         M.dinv = (double *)malloc((size_t)n * sizeof(double));
         int bad = 0;
@@ -662,6 +806,7 @@ int orc_gmres(int32_t n, const int32_t *rp, const int32_t *ci, const double *val
     free(Q); free(sc); free(r); free(v); free(z); free(w); free(s); free(xprev);
     free(part); free(H); free(h); free(u); free(cs); free(sn); free(g); free(y);
     free(M.dinv);
+    free(M.bj);
     return status;
 }
 

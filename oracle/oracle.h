@@ -29,7 +29,7 @@ enum {
     ORC_E4M3 = 4, ORC_INT32 = 5, ORC_INT16 = 6
 };
 
-enum { ORC_PC_NONE = 0, ORC_PC_JACOBI = 1, ORC_PC_SPARSE = 2 };
+enum { ORC_PC_NONE = 0, ORC_PC_JACOBI = 1, ORC_PC_SPARSE = 2, ORC_PC_BLOCK_JACOBI = 3 };
 
 enum { ORC_OK = 0, ORC_NOT_CONVERGED = 1, ORC_E_ARG = -1, ORC_E_NONFINITE = -4 };
 
@@ -58,6 +58,9 @@ typedef struct {
     int32_t precond;          /* ORC_PC_* */
     const float *p_val;       /* ORC_PC_SPARSE: values of P on A's pattern */
     int32_t fallback;         /* ORC_PC_SPARSE: switch to M = I on stagnation */
+    int32_t pc_block;         /* ORC_PC_BLOCK_JACOBI: block size 1..8 (0: 4) */
+    int32_t pc_prec;          /* ORC_PC_BLOCK_JACOBI: lowest storage precision 16, 32
+                                 or 64 bits (0: 16) */
 } orc_opts;
 
 typedef struct {
@@ -71,6 +74,25 @@ typedef struct {
     double  true_rel_res;     /* ||b - A x||_2 / ||b||_2 at exit */
     double  recurrence_rel_res; /* last |g_{j+1}| / ||b||_2 */
 } orc_result;
+
+/* Block-Jacobi preconditioner with adaptive-precision storage (this
+ * project's definition; the paper's Section 6 discusses block-Jacobi and
+ * its references store the inverted blocks at a precision chosen per block).
+ * Blocks are the consecutive index ranges [b*bs, min((b+1)*bs, n)); D_b is A
+ * restricted to block b.  Each D_b is inverted by Gauss-Jordan elimination
+ * with partial pivoting in FP64 (the first row with the largest |entry| is
+ * the pivot).  kappa_b = ||D_b||_1 ||D_b^-1||_1.  The inverse is stored in
+ * the lowest precision, not below prec_min bits, whose unit roundoff u
+ * (2^-11 for fp16, 2^-24 for fp32) gives kappa_b * u <= 1/100 and whose
+ * normal range holds the block's largest entry (smaller entries may round
+ * to subnormals, with absolute error below u times the largest); otherwise
+ * in fp64; entries are rounded to nearest even.  vals [n_blocks*bs*bs]: the stored values (as
+ * doubles), block b at b*bs*bs, row-major with row stride bs, zero beyond
+ * the block's size; prec [n_blocks]: 16, 32 or 64.  Returns 0, or ORC_E_ARG
+ * for invalid arguments or a singular block. */
+int orc_block_jacobi(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                     const double *val, int32_t bs, int32_t prec_min, double *vals,
+                     int8_t *prec);
 
 /* Restarted CB-GMRES (Fig. 1).  x is x0 on entry and the result on exit.
  * hist (optional, maxiter entries): recurrence residual |g_{j+1}|/||b|| per

@@ -10,14 +10,16 @@ device memory and streams only.
 """
 from . import problems
 from ._binding import (FORMATS, FORMAT_BYTES, PRECONDS, CbgError, DeviceCSR, SolveResult,
-                       adam_step, basis_ld, csr_transpose_values, decode, encode,
+                       adam_step, basis_ld, block_jacobi_apply, block_jacobi_setup,
+                       csr_transpose_values, decode, encode,
                        kernel_workspace_bytes, learned_build, lib, mlp_backward, mlp_forward,
                        multidot, solve, spai_assemble, spai_features, spai_grad_o, spai_grad_p,
                        spai_loss_grad, spai_pack, spai_round_weights, spai_workspace_bytes, spmv,
                        strerror, update, update_redot, workspace_basis, workspace_bytes)
 
 __all__ = ["problems", "FORMATS", "FORMAT_BYTES", "PRECONDS", "CbgError", "DeviceCSR",
-           "SolveResult", "adam_step", "basis_ld", "csr_transpose_values", "decode", "encode",
+           "SolveResult", "adam_step", "basis_ld", "block_jacobi_apply", "block_jacobi_setup",
+           "csr_transpose_values", "decode", "encode",
            "kernel_workspace_bytes", "learned_build", "lib", "mlp_backward", "mlp_forward",
            "multidot", "solve", "spai_assemble", "spai_features", "spai_grad_o", "spai_grad_p",
            "spai_loss_grad", "spai_pack", "spai_round_weights", "spai_workspace_bytes", "spmv",

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libcbgmres.so")
 
 FORMATS = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "e4m3": 4, "int32": 5, "int16": 6}
 FORMAT_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2, "e4m3": 1, "int32": 4, "int16": 2}
-PRECONDS = {"none": 0, "jacobi": 1, "sparse": 2}
+PRECONDS = {"none": 0, "jacobi": 1, "sparse": 2, "block_jacobi": 3}
 OK, NOT_CONVERGED = 0, 1
 E_ARG, E_WORKSPACE, E_HIP, E_NONFINITE, E_UNSUPPORTED = -1, -2, -3, -4, -5
 FLAG_PROFILE = 1
@@ -27,8 +27,8 @@ MAX_RESTART = 512
 
 EXPORTS = ["cbg_strerror", "cbg_basis_ld", "cbg_workspace_bytes", "cbg_kernel_workspace_bytes",
            "cbg_workspace_basis", "cbgmres_solve", "cbg_encode", "cbg_decode", "cbg_spmv",
-           "cbg_multidot", "cbg_update", "cbg_update_redot",
-           "cbg_spai_workspace_bytes", "cbg_spai_features", "cbg_mlp_forward",
+           "cbg_multidot", "cbg_update", "cbg_update_redot", "cbg_block_jacobi_setup",
+           "cbg_block_jacobi_apply", "cbg_spai_workspace_bytes", "cbg_spai_features", "cbg_mlp_forward",
            "cbg_spai_assemble", "cbg_learned_build", "cbg_csr_transpose_values",
            "cbg_spai_pack", "cbg_spai_grad_p", "cbg_spai_grad_o", "cbg_mlp_backward",
            "cbg_spai_loss_grad", "cbg_spai_round_weights", "cbg_adam_step"]
@@ -46,7 +46,7 @@ class CbgOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("format", C.c_int32), ("tol", C.c_double),
                 ("maxiter", C.c_int64), ("eta", C.c_double), ("precond", C.c_int32),
                 ("fallback", C.c_int32), ("p_val", C.c_void_p), ("flags", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("reserved", C.c_int32), ("pc_block", C.c_int32), ("pc_prec", C.c_int32)]
 
 
 class CbgResult(C.Structure):
@@ -95,6 +95,9 @@ def lib():
         L.cbg_multidot.argtypes = [i32, vp, i64, vp, i32, i32, vp, vp, vp, sz, vp]
         L.cbg_update.argtypes = [i32, vp, i64, vp, i32, i32, vp, vp, vp, vp, sz, vp]
         L.cbg_update_redot.argtypes = [i32, vp, i64, vp, i32, i32, vp, vp, vp, vp, vp, sz, vp]
+        L.cbg_block_jacobi_setup.argtypes = [C.POINTER(CbgCsr), i32, i32, vp, vp, vp, vp, vp, sz,
+                                             vp]
+        L.cbg_block_jacobi_apply.argtypes = [i32, i32, vp, vp, vp, vp, vp, vp, vp]
         L.cbg_workspace_basis.argtypes = [i32, i32, i32, i32, C.POINTER(sz), C.POINTER(sz)]
         pcsr, f64 = C.POINTER(CbgCsr), C.c_double
         L.cbg_spai_workspace_bytes.argtypes = [i32, i64, i32]
@@ -113,7 +116,8 @@ def lib():
         L.cbg_spai_round_weights.argtypes = [vp, vp, vp]
         L.cbg_adam_step.argtypes = [vp, vp, vp, vp, vp, i64, f64, f64, f64, f64, vp]
         for f in ("cbgmres_solve", "cbg_encode", "cbg_decode", "cbg_spmv", "cbg_multidot",
-                  "cbg_update", "cbg_update_redot", "cbg_workspace_basis", "cbg_spai_features", "cbg_mlp_forward",
+                  "cbg_update", "cbg_update_redot", "cbg_block_jacobi_setup",
+                  "cbg_block_jacobi_apply", "cbg_workspace_basis", "cbg_spai_features", "cbg_mlp_forward",
                   "cbg_spai_assemble", "cbg_learned_build", "cbg_csr_transpose_values",
                   "cbg_spai_pack", "cbg_spai_grad_p", "cbg_spai_grad_o", "cbg_mlp_backward",
                   "cbg_spai_loss_grad", "cbg_spai_round_weights", "cbg_adam_step"):
@@ -221,7 +225,7 @@ class SolveResult:
 
 def solve(A: DeviceCSR, b, x0=None, restart=100, fmt="fp64", tol=1e-10, maxiter=10000,
           eta=0.0, precond="none", p_val=None, fallback=False, profile=False, workspace=None,
-          hist=True, fuse=True) -> SolveResult:
+          hist=True, fuse=True, pc_block=0, pc_prec=0) -> SolveResult:
     """cbgmres_solve on device tensors; returns the solution and counters.
     profile: False, True (event-time every basis-streaming launch) or "dot"
     (only the multi-dot launches).  Raises CbgError on a negative status."""
@@ -235,7 +239,7 @@ def solve(A: DeviceCSR, b, x0=None, restart=100, fmt="fp64", tol=1e-10, maxiter=
     opts = CbgOpts(restart, FORMATS[fmt], tol, maxiter, eta, PRECONDS[precond],
                    int(bool(fallback)), None if p_val is None else p_val.data_ptr(),
                    {False: 0, True: FLAG_PROFILE, "dot": FLAG_PROFILE_DOT}[profile]
-                   | (0 if fuse else FLAG_NO_FUSE), 0)
+                   | (0 if fuse else FLAG_NO_FUSE), 0, pc_block, pc_prec)
     res = CbgResult()
     hl = int(maxiter) if hist else 0
     h = np.zeros(max(hl, 1))
@@ -324,6 +328,33 @@ def update_redot(fmt: str, V, ld: int, scales, n: int, j: int, h, w, ws=None):
                                   _ptr(w), _ptr(u), _ptr(norms), _ptr(ws), ws.numel(),
                                   _stream()), "cbg_update_redot")
     return u[:j], norms
+
+
+def block_jacobi_setup(A: DeviceCSR, bs=4, prec_min=16):
+    """(tags int8[nblk], x64, x32, x16) device tensors of the block-Jacobi
+    preconditioner's stored inverse blocks."""
+    torch = _torch()
+    dev = A.val.device
+    nblk = (A.n + bs - 1) // bs
+    tags = torch.empty(max(nblk, 1), dtype=torch.int8, device=dev)
+    x64 = torch.zeros(max(nblk * bs * bs, 1), dtype=torch.float64, device=dev)
+    x32 = torch.zeros_like(x64, dtype=torch.float32)
+    x16 = torch.zeros_like(x64, dtype=torch.int16)
+    ws = _kws(A.n, 0, dev)
+    csr = A.cstruct()
+    _check(lib().cbg_block_jacobi_setup(C.byref(csr), bs, prec_min, _ptr(tags), _ptr(x64),
+                                        _ptr(x32), _ptr(x16), _ptr(ws), ws.numel(), _stream()),
+           "cbg_block_jacobi_setup")
+    return tags, x64, x32, x16
+
+
+def block_jacobi_apply(n, bs, blocks, v, z=None):
+    torch = _torch()
+    tags, x64, x32, x16 = blocks
+    z = torch.empty(n, dtype=torch.float64, device=v.device) if z is None else z
+    _check(lib().cbg_block_jacobi_apply(n, bs, _ptr(tags), _ptr(x64), _ptr(x32), _ptr(x16),
+                                        _ptr(v), _ptr(z), _stream()), "cbg_block_jacobi_apply")
+    return z
 
 
 # ------------------------------------------------ learned preconditioner

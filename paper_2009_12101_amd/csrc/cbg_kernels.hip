@@ -871,6 +871,201 @@ __global__ __launch_bounds__(BLK) void k_update_redot(const uint8_t *__restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Block-Jacobi right preconditioner with adaptive-precision storage (an
+// extension: the paper discusses block-Jacobi preconditioners in Section 6;
+// the selection rule is this project's own).  Block b covers the rows and
+// columns [b*BS, min((b+1)*BS, n)); its inverse is stored in fp16, fp32 or
+// fp64 (tag 16/32/64), in the array of that precision at b*BS*BS, row-major
+// with row stride BS and zeros beyond the block's size.
+// ---------------------------------------------------------------------------
+
+// Gauss-Jordan inversion with partial pivoting, every operation a separate
+// IEEE multiply, subtract or divide in a fixed order (the result is the same
+// bits on any IEEE machine).  A ragged last block (sz < BS) is padded with
+// identity rows and columns: padded rows are never pivots (their entries in
+// the block's columns are 0) and elimination leaves them unchanged, so the
+// top-left sz x sz of the result is the inverse of the block itself.
+template <int BS>
+__global__ __launch_bounds__(BLK) void k_bj_setup(int n, const int32_t *__restrict__ rp,
+                                                  const int32_t *__restrict__ ci,
+                                                  const double *__restrict__ val, int prec_min,
+                                                  int8_t *__restrict__ tags,
+                                                  double *__restrict__ x64,
+                                                  float *__restrict__ x32,
+                                                  uint16_t *__restrict__ x16,
+                                                  unsigned *__restrict__ bad)
+{
+#pragma clang fp contract(off)
+    const int nblk = (n + BS - 1) / BS;
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < nblk; b += gridDim.x * blockDim.x) {
+        const int i0 = b * BS;
+        const int sz = min(BS, n - i0);
+        double D[BS][BS], A0[BS][BS], X[BS][BS];
+#pragma unroll
+        for (int i = 0; i < BS; ++i)
+#pragma unroll
+            for (int k = 0; k < BS; ++k) {
+                D[i][k] = (i == k && i >= sz) ? 1.0 : 0.0;
+                X[i][k] = (i == k) ? 1.0 : 0.0;
+            }
+#pragma unroll
+        for (int i = 0; i < BS; ++i) {
+            if (i < sz) {
+                for (int p = rp[i0 + i]; p < rp[i0 + i + 1]; ++p) {
+                    const int c = ci[p] - i0;
+                    const double a = val[p];
+#pragma unroll
+                    for (int k = 0; k < BS; ++k)
+                        if (c == k && k < sz)
+                            D[i][k] = a;
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < BS; ++i)
+#pragma unroll
+            for (int k = 0; k < BS; ++k)
+                A0[i][k] = D[i][k];
+        bool singular = false;
+#pragma unroll
+        for (int c = 0; c < BS; ++c) {
+            // pivot: the first row at or below c with the largest |entry|
+            int r = c;
+            double best = fabs(D[c][c]);
+#pragma unroll
+            for (int i = c + 1; i < BS; ++i)
+                if (fabs(D[i][c]) > best) {
+                    best = fabs(D[i][c]);
+                    r = i;
+                }
+            if (best == 0.0)
+                singular = true;
+#pragma unroll
+            for (int i = c + 1; i < BS; ++i) {
+                if (i == r) {
+#pragma unroll
+                    for (int k = 0; k < BS; ++k) {
+                        double t = D[c][k]; D[c][k] = D[i][k]; D[i][k] = t;
+                        t = X[c][k]; X[c][k] = X[i][k]; X[i][k] = t;
+                    }
+                }
+            }
+            const double piv = D[c][c];
+#pragma unroll
+            for (int k = 0; k < BS; ++k) {
+                D[c][k] = D[c][k] / piv;
+                X[c][k] = X[c][k] / piv;
+            }
+#pragma unroll
+            for (int i = 0; i < BS; ++i) {
+                if (i == c)
+                    continue;
+                const double f = D[i][c];
+#pragma unroll
+                for (int k = 0; k < BS; ++k) {
+                    const double pd = f * D[c][k];
+                    D[i][k] = D[i][k] - pd;
+                    const double px = f * X[c][k];
+                    X[i][k] = X[i][k] - px;
+                }
+            }
+        }
+        if (singular) {
+            *bad = 1u;
+            tags[b] = 64;
+            continue;
+        }
+        // kappa_1 = ||D_b||_1 ||D_b^-1||_1 over the block's own sz x sz
+        double na = 0.0, nx = 0.0, mx = 0.0;
+#pragma unroll
+        for (int k = 0; k < BS; ++k) {
+            double sa = 0.0, sx = 0.0;
+#pragma unroll
+            for (int i = 0; i < BS; ++i)
+                if (i < sz && k < sz) {
+                    sa = sa + fabs(A0[i][k]);
+                    sx = sx + fabs(X[i][k]);
+                    mx = fmax(mx, fabs(X[i][k]));
+                }
+            if (sa > na) na = sa;
+            if (sx > nx) nx = sx;
+        }
+        const double kappa = na * nx;
+        int pr = 64;
+        if (prec_min <= 16 && kappa * 0x1p-11 <= 0.01 && mx <= 65504.0 && mx >= 0x1p-14)
+            pr = 16;
+        else if (prec_min <= 32 && kappa * 0x1p-24 <= 0.01 && mx <= 3.40282346638528859812e38 &&
+                 mx >= 0x1p-126)
+            pr = 32;
+        tags[b] = (int8_t)pr;
+        const size_t o = (size_t)b * BS * BS;
+#pragma unroll
+        for (int i = 0; i < BS; ++i)
+#pragma unroll
+            for (int k = 0; k < BS; ++k) {
+                const double v = (i < sz && k < sz) ? X[i][k] : 0.0;
+                if (pr == 16)
+                    x16[o + i * BS + k] = (uint16_t)Fmt<F_FP16>::code(v, EncParam{1.0, 0});
+                else if (pr == 32)
+                    x32[o + i * BS + k] = (float)v;
+                else
+                    x64[o + i * BS + k] = v;
+            }
+    }
+}
+
+// Row i of the stored inverse of its block, widened to FP64.
+__device__ __forceinline__ double bj_entry(int tag, size_t o, const double *__restrict__ x64,
+                                           const float *__restrict__ x32,
+                                           const uint16_t *__restrict__ x16)
+{
+    return tag == 16 ? dec_f16(x16[o]) : tag == 32 ? (double)x32[o] : x64[o];
+}
+
+// Fig. 1 steps 13-14 and 3 for block-Jacobi: v = w / t, stored as basis
+// vector j through the accessor (rows up to ld, padding w = 0), and
+// z = M^-1 v for the rows below n.  MODE 1 (no state): z = M^-1 w (or
+// z += M^-1 w with accumulate), the kernel-level apply and the solution
+// update.
+__global__ __launch_bounds__(BLK) void k_bj_apply(int n, int64_t ldq, int bs,
+                                                  const int8_t *__restrict__ tags,
+                                                  const double *__restrict__ x64,
+                                                  const float *__restrict__ x32,
+                                                  const uint16_t *__restrict__ x16,
+                                                  const double *__restrict__ w,
+                                                  double *__restrict__ z, int accumulate,
+                                                  const DevState *st, uint8_t *__restrict__ Q,
+                                                  const double *__restrict__ qscale, int fmt)
+{
+    double t = 1.0;
+    EncParam ep{1.0, 0};
+    if (st) {
+        if (st->done)
+            return;
+        t = st->t;
+        ep = param_from_scale(fmt, *qscale);
+    }
+    const int64_t rows = st ? ldq : n;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (st)
+            store_entry(fmt, Q, i, w[i] / t, ep);
+        if (i >= n)
+            continue;
+        const int64_t b = i / bs, i0 = b * bs;
+        const int sz = (int)min((int64_t)bs, (int64_t)n - i0);
+        const int tag = tags[b];
+        const size_t o = (size_t)b * bs * bs + (size_t)(i - i0) * bs;
+        double s = 0.0;
+        for (int l = 0; l < sz; ++l) {
+            const double v = st ? w[i0 + l] / t : w[i0 + l];
+            s = fma(bj_entry(tag, o + l, x64, x32, x16), v, s);
+        }
+        z[i] = accumulate ? z[i] + s : s;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // One-block reductions of the producers' partials (fixed order: lane l sums
 // blocks l, l+64, ... in turn, then a butterfly across the wave), followed
 // by the scalar work that needs the totals.
@@ -1241,6 +1436,35 @@ static int tile_elems() { return BLK * Fmt<F>::VW * Fmt<F>::CH; }
     case F_INT32: { constexpr int F = F_INT32; CALL; } break; \
     default: { constexpr int F = F_INT16; CALL; } break;    \
     }
+
+int launch_bj_setup(int n, const int32_t *rp, const int32_t *ci, const double *val, int bs,
+                    int prec_min, int8_t *tags, double *x64, float *x32, uint16_t *x16,
+                    unsigned *bad, hipStream_t s)
+{
+    const int nblk = (n + bs - 1) / bs;
+    const int g = grid_for(nblk, BLK);
+#define CBG_BJ_CASE(B)                                                                      \
+    case B:                                                                                 \
+        k_bj_setup<B><<<g, BLK, 0, s>>>(n, rp, ci, val, prec_min, tags, x64, x32, x16, bad); \
+        break;
+    switch (bs) {
+        CBG_BJ_CASE(1) CBG_BJ_CASE(2) CBG_BJ_CASE(3) CBG_BJ_CASE(4)
+        CBG_BJ_CASE(5) CBG_BJ_CASE(6) CBG_BJ_CASE(7) CBG_BJ_CASE(8)
+    default: return -1;
+    }
+#undef CBG_BJ_CASE
+    return 0;
+}
+
+void launch_bj_apply(int n, int64_t ldq, int bs, const int8_t *tags, const double *x64,
+                     const float *x32, const uint16_t *x16, const double *w, double *z,
+                     int accumulate, const DevState *st, void *Q, const double *qscale, int fmt,
+                     hipStream_t s)
+{
+    const int64_t rows = st ? ldq : n;
+    k_bj_apply<<<grid_for(rows, BLK), BLK, 0, s>>>(n, ldq, bs, tags, x64, x32, x16, w, z,
+                                                    accumulate, st, (uint8_t *)Q, qscale, fmt);
+}
 
 int orth_grid(int fmt, int64_t n)
 {

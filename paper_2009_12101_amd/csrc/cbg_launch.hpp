@@ -66,6 +66,17 @@ void launch_update(const OrthArgs &a, hipStream_t s);
 // partials per value), or 0 if j is beyond the fused kernel's register tile
 // (then nothing is launched).
 int launch_update_redot(const OrthArgs &a, hipStream_t s);
+// Block-Jacobi: invert the bs x bs diagonal blocks (1 <= bs <= 8) and store
+// each in fp16/fp32/fp64 by the precision rule (-1: bs out of range).
+int launch_bj_setup(int n, const int32_t *rp, const int32_t *ci, const double *val, int bs,
+                    int prec_min, int8_t *tags, double *x64, float *x32, uint16_t *x16,
+                    unsigned *bad, hipStream_t s);
+// With st: v = w / t stored as basis vector (Q, qscale) for rows < ldq and
+// z = M^-1 v; without: z (+)= M^-1 w.
+void launch_bj_apply(int n, int64_t ldq, int bs, const int8_t *tags, const double *x64,
+                     const float *x32, const uint16_t *x16, const double *w, double *z,
+                     int accumulate, const DevState *st, void *Q, const double *qscale, int fmt,
+                     hipStream_t s);
 int fused_jmax(int fmt);   // largest j launch_update_redot takes
 // Whether launch_update_redot takes step j for basis vectors of leading
 // dimension ld (the one predicate the solver and the launcher share).

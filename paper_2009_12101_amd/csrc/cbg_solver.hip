@@ -6,6 +6,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <vector>
 
@@ -18,6 +19,7 @@ using namespace cbg;
 namespace {
 
 constexpr size_t ALIGN = 256;
+constexpr int BJ_MAX = 8;          // largest block-Jacobi block size
 constexpr double ETA_DEFAULT = 0.70710678118654752440;   // 1/sqrt(2), nearest double
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
@@ -59,6 +61,10 @@ struct SolveWs {
     DevState *st;
     uint8_t *V;
     double *scales, *w0, *w1, *z, *dinv, *xprev;
+    int8_t *bj_tags;               // block-Jacobi: per-block storage precision
+    double *bj64;                  // and the inverted blocks by precision
+    float *bj32;
+    uint16_t *bj16;
     double *H, *h, *u, *cs, *sn, *g, *y, *hist;
     int32_t *flags;
     unsigned *bad;
@@ -77,9 +83,16 @@ SolveWs carve_solve(void *ws, int32_t n, int32_t m, int fmt, int pc, size_t *tot
     s.scales = c.take<double>(m + 1);
     s.w0 = c.take<double>(ld);   // the step's w and the previous step's w
     s.w1 = c.take<double>(ld);   // alternate between these two buffers
-    s.z = c.take<double>(pc == CBG_PC_SPARSE ? ld : 1);
+    const bool bj = pc == CBG_PC_BLOCK_JACOBI;
+    s.z = c.take<double>(pc == CBG_PC_SPARSE || bj ? ld : 1);
     s.dinv = c.take<double>(pc == CBG_PC_JACOBI ? ld : 1);
     s.xprev = c.take<double>(pc == CBG_PC_SPARSE ? ld : 1);
+    // sized for the largest block size: ceil(n/bs) bs^2 <= n BJ_MAX + BJ_MAX^2
+    const size_t bjv = bj ? (size_t)n * BJ_MAX + BJ_MAX * BJ_MAX : 1;
+    s.bj_tags = c.take<int8_t>(bj ? (size_t)n + 1 : 1);
+    s.bj64 = c.take<double>(bjv);
+    s.bj32 = c.take<float>(bjv);
+    s.bj16 = c.take<uint16_t>(bjv);
     s.H = c.take<double>((size_t)(m + 1) * m);
     s.h = c.take<double>(m + 1);
     s.u = c.take<double>(m + 1);
@@ -173,7 +186,7 @@ int64_t cbg_basis_ld(int32_t n) { return n < 0 ? 0 : basis_ld(n); }
 size_t cbg_workspace_bytes(int32_t n, int32_t restart, int32_t format, int32_t precond)
 {
     if (n < 0 || restart < 1 || restart > CBG_MAX_RESTART || !valid_format(format) ||
-        precond < CBG_PC_NONE || precond > CBG_PC_SPARSE)
+        precond < CBG_PC_NONE || precond > CBG_PC_BLOCK_JACOBI)
         return 0;
     size_t total = 0;
     carve_solve(nullptr, n, restart, format, precond, &total);
@@ -184,7 +197,8 @@ int cbg_workspace_basis(int32_t n, int32_t restart, int32_t format, int32_t prec
                         size_t *basis_offset, size_t *scales_offset)
 {
     if (n < 0 || restart < 1 || restart > CBG_MAX_RESTART || !valid_format(format) ||
-        precond < CBG_PC_NONE || precond > CBG_PC_SPARSE || !basis_offset || !scales_offset)
+        precond < CBG_PC_NONE || precond > CBG_PC_BLOCK_JACOBI || !basis_offset ||
+        !scales_offset)
         return CBG_E_ARG;
     const SolveWs w = carve_solve(nullptr, n, restart, format, precond, nullptr);
     *basis_offset = w.v_off;
@@ -218,7 +232,12 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
     const int fmt = opt->format, pc0 = opt->precond;
     if (n < 0 || A->nnz < 0 || m < 1 || m > CBG_MAX_RESTART || !valid_format(fmt) ||
         !(opt->tol >= 0.0) || !isfinite(opt->tol) || opt->maxiter < 0 || pc0 < CBG_PC_NONE ||
-        pc0 > CBG_PC_SPARSE || (hist_len > 0 && !hist_out) || hist_len < 0)
+        pc0 > CBG_PC_BLOCK_JACOBI || (hist_len > 0 && !hist_out) || hist_len < 0)
+        return fail(CBG_E_ARG);
+    const int bj_bs = opt->pc_block > 0 ? opt->pc_block : 4;
+    const int bj_prec = opt->pc_prec > 0 ? opt->pc_prec : 16;
+    if (pc0 == CBG_PC_BLOCK_JACOBI &&
+        (bj_bs > BJ_MAX || (bj_prec != 16 && bj_prec != 32 && bj_prec != 64)))
         return fail(CBG_E_ARG);
     if (n > 0 && (!A->row_ptr || !A->col_idx || !A->val || !b || !x || !aligned16(b) ||
                   !aligned16(x) || (A->nnz > 0 && (!A->col_idx || !A->val))))
@@ -263,6 +282,14 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
     int pc = pc0;
     if (pc == CBG_PC_JACOBI)
         launch_jacobi_setup(n, ld, A->row_ptr, A->col_idx, A->val, W.dinv, W.bad, s);
+    const int bj_nblk = (n + bj_bs - 1) / bj_bs;
+    std::vector<int8_t> bj_tags;
+    if (pc == CBG_PC_BLOCK_JACOBI) {
+        launch_bj_setup(n, A->row_ptr, A->col_idx, A->val, bj_bs, bj_prec, W.bj_tags, W.bj64,
+                        W.bj32, W.bj16, W.bad, s);
+        bj_tags.resize(bj_nblk);
+        HIP_TRY(hipMemcpyAsync(bj_tags.data(), W.bj_tags, bj_nblk, hipMemcpyDeviceToHost, s));
+    }
     HIP_TRY(hipGetLastError());
 
     DevState hs;
@@ -272,6 +299,12 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
     HIP_TRY(hipStreamSynchronize(s));
     if (bad)
         return fail(CBG_E_ARG);
+    // bytes of one block-Jacobi apply's inverse values (a row reads its block row)
+    double bj_bytes = 0.0;
+    for (int b = 0; b < (int)bj_tags.size(); ++b) {
+        const int sz = std::min(bj_bs, n - b * bj_bs);
+        bj_bytes += (double)sz * sz * (bj_tags[b] / 8);
+    }
     if (!isfinite(hs.nb))
         return fail(CBG_E_NONFINITE);
     if (hs.nb == 0.0) {                       // b = 0: the solution is x = 0
@@ -356,6 +389,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                 double b_step = bm.spmv_step() + bm.dot(j) + bm.upd(j);
                 if (prev_pc == CBG_PC_JACOBI) b_step += 8.0 * n;
                 if (prev_pc == CBG_PC_SPARSE) b_step += 8.0 * A->nnz + 4.0 * (n + 1) + 16.0 * n;
+                if (prev_pc == CBG_PC_BLOCK_JACOBI) b_step += bj_bytes + 16.0 * n;
                 if (!fused(j))
                     b_step += bm.dot(j);             // the separate re-dot pass
                 if (ro) b_step += bm.upd(j);
@@ -413,7 +447,16 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
             // vector j) fused with steps 3-4: w = A M^-1 v_j, omega
             void *slot = W.V + (size_t)(j - 1) * vbytes;
             int nb_spmv;
-            if (pc == CBG_PC_SPARSE) {
+            if (pc == CBG_PC_BLOCK_JACOBI) {
+                // v_j = w / t stored, z = M^-1 v_j; then w = A z, omega
+                launch_bj_apply(n, ld, bj_bs, W.bj_tags, W.bj64, W.bj32, W.bj16, cur, W.z, 0,
+                                W.st, slot, W.scales + (j - 1), fmt, s);
+                SpmvArgs b2{};
+                b2.n = n; b2.ldy = ld; b2.rp = A->row_ptr; b2.ci = A->col_idx; b2.val = A->val;
+                b2.x = W.z; b2.y = nxt; b2.ws = W.red; b2.mode = 0 /*SP_PLAIN*/;
+                b2.role = 1 /*SR_STEP*/; b2.sg = sg; b2.st = W.st;
+                nb_spmv = launch_spmv(b2, s);
+            } else if (pc == CBG_PC_SPARSE) {
                 SpmvArgs a{};
                 a.n = n; a.ldy = ld; a.rp = A->row_ptr; a.ci = A->col_idx; a.fval = opt->p_val;
                 a.x = cur; a.y = W.z; a.ws = W.red; a.mode = 8 | 3 /*SP_STEP_FLOATVAL*/;
@@ -476,7 +519,13 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
             OrthArgs o{};
             o.fmt = fmt; o.V = W.V; o.ld = ld; o.scales = W.scales; o.n = n; o.j = 0;
             o.coef = W.y; o.ws = W.red; o.st = W.st;
-            if (pc == CBG_PC_SPARSE) {
+            if (pc == CBG_PC_BLOCK_JACOBI) {
+                o.role = 4 /*U_COMBINE*/;       // z = V y
+                o.wio = W.z;
+                launch_update(o, s);
+                launch_bj_apply(n, ld, bj_bs, W.bj_tags, W.bj64, W.bj32, W.bj16, W.z, x, 1,
+                                nullptr, nullptr, nullptr, fmt, s);   // x += M^-1 z
+            } else if (pc == CBG_PC_SPARSE) {
                 o.role = 4 /*U_COMBINE*/;       // z = V y
                 o.wio = W.z;
                 launch_update(o, s);
@@ -667,6 +716,46 @@ int cbg_update_redot(int32_t format, const void *V, int64_t ld, const double *sc
     RedWs tail = o.ws;                  // ||w||^2 and max|w| follow the j values
     tail.orth += (size_t)j * tail.stride;
     launch_reduce(tail, RR_NORMS, nb, 0, 0, nullptr, nullptr, norms, format, s);
+    HIP_TRY(hipGetLastError());
+    return CBG_OK;
+}
+
+int cbg_block_jacobi_setup(const cbg_csr *A, int32_t bs, int32_t prec_min, int8_t *tags,
+                           double *x64, float *x32, uint16_t *x16, void *ws, size_t ws_bytes,
+                           void *stream)
+{
+    if (!A || A->n < 0 || bs < 1 || bs > BJ_MAX ||
+        (prec_min != 16 && prec_min != 32 && prec_min != 64) ||
+        (A->n > 0 && (!A->row_ptr || !tags || !x64 || !x32 || !x16 ||
+                      (A->nnz > 0 && (!A->col_idx || !A->val)))))
+        return CBG_E_ARG;
+    if (!kernel_ws_ok(ws, ws_bytes, 0))
+        return CBG_E_WORKSPACE;
+    if (A->n == 0)
+        return CBG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned *bad = (unsigned *)ws;
+    HIP_TRY(hipMemsetAsync(bad, 0, sizeof(unsigned), s));
+    launch_bj_setup(A->n, A->row_ptr, A->col_idx, A->val, bs, prec_min, tags, x64, x32, x16,
+                    bad, s);
+    HIP_TRY(hipGetLastError());
+    unsigned hb = 0;
+    HIP_TRY(hipMemcpyAsync(&hb, bad, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return hb ? CBG_E_ARG : CBG_OK;
+}
+
+int cbg_block_jacobi_apply(int32_t n, int32_t bs, const int8_t *tags, const double *x64,
+                           const float *x32, const uint16_t *x16, const double *v, double *z,
+                           void *stream)
+{
+    if (n < 0 || bs < 1 || bs > BJ_MAX ||
+        (n > 0 && (!tags || !x64 || !x32 || !x16 || !v || !z)))
+        return CBG_E_ARG;
+    if (n == 0)
+        return CBG_OK;
+    launch_bj_apply(n, n, bs, tags, x64, x32, x16, v, z, 0, nullptr, nullptr, nullptr, 0,
+                    (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
     return CBG_OK;
 }

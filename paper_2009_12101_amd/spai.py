@@ -183,18 +183,22 @@ def make_instances(seeds, N: int, device, pool=None, log=None):
 
 def compare(model: LearnedSPAI, A, b, fmt="fp16", restart=100, tol=1e-10, maxiter=20000,
             repeats=1, device="cuda", plain_fp64=False):
-    """Time to solution of CB-GMRES with M = I, Jacobi and the learned P
-    (its build, features to P values, included in the time), all with the
-    `fmt` basis; with plain_fp64 also plain GMRES (fp64 basis, M = I)."""
+    """Time to solution of CB-GMRES with M = I, Jacobi, block-Jacobi (4 x 4
+    blocks, adaptive or fp64 storage) and the learned P (its build, features
+    to P values, included in the time), all with the `fmt` basis; with
+    plain_fp64 also plain GMRES (fp64 basis, M = I).  Block-Jacobi's set-up
+    (inverting the blocks) is part of its solve."""
     torch = _torch()
     Ad = B.DeviceCSR.from_host(A, device)
     bd = torch.from_numpy(b).to(device)
     need = max(B.workspace_bytes(A.n, restart, fmt, "sparse"),
+               B.workspace_bytes(A.n, restart, fmt, "block_jacobi"),
                B.workspace_bytes(A.n, restart, "fp64", "none") if plain_fp64 else 0)
     ws = torch.empty(need, dtype=torch.uint8, device=device)
     sws = torch.empty(B.spai_workspace_bytes(A.n, A.nnz, 0), dtype=torch.uint8, device=device)
     rows = {}
-    kinds = ["none", "jacobi", "learned"] + (["plain_fp64"] if plain_fp64 else [])
+    kinds = ["none", "jacobi", "block_jacobi", "block_jacobi_fp64", "learned"] + \
+        (["plain_fp64"] if plain_fp64 else [])
     for kind in kinds:
         best = None
         for _ in range(repeats + 1):            # the first run warms up
@@ -204,6 +208,12 @@ def compare(model: LearnedSPAI, A, b, fmt="fp16", restart=100, tol=1e-10, maxite
                 pv = model.build(Ad, A.grid, ws=sws)
                 r = B.solve(Ad, bd, restart=restart, fmt=fmt, tol=tol, maxiter=maxiter,
                             precond="sparse", p_val=pv, fallback=True, workspace=ws,
+                            hist=False)
+            elif kind.startswith("block_jacobi"):
+                # 4 x 4 blocks; stored at the adaptive precision, or all fp64
+                r = B.solve(Ad, bd, restart=restart, fmt=fmt, tol=tol, maxiter=maxiter,
+                            precond="block_jacobi", pc_block=4,
+                            pc_prec=64 if kind.endswith("fp64") else 16, workspace=ws,
                             hist=False)
             elif kind == "plain_fp64":
                 r = B.solve(Ad, bd, restart=restart, fmt="fp64", tol=tol, maxiter=maxiter,
@@ -230,6 +240,8 @@ def main(argv=None) -> int:
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--init-seed", type=int, default=0)
     ap.add_argument("--test-grid", type=int, default=128)
+    ap.add_argument("--test-system", default="lognormal27", choices=["lognormal27", "convdiff7"],
+                    help="held-out system family (the network is trained on lognormal27)")
     ap.add_argument("--test-seed", type=int, default=0)
     ap.add_argument("--format", default="fp16",
                     help="basis storage of the test solves (comma list allowed)")
@@ -276,7 +288,8 @@ def main(argv=None) -> int:
         if a.out:
             model.save(a.out)
     if a.test_grid > 0:
-        A = P.lognormal27(a.test_grid, a.test_seed)
+        A = (P.lognormal27(a.test_grid, a.test_seed) if a.test_system == "lognormal27"
+             else P.convdiff7(a.test_grid))
         b = P.rhs_uniform(A.n, a.test_seed)
         report["test"] = []
         for i, fmt in enumerate(a.format.split(",")):
