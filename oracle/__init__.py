@@ -20,10 +20,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 SRC = os.path.join(_HERE, "oracle.c")
 
-FORMATS = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "e4m3": 4, "int32": 5, "int16": 6}
-FORMAT_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2, "e4m3": 1, "int32": 4, "int16": 2}
+FORMATS = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "e4m3": 4, "int32": 5, "int16": 6,
+           "fp16s": 7}
+FORMAT_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2, "e4m3": 1, "int32": 4, "int16": 2,
+                "fp16s": 2}
 STORAGE_DTYPE = {"fp64": np.float64, "fp32": np.float32, "fp16": np.uint16, "bf16": np.uint16,
-                 "e4m3": np.uint8, "int32": np.int32, "int16": np.int16}
+                 "e4m3": np.uint8, "int32": np.int32, "int16": np.int16, "fp16s": np.uint16}
+# Arnoldi-step variants for ablations (bits of the options' `variant`)
+VARIANTS = {"spmv_vhat": 1, "always_reorth": 2, "mgs": 4}
 PRECONDS = {"none": 0, "jacobi": 1, "sparse": 2, "block_jacobi": 3}
 OK, NOT_CONVERGED, E_ARG, E_NONFINITE = 0, 1, -1, -4
 
@@ -43,7 +47,7 @@ class _Opts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("format", C.c_int32), ("tol", C.c_double),
                 ("maxiter", C.c_int64), ("eta", C.c_double), ("precond", C.c_int32),
                 ("p_val", C.c_void_p), ("fallback", C.c_int32), ("pc_block", C.c_int32),
-                ("pc_prec", C.c_int32)]
+                ("pc_prec", C.c_int32), ("variant", C.c_int32), ("pad", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -144,19 +148,25 @@ def block_jacobi(A, bs=4, prec_min=16):
 
 
 def gmres(A, b, x0=None, restart=100, fmt="fp64", tol=1e-10, maxiter=10000, eta=0.0,
-          precond="none", p_val=None, fallback=False, debug=False, pc_block=0, pc_prec=0):
+          precond="none", p_val=None, fallback=False, debug=False, pc_block=0, pc_prec=0,
+          variant=()):
     """Run the oracle solver. Returns a dict with x, status, counts, the
     recurrence-residual history and the explicit residual per cycle; with
     ``debug`` also the first cycle's decoded basis V (k x n) and its
-    Hessenberg matrix H ((m+1) x m, before Givens)."""
+    Hessenberg matrix H ((m+1) x m, before Givens).  ``variant``: names from
+    VARIANTS (ablations of the Arnoldi step; empty is Fig. 1 as written)."""
     n = A.n
     b = _f64(b)
     x = np.zeros(n) if x0 is None else _f64(x0).copy()
     pv = None
     if precond == "sparse":
         pv = np.ascontiguousarray(p_val, dtype=np.float32)
+    vbits = 0
+    for name in ((variant,) if isinstance(variant, str) else variant):
+        vbits |= VARIANTS[name]
     opts = _Opts(restart, FORMATS[fmt], tol, maxiter, eta, PRECONDS[precond],
-                 None if pv is None else pv.ctypes.data, int(bool(fallback)), pc_block, pc_prec)
+                 None if pv is None else pv.ctypes.data, int(bool(fallback)), pc_block, pc_prec,
+                 vbits, 0)
     res = _Result()
     hist = np.full(max(maxiter, 1), np.nan)
     cyc = np.full(max(maxiter, 1) + 2, np.nan)

@@ -59,6 +59,7 @@ int orc_format_bytes(int fmt)
     case ORC_E4M3: return 1;
     case ORC_INT32: return 4;
     case ORC_INT16: return 2;
+    case ORC_FP16S: return 2;
     default: return 0;
     }
 }
@@ -196,6 +197,25 @@ int orc_encode(int fmt, int64_t n, const double *v, void *q, double *scale)
             o[i] = (uint8_t)float_bits(round_to_p(ldexp(v[i], -k), E4M3.p, E4M3.emin), &E4M3);
         break;
     }
+    case ORC_FP16S: {
+        /* float16 with a per-vector power-of-two scale 2^k, max|v| * 2^-k in
+         * (32752, 65504]: the largest entry lands in the top binade and the
+         * small entries stay clear of the subnormal range.  Scaling by 2^-k
+         * is exact, so each entry is rounded once. */
+        double vinf = max_abs(n, v);
+        int k = 0;
+        if (vinf > 0.0) {
+            k = ilogb(vinf) - 15;
+            if (ldexp(vinf, -k) > 65504.0)
+                k += 1;
+        }
+        *scale = ldexp(1.0, k);
+        uint16_t *o = (uint16_t *)q;
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i)
+            o[i] = (uint16_t)float_bits(round_to_p(ldexp(v[i], -k), F16.p, F16.emin), &F16);
+        break;
+    }
     case ORC_INT32:
     case ORC_INT16: {
         /* Section 5.2: sigma = (||v||_inf / ||v||_2) / max_int for the raw
@@ -235,6 +255,7 @@ static void decode_range(int fmt, const void *q, double s, int64_t i0, int64_t i
     case ORC_E4M3: for (int64_t i = 0; i < m; ++i) out[i] = tab_e4m3[((const uint8_t *)q)[i0 + i]] * s; break;
     case ORC_INT32: for (int64_t i = 0; i < m; ++i) out[i] = s * (double)((const int32_t *)q)[i0 + i]; break;
     case ORC_INT16: for (int64_t i = 0; i < m; ++i) out[i] = s * (double)((const int16_t *)q)[i0 + i]; break;
+    case ORC_FP16S: for (int64_t i = 0; i < m; ++i) out[i] = tab_f16[((const uint16_t *)q)[i0 + i]] * s; break;
     }
 }
 
@@ -346,6 +367,22 @@ static void basis_combine(int fmt, int32_t j, void *const *Q, const double *sc, 
         }
         for (int64_t i = i0; i < i1; ++i)
             out[i] = acc[i - i0];
+    }
+}
+
+/* Modified Gram-Schmidt over the stored vectors (the ORC_V_MGS variant of
+ * steps 5 and 8): for k = 0..j-1 in order, h_k = dec(Q_k)^T w in the fixed
+ * block order of orc_dot, then w_i -= h_k dec(Q_k)_i.  buf: n doubles. */
+static void mgs_pass(int fmt, int32_t j, void *const *Q, const double *sc, int64_t n,
+                     double *w, double *h, double *buf)
+{
+    for (int32_t k = 0; k < j; ++k) {
+        orc_decode(fmt, n, Q[k], sc[k], buf);
+        h[k] = orc_dot(n, buf, w);
+        const double hk = h[k];
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i)
+            w[i] = w[i] - hk * buf[i];
     }
 }
 
@@ -526,6 +563,7 @@ int orc_gmres(int32_t n, const int32_t *rp, const int32_t *ci, const double *val
     const int bs = orc_format_bytes(fmt);
     if (n < 0 || m < 1 || bs == 0 || !(opt->tol >= 0.0) || opt->maxiter < 0 ||
         opt->precond < ORC_PC_NONE || opt->precond > ORC_PC_BLOCK_JACOBI ||
+        (opt->variant & ~(ORC_V_SPMV_VHAT | ORC_V_ALWAYS_REORTH | ORC_V_MGS)) != 0 ||
         (opt->precond == ORC_PC_SPARSE && !opt->p_val) ||
         (n > 0 && (!rp || !ci || !val || !b || !x))) {
         res->status = ORC_E_ARG;
@@ -540,6 +578,9 @@ int orc_gmres(int32_t n, const int32_t *rp, const int32_t *ci, const double *val
     }
     const double eta = opt->eta > 0.0 ? opt->eta : ETA_DEFAULT;
     const double tau = opt->tol;
+    const int spmv_vhat = (opt->variant & ORC_V_SPMV_VHAT) != 0;
+    const int always_reorth = (opt->variant & ORC_V_ALWAYS_REORTH) != 0;
+    const int mgs = (opt->variant & ORC_V_MGS) != 0;
 
     /* Fig. 1 works with ||b||_2 as the reference of the stop test (R8). */
     const double nb = sqrt(orc_dot(n, b, b));
@@ -676,27 +717,38 @@ int orc_gmres(int32_t n, const int32_t *rp, const int32_t *ci, const double *val
             const int32_t jc = j - 1;            /* 0-based column */
             /* Step 3: w = A M^{-1} v, with v the FP64 vector of step 13
              * (reading R3: the accessor is named for steps 5, 8, 13-14 and
-             * 17, not for step 3). */
+             * 17, not for step 3).  The SPMV_VHAT variant reads the stored
+             * vector back through the accessor instead. */
+            if (spmv_vhat)
+                orc_decode(fmt, n, Q[jc], sc[jc], v);
             apply_precond(&M, n, rp, ci, v, z);
             orc_spmv(n, rp, ci, val, z, w);
             /* Step 4 */
             double omega = sqrt(orc_dot(n, w, w));
             /* Step 5: h = V_j^T w; w = w - V_j h, V_j widened from storage. */
-            multidot(fmt, j, Q, sc, n, w, h, part);
-            basis_combine(fmt, j, Q, sc, n, h, s);
-#pragma omp parallel for schedule(static)
-            for (int32_t i = 0; i < n; ++i)
-                w[i] = w[i] - s[i];
-            /* Step 6 */
-            double t = sqrt(orc_dot(n, w, w));
-            int brk;
-            if (t < eta * omega) {
-                /* Steps 8-10: one more CGS pass. */
-                multidot(fmt, j, Q, sc, n, w, u, part);
-                basis_combine(fmt, j, Q, sc, n, u, s);
+            if (mgs) {
+                mgs_pass(fmt, j, Q, sc, n, w, h, s);
+            } else {
+                multidot(fmt, j, Q, sc, n, w, h, part);
+                basis_combine(fmt, j, Q, sc, n, h, s);
 #pragma omp parallel for schedule(static)
                 for (int32_t i = 0; i < n; ++i)
                     w[i] = w[i] - s[i];
+            }
+            /* Step 6 */
+            double t = sqrt(orc_dot(n, w, w));
+            int brk;
+            if (always_reorth || t < eta * omega) {
+                /* Steps 8-10: one more CGS (or MGS) pass. */
+                if (mgs) {
+                    mgs_pass(fmt, j, Q, sc, n, w, u, s);
+                } else {
+                    multidot(fmt, j, Q, sc, n, w, u, part);
+                    basis_combine(fmt, j, Q, sc, n, u, s);
+#pragma omp parallel for schedule(static)
+                    for (int32_t i = 0; i < n; ++i)
+                        w[i] = w[i] - s[i];
+                }
                 for (int32_t k = 0; k < j; ++k)
                     h[k] = h[k] + u[k];
                 double t2 = sqrt(orc_dot(n, w, w));

@@ -23,11 +23,23 @@ extern "C" {
 #endif
 
 /* Storage formats of the basis (Section 5.2 lists float64, float32, float16,
- * int32, int16; bf16 and e4m3 are extensions defined the same way). */
+ * int32, int16; bf16, e4m3 and the scaled float16 are extensions defined the
+ * same way). */
 enum {
     ORC_FP64 = 0, ORC_FP32 = 1, ORC_FP16 = 2, ORC_BF16 = 3,
-    ORC_E4M3 = 4, ORC_INT32 = 5, ORC_INT16 = 6
+    ORC_E4M3 = 4, ORC_INT32 = 5, ORC_INT16 = 6, ORC_FP16S = 7
 };
+
+/* Variants of the Arnoldi step for numerical ablations (bits of
+ * orc_opts.variant; 0 is Fig. 1 as written):
+ *   ORC_V_SPMV_VHAT     step 3 multiplies by the decoded stored vector
+ *                       dec(v^_j) instead of the FP64 v_j;
+ *   ORC_V_ALWAYS_REORTH step 7's test is replaced by "always" (CGS2); the
+ *                       breakdown test of step 12 is unchanged;
+ *   ORC_V_MGS           modified Gram-Schmidt: steps 5 and 8 project out
+ *                       one stored vector at a time, h_k = dec(v^_k)^T w
+ *                       followed by w -= h_k dec(v^_k), k = 1..j in order. */
+enum { ORC_V_SPMV_VHAT = 1, ORC_V_ALWAYS_REORTH = 2, ORC_V_MGS = 4 };
 
 enum { ORC_PC_NONE = 0, ORC_PC_JACOBI = 1, ORC_PC_SPARSE = 2, ORC_PC_BLOCK_JACOBI = 3 };
 
@@ -37,8 +49,9 @@ enum { ORC_OK = 0, ORC_NOT_CONVERGED = 1, ORC_E_ARG = -1, ORC_E_NONFINITE = -4 }
 int orc_format_bytes(int fmt);
 
 /* Encode n entries of v into q (orc_format_bytes(fmt)*n bytes) and the
- * per-vector scale.  Scale meaning: fp64/fp32/fp16/bf16: 1; e4m3: 2^k; int:
- * sigma = max|v| / max_int.  Returns 0, or ORC_E_ARG. */
+ * per-vector scale.  Scale meaning: fp64/fp32/fp16/bf16: 1; e4m3: 2^k with
+ * max|v| 2^-k in (224, 448]; fp16s: 2^k with max|v| 2^-k in (32752, 65504];
+ * int: sigma = max|v| / max_int.  Returns 0, or ORC_E_ARG. */
 int orc_encode(int fmt, int64_t n, const double *v, void *q, double *scale);
 /* Widen n stored entries to FP64. */
 int orc_decode(int fmt, int64_t n, const void *q, double scale, double *out);
@@ -61,6 +74,8 @@ typedef struct {
     int32_t pc_block;         /* ORC_PC_BLOCK_JACOBI: block size 1..8 (0: 4) */
     int32_t pc_prec;          /* ORC_PC_BLOCK_JACOBI: lowest storage precision 16, 32
                                  or 64 bits (0: 16) */
+    int32_t variant;          /* ORC_V_* bits (0: Fig. 1 as written) */
+    int32_t pad;
 } orc_opts;
 
 typedef struct {
