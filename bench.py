@@ -56,7 +56,8 @@ def pmc_summary(fetch_csv: str, write_csv: str, fmt: str, grid: int) -> dict:
     same counter reads for the plain 256 MiB elementwise pass (torch.neg)
     that `bench.py --calib-copy` runs first."""
     import csv
-    fmt_id = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "e4m3": 4, "int32": 5, "int16": 6}[fmt]
+    fmt_id = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "e4m3": 4, "int32": 5, "int16": 6,
+              "fp16s": 7}[fmt]
     kname = f"k_multidot<{fmt_id}>"
 
     def read(path, counter):

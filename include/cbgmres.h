@@ -34,17 +34,20 @@ extern "C" {
 #endif
 
 /* Storage format of the Krylov basis (Section 5.2 lists float64, float32,
- * float16, int32 and int16; bf16 and fp8 e4m3 are extensions stored the same
- * way).  Bytes per entry: 8, 4, 2, 2, 1, 4, 2.
+ * float16, int32 and int16; bf16, fp8 e4m3 and the scaled float16 are
+ * extensions stored the same way).  Bytes per entry: 8, 4, 2, 2, 1, 4, 2, 2.
  *   CBG_FP32/FP16/BF16: one round-to-nearest-even conversion from FP64.
  *   CBG_E4M3 (OCP E4M3FN): per-vector power-of-two scale 2^k chosen so that
  *     max|v| * 2^-k lies in (224, 448]; entries RNE(v_i * 2^-k).
+ *   CBG_FP16S: float16 with a per-vector power-of-two scale 2^k chosen so
+ *     that max|v| * 2^-k lies in (32752, 65504]; entries RNE(v_i * 2^-k), so
+ *     entries far below the largest keep float16's relative precision.
  *   CBG_INT32/INT16: fixed point with per-vector scale
  *     sigma = max|v| / max_int (the scale of Section 5.2 for a unit vector);
  *     entries rint(v_i / sigma) clamped to [-max_int, max_int]. */
 typedef enum {
     CBG_FP64 = 0, CBG_FP32 = 1, CBG_FP16 = 2, CBG_BF16 = 3,
-    CBG_E4M3 = 4, CBG_INT32 = 5, CBG_INT16 = 6
+    CBG_E4M3 = 4, CBG_INT32 = 5, CBG_INT16 = 6, CBG_FP16S = 7
 } cbg_format;
 
 /* Right preconditioner M^{-1} of Fig. 1 steps 3 and 17. */
@@ -113,6 +116,16 @@ typedef struct {
 /* time only the multi-dot launches with HIP events (cbg_result.prof_dot_*;
  * one event pair per launch instead of four per step) */
 #define CBG_FLAG_PROFILE_DOT 4
+/* Ablations of the Arnoldi step (numerical studies; off by default).
+ * SPMV_VHAT: step 3 multiplies by the stored vector read back, dec(v^_j),
+ * instead of the FP64 v_j that step 13 formed (the solver's default, which
+ * takes the accessor to serve steps 5, 8, 13-14 and 17 only).
+ * ALWAYS_REORTH: re-orthogonalise on every step (CGS2) instead of only when
+ * step 7's test h_{j+1,j} < eta * omega fires; the breakdown test is
+ * unchanged. */
+#define CBG_FLAG_SPMV_VHAT 8
+#define CBG_FLAG_ALWAYS_REORTH 16
+#define CBG_FLAG_ALL 31     /* any other bit is an argument error */
 
 typedef struct {
     int64_t iterations;        /* Arnoldi steps (SpMVs with A inside cycles) */

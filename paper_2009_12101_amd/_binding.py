@@ -15,14 +15,20 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcbgmres.so")
 
-FORMATS = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "e4m3": 4, "int32": 5, "int16": 6}
-FORMAT_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2, "e4m3": 1, "int32": 4, "int16": 2}
+FORMATS = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "e4m3": 4, "int32": 5, "int16": 6,
+           "fp16s": 7}
+FORMAT_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2, "e4m3": 1, "int32": 4, "int16": 2,
+                "fp16s": 2}
 PRECONDS = {"none": 0, "jacobi": 1, "sparse": 2, "block_jacobi": 3}
 OK, NOT_CONVERGED = 0, 1
 E_ARG, E_WORKSPACE, E_HIP, E_NONFINITE, E_UNSUPPORTED = -1, -2, -3, -4, -5
 FLAG_PROFILE = 1
 FLAG_NO_FUSE = 2
 FLAG_PROFILE_DOT = 4
+FLAG_SPMV_VHAT = 8
+FLAG_ALWAYS_REORTH = 16
+# Arnoldi-step ablations by name (solve(..., variant=...))
+VARIANTS = {"spmv_vhat": FLAG_SPMV_VHAT, "always_reorth": FLAG_ALWAYS_REORTH}
 MAX_RESTART = 512
 
 EXPORTS = ["cbg_strerror", "cbg_basis_ld", "cbg_workspace_bytes", "cbg_kernel_workspace_bytes",
@@ -225,10 +231,11 @@ class SolveResult:
 
 def solve(A: DeviceCSR, b, x0=None, restart=100, fmt="fp64", tol=1e-10, maxiter=10000,
           eta=0.0, precond="none", p_val=None, fallback=False, profile=False, workspace=None,
-          hist=True, fuse=True, pc_block=0, pc_prec=0) -> SolveResult:
+          hist=True, fuse=True, pc_block=0, pc_prec=0, variant=()) -> SolveResult:
     """cbgmres_solve on device tensors; returns the solution and counters.
     profile: False, True (event-time every basis-streaming launch) or "dot"
-    (only the multi-dot launches).  Raises CbgError on a negative status."""
+    (only the multi-dot launches).  variant: names from VARIANTS (ablations
+    of the Arnoldi step).  Raises CbgError on a negative status."""
     torch = _torch()
     x = torch.zeros(A.n, dtype=torch.float64, device=b.device) if x0 is None else x0.clone()
     need = workspace_bytes(A.n, restart, fmt, precond)
@@ -236,10 +243,13 @@ def solve(A: DeviceCSR, b, x0=None, restart=100, fmt="fp64", tol=1e-10, maxiter=
         raise CbgError(E_ARG, "cbg_workspace_bytes")
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=b.device)
+    flags = {False: 0, True: FLAG_PROFILE, "dot": FLAG_PROFILE_DOT}[profile] \
+        | (0 if fuse else FLAG_NO_FUSE)
+    for name in ((variant,) if isinstance(variant, str) else variant):
+        flags |= VARIANTS[name]
     opts = CbgOpts(restart, FORMATS[fmt], tol, maxiter, eta, PRECONDS[precond],
                    int(bool(fallback)), None if p_val is None else p_val.data_ptr(),
-                   {False: 0, True: FLAG_PROFILE, "dot": FLAG_PROFILE_DOT}[profile]
-                   | (0 if fuse else FLAG_NO_FUSE), 0, pc_block, pc_prec)
+                   flags, 0, pc_block, pc_prec)
     res = CbgResult()
     hl = int(maxiter) if hist else 0
     h = np.zeros(max(hl, 1))
@@ -271,7 +281,8 @@ def encode(fmt: str, v, out=None, scale=None, ws=None):
     torch = _torch()
     n = v.numel()
     dt = {"fp64": torch.float64, "fp32": torch.float32, "fp16": torch.int16, "bf16": torch.int16,
-          "e4m3": torch.uint8, "int32": torch.int32, "int16": torch.int16}[fmt]
+          "e4m3": torch.uint8, "int32": torch.int32, "int16": torch.int16,
+          "fp16s": torch.int16}[fmt]
     q = torch.empty(n, dtype=dt, device=v.device) if out is None else out
     sc = torch.empty(1, dtype=torch.float64, device=v.device) if scale is None else scale
     ws = _kws(n, 0, v.device) if ws is None else ws

@@ -28,7 +28,8 @@ typedef double f64x2 __attribute__((ext_vector_type(2)));
 // chunk index is contiguous.
 // ---------------------------------------------------------------------------
 
-enum { F_FP64 = 0, F_FP32 = 1, F_FP16 = 2, F_BF16 = 3, F_E4M3 = 4, F_INT32 = 5, F_INT16 = 6 };
+enum { F_FP64 = 0, F_FP32 = 1, F_FP16 = 2, F_BF16 = 3, F_E4M3 = 4, F_INT32 = 5, F_INT16 = 6,
+       F_FP16S = 7 };
 
 __host__ __device__ constexpr int fmt_bytes(int f)
 {
@@ -77,8 +78,8 @@ __device__ __forceinline__ double dec_e4m3(uint32_t c)
 
 // Encoding parameters of one stored vector, derived from its scale.
 struct EncParam {
-    double scale;   // e4m3: 2^k ; int: sigma ; else 1
-    int k;          // e4m3 exponent
+    double scale;   // e4m3, fp16s: 2^k ; int: sigma ; else 1
+    int k;          // e4m3, fp16s exponent
 };
 
 template <int F> struct Fmt;
@@ -129,10 +130,11 @@ template <> struct Fmt<F_FP32> {
 #endif
 template <int F> struct Fmt16 {
     static constexpr int VW = 8, CH = CBG_CH16, KC = CBG_KC16, UNR = CBG_UNR16;
-    static constexpr bool SCALED = (F == F_INT16);
+    static constexpr bool SCALED = (F == F_INT16 || F == F_FP16S);
     __device__ static double one(uint32_t c, double s)
     {
         if constexpr (F == F_FP16) return dec_f16(c);
+        else if constexpr (F == F_FP16S) return dec_f16(c) * s;   // s = 2^k: exact
         else if constexpr (F == F_BF16) return dec_bf16(c);
         else return s * (double)(int16_t)(uint16_t)c;
     }
@@ -148,7 +150,10 @@ template <int F> struct Fmt16 {
     __device__ static uint32_t code(double v, EncParam p)
     {
         if constexpr (F == F_FP16) return rne_code<10, -14, 15>(v) | (sign_of(v) << 15);
-        else if constexpr (F == F_BF16) return rne_code<7, -126, 127>(v) | (sign_of(v) << 15);
+        else if constexpr (F == F_FP16S) {
+            const double x = ldexp(v, -p.k);                           // exact
+            return rne_code<10, -14, 15>(x) | (sign_of(x) << 15);
+        } else if constexpr (F == F_BF16) return rne_code<7, -126, 127>(v) | (sign_of(v) << 15);
         else {
             double t = p.scale > 0.0 ? rint(v / p.scale) : 0.0;
             t = fmin(fmax(t, -32767.0), 32767.0);
@@ -168,6 +173,7 @@ template <int F> struct Fmt16 {
 template <> struct Fmt<F_FP16> : Fmt16<F_FP16> {};
 template <> struct Fmt<F_BF16> : Fmt16<F_BF16> {};
 template <> struct Fmt<F_INT16> : Fmt16<F_INT16> {};
+template <> struct Fmt<F_FP16S> : Fmt16<F_FP16S> {};
 
 template <> struct Fmt<F_INT32> {
     static constexpr int VW = 4, CH = 2, KC = 8, UNR = 4;
@@ -220,7 +226,8 @@ template <> struct Fmt<F_E4M3> {
 };
 
 // Scale of a unit vector whose largest magnitude is vinf (Section 5.2 for
-// the integer formats; the power-of-two rule for e4m3).
+// the integer formats; the power-of-two rules for e4m3, max|v| 2^-k in
+// (224, 448], and the scaled float16, max|v| 2^-k in (32752, 65504]).
 __device__ inline EncParam make_param(int f, double vinf)
 {
     EncParam p{1.0, 0};
@@ -237,6 +244,15 @@ __device__ inline EncParam make_param(int f, double vinf)
         }
         p.k = k;
         p.scale = ldexp(1.0, k);
+    } else if (f == F_FP16S) {
+        int k = 0;
+        if (vinf > 0.0) {
+            k = ilogb(vinf) - 15;
+            if (ldexp(vinf, -k) > 65504.0)
+                k += 1;
+        }
+        p.k = k;
+        p.scale = ldexp(1.0, k);
     }
     return p;
 }
@@ -244,7 +260,7 @@ __device__ inline EncParam make_param(int f, double vinf)
 __device__ __forceinline__ EncParam param_from_scale(int f, double s)
 {
     EncParam p{s, 0};
-    if (f == F_E4M3)
+    if (f == F_E4M3 || f == F_FP16S)
         p.k = ilogb(s);
     return p;
 }
@@ -358,7 +374,7 @@ struct DevState {
     int32_t done;       // cycle finished: later step kernels do nothing
     int32_t jeff;       // steps taken in this cycle
     int32_t jprev;      // steps taken in the previous cycle
-    int32_t pad1;
+    int32_t reorth_all; // re-orthogonalise on every step (CGS2 ablation)
     int32_t reorth;     // the current step re-orthogonalises
     int32_t conv;       // recurrence residual met the tolerance
     double beta;        // ||r||_2 at the cycle start

@@ -187,7 +187,7 @@ __device__ void finish_step(DevState *st, const StepArrays &a, int j, bool reort
 // ---------------------------------------------------------------------------
 
 __global__ void k_init_state(DevState *st, int n, int m, int fmt, double tol, double eta,
-                             int64_t maxiter)
+                             int64_t maxiter, int reorth_all)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         DevState s{};
@@ -196,6 +196,7 @@ __global__ void k_init_state(DevState *st, int n, int m, int fmt, double tol, do
         s.fmt = fmt;
         s.eta = eta;
         s.maxiter = maxiter;
+        s.reorth_all = reorth_all;
         s.tau_nb = tol;       // scaled by ||b|| once it is known
         *st = s;
     }
@@ -262,7 +263,13 @@ enum {
     // for its own rows (step 14) while it computes A M^-1 v (step 3)
     SP_STEP_PLAIN = 8 | SP_PLAIN,
     SP_STEP_JACOBI = 8 | SP_JACOBI,
-    SP_STEP_FLOATVAL = 8 | SP_FLOATVAL
+    SP_STEP_FLOATVAL = 8 | SP_FLOATVAL,
+    // ablation: the step variants multiply by dec(enc(v)), the stored vector
+    // read back, instead of the FP64 v
+    SP_QUANT = 16,
+    SP_STEP_PLAIN_Q = SP_QUANT | SP_STEP_PLAIN,
+    SP_STEP_JACOBI_Q = SP_QUANT | SP_STEP_JACOBI,
+    SP_STEP_FLOATVAL_Q = SP_QUANT | SP_STEP_FLOATVAL
 };
 // roles: SR_NONE no partials (skipped once the cycle is done); SR_STEP
 // partials of ||y||^2 and max|y_i| (skipped once done); SR_FREE partials,
@@ -270,28 +277,7 @@ enum {
 enum { SR_NONE = 0, SR_STEP = 1, SR_FREE = 2 };
 
 constexpr bool sp_step(int mode) { return (mode & 8) != 0; }
-
-template <int MODE>
-__device__ __forceinline__ double spmv_term(int p, const int32_t *__restrict__ ci,
-                                            const double *__restrict__ val,
-                                            const float *__restrict__ fval,
-                                            const double *__restrict__ x,
-                                            const double *__restrict__ dinv, double tdiv)
-{
-    constexpr int BASE = MODE & 7;
-    const int c = ci[p];
-    double a;
-    if constexpr (BASE == SP_FLOATVAL || BASE == SP_ACCUM)
-        a = (double)fval[p];
-    else
-        a = val[p];
-    double xv = x[c];
-    if constexpr (sp_step(MODE))
-        xv = xv / tdiv;
-    if constexpr (BASE == SP_JACOBI)
-        xv = dinv[c] * xv;
-    return a * xv;
-}
+constexpr bool sp_quant(int mode) { return (mode & SP_QUANT) != 0; }
 
 // Store entry i of a vector through the accessor (one entry; the vector's
 // scale parameters in p).
@@ -305,8 +291,50 @@ __device__ __forceinline__ void store_entry(int fmt, uint8_t *__restrict__ Q, in
     case F_BF16: ((uint16_t *)Q)[i] = (uint16_t)Fmt<F_BF16>::code(v, p); break;
     case F_E4M3: Q[i] = (uint8_t)Fmt<F_E4M3>::code(v, p); break;
     case F_INT32: ((uint32_t *)Q)[i] = Fmt<F_INT32>::code(v, p); break;
+    case F_FP16S: ((uint16_t *)Q)[i] = (uint16_t)Fmt<F_FP16S>::code(v, p); break;
     default: ((uint16_t *)Q)[i] = (uint16_t)Fmt<F_INT16>::code(v, p); break;
     }
+}
+
+// dec(enc(v)): the value entry v reads back as once stored with the vector's
+// scale parameters p (the SpMV-on-the-stored-vector ablation).
+__device__ __forceinline__ double quantize(int fmt, double v, EncParam p)
+{
+    switch (fmt) {
+    case F_FP64: return v;
+    case F_FP32: return (double)(float)v;
+    case F_FP16: return Fmt<F_FP16>::one(Fmt<F_FP16>::code(v, p), p.scale);
+    case F_BF16: return Fmt<F_BF16>::one(Fmt<F_BF16>::code(v, p), p.scale);
+    case F_E4M3: return dec_e4m3(Fmt<F_E4M3>::code(v, p)) * p.scale;
+    case F_INT32: return p.scale * (double)(int32_t)Fmt<F_INT32>::code(v, p);
+    case F_FP16S: return Fmt<F_FP16S>::one(Fmt<F_FP16S>::code(v, p), p.scale);
+    default: return Fmt<F_INT16>::one(Fmt<F_INT16>::code(v, p), p.scale);
+    }
+}
+
+template <int MODE>
+__device__ __forceinline__ double spmv_term(int p, const int32_t *__restrict__ ci,
+                                            const double *__restrict__ val,
+                                            const float *__restrict__ fval,
+                                            const double *__restrict__ x,
+                                            const double *__restrict__ dinv, double tdiv,
+                                            int fmt, EncParam ep)
+{
+    constexpr int BASE = MODE & 7;
+    const int c = ci[p];
+    double a;
+    if constexpr (BASE == SP_FLOATVAL || BASE == SP_ACCUM)
+        a = (double)fval[p];
+    else
+        a = val[p];
+    double xv = x[c];
+    if constexpr (sp_step(MODE))
+        xv = xv / tdiv;
+    if constexpr (sp_quant(MODE))
+        xv = quantize(fmt, xv, ep);
+    if constexpr (BASE == SP_JACOBI)
+        xv = dinv[c] * xv;
+    return a * xv;
 }
 
 template <int RPB, int CAP, int MODE>
@@ -352,7 +380,7 @@ __global__ __launch_bounds__(BLK) void k_spmv(int n, int64_t ldy, const int32_t 
 #pragma unroll
                 for (int u = 0; u < UNR; ++u) {
                     const int qq = min(q + u * BLK, cnt - 1);      // clamped: loads stay in bounds
-                    v[u] = spmv_term<MODE>(p0 + qq, ci, val, fval, x, dinv, tdiv);
+                    v[u] = spmv_term<MODE>(p0 + qq, ci, val, fval, x, dinv, tdiv, fmt, ep);
                 }
 #pragma unroll
                 for (int u = 0; u < UNR; ++u)
@@ -371,7 +399,7 @@ __global__ __launch_bounds__(BLK) void k_spmv(int n, int64_t ldy, const int32_t 
                     s += prod[q];
             } else {
                 for (int q = a0 + part; q < a1; q += TPR)
-                    s += spmv_term<MODE>(p0 + q, ci, val, fval, x, dinv, tdiv);
+                    s += spmv_term<MODE>(p0 + q, ci, val, fval, x, dinv, tdiv, fmt, ep);
             }
         }
 #pragma unroll
@@ -707,6 +735,7 @@ template <int F> struct Lane8_16 {
 template <> struct Lane8<F_FP16> : Lane8_16<F_FP16> {};
 template <> struct Lane8<F_BF16> : Lane8_16<F_BF16> {};
 template <> struct Lane8<F_INT16> : Lane8_16<F_INT16> {};
+template <> struct Lane8<F_FP16S> : Lane8_16<F_FP16S> {};
 template <> struct Lane8<F_E4M3> {
     static constexpr int LW = 8;
     __device__ static void dec(u32x2 q, double s, double *d)
@@ -1035,7 +1064,8 @@ __global__ __launch_bounds__(BLK) void k_bj_apply(int n, int64_t ldq, int bs,
                                                   const double *__restrict__ w,
                                                   double *__restrict__ z, int accumulate,
                                                   const DevState *st, uint8_t *__restrict__ Q,
-                                                  const double *__restrict__ qscale, int fmt)
+                                                  const double *__restrict__ qscale, int fmt,
+                                                  int quant)
 {
     double t = 1.0;
     EncParam ep{1.0, 0};
@@ -1058,7 +1088,9 @@ __global__ __launch_bounds__(BLK) void k_bj_apply(int n, int64_t ldq, int bs,
         const size_t o = (size_t)b * bs * bs + (size_t)(i - i0) * bs;
         double s = 0.0;
         for (int l = 0; l < sz; ++l) {
-            const double v = st ? w[i0 + l] / t : w[i0 + l];
+            double v = st ? w[i0 + l] / t : w[i0 + l];
+            if (quant)
+                v = quantize(fmt, v, ep);
             s = fma(bj_entry(tag, o + l, x64, x32, x16), v, s);
         }
         z[i] = accumulate ? z[i] + s : s;
@@ -1250,7 +1282,7 @@ __global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth
         // Fig. 1 steps 6-7; without re-orthogonalisation the step ends here
         // (finish_step needs h, which the previous kernel stored, not u)
         const double t = sqrt(sv[0]);
-        const bool ro = t < st->eta * st->omega;
+        const bool ro = st->reorth_all || t < st->eta * st->omega;
         __syncthreads();
         if (tid == 0) {
             st->t = t;
@@ -1406,6 +1438,9 @@ static int spmv_shape(const SpmvArgs &a, hipStream_t s)
         CBG_SPMV_CASE(SP_STEP_PLAIN)
         CBG_SPMV_CASE(SP_STEP_JACOBI)
         CBG_SPMV_CASE(SP_STEP_FLOATVAL)
+        CBG_SPMV_CASE(SP_STEP_PLAIN_Q)
+        CBG_SPMV_CASE(SP_STEP_JACOBI_Q)
+        CBG_SPMV_CASE(SP_STEP_FLOATVAL_Q)
     }
 #undef CBG_SPMV_CASE
     return g;
@@ -1434,6 +1469,7 @@ static int tile_elems() { return BLK * Fmt<F>::VW * Fmt<F>::CH; }
     case F_BF16: { constexpr int F = F_BF16; CALL; } break; \
     case F_E4M3: { constexpr int F = F_E4M3; CALL; } break; \
     case F_INT32: { constexpr int F = F_INT32; CALL; } break; \
+    case F_FP16S: { constexpr int F = F_FP16S; CALL; } break; \
     default: { constexpr int F = F_INT16; CALL; } break;    \
     }
 
@@ -1459,11 +1495,12 @@ int launch_bj_setup(int n, const int32_t *rp, const int32_t *ci, const double *v
 void launch_bj_apply(int n, int64_t ldq, int bs, const int8_t *tags, const double *x64,
                      const float *x32, const uint16_t *x16, const double *w, double *z,
                      int accumulate, const DevState *st, void *Q, const double *qscale, int fmt,
-                     hipStream_t s)
+                     int quant, hipStream_t s)
 {
     const int64_t rows = st ? ldq : n;
     k_bj_apply<<<grid_for(rows, BLK), BLK, 0, s>>>(n, ldq, bs, tags, x64, x32, x16, w, z,
-                                                    accumulate, st, (uint8_t *)Q, qscale, fmt);
+                                                    accumulate, st, (uint8_t *)Q, qscale, fmt,
+                                                    st ? quant : 0);
 }
 
 int orth_grid(int fmt, int64_t n)
@@ -1521,7 +1558,8 @@ template <int F, int JM>
 static void fused_launch(const OrthArgs &a, int g, const RedArgs &ra, const uint8_t *V,
                          hipStream_t s)
 {
-    if constexpr (F == F_E4M3 || (F == F_BF16 && JM > 48) || (F == F_INT16 && JM > 80)) {
+    if constexpr (F == F_E4M3 || (F == F_BF16 && JM > 48) ||
+                  ((F == F_INT16 || F == F_FP16S) && JM > 80)) {
         return;              // not instantiated: beyond the format's fused range
     } else if (a.ev0) {
         hipExtLaunchKernelGGL(k_update_redot<F, JM>, dim3(g), dim3(BLK), 0, s, a.ev0, a.ev1, 0,
@@ -1547,6 +1585,7 @@ int fused_jmax(int fmt)
     switch (fmt) {
     case F_BF16: return 48;
     case F_INT16: return 80;
+    case F_FP16S: return 80;        // decoded like int16: one scale product per entry
     case F_E4M3: return 0;
     default: return FUSED_JMAX;
     }
@@ -1620,9 +1659,9 @@ int launch_norm(const double *x, int64_t n, const RedWs &ws, hipStream_t s)
 }
 
 void launch_init_state(DevState *st, int n, int m, int fmt, double tol, double eta,
-                       int64_t maxiter, hipStream_t s)
+                       int64_t maxiter, int reorth_all, hipStream_t s)
 {
-    k_init_state<<<1, 64, 0, s>>>(st, n, m, fmt, tol, eta, maxiter);
+    k_init_state<<<1, 64, 0, s>>>(st, n, m, fmt, tol, eta, maxiter, reorth_all);
 }
 
 void launch_jacobi_setup(int n, int64_t ld, const int32_t *rp, const int32_t *ci,

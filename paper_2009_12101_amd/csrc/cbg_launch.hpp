@@ -72,11 +72,11 @@ int launch_bj_setup(int n, const int32_t *rp, const int32_t *ci, const double *v
                     int prec_min, int8_t *tags, double *x64, float *x32, uint16_t *x16,
                     unsigned *bad, hipStream_t s);
 // With st: v = w / t stored as basis vector (Q, qscale) for rows < ldq and
-// z = M^-1 v; without: z (+)= M^-1 w.
+// z = M^-1 v (z = M^-1 dec(enc(v)) with quant); without: z (+)= M^-1 w.
 void launch_bj_apply(int n, int64_t ldq, int bs, const int8_t *tags, const double *x64,
                      const float *x32, const uint16_t *x16, const double *w, double *z,
                      int accumulate, const DevState *st, void *Q, const double *qscale, int fmt,
-                     hipStream_t s);
+                     int quant, hipStream_t s);
 int fused_jmax(int fmt);   // largest j launch_update_redot takes
 // Whether launch_update_redot takes step j for basis vectors of leading
 // dimension ld (the one predicate the solver and the launcher share).
@@ -89,7 +89,7 @@ void launch_normalize(int fmt, const double *w, int n, int64_t nst, double *v_ou
 void launch_decode(int fmt, const void *Q, int n, const double *scale, double *v, hipStream_t s);
 int launch_norm(const double *x, int64_t n, const RedWs &ws, hipStream_t s);
 void launch_init_state(DevState *st, int n, int m, int fmt, double tol, double eta,
-                       int64_t maxiter, hipStream_t s);
+                       int64_t maxiter, int reorth_all, hipStream_t s);
 void launch_jacobi_setup(int n, int64_t ld, const int32_t *rp, const int32_t *ci,
                          const double *val, double *dinv, unsigned *bad, hipStream_t s);
 void launch_clear_flags(DevState *st, unsigned *bad, hipStream_t s);

@@ -24,7 +24,7 @@ constexpr double ETA_DEFAULT = 0.70710678118654752440;   // 1/sqrt(2), nearest d
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
-bool valid_format(int f) { return f >= CBG_FP64 && f <= CBG_INT16; }
+bool valid_format(int f) { return f >= CBG_FP64 && f <= CBG_FP16S; }
 
 int64_t basis_ld(int32_t n) { return ((int64_t)n + 255) / 256 * 256; }
 
@@ -232,7 +232,8 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
     const int fmt = opt->format, pc0 = opt->precond;
     if (n < 0 || A->nnz < 0 || m < 1 || m > CBG_MAX_RESTART || !valid_format(fmt) ||
         !(opt->tol >= 0.0) || !isfinite(opt->tol) || opt->maxiter < 0 || pc0 < CBG_PC_NONE ||
-        pc0 > CBG_PC_BLOCK_JACOBI || (hist_len > 0 && !hist_out) || hist_len < 0)
+        pc0 > CBG_PC_BLOCK_JACOBI || (hist_len > 0 && !hist_out) || hist_len < 0 ||
+        (opt->flags & ~CBG_FLAG_ALL) != 0)
         return fail(CBG_E_ARG);
     const int bj_bs = opt->pc_block > 0 ? opt->pc_block : 4;
     const int bj_prec = opt->pc_prec > 0 ? opt->pc_prec : 16;
@@ -263,6 +264,9 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
     // re-dot), 2 re-dot multi-dot, 3 re-orthogonalising update
     auto profiled = [&](int k) { return prof_all || k % 2 == 0; };
     const bool fuse = (opt->flags & CBG_FLAG_NO_FUSE) == 0;
+    // ablations of the Arnoldi step
+    const int vhat = (opt->flags & CBG_FLAG_SPMV_VHAT) ? 1 : 0;
+    const int reorth_all = (opt->flags & CBG_FLAG_ALWAYS_REORTH) ? 1 : 0;
     // steps whose update and re-dot share one basis pass
     auto fused = [&](int j) { return fuse && fused_takes(fmt, basis_ld(n), j); };
     ByteModel bm{(double)n, (double)A->nnz, (double)fmt_bytes(fmt)};
@@ -274,7 +278,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
     // set-up: initialise the state, ||b||
     const int nb_orth = orth_grid(fmt, n);
     launch_clear_flags(nullptr, W.bad, s);
-    launch_init_state(W.st, n, m, fmt, opt->tol, eta, opt->maxiter, s);
+    launch_init_state(W.st, n, m, fmt, opt->tol, eta, opt->maxiter, reorth_all, s);
     {
         const int g = launch_norm(b, n, W.red, s);
         launch_reduce(W.red, RR_NB, 0, g, 0, W.st, sa, nullptr, fmt, s);
@@ -450,7 +454,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
             if (pc == CBG_PC_BLOCK_JACOBI) {
                 // v_j = w / t stored, z = M^-1 v_j; then w = A z, omega
                 launch_bj_apply(n, ld, bj_bs, W.bj_tags, W.bj64, W.bj32, W.bj16, cur, W.z, 0,
-                                W.st, slot, W.scales + (j - 1), fmt, s);
+                                W.st, slot, W.scales + (j - 1), fmt, vhat, s);
                 SpmvArgs b2{};
                 b2.n = n; b2.ldy = ld; b2.rp = A->row_ptr; b2.ci = A->col_idx; b2.val = A->val;
                 b2.x = W.z; b2.y = nxt; b2.ws = W.red; b2.mode = 0 /*SP_PLAIN*/;
@@ -459,7 +463,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
             } else if (pc == CBG_PC_SPARSE) {
                 SpmvArgs a{};
                 a.n = n; a.ldy = ld; a.rp = A->row_ptr; a.ci = A->col_idx; a.fval = opt->p_val;
-                a.x = cur; a.y = W.z; a.ws = W.red; a.mode = 8 | 3 /*SP_STEP_FLOATVAL*/;
+                a.x = cur; a.y = W.z; a.ws = W.red; a.mode = (vhat << 4) | 8 | 3 /*SP_STEP_FLOATVAL*/;
                 a.role = 0 /*SR_NONE*/; a.sg = sg; a.st = W.st;
                 a.Q = slot; a.qscale = W.scales + (j - 1); a.fmt = fmt;
                 launch_spmv(a, s);
@@ -472,7 +476,8 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                 SpmvArgs a{};
                 a.n = n; a.ldy = ld; a.rp = A->row_ptr; a.ci = A->col_idx; a.val = A->val;
                 a.x = cur; a.dinv = W.dinv; a.y = nxt; a.ws = W.red;
-                a.mode = pc == CBG_PC_JACOBI ? (8 | 1) : (8 | 0); a.role = 1 /*SR_STEP*/;
+                a.mode = (vhat << 4) | (pc == CBG_PC_JACOBI ? (8 | 1) : (8 | 0));
+                a.role = 1 /*SR_STEP*/;
                 a.sg = sg; a.st = W.st; a.Q = slot; a.qscale = W.scales + (j - 1); a.fmt = fmt;
                 nb_spmv = launch_spmv(a, s);
             }
@@ -524,7 +529,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                 o.wio = W.z;
                 launch_update(o, s);
                 launch_bj_apply(n, ld, bj_bs, W.bj_tags, W.bj64, W.bj32, W.bj16, W.z, x, 1,
-                                nullptr, nullptr, nullptr, fmt, s);   // x += M^-1 z
+                                nullptr, nullptr, nullptr, fmt, 0, s);   // x += M^-1 z
             } else if (pc == CBG_PC_SPARSE) {
                 o.role = 4 /*U_COMBINE*/;       // z = V y
                 o.wio = W.z;
@@ -754,7 +759,7 @@ int cbg_block_jacobi_apply(int32_t n, int32_t bs, const int8_t *tags, const doub
         return CBG_E_ARG;
     if (n == 0)
         return CBG_OK;
-    launch_bj_apply(n, n, bs, tags, x64, x32, x16, v, z, 0, nullptr, nullptr, nullptr, 0,
+    launch_bj_apply(n, n, bs, tags, x64, x32, x16, v, z, 0, nullptr, nullptr, nullptr, 0, 0,
                     (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
     return CBG_OK;

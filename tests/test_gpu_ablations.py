@@ -1,0 +1,134 @@
+"""GPU ablation variants of the Arnoldi step against the CPU oracle, through
+the C ABI (CBG_FLAG_SPMV_VHAT, CBG_FLAG_ALWAYS_REORTH, the scaled float16
+basis).
+
+fp64 basis: a variant follows the oracle's same variant up to rounding
+(counts within one step, iteration-matched x within 1e-8, first-cycle
+recurrence residuals to 1e-9).  Compressed bases: the first steps agree to
+1e-12 with the oracle's same variant and differ from its default (so the
+variant really runs), and the solve reaches the tolerance with a count close
+to the oracle's.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2009_12101_amd import problems as P
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def cbg():
+    import paper_2009_12101_amd as cbg
+    cbg.lib()
+    return cbg
+
+
+def true_res(orc, A, b, x):
+    return np.linalg.norm(b - orc.spmv(A, x)) / np.linalg.norm(b)
+
+
+VARIANTS = [("spmv_vhat",), ("always_reorth",), ("spmv_vhat", "always_reorth")]
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("precond", ["none", "jacobi", "block_jacobi"])
+def test_fp64_variant_parity(cbg, orc, dev, variant, precond):
+    print(f"ablation fp64 {variant} {precond}", flush=True)
+    A = P.lognormal27(10, 6)
+    b = P.rhs_uniform(A.n, 6)
+    kw = dict(restart=30, fmt="fp64", tol=TOL, maxiter=5000, precond=precond, variant=variant)
+    ref = orc.gmres(A, b, **kw)
+    Ad = cbg.DeviceCSR.from_host(A, dev)
+    bd = torch.from_numpy(b).to(dev)
+    r = cbg.solve(Ad, bd, **kw)
+    assert r.status == 0 and ref["status"] == 0
+    assert abs(r.iterations - ref["iterations"]) <= 1
+    if "always_reorth" in variant:
+        assert r.reorths == r.iterations and ref["reorths"] == ref["iterations"]
+    assert true_res(orc, A, b, r.x.cpu().numpy()) <= TOL
+    it = ref["iterations"]
+    rm = cbg.solve(Ad, bd, **dict(kw, tol=0.0, maxiter=it))
+    om = orc.gmres(A, b, **dict(kw, tol=0.0, maxiter=it))
+    assert np.linalg.norm(rm.x.cpu().numpy() - om["x"]) <= 1e-8 * np.linalg.norm(om["x"])
+    k = min(30, it)
+    assert np.allclose(rm.hist[:k], om["hist"][:k], rtol=1e-9, atol=0)
+
+
+def test_spmv_vhat_is_identity_in_fp64(cbg, dev):
+    A = P.convdiff7(12)
+    b = P.rhs_uniform(A.n, 2)
+    Ad = cbg.DeviceCSR.from_host(A, dev)
+    bd = torch.from_numpy(b).to(dev)
+    r0 = cbg.solve(Ad, bd, restart=25, fmt="fp64", tol=TOL, maxiter=3000)
+    r1 = cbg.solve(Ad, bd, restart=25, fmt="fp64", tol=TOL, maxiter=3000, variant="spmv_vhat")
+    assert r0.iterations == r1.iterations
+    assert np.array_equal(r0.x.cpu().numpy().view(np.uint64), r1.x.cpu().numpy().view(np.uint64))
+
+
+@pytest.mark.parametrize("fmt", ["fp16", "fp16s", "bf16", "int16", "e4m3", "fp32"])
+@pytest.mark.parametrize("precond", ["none", "jacobi", "block_jacobi"])
+def test_spmv_vhat_first_steps(cbg, orc, dev, fmt, precond):
+    """The first steps coincide with the oracle's SpMV-on-v^ run to 1e-12
+    and differ from its default run by far more."""
+    print(f"ablation vhat {fmt} {precond}", flush=True)
+    A = P.convdiff7(14)
+    b = P.rhs_uniform(A.n, 7)
+    Ad = cbg.DeviceCSR.from_host(A, dev)
+    kw = dict(restart=30, fmt=fmt, tol=0.0, maxiter=3, precond=precond)
+    r = cbg.solve(Ad, torch.from_numpy(b).to(dev), variant="spmv_vhat", **kw)
+    on = orc.gmres(A, b, variant="spmv_vhat", **kw)
+    off = orc.gmres(A, b, **kw)
+    assert np.allclose(r.hist, on["hist"], rtol=1e-12, atol=0)
+    assert np.max(np.abs(off["hist"] - on["hist"]) / on["hist"]) > 1e-9
+    xg = r.x.cpu().numpy()
+    assert np.linalg.norm(xg - on["x"]) <= 1e-12 * np.linalg.norm(on["x"])
+
+
+@pytest.mark.parametrize("fmt,variant", [("fp16", ("spmv_vhat",)),
+                                         ("fp16s", ()),
+                                         ("fp16s", ("spmv_vhat", "always_reorth")),
+                                         ("int16", ("always_reorth",)),
+                                         ("bf16", ("spmv_vhat",))])
+def test_compressed_variant_solves(cbg, orc, dev, fmt, variant):
+    print(f"ablation solve {fmt} {variant}", flush=True)
+    A = P.convdiff7(20)
+    b = P.rhs_uniform(A.n, 8)
+    Ad = cbg.DeviceCSR.from_host(A, dev)
+    kw = dict(restart=30, fmt=fmt, tol=TOL, maxiter=20000, variant=variant)
+    r = cbg.solve(Ad, torch.from_numpy(b).to(dev), **kw)
+    o = orc.gmres(A, b, **kw)
+    assert r.status == 0 and o["status"] == 0
+    assert true_res(orc, A, b, r.x.cpu().numpy()) <= TOL
+    assert abs(r.iterations - o["iterations"]) <= 0.10 * o["iterations"] + 3
+    if "always_reorth" in variant:
+        assert r.reorths == r.iterations
+    r3 = cbg.solve(Ad, torch.from_numpy(b).to(dev), **dict(kw, tol=0.0, maxiter=3))
+    o3 = orc.gmres(A, b, **dict(kw, tol=0.0, maxiter=3))
+    assert np.allclose(r3.hist, o3["hist"], rtol=1e-12, atol=0)
+
+
+def test_unknown_flag_bits_are_argument_errors(cbg, dev):
+    import ctypes as C
+    from paper_2009_12101_amd import _binding as B
+    A = P.poisson2d(4)
+    Ad = cbg.DeviceCSR.from_host(A, dev)
+    b = torch.ones(A.n, dtype=torch.float64, device=dev)
+    x = torch.zeros_like(b)
+    ws = torch.empty(B.workspace_bytes(A.n, 8, "fp64"), dtype=torch.uint8, device=dev)
+    opts = B.CbgOpts(8, 0, 1e-10, 10, 0.0, 0, 0, None, 32, 0, 0, 0)
+    res = B.CbgResult()
+    csr = Ad.cstruct()
+    rc = B.lib().cbgmres_solve(C.byref(csr), B._ptr(b), B._ptr(x), C.byref(opts), B._ptr(ws),
+                               ws.numel(), B._stream(), C.byref(res), None, 0)
+    assert rc == B.E_ARG

@@ -11,9 +11,9 @@ import pytest
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-FORMATS = ["fp64", "fp32", "fp16", "bf16", "e4m3", "int32", "int16"]
+FORMATS = ["fp64", "fp32", "fp16", "bf16", "e4m3", "int32", "int16", "fp16s"]
 STORE = {"fp64": np.float64, "fp32": np.float32, "fp16": np.uint16, "bf16": np.uint16,
-         "e4m3": np.uint8, "int32": np.int32, "int16": np.int16}
+         "e4m3": np.uint8, "int32": np.int32, "int16": np.int16, "fp16s": np.uint16}
 U = 2.0 ** -53
 
 
@@ -60,11 +60,11 @@ def test_encode_bit_exact(cbg, orc, dev, fmt, n, kind):
     assert np.array_equal(d.view(np.uint64), orc.decode(fmt, qo, so).view(np.uint64))
 
 
-@pytest.mark.parametrize("fmt", ["fp16", "bf16"])
+@pytest.mark.parametrize("fmt", ["fp16", "bf16", "fp16s"])
 def test_encode_midpoints_bit_exact(cbg, orc, dev, fmt):
     """Every tie between neighbouring representable values in [0, 1], and
     the values one fp64 ulp either side of it."""
-    if fmt == "fp16":
+    if fmt in ("fp16", "fp16s"):
         c = np.arange(0, 0x3C01, dtype=np.uint16)
         vals = c.view(np.float16).astype(np.float64)
     else:
@@ -73,6 +73,8 @@ def test_encode_midpoints_bit_exact(cbg, orc, dev, fmt):
     mid = (vals[:-1] + vals[1:]) / 2
     x = np.concatenate([mid, np.nextafter(mid, 2.0), np.nextafter(mid, -1.0), -mid, vals])
     x[0] = 1.0       # keeps max|x| = 1 (irrelevant for unscaled formats)
+    if fmt == "fp16s":
+        x = x * 2.0 ** 15   # scale 1: the scaled values are the ties themselves
     q, _ = cbg.encode(fmt, torch.from_numpy(x).to(dev))
     qo, _ = orc.encode(fmt, x)
     assert np.array_equal(gpu_codes(q, fmt).view(np.uint16), qo.view(np.uint16))

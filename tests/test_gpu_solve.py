@@ -23,7 +23,7 @@ import pytest
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-FORMATS = ["fp64", "fp32", "fp16", "bf16", "e4m3", "int32", "int16"]
+FORMATS = ["fp64", "fp32", "fp16", "bf16", "e4m3", "int32", "int16", "fp16s"]
 PROBLEMS = [("poisson2d_64", 100), ("convdiff7_20", 30), ("lognormal27_12", 40)]
 TOL = 1e-10
 NPERT = 11
