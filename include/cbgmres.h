@@ -125,7 +125,13 @@ typedef struct {
  * unchanged. */
 #define CBG_FLAG_SPMV_VHAT 8
 #define CBG_FLAG_ALWAYS_REORTH 16
-#define CBG_FLAG_ALL 31     /* any other bit is an argument error */
+/* MGS: modified Gram-Schmidt for steps 5 and 8 -- for k = 1..j in order,
+ * h_k = dec(v^_k)^T w, then w -= h_k dec(v^_k); one kernel launch and one
+ * fold per stored vector and pass (slow by design: the ablation measures
+ * what the sequential projections buy).  Not combinable with the PROFILE
+ * flags (CBG_E_UNSUPPORTED). */
+#define CBG_FLAG_MGS 32
+#define CBG_FLAG_ALL 63     /* any other bit is an argument error */
 
 typedef struct {
     int64_t iterations;        /* Arnoldi steps (SpMVs with A inside cycles) */

@@ -27,8 +27,9 @@ FLAG_NO_FUSE = 2
 FLAG_PROFILE_DOT = 4
 FLAG_SPMV_VHAT = 8
 FLAG_ALWAYS_REORTH = 16
+FLAG_MGS = 32
 # Arnoldi-step ablations by name (solve(..., variant=...))
-VARIANTS = {"spmv_vhat": FLAG_SPMV_VHAT, "always_reorth": FLAG_ALWAYS_REORTH}
+VARIANTS = {"spmv_vhat": FLAG_SPMV_VHAT, "always_reorth": FLAG_ALWAYS_REORTH, "mgs": FLAG_MGS}
 MAX_RESTART = 512
 
 EXPORTS = ["cbg_strerror", "cbg_basis_ld", "cbg_workspace_bytes", "cbg_kernel_workspace_bytes",

@@ -1098,6 +1098,65 @@ __global__ __launch_bounds__(BLK) void k_bj_apply(int n, int64_t ldq, int bs,
 }
 
 // ---------------------------------------------------------------------------
+// Modified Gram-Schmidt, one stored vector per launch (ablation of Fig. 1
+// steps 5 and 8): launch k subtracts coef[k-1] dec(V_{k-1}) from w (k > 0)
+// and forms block partials of dec(V_k)^T w with the updated w (k < j), or
+// of ||w||^2 and max|w_i| (k = j).  A fold between launches turns the
+// partials into coef[k].  j + 1 launches per pass instead of two basis
+// passes: the cost of the sequential projections this variant studies.
+// ---------------------------------------------------------------------------
+
+template <int F>
+__global__ __launch_bounds__(BLK) void k_mgs(const uint8_t *__restrict__ V, int64_t ld,
+                                             const double *__restrict__ scales, int n, int k,
+                                             int j, double *__restrict__ w,
+                                             const double *__restrict__ coef, RedArgs ra,
+                                             const DevState *st, int pass)
+{
+    if (st->done || (pass == 2 && !st->reorth))
+        return;
+    using T = Fmt<F>;
+    constexpr int VW = T::VW;
+    const int64_t ldb = ld * fmt_bytes(F);
+    const double c = k > 0 ? coef[k - 1] : 0.0;
+    const double sp = k > 0 ? scales[k - 1] : 1.0;
+    const double sk = k < j ? scales[k] : 1.0;
+    double acc = 0.0, mx = 0.0;
+    const int64_t nch = ((int64_t)n + VW - 1) / VW;
+    for (int64_t ch = blockIdx.x * (int64_t)BLK + threadIdx.x; ch < nch;
+         ch += (int64_t)gridDim.x * BLK) {
+        const int64_t i0 = ch * VW;               // i0 < n <= ld: the chunk is in the row
+        double wv[VW], d[VW];
+        load_w<VW>(w, n, i0, wv);                 // entries >= n read as 0
+        if (k > 0) {
+            T::dec(*(const u32x4 *)(V + (int64_t)(k - 1) * ldb + i0 * fmt_bytes(F)), sp, d);
+#pragma unroll
+            for (int e = 0; e < VW; ++e)
+                wv[e] = wv[e] - c * d[e];
+            store_w<VW>(w, n, i0, wv);            // entries >= n are not written
+        }
+        if (k < j) {
+            T::dec(*(const u32x4 *)(V + (int64_t)k * ldb + i0 * fmt_bytes(F)), sk, d);
+#pragma unroll
+            for (int e = 0; e < VW; ++e)
+                acc += d[e] * wv[e];              // padding codes decode to 0
+        } else {
+#pragma unroll
+            for (int e = 0; e < VW; ++e) {
+                acc += wv[e] * wv[e];
+                mx = fmax(mx, fabs(wv[e]));
+            }
+        }
+    }
+    block_sum_max(acc, mx);
+    if (threadIdx.x == 0) {
+        ra.part[blockIdx.x] = acc;
+        if (k == j)
+            ra.part[(size_t)ra.stride + blockIdx.x] = mx;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // One-block reductions of the producers' partials (fixed order: lane l sums
 // blocks l, l+64, ... in turn, then a butterfly across the wave), followed
 // by the scalar work that needs the totals.
@@ -1113,6 +1172,9 @@ __global__ __launch_bounds__(BLK) void k_bj_apply(int n, int64_t ldq, int bs,
 //   RR_T2      after the re-orthogonalisation pass (steps 9-12)
 //   RR_VALUES  kernel-level multi-dot
 //   RR_NORMS   kernel-level update: ||w||_2, ||w||_inf
+//   RR_MGS_H   MGS pass 1: one coefficient h_k into *out
+//   RR_MGS_U   MGS pass 2: one coefficient u_k into *out
+//   RR_MGS_T   end of MGS pass 1: as RR_U's scalars, from partials 0 and 1
 
 constexpr int RBLK = 256;
 constexpr int RWAVES = RBLK / 64;
@@ -1180,11 +1242,17 @@ __global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth
                                                  int j, DevState *st, StepArrays sa,
                                                  double *out, int fmt)
 {
-    if (role == RR_H || role == RR_U || role == RR_T2) {
+    if (role == RR_H || role == RR_U || role == RR_T2 || role >= RR_MGS_H) {
         if (st->done)
             return;
-        if (role == RR_T2 && !st->reorth)
+        if ((role == RR_T2 || role == RR_MGS_U) && !st->reorth)
             return;
+    }
+    if (role == RR_MGS_H || role == RR_MGS_U) {       // one value, one block
+        const double a = block_fold(ws.orth, nb_orth, false);
+        if (threadIdx.x == 0)
+            *out = a;
+        return;
     }
     const int tid = threadIdx.x;
     // coefficients h_k / u_k / kernel-level values: block 1 + k folds value k
@@ -1210,7 +1278,7 @@ __global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth
         s0 = ws.orth + (size_t)j * ws.stride;           // ||w||^2, max|w_i|
         s1 = ws.orth + (size_t)(j + 1) * ws.stride;
         nb = nb_orth;
-    } else if (role == RR_T2 || role == RR_NORMS) {
+    } else if (role == RR_T2 || role == RR_NORMS || role == RR_MGS_T) {
         s0 = ws.orth;
         s1 = ws.orth + ws.stride;
         nb = nb_orth;
@@ -1278,7 +1346,8 @@ __global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth
         if (tid == 0)
             st->omega = sqrt(sv[0]);
         break;
-    case RR_U: {
+    case RR_U:
+    case RR_MGS_T: {
         // Fig. 1 steps 6-7; without re-orthogonalisation the step ends here
         // (finish_step needs h, which the previous kernel stored, not u)
         const double t = sqrt(sv[0]);
@@ -1620,6 +1689,18 @@ int launch_update_redot(const OrthArgs &a, hipStream_t s)
         fused_shape<80>(a, g, ra, V, s);
     else
         fused_shape<FUSED_JMAX>(a, g, ra, V, s);
+    return g;
+}
+
+int launch_mgs(int fmt, const void *V, int64_t ld, const double *scales, int n, int k, int j,
+               double *w, const double *coef, const RedWs &ws, const DevState *st, int pass,
+               hipStream_t s)
+{
+    int g = 1;
+    RedArgs ra{ws.orth, ws.stride};
+    CBG_FMT_SWITCH(fmt, (g = grid_for(((int64_t)n + Fmt<F>::VW - 1) / Fmt<F>::VW, BLK),
+                         k_mgs<F><<<g, BLK, 0, s>>>((const uint8_t *)V, ld, scales, n, k, j, w,
+                                                    coef, ra, st, pass)))
     return g;
 }
 

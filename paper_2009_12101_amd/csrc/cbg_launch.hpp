@@ -53,7 +53,7 @@ struct OrthArgs {
 
 // reduce roles (k_reduce)
 enum { RR_NB = 0, RR_SCALE = 1, RR_NORM2 = 2, RR_RESID = 3, RR_H = 4, RR_U = 5, RR_T2 = 6,
-       RR_VALUES = 7, RR_NORMS = 8 };
+       RR_VALUES = 7, RR_NORMS = 8, RR_MGS_H = 9, RR_MGS_U = 10, RR_MGS_T = 11 };
 
 int spmv_lanes(int n, int64_t nnz);
 int spmv_grid(int sg, int64_t ldy);
@@ -78,6 +78,14 @@ void launch_bj_apply(int n, int64_t ldq, int bs, const int8_t *tags, const doubl
                      int accumulate, const DevState *st, void *Q, const double *qscale, int fmt,
                      int quant, hipStream_t s);
 int fused_jmax(int fmt);   // largest j launch_update_redot takes
+// One launch of a modified Gram-Schmidt pass over the stored vectors (the
+// MGS ablation of steps 5 and 8): w -= coef[k-1] dec(V_{k-1}) for k > 0,
+// then partials of dec(V_k)^T w (k < j) or of ||w||^2, max|w| (k = j).
+// pass 1 is skipped once the cycle is done, pass 2 also unless the step
+// re-orthogonalises.  Returns the grid (the number of partials).
+int launch_mgs(int fmt, const void *V, int64_t ld, const double *scales, int n, int k, int j,
+               double *w, const double *coef, const RedWs &ws, const DevState *st, int pass,
+               hipStream_t s);
 // Whether launch_update_redot takes step j for basis vectors of leading
 // dimension ld (the one predicate the solver and the launcher share).
 bool fused_takes(int fmt, int64_t ld, int j);

@@ -267,6 +267,9 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
     // ablations of the Arnoldi step
     const int vhat = (opt->flags & CBG_FLAG_SPMV_VHAT) ? 1 : 0;
     const int reorth_all = (opt->flags & CBG_FLAG_ALWAYS_REORTH) ? 1 : 0;
+    const bool mgs = (opt->flags & CBG_FLAG_MGS) != 0;
+    if (mgs && prof)
+        return fail(CBG_E_UNSUPPORTED);     // event timing covers the CGS kernels only
     // steps whose update and re-dot share one basis pass
     auto fused = [&](int j) { return fuse && fused_takes(fmt, basis_ld(n), j); };
     ByteModel bm{(double)n, (double)A->nnz, (double)fmt_bytes(fmt)};
@@ -390,13 +393,16 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                 if (hist_n < hist_len)
                     hist_out[hist_n] = cyc_hist[j - 1];
                 ++hist_n;
-                double b_step = bm.spmv_step() + bm.dot(j) + bm.upd(j);
+                // MGS pass: w read j + 1 times and written j times, each
+                // stored vector read twice
+                const double b_mgs = 2.0 * j * n * bm.bs + (2.0 * j + 1.0) * 8.0 * n;
+                double b_step = bm.spmv_step() + (mgs ? b_mgs : bm.dot(j) + bm.upd(j));
                 if (prev_pc == CBG_PC_JACOBI) b_step += 8.0 * n;
                 if (prev_pc == CBG_PC_SPARSE) b_step += 8.0 * A->nnz + 4.0 * (n + 1) + 16.0 * n;
                 if (prev_pc == CBG_PC_BLOCK_JACOBI) b_step += bj_bytes + 16.0 * n;
-                if (!fused(j))
+                if (!fused(j) && !mgs)
                     b_step += bm.dot(j);             // the separate re-dot pass
-                if (ro) b_step += bm.upd(j);
+                if (ro) b_step += mgs ? b_mgs : bm.upd(j);
                 model_bytes += b_step;
             }
             model_bytes += jeff * n * bm.bs + 16.0 * n;     // solution update
@@ -480,6 +486,26 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                 a.role = 1 /*SR_STEP*/;
                 a.sg = sg; a.st = W.st; a.Q = slot; a.qscale = W.scales + (j - 1); a.fmt = fmt;
                 nb_spmv = launch_spmv(a, s);
+            }
+            if (mgs) {
+                // steps 5-12 by modified Gram-Schmidt: omega, then one launch
+                // and one fold per stored vector, per pass
+                launch_reduce(W.red, RR_H, 0, nb_spmv, 0, W.st, sa, nullptr, fmt, s);
+                for (int pass = 1; pass <= 2; ++pass) {
+                    double *coef = pass == 1 ? W.h : W.u;
+                    for (int k = 0; k <= j; ++k) {
+                        const int g = launch_mgs(fmt, W.V, ld, W.scales, n, k, j, nxt, coef,
+                                                 W.red, W.st, pass, s);
+                        const int role = k < j ? (pass == 1 ? RR_MGS_H : RR_MGS_U)
+                                               : (pass == 1 ? RR_MGS_T : RR_T2);
+                        launch_reduce(W.red, role, g, 0, j, W.st, sa, k < j ? coef + k : nullptr,
+                                      fmt, s);
+                    }
+                }
+                double *t = cur;
+                cur = nxt;
+                nxt = t;
+                continue;
             }
             OrthArgs o{};
             o.fmt = fmt; o.V = W.V; o.ld = ld; o.scales = W.scales; o.n = n; o.j = j;

@@ -1,6 +1,6 @@
 """GPU ablation variants of the Arnoldi step against the CPU oracle, through
-the C ABI (CBG_FLAG_SPMV_VHAT, CBG_FLAG_ALWAYS_REORTH, the scaled float16
-basis).
+the C ABI (CBG_FLAG_SPMV_VHAT, CBG_FLAG_ALWAYS_REORTH, CBG_FLAG_MGS, the
+scaled float16 basis).
 
 fp64 basis: a variant follows the oracle's same variant up to rounding
 (counts within one step, iteration-matched x within 1e-8, first-cycle
@@ -38,7 +38,8 @@ def true_res(orc, A, b, x):
     return np.linalg.norm(b - orc.spmv(A, x)) / np.linalg.norm(b)
 
 
-VARIANTS = [("spmv_vhat",), ("always_reorth",), ("spmv_vhat", "always_reorth")]
+VARIANTS = [("spmv_vhat",), ("always_reorth",), ("spmv_vhat", "always_reorth"), ("mgs",),
+            ("mgs", "always_reorth")]
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
@@ -95,7 +96,36 @@ def test_spmv_vhat_first_steps(cbg, orc, dev, fmt, precond):
     assert np.linalg.norm(xg - on["x"]) <= 1e-12 * np.linalg.norm(on["x"])
 
 
+@pytest.mark.parametrize("fmt", ["fp16", "int16", "bf16", "fp16s", "e4m3"])
+def test_mgs_first_steps(cbg, orc, dev, fmt):
+    """Modified Gram-Schmidt: the first steps coincide with the oracle's MGS
+    run to 1e-12 and differ from its CGS run (the compressed basis is not
+    orthogonal to working precision, so the projections differ)."""
+    print(f"ablation mgs {fmt}", flush=True)
+    A = P.lognormal27(12, 2)
+    b = P.rhs_uniform(A.n, 9)
+    Ad = cbg.DeviceCSR.from_host(A, dev)
+    kw = dict(restart=30, fmt=fmt, tol=0.0, maxiter=4, eta=1e-300)
+    r = cbg.solve(Ad, torch.from_numpy(b).to(dev), variant="mgs", **kw)
+    on = orc.gmres(A, b, variant="mgs", **kw)
+    off = orc.gmres(A, b, **kw)
+    assert np.allclose(r.hist, on["hist"], rtol=1e-12, atol=0)
+    assert np.max(np.abs(off["hist"] - on["hist"]) / on["hist"]) > 1e-12
+    assert np.linalg.norm(r.x.cpu().numpy() - on["x"]) <= 1e-12 * np.linalg.norm(on["x"])
+
+
+def test_mgs_with_profiling_is_unsupported(cbg, dev):
+    A = P.poisson2d(6)
+    Ad = cbg.DeviceCSR.from_host(A, dev)
+    with pytest.raises(cbg.CbgError) as e:
+        cbg.solve(Ad, torch.ones(A.n, dtype=torch.float64, device=dev), restart=5,
+                  variant="mgs", profile=True)
+    assert e.value.status == -5
+
+
 @pytest.mark.parametrize("fmt,variant", [("fp16", ("spmv_vhat",)),
+                                         ("fp16", ("mgs",)),
+                                         ("bf16", ("mgs", "spmv_vhat")),
                                          ("fp16s", ()),
                                          ("fp16s", ("spmv_vhat", "always_reorth")),
                                          ("int16", ("always_reorth",)),
@@ -126,7 +156,7 @@ def test_unknown_flag_bits_are_argument_errors(cbg, dev):
     b = torch.ones(A.n, dtype=torch.float64, device=dev)
     x = torch.zeros_like(b)
     ws = torch.empty(B.workspace_bytes(A.n, 8, "fp64"), dtype=torch.uint8, device=dev)
-    opts = B.CbgOpts(8, 0, 1e-10, 10, 0.0, 0, 0, None, 32, 0, 0, 0)
+    opts = B.CbgOpts(8, 0, 1e-10, 10, 0.0, 0, 0, None, 64, 0, 0, 0)
     res = B.CbgResult()
     csr = Ad.cstruct()
     rc = B.lib().cbgmres_solve(C.byref(csr), B._ptr(b), B._ptr(x), C.byref(opts), B._ptr(ws),
