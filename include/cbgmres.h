@@ -198,6 +198,12 @@ int cbg_workspace_basis(int32_t n, int32_t restart, int32_t format, int32_t prec
 /* Static description of a status code. */
 const char *cbg_strerror(int status);
 
+/* After a call returned CBG_E_HIP: the hipError_t of the HIP runtime call
+ * that failed (0 if none has failed on this host thread), the source line
+ * of the library where it was made (line, optional) and the runtime's name
+ * for the error (name, optional; a static string). */
+int cbg_last_hip_error(int *line, const char **name);
+
 /* Padded leading dimension (elements) the solver uses for basis vectors of
  * length n: a multiple of 256.  Kernel-level calls accept any ld >= n that
  * is a multiple of 16. */

@@ -32,7 +32,7 @@ FLAG_MGS = 32
 VARIANTS = {"spmv_vhat": FLAG_SPMV_VHAT, "always_reorth": FLAG_ALWAYS_REORTH, "mgs": FLAG_MGS}
 MAX_RESTART = 512
 
-EXPORTS = ["cbg_strerror", "cbg_basis_ld", "cbg_workspace_bytes", "cbg_kernel_workspace_bytes",
+EXPORTS = ["cbg_strerror", "cbg_last_hip_error", "cbg_basis_ld", "cbg_workspace_bytes", "cbg_kernel_workspace_bytes",
            "cbg_workspace_basis", "cbgmres_solve", "cbg_encode", "cbg_decode", "cbg_spmv",
            "cbg_multidot", "cbg_update", "cbg_update_redot", "cbg_block_jacobi_setup",
            "cbg_block_jacobi_apply", "cbg_spai_workspace_bytes", "cbg_spai_features", "cbg_mlp_forward",
@@ -84,10 +84,19 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2009_12101_amd.build` (hipcc, gfx950)")
+        # torch first: the library then binds to the HIP runtime torch has
+        # loaded, so device pointers and streams from torch are valid in it
+        # (loaded the other way round, a second runtime reports no device)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp, i32, i64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_size_t
         L.cbg_strerror.argtypes = [C.c_int]
         L.cbg_strerror.restype = C.c_char_p
+        L.cbg_last_hip_error.argtypes = [C.POINTER(C.c_int), C.POINTER(C.c_char_p)]
+        L.cbg_last_hip_error.restype = C.c_int
         L.cbg_basis_ld.argtypes = [i32]
         L.cbg_basis_ld.restype = i64
         L.cbg_workspace_bytes.argtypes = [i32, i32, i32, i32]
@@ -177,8 +186,20 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def last_hip_error():
+    """(hipError_t, library source line, error name) of the last failing HIP
+    call on this thread (0 if none)."""
+    line = C.c_int(0)
+    name = C.c_char_p()
+    code = lib().cbg_last_hip_error(C.byref(line), C.byref(name))
+    return code, line.value, (name.value or b"").decode()
+
+
 def _check(rc: int, where: str):
     if rc < 0:
+        if rc == E_HIP:
+            code, line, name = last_hip_error()
+            where = f"{where} [{name} ({code}) at line {line}]"
         raise CbgError(rc, where)
     return rc
 

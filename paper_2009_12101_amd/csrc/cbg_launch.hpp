@@ -78,6 +78,9 @@ void launch_bj_apply(int n, int64_t ldq, int bs, const int8_t *tags, const doubl
                      int accumulate, const DevState *st, void *Q, const double *qscale, int fmt,
                      int quant, hipStream_t s);
 int fused_jmax(int fmt);   // largest j launch_update_redot takes
+// Records a failing HIP call (error code, library source line) for
+// cbg_last_hip_error.
+void note_hip_error(hipError_t e, int line);
 // One launch of a modified Gram-Schmidt pass over the stored vectors (the
 // MGS ablation of steps 5 and 8): w -= coef[k-1] dec(V_{k-1}) for k > 0,
 // then partials of dec(V_k)^T w (k < j) or of ||w||^2, max|w| (k = j).

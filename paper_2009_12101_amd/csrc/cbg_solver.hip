@@ -117,12 +117,14 @@ double now_s()
         .count();
 }
 
-#define HIP_TRY(x)                          \
-    do {                                    \
-        if ((x) != hipSuccess) {            \
-            (void)hipGetLastError();        \
-            return CBG_E_HIP;               \
-        }                                   \
+#define HIP_TRY(x)                              \
+    do {                                        \
+        const hipError_t e_ = (x);              \
+        if (e_ != hipSuccess) {                 \
+            note_hip_error(e_, __LINE__);       \
+            (void)hipGetLastError();            \
+            return CBG_E_HIP;                   \
+        }                                       \
     } while (0)
 
 // Algorithmic HBM bytes (what each kernel must move at least).
@@ -165,6 +167,17 @@ struct CycleEvents {
 
 }  // namespace
 
+// The failing HIP call's error code and source line, per host thread, for
+// cbg_last_hip_error.
+namespace {
+thread_local int g_hip_err = 0, g_hip_line = 0;
+}
+void cbg::note_hip_error(hipError_t e, int line)
+{
+    g_hip_err = (int)e;
+    g_hip_line = line;
+}
+
 extern "C" {
 
 const char *cbg_strerror(int status)
@@ -179,6 +192,15 @@ const char *cbg_strerror(int status)
     case CBG_E_UNSUPPORTED: return "unsupported request";
     default: return "unknown status";
     }
+}
+
+int cbg_last_hip_error(int *line, const char **name)
+{
+    if (line)
+        *line = g_hip_line;
+    if (name)
+        *name = g_hip_err ? hipGetErrorName((hipError_t)g_hip_err) : "hipSuccess";
+    return g_hip_err;
 }
 
 int64_t cbg_basis_ld(int32_t n) { return n < 0 ? 0 : basis_ld(n); }

@@ -18,6 +18,7 @@
 
 #include "../../include/cbgmres.h"
 #include "cbg_device.hpp"
+#include "cbg_launch.hpp"
 
 namespace cbg {
 namespace spai {
@@ -818,7 +819,9 @@ size_t ws_need(int64_t n, int64_t nnz, int64_t K)
 
 #define SP_TRY(x)                           \
     do {                                    \
-        if ((x) != hipSuccess) {            \
+        const hipError_t e_ = (x);          \
+        if (e_ != hipSuccess) {             \
+            cbg::note_hip_error(e_, __LINE__); \
             (void)hipGetLastError();        \
             return CBG_E_HIP;               \
         }                                   \

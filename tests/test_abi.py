@@ -47,6 +47,8 @@ def test_strerror_and_sizes(L):
     assert d == 101 * B.basis_ld(10 ** 6) * 6
     assert B.kernel_workspace_bytes(100, 10) > 0
     assert B.kernel_workspace_bytes(100, 10 ** 6) == 0
+    # no HIP call has failed on this thread: code 0, no line
+    assert B.last_hip_error() == (0, 0, "hipSuccess")
 
 
 def test_solve_rejects_bad_arguments_on_host(L):

@@ -172,7 +172,10 @@ def test_multidot_and_update_parity(cbg, orc, dev, fmt, n, j):
 @pytest.mark.parametrize("fmt", FORMATS)
 @pytest.mark.parametrize("n,j", [(1, 1), (33, 3), (5001, 32), (70001, 33), (70001, 64),
                                  (70003, 65), (300000, 100), (300001, 104), (20000, 105),
-                                 (20000, 130)])
+                                 (20000, 130),
+                                 # large n: more tiles than blocks for the
+                                 # 8-byte formats (256-row tiles)
+                                 (3000001, 16), (1200007, 48), (2000003, 72)])
 def test_update_redot_parity(cbg, orc, dev, fmt, n, j):
     """Fused update + re-dot (one basis pass while j fits the register tile,
     two passes beyond it) against the oracle's update and dots."""
