@@ -15,6 +15,9 @@ solver records at each multi-dot launch's own start and end (only those
 launches are event-timed in the timed region).  One more solve after the
 timed region times every basis-streaming kernel (`orth_kernels_gbps`,
 `fused_update_redot`).
+`roofline.copy_gbps` is a 1 GiB device-to-device copy timed the same way
+(`frac_of_copy` reads the multi-dot against it).  `--trace-summary` turns a
+rocprofv3 kernel trace of these runs into per-j multi-dot rates.
 `cpu_baseline` is the CPU oracle timed on one restart cycle of the same
 solve on the host cores, scaled to the GPU's iteration count.
 """
@@ -87,6 +90,63 @@ def pmc_summary(fetch_csv: str, write_csv: str, fmt: str, grid: int) -> dict:
     return out
 
 
+def trace_summary(trace_csv: str, fmt: str, grid: int, restart: int = 100) -> dict:
+    """Per-j durations of the multi-dot from a rocprofv3 --kernel-trace CSV
+    of bench runs: the solver launches one multi-dot per Arnoldi step, j =
+    1..restart in every cycle (launches after a cycle ended return at once),
+    so dispatch k in launch order belongs to step j = k mod restart + 1.
+    Per j: the median duration over all cycles and the algorithmic GB/s
+    (j n b_s + 8 n bytes); plus the j-weighted rate over j >= 20."""
+    import csv
+    import statistics
+    fmt_id = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "e4m3": 4, "int32": 5, "int16": 6,
+              "fp16s": 7}[fmt]
+    bs = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2, "e4m3": 1, "int32": 4, "int16": 2,
+          "fp16s": 2}[fmt]
+    kname = f"k_multidot<{fmt_id}>"
+    rows = [r for r in csv.DictReader(open(trace_csv)) if kname in r["Kernel_Name"]]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    if not rows or len(rows) % restart:
+        raise SystemExit(f"{trace_csv}: {len(rows)} {kname} dispatches, not a multiple of "
+                         f"{restart}")
+    n = grid ** 3
+    per_j = {}
+    for k, r in enumerate(rows):
+        per_j.setdefault(k % restart + 1, []).append(
+            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
+    table = []
+    for j in sorted(per_j):
+        med = statistics.median(per_j[j])
+        by = j * n * bs + 8.0 * n
+        table.append({"j": j, "median_us": med * 1e6, "gbps": by / med / 1e9,
+                      "samples": len(per_j[j])})
+    sel = [t for t in table if t["j"] >= 20]
+    tot_b = sum(t["j"] * n * bs + 8.0 * n for t in sel)
+    tot_t = sum(t["median_us"] * 1e-6 for t in sel)
+    return {"kernel": kname, "format": fmt, "grid": grid, "dispatches": len(rows),
+            "j_weighted_gbps_j_ge_20": tot_b / tot_t / 1e9, "per_j": table}
+
+
+def copy_rate_gbps(torch, dev, nbytes: int = 2 ** 30) -> float:
+    """Device-to-device copy of nbytes (reads and writes nbytes), best of 5,
+    timed with events on torch's current stream: the practical streaming
+    rate the roofline fraction can also be read against."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = None
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    return 2.0 * nbytes / (best * 1e-3) / 1e9
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -107,7 +167,12 @@ def main() -> int:
                     help="run a plain 256 MiB device copy first (counter calibration)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the multi-dot traffic record from two counter runs and exit")
+    ap.add_argument("--trace-summary", metavar="KERNEL_TRACE_CSV",
+                    help="print the multi-dot's per-j durations from a kernel trace and exit")
     args = ap.parse_args()
+    if args.trace_summary:
+        print(json.dumps(trace_summary(args.trace_summary, args.format, args.grid)))
+        return 0
     if args.pmc_summary:
         rec = pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.format, args.grid)
         with open(traffic_file(args.format, args.grid), "w") as f:
@@ -197,6 +262,9 @@ def main() -> int:
                             arnoldi_gbps=r.model_bytes / r.seconds / 1e9)
         log(f"{fmt}: {dt * 1e3:.1f} ms it={r.iterations}")
 
+    copy_gbps = copy_rate_gbps(torch, dev)
+    log(f"device copy: {copy_gbps:.0f} GB/s")
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -242,6 +310,7 @@ def main() -> int:
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                      "kernel": f"k_multidot<{args.format}>",
                      "launches": dot_launch,
+                     "copy_gbps": copy_gbps, "frac_of_copy": achieved / copy_gbps,
                      "avg_launch_us": dot_ms * 1e3 / max(dot_launch, 1),
                      "algorithmic_bytes_per_launch": dot_bytes / max(dot_launch, 1)},
         "cpu_baseline": cpu,
