@@ -284,6 +284,30 @@ __device__ __forceinline__ double wave_max(double x)
     return x;
 }
 
+// The value of lane (l xor P>>10) for an immediate ds_swizzle bit-mask
+// pattern P (and-mask 31, or-mask 0, xor-mask P>>10: the partner within the
+// lane's 32-lane half, no address arithmetic).
+template <int P>
+__device__ __forceinline__ double swizzle64(double v)
+{
+    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), P);
+    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), P);
+    return __hiloint2double(hi, lo);
+}
+
+// The value of lane (l xor d); d a power of two known after unrolling.
+__device__ __forceinline__ double xor_lane(double v, int d)
+{
+    switch (d) {
+    case 1: return swizzle64<(1 << 10) | 0x1F>(v);
+    case 2: return swizzle64<(2 << 10) | 0x1F>(v);
+    case 4: return swizzle64<(4 << 10) | 0x1F>(v);
+    case 8: return swizzle64<(8 << 10) | 0x1F>(v);
+    case 16: return swizzle64<(16 << 10) | 0x1F>(v);
+    default: return __shfl_xor(v, d);
+    }
+}
+
 // Reduce N per-lane values across the wave at once: N-1 exchanges halve the
 // set each lane holds, then log2(64/N) exchanges finish the sums.  Lane l
 // ends with (in a[0]) the wave total of index bitrev_N(l mod N).
@@ -303,12 +327,12 @@ __device__ __forceinline__ void wave_transpose_sum(double (&a)[N])
             asm volatile("" : "+v"(lo), "+v"(hi));
             const double send = up ? lo : hi;
             const double keep = up ? hi : lo;
-            a[i] = keep + __shfl_xor(send, d);
+            a[i] = keep + xor_lane(send, d);
         }
     }
 #pragma unroll
     for (int d = N; d < 64; d <<= 1)
-        a[0] += __shfl_xor(a[0], d);
+        a[0] += xor_lane(a[0], d);
 }
 
 template <int N>
