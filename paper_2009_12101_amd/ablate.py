@@ -4,7 +4,9 @@ The compressed bases cost extra iterations against the FP64 basis (the
 paper's Table 2 reports this overhead per matrix and format).  This tool
 solves one system to tolerance for each storage format and each variant of
 the step, and reports iterations, time and the overhead against the FP64
-basis with the unablated step:
+basis with the unablated step, and the relative difference of each solution
+from that fp64-basis solution (``x_err``; two solves that both meet the
+tolerance can differ by up to 2 tol ||b|| / sigma_min(A)):
 
 * ``default``: Fig. 1 as the solver runs it (SpMV on the FP64 v, CGS with
   the step-7 test, eta = 1/sqrt(2));
@@ -46,6 +48,7 @@ def ablate(A, b, formats, variants, restart=100, tol=1e-10, maxiter=20000, preco
     ws = torch.empty(B.workspace_bytes(A.n, restart, "fp64", precond), dtype=torch.uint8,
                      device=device)
     rows = []
+    x_ref = None
     for fmt in formats:
         for vname in variants:
             kw = dict(restart=restart, fmt=fmt, tol=tol, maxiter=maxiter, precond=precond,
@@ -60,13 +63,17 @@ def ablate(A, b, formats, variants, restart=100, tol=1e-10, maxiter=20000, preco
                 dt = time.perf_counter() - t0
                 best = dt if best is None else min(best, dt)
             tr = r.true_rel_res          # the solver's closing ||b - A x|| / ||b||
+            if fmt == "fp64" and vname == "default":
+                x_ref = r.x.clone()
+            x_err = None if x_ref is None else \
+                float(torch.linalg.norm(r.x - x_ref) / torch.linalg.norm(x_ref))
             row = dict(format=fmt, variant=vname, status=r.status, iterations=r.iterations,
                        reorths=r.reorths, restarts=r.restarts, seconds=best,
-                       true_rel_res=tr)
+                       true_rel_res=tr, x_err=x_err)
             rows.append(row)
             if log:
                 log(f"{fmt:6s} {vname:10s} it={r.iterations:6d} reorth={r.reorths:6d} "
-                    f"{best * 1e3:8.1f} ms res={tr:.2e} status={r.status}")
+                    f"{best * 1e3:8.1f} ms res={tr:.2e} x_err={x_err} status={r.status}")
     base = {r["variant"]: r for r in rows if r["format"] == "fp64"}
     ref = base.get("default")
     for r in rows:
