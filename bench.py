@@ -18,8 +18,9 @@ timed region times every basis-streaming kernel (`orth_kernels_gbps`,
 `roofline.copy_gbps` is a 1 GiB device-to-device copy timed the same way
 (`frac_of_copy` reads the multi-dot against it).  `--trace-summary` turns a
 rocprofv3 kernel trace of these runs into per-j multi-dot rates.
-`cpu_baseline` is the CPU oracle timed on one restart cycle of the same
-solve on the host cores, scaled to the GPU's iteration count.
+`cpu_baseline` is the CPU oracle timed on five restart cycles (500 Arnoldi
+steps) of the same solve on the host cores, scaled to the GPU's iteration
+count.
 """
 from __future__ import annotations
 
@@ -162,7 +163,8 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fuse", action="store_true",
                     help="ablation: update and re-dot as two basis passes")
-    ap.add_argument("--cpu-cycles", type=int, default=1)
+    ap.add_argument("--cpu-cycles", type=int, default=5,
+                    help="restart cycles of the CPU oracle sample (about 2.5 s each on 16 cores)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain 256 MiB device copy first (counter calibration)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -275,7 +277,7 @@ def main() -> int:
         per_step = dt / max(o["iterations"], 1)
         cpu = {"value": per_step * r0.iterations, "unit": "s", "cores": oracle.get_threads(),
                "kind": "oracle",
-               "sample": f"{o['iterations']} Arnoldi steps ({cyc} restart cycle) of the same "
+               "sample": f"{o['iterations']} Arnoldi steps ({cyc} restart cycles) of the same "
                          f"{args.format}-basis solve on the host cores in {dt:.1f} s, scaled to "
                          f"the GPU's {r0.iterations} steps"}
         log(f"cpu oracle: {dt:.1f}s for {o['iterations']} steps")
