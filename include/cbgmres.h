@@ -66,7 +66,7 @@ enum {
     CBG_E_WORKSPACE = -2,    /* workspace missing, misaligned or too small */
     CBG_E_HIP = -3,          /* a HIP runtime call failed */
     CBG_E_NONFINITE = -4,    /* NaN/Inf met (b, x0, A, or during the solve) */
-    CBG_E_UNSUPPORTED = -5   /* valid request this build does not support */
+    CBG_E_UNSUPPORTED = -5   /* valid request the library does not support */
 };
 
 /* CSR matrix, 0-based, column indices sorted within each row.

@@ -1,5 +1,5 @@
 """Host-side pieces of the learned preconditioner (no GPU): the parameter
-layout the binding uses matches the C header, and the driver's seeded
+layout the binding uses matches the C header, and the training module's seeded
 initialisation matches the oracle's (the same counter-based normal stream,
 W3 and the biases zero, so the untrained P is Jacobi)."""
 import os
