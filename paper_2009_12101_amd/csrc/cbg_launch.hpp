@@ -26,7 +26,7 @@ struct SpmvArgs {
     RedWs ws;
     int mode;             // SP_* of the kernels (8 | base: Arnoldi-step variant)
     int role;             // SR_*: 0 none, 1 step (partials, skipped when done), 2 free
-    int sg;               // rows per block (spmv_lanes)
+    int sg;               // launch shape (SPMV_*, from spmv_shape_of)
     const DevState *st;
     void *Q;              // step variants: basis slot receiving enc(x / t)
     const double *qscale; // step variants: that slot's scale
@@ -55,8 +55,11 @@ struct OrthArgs {
 enum { RR_NB = 0, RR_SCALE = 1, RR_NORM2 = 2, RR_RESID = 3, RR_H = 4, RR_U = 5, RR_T2 = 6,
        RR_VALUES = 7, RR_NORMS = 8, RR_MGS_H = 9, RR_MGS_U = 10, RR_MGS_T = 11 };
 
-int spmv_lanes(int n, int64_t nnz);
-int spmv_grid(int sg, int64_t ldy);
+// SpMV launch shapes: rows per block and LDS product-buffer entries
+enum { SPMV_R256_C2K = 0, SPMV_R64_C2K = 1, SPMV_R64_C4K = 2, SPMV_R32_C4K = 3 };
+int spmv_shape_of(int n, int64_t nnz);     // from the mean row length
+int spmv_rows(int shape);
+int spmv_grid(int shape, int64_t ldy);
 int orth_grid(int fmt, int64_t n);
 int launch_spmv(const SpmvArgs &a, hipStream_t s);
 void launch_multidot(const OrthArgs &a, hipStream_t s);

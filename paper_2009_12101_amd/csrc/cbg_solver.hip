@@ -279,7 +279,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
     const int64_t ld = basis_ld(n);
     const size_t vbytes = (size_t)ld * fmt_bytes(fmt);
     const double eta = opt->eta > 0.0 ? opt->eta : ETA_DEFAULT;
-    const int sg = spmv_lanes(n, A->nnz);
+    const int sg = spmv_shape_of(n, A->nnz);
     const bool prof_all = (opt->flags & CBG_FLAG_PROFILE) != 0;
     const bool prof = prof_all || (opt->flags & CBG_FLAG_PROFILE_DOT) != 0;
     // launch slots k of a step: 0 multi-dot, 1 update (or fused update +
@@ -670,7 +670,7 @@ int cbg_spmv(const cbg_csr *A, const double *x, double *y, double *norm2, void *
     }
     SpmvArgs a{};
     a.n = A->n; a.ldy = A->n; a.rp = A->row_ptr; a.ci = A->col_idx; a.val = A->val; a.x = x;
-    a.y = y; a.mode = 0; a.sg = spmv_lanes(A->n, A->nnz);
+    a.y = y; a.mode = 0; a.sg = spmv_shape_of(A->n, A->nnz);
     a.role = norm2 ? 2 /*SR_FREE*/ : 0;
     if (norm2)
         a.ws = kernel_red(ws, 0);
