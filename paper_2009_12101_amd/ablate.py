@@ -88,6 +88,8 @@ def main(argv=None) -> int:
     ap.add_argument("--system", default="convdiff7_128")
     ap.add_argument("--formats", default="fp64,fp32,fp16,fp16s,bf16,int16")
     ap.add_argument("--variants", default=",".join(VARIANTS))
+    ap.add_argument("--etas", default="",
+                    help="extra variants: step-7 thresholds to sweep, e.g. 0.5,0.2,0.1")
     ap.add_argument("--restart", type=int, default=100)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--maxiter", type=int, default=20000)
@@ -97,7 +99,11 @@ def main(argv=None) -> int:
     a = ap.parse_args(argv)
     import torch
     A, b = system(a.system)
-    rows = ablate(A, b, a.formats.split(","), a.variants.split(","), a.restart, a.tol,
+    names = [v for v in a.variants.split(",") if v]
+    for e in [x for x in a.etas.split(",") if x]:
+        VARIANTS[f"eta={e}"] = dict(eta=float(e))
+        names.append(f"eta={e}")
+    rows = ablate(A, b, a.formats.split(","), names, a.restart, a.tol,
                   a.maxiter, a.precond, a.repeats, torch.device("cuda:0"),
                   log=lambda s: print(s, file=sys.stderr, flush=True))
     out = dict(system=A.name, n=A.n, nnz=A.nnz, restart=a.restart, tol=a.tol,
