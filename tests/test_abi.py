@@ -80,6 +80,17 @@ def test_solve_rejects_bad_arguments_on_host(L):
     assert call(ws=None) == B.E_WORKSPACE          # missing workspace
     assert call(ws=4096 + 8, wsb=1 << 40) == B.E_WORKSPACE   # misaligned workspace
     assert call(ws=4096, wsb=10) == B.E_WORKSPACE            # too small
+    # formats 0..7 (7: scaled float16), flag bits 1..32, block-Jacobi sizes
+    assert call(format=8) == B.E_ARG
+    assert call(format=7) == B.E_WORKSPACE                    # valid: reaches the workspace check
+    assert call(flags=64) == B.E_ARG
+    assert call(flags=B.FLAG_SPMV_VHAT | B.FLAG_ALWAYS_REORTH | B.FLAG_MGS) == B.E_WORKSPACE
+    assert call(precond=3, pc_block=9) == B.E_ARG
+    assert call(precond=3, pc_prec=20) == B.E_ARG
+    assert call(precond=3, pc_block=8, pc_prec=32) == B.E_WORKSPACE
+    # MGS with event timing: refused before any HIP call (host arithmetic only
+    # runs between the workspace check and this test)
+    assert call(flags=B.FLAG_MGS | B.FLAG_PROFILE, ws=1 << 20, wsb=1 << 40) == B.E_UNSUPPORTED
     empty = B.CbgCsr(0, 0, 0, None, None, None)
     assert call(A=empty, b=0, x=0) == B.OK                   # n = 0: nothing to do
     assert L.cbgmres_solve(C.byref(csr), None, None, None, None, 0, None, C.byref(res),
