@@ -55,23 +55,93 @@ __device__ __forceinline__ f32x4 mfma(s16x4 a, s16x4 b, f32x4 c)
 }
 
 // 27-point slot of entry (row, col) on an nx*ny*nz grid, or -1.
-__device__ __forceinline__ int slot_of(int64_t row, int64_t col, int nx, int ny)
+// Grid position of row i (x fastest); n < 2^31, so 32-bit arithmetic.
+struct RowPos {
+    int x, y;
+};
+__device__ __forceinline__ RowPos row_pos(int64_t i, int nx, int ny)
 {
-    const int64_t xr = row % nx, yr = (row / nx) % ny, zr = row / ((int64_t)nx * ny);
-    const int64_t xc = col % nx, yc = (col / nx) % ny, zc = col / ((int64_t)nx * ny);
-    const int64_t dx = xc - xr, dy = yc - yr, dz = zc - zr;
-    if (dx < -1 || dx > 1 || dy < -1 || dy > 1 || dz < -1 || dz > 1)
-        return -1;
-    return (int)((dz + 1) * 9 + (dy + 1) * 3 + (dx + 1));
+    const uint32_t u = (uint32_t)i, q = u / (uint32_t)nx;
+    return {(int)(u - q * (uint32_t)nx), (int)(q % (uint32_t)ny)};
 }
 
-__device__ __forceinline__ double row_diag(int64_t i, const int32_t *rp, const int32_t *ci,
-                                           const double *val)
+// Slot (0..26, 13 = the diagonal) of column c in row i on an nx x ny x nz
+// grid, or -1 if c is not one of i's 27 stencil neighbours.  A neighbour is
+// at offset d = c - i = dz nx ny + dy nx + dx with dx, dy, dz in {-1, 0, 1}
+// and its x, y inside the grid (then its z is too, as 0 <= c < n); since
+// grid points and indices correspond one to one, a triple that passes these
+// tests is the column's true offset.  For nx, ny >= 3 the ranges of d for
+// dz = -1, 0, 1 (and then of d - dz nx ny for dy) are disjoint, so the
+// triple follows from comparisons; smaller grids try the nine (dz, dy).
+__device__ __forceinline__ int slot_at(RowPos r, int64_t i, int64_t c, int nx, int ny)
 {
+    const int64_t d = c - i, S = (int64_t)nx * ny;
+    auto check = [&](int64_t dz, int64_t dy) -> int {
+        const int64_t dx = d - dz * S - dy * nx;
+        if (dx < -1 || dx > 1)
+            return -1;
+        const int64_t x = r.x + dx, y = r.y + dy;
+        if (x < 0 || x >= nx || y < 0 || y >= ny)
+            return -1;
+        return (int)((dz + 1) * 9 + (dy + 1) * 3 + (dx + 1));
+    };
+    if (nx >= 3 && ny >= 3) {
+        const int64_t zb = S - nx - 1;            // |d| >= zb only for dz = +-1
+        const int64_t dz = d >= zb ? 1 : (d <= -zb ? -1 : 0);
+        const int64_t rem = d - dz * S;
+        const int64_t dy = rem >= nx - 1 ? 1 : (rem <= -(nx - 1) ? -1 : 0);
+        return check(dz, dy);
+    }
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy) {
+            const int s = check(dz, dy);
+            if (s >= 0)
+                return s;
+        }
+    return -1;
+}
+
+// Row kernels: a half-wave (32 lanes) per row, HWR rows per 256-thread
+// block, lane l on the row's entries l, l + 32, ...: a row's indices and
+// values are read as one contiguous run, its outputs written the same way.
+// Loops that contain a barrier run the same number of times in every
+// half-wave of the block (the block's largest chunk count).
+constexpr int HWR = 8;
+
+// Largest number of 32-entry chunks over the block's rows (block-uniform
+// call).
+__device__ __forceinline__ int block_chunks(int chunks)
+{
+    __shared__ int m[HWR];
+    const int g = threadIdx.x >> 5;
+    if ((threadIdx.x & 31) == 0)
+        m[g] = chunks;
+    __syncthreads();
+    int r = 0;
+#pragma unroll
+    for (int k = 0; k < HWR; ++k)
+        r = max(r, m[k]);
+    __syncthreads();
+    return r;
+}
+
+// Row i's diagonal entry (the last one in CSR order if stored twice, 0 if
+// none), on every lane of the half-wave; `chunks` is uniform over the wave.
+__device__ __forceinline__ double hw_row_diag(int64_t i, int beg, int end, int chunks,
+                                              const int32_t *__restrict__ ci,
+                                              const double *__restrict__ val)
+{
+    const int lane = threadIdx.x & 31, half = threadIdx.x & 32;
     double d = 0.0;
-    for (int p = rp[i]; p < rp[i + 1]; ++p)
-        if (ci[p] == i)
-            d = val[p];
+    for (int q = 0; q < chunks; ++q) {
+        const int p = beg + q * 32 + lane;
+        const bool hit = p < end && ci[p] == i;
+        const double v = hit ? val[p] : 0.0;
+        const uint32_t mine = (uint32_t)(__ballot(hit) >> half);
+        const double last = __shfl(v, half + (mine ? 31 - __clz(mine) : 0));
+        if (mine)
+            d = last;
+    }
     return d;
 }
 
@@ -81,15 +151,25 @@ __global__ __launch_bounds__(256) void k_diag(int n, const int32_t *__restrict__
                                               const double *__restrict__ val,
                                               double *__restrict__ diag)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        diag[i] = row_diag(i, rp, ci, val);
+    const int g = threadIdx.x >> 5, lane = threadIdx.x & 31;
+    for (int64_t base = (int64_t)blockIdx.x * HWR; base < n; base += (int64_t)gridDim.x * HWR) {
+        const int64_t i = base + g;
+        const bool live = i < n;
+        const int beg = live ? rp[i] : 0, end = live ? rp[i + 1] : 0;
+        const int ch = (end - beg + 31) / 32;
+        const int chunks = max(ch, __shfl_xor(ch, 32));          // uniform over the wave
+        const double d = hw_row_diag(i, beg, end, chunks, ci, val);
+        if (live && lane == 0)
+            diag[i] = d;
+    }
 }
 
 // Features of each row: f_p = fl32(a_{i,c(p)} / a_ii) and f_{32+p} =
 // fl32(a_{c(p),c(p)} / a_ii) on present slots, f_27 = fl32((a_ii -
 // sum_{c != i} |a_ic|) / a_ii) with the sum in CSR order, the rest 0; all
-// rounded to bf16.
+// rounded to bf16.  The entries' terms go through LDS; one lane adds them
+// in CSR order.  (Columns are unique within a row, so each slot is written
+// at most once.)
 __global__ __launch_bounds__(256) void k_features(int n, const int32_t *__restrict__ rp,
                                                   const int32_t *__restrict__ ci,
                                                   const double *__restrict__ val, int nx, int ny,
@@ -97,47 +177,49 @@ __global__ __launch_bounds__(256) void k_features(int n, const int32_t *__restri
                                                   uint16_t *__restrict__ feat,
                                                   unsigned *__restrict__ bad)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const double d = diag[i];
-        uint16_t f[NF];
-#pragma unroll
-        for (int k = 0; k < NF; ++k)
-            f[k] = 0;
+    __shared__ double loff[HWR][32];
+    __shared__ uint16_t lf[HWR][NF];
+    const int g = threadIdx.x >> 5, lane = threadIdx.x & 31;
+    for (int64_t base = (int64_t)blockIdx.x * HWR; base < n; base += (int64_t)gridDim.x * HWR) {
+        const int64_t i = base + g;
+        const bool live = i < n;
+        const int beg = live ? rp[i] : 0, end = live ? rp[i + 1] : 0;
+        const double d = live ? diag[i] : 1.0;
+        const RowPos rpos = row_pos(live ? i : 0, nx, ny);
+        lf[g][2 * lane] = 0;
+        lf[g][2 * lane + 1] = 0;
+        const int chunks = block_chunks((end - beg + 31) / 32);
         double off = 0.0;
-        for (int p = rp[i]; p < rp[i + 1]; ++p) {
-            const int64_t c = ci[p];
-            const double a = val[p];
-            if (c != i)
-                off += fabs(a);
-            const int s = slot_of(i, c, nx, ny);
+        for (int q = 0; q < chunks; ++q) {
+            const int p = beg + q * 32 + lane;
+            const bool in = p < end;
+            const int64_t c = in ? ci[p] : -1;
+            const double a = in ? val[p] : 0.0;
+            loff[g][lane] = (in && c != i) ? fabs(a) : 0.0;
+            const int s = in ? slot_at(rpos, i, c, nx, ny) : -1;
             if (s >= 0) {
-                const uint16_t fa = bf16_of((float)(a / d));
-                const uint16_t fd = bf16_of((float)(diag[c] / d));
-                // slot index is data-dependent: write through a switch-free
-                // select so f stays in registers
-#pragma unroll
-                for (int k = 0; k < NSLOT; ++k)
-                    if (k == s) {
-                        f[k] = fa;
-                        f[NBR + k] = fd;
-                    }
+                lf[g][s] = bf16_of((float)(a / d));
+                lf[g][NBR + s] = bf16_of((float)(diag[c] / d));
             }
+            __syncthreads();
+            if (lane == 0) {
+                const int m = min(32, end - (beg + q * 32));
+                for (int k = 0; k < m; ++k)
+                    off += loff[g][k];
+            }
+            __syncthreads();
         }
-        const double margin = (d - off) / d;
-        if (!(d != 0.0) || !isfinite(margin))
-            *bad = 1u;
-        f[27] = bf16_of((float)margin);
-        uint32_t w[NF / 2];
-#pragma unroll
-        for (int k = 0; k < NF / 2; ++k)
-            w[k] = (uint32_t)f[2 * k] | ((uint32_t)f[2 * k + 1] << 16);
-        u32x4 *dst = (u32x4 *)(feat + i * NF);
-#pragma unroll
-        for (int q = 0; q < NF / 8; ++q) {
-            u32x4 v = {w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]};
-            dst[q] = v;
+        if (lane == 0 && live) {
+            const double margin = (d - off) / d;
+            if (!(d != 0.0) || !isfinite(margin))
+                *bad = 1u;
+            lf[g][27] = bf16_of((float)margin);
         }
+        __syncthreads();
+        if (live)
+            ((uint32_t *)(feat + i * NF))[lane] =
+                (uint32_t)lf[g][2 * lane] | ((uint32_t)lf[g][2 * lane + 1] << 16);
+        __syncthreads();
     }
 }
 
@@ -277,60 +359,66 @@ __global__ __launch_bounds__(256) void k_forward(int n, const uint16_t *__restri
     }
 }
 
-// P on A's pattern from the network output (one thread per row).
+// P on A's pattern from the network output (a half-wave per row).
 __global__ __launch_bounds__(256) void k_assemble(int n, const int32_t *__restrict__ rp,
                                                   const int32_t *__restrict__ ci,
                                                   const double *__restrict__ val, int nx, int ny,
                                                   const float *__restrict__ O,
                                                   float *__restrict__ pval)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const double d = row_diag(i, rp, ci, val);
-        for (int p = rp[i]; p < rp[i + 1]; ++p) {
-            const int s = slot_of(i, ci[p], nx, ny);
-            double v = 0.0;
-            if (s >= 0)
-                v = ((s == CENTER ? 1.0 : 0.0) + (double)O[i * NO + s]) / d;
-            pval[p] = (float)v;
+    const int g = threadIdx.x >> 5, lane = threadIdx.x & 31;
+    for (int64_t base = (int64_t)blockIdx.x * HWR; base < n; base += (int64_t)gridDim.x * HWR) {
+        const int64_t i = base + g;
+        const bool live = i < n;
+        const int beg = live ? rp[i] : 0, end = live ? rp[i + 1] : 0;
+        const int ch = (end - beg + 31) / 32;
+        const int chunks = max(ch, __shfl_xor(ch, 32));
+        const double d = hw_row_diag(i, beg, end, chunks, ci, val);
+        const RowPos rpos = row_pos(live ? i : 0, nx, ny);
+        for (int q = 0; q < chunks; ++q) {
+            const int p = beg + q * 32 + lane;
+            if (p < end) {
+                const int s = slot_at(rpos, i, ci[p], nx, ny);
+                double v = 0.0;
+                if (s >= 0)
+                    v = ((s == CENTER ? 1.0 : 0.0) + (double)O[i * NO + s]) / d;
+                pval[p] = (float)v;
+            }
         }
     }
 }
 
-// dL/dO (bf16, n x 32) from dL/dP: dO_{i,p} = dP_{i,c(p)} / a_ii.
+// dL/dO (bf16, n x 32) from dL/dP: dO_{i,p} = dP_{i,c(p)} / a_ii (a
+// half-wave per row; the row's 32 slots assembled in LDS).
 __global__ __launch_bounds__(256) void k_grad_o(int n, const int32_t *__restrict__ rp,
                                                 const int32_t *__restrict__ ci,
                                                 const double *__restrict__ val, int nx, int ny,
                                                 const double *__restrict__ dP,
                                                 uint16_t *__restrict__ dO)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const double d = row_diag(i, rp, ci, val);
-        uint16_t g[NO];
-#pragma unroll
-        for (int k = 0; k < NO; ++k)
-            g[k] = 0;
-        for (int p = rp[i]; p < rp[i + 1]; ++p) {
-            const int s = slot_of(i, ci[p], nx, ny);
-            if (s >= 0) {
-                const uint16_t b = bf16_of_d(dP[p] / d);
-#pragma unroll
-                for (int k = 0; k < NSLOT; ++k)
-                    if (k == s)
-                        g[k] = b;
+    __shared__ uint16_t lg[HWR][NO];
+    const int g = threadIdx.x >> 5, lane = threadIdx.x & 31;
+    for (int64_t base = (int64_t)blockIdx.x * HWR; base < n; base += (int64_t)gridDim.x * HWR) {
+        const int64_t i = base + g;
+        const bool live = i < n;
+        const int beg = live ? rp[i] : 0, end = live ? rp[i + 1] : 0;
+        const int chunks = block_chunks((end - beg + 31) / 32);
+        const double d = hw_row_diag(i, beg, end, chunks, ci, val);
+        const RowPos rpos = row_pos(live ? i : 0, nx, ny);
+        lg[g][lane] = 0;
+        __syncthreads();
+        for (int q = 0; q < chunks; ++q) {
+            const int p = beg + q * 32 + lane;
+            if (p < end) {
+                const int s = slot_at(rpos, i, ci[p], nx, ny);
+                if (s >= 0)
+                    lg[g][s] = bf16_of_d(dP[p] / d);
             }
         }
-        uint32_t w[NO / 2];
-#pragma unroll
-        for (int k = 0; k < NO / 2; ++k)
-            w[k] = (uint32_t)g[2 * k] | ((uint32_t)g[2 * k + 1] << 16);
-        u32x4 *dst = (u32x4 *)(dO + i * NO);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            u32x4 v = {w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]};
-            dst[q] = v;
-        }
+        __syncthreads();
+        if (live)
+            dO[i * NO + lane] = lg[g][lane];
+        __syncthreads();
     }
 }
 
@@ -907,9 +995,9 @@ int cbg_spai_features(const cbg_csr *A, const int32_t grid[3], uint16_t *feat, v
     hipStream_t s = (hipStream_t)stream;
     SpaiWs W = carve_spai(ws, A->n, A->nnz, 0, nullptr);
     SP_TRY(hipMemsetAsync(W.bad, 0, sizeof(unsigned), s));
-    hipLaunchKernelGGL(k_diag, dim3(row_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
+    hipLaunchKernelGGL(k_diag, dim3(group_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
                        A->col_idx, A->val, W.diag);
-    hipLaunchKernelGGL(k_features, dim3(row_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
+    hipLaunchKernelGGL(k_features, dim3(group_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
                        A->col_idx, A->val, grid[0], grid[1], (const double *)W.diag, feat,
                        W.bad);
     SP_TRY(hipGetLastError());
@@ -940,7 +1028,7 @@ int cbg_spai_assemble(const cbg_csr *A, const int32_t grid[3], const float *out,
         return CBG_E_ARG;
     if (A->n == 0)
         return CBG_OK;
-    hipLaunchKernelGGL(k_assemble, dim3(row_grid(A->n)), dim3(256), 0, (hipStream_t)stream, A->n,
+    hipLaunchKernelGGL(k_assemble, dim3(group_grid(A->n)), dim3(256), 0, (hipStream_t)stream, A->n,
                        A->row_ptr, A->col_idx, A->val, grid[0], grid[1], out, p_val);
     SP_TRY(hipGetLastError());
     return CBG_OK;
@@ -960,13 +1048,13 @@ int cbg_learned_build(const cbg_csr *A, const int32_t grid[3], const uint16_t *w
     hipStream_t s = (hipStream_t)stream;
     SpaiWs W = carve_spai(ws, A->n, A->nnz, 0, nullptr);
     SP_TRY(hipMemsetAsync(W.bad, 0, sizeof(unsigned), s));
-    hipLaunchKernelGGL(k_diag, dim3(row_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
+    hipLaunchKernelGGL(k_diag, dim3(group_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
                        A->col_idx, A->val, W.diag);
-    hipLaunchKernelGGL(k_features, dim3(row_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
+    hipLaunchKernelGGL(k_features, dim3(group_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
                        A->col_idx, A->val, grid[0], grid[1], (const double *)W.diag, W.feat,
                        W.bad);
     enqueue_forward(A->n, W.feat, weights, params, W.O, nullptr, nullptr, s);
-    hipLaunchKernelGGL(k_assemble, dim3(row_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
+    hipLaunchKernelGGL(k_assemble, dim3(group_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
                        A->col_idx, A->val, grid[0], grid[1], (const float *)W.O, p_val);
     SP_TRY(hipGetLastError());
     unsigned bad = 0;
@@ -1034,7 +1122,7 @@ int cbg_spai_grad_o(const cbg_csr *A, const int32_t grid[3], const double *dP, u
         return CBG_E_ARG;
     if (A->n == 0)
         return CBG_OK;
-    hipLaunchKernelGGL(k_grad_o, dim3(row_grid(A->n)), dim3(256), 0, (hipStream_t)stream, A->n,
+    hipLaunchKernelGGL(k_grad_o, dim3(group_grid(A->n)), dim3(256), 0, (hipStream_t)stream, A->n,
                        A->row_ptr, A->col_idx, A->val, grid[0], grid[1], dP, dO);
     SP_TRY(hipGetLastError());
     return CBG_OK;
@@ -1077,11 +1165,11 @@ int cbg_spai_loss_grad(const cbg_csr *A, const double *t_val, const int32_t grid
         return CBG_OK;
     }
     enqueue_forward(A->n, feat, weights, params, W.O, W.h1, W.h2, s);
-    hipLaunchKernelGGL(k_assemble, dim3(row_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
+    hipLaunchKernelGGL(k_assemble, dim3(group_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
                        A->col_idx, A->val, grid[0], grid[1], (const float *)W.O, W.pval);
     if ((e = enqueue_grad_p(A, t_val, W.pval, K, V, scale, loss, accumulate, W.dP, W, s)))
         return e;
-    hipLaunchKernelGGL(k_grad_o, dim3(row_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
+    hipLaunchKernelGGL(k_grad_o, dim3(group_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
                        A->col_idx, A->val, grid[0], grid[1], (const double *)W.dP, W.dO);
     return enqueue_backward(A->n, feat, W.h1, W.h2, W.dO, weights, grad, accumulate, W, s);
 }
