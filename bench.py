@@ -92,40 +92,57 @@ def pmc_summary(fetch_csv: str, write_csv: str, fmt: str, grid: int) -> dict:
 
 
 def trace_summary(trace_csv: str, fmt: str, grid: int, restart: int = 100) -> dict:
-    """Per-j durations of the multi-dot from a rocprofv3 --kernel-trace CSV
-    of bench runs: the solver launches one multi-dot per Arnoldi step, j =
-    1..restart in every cycle (launches after a cycle ended return at once),
-    so dispatch k in launch order belongs to step j = k mod restart + 1.
-    Per j: the median duration over all cycles and the algorithmic GB/s
-    (j n b_s + 8 n bytes); plus the j-weighted rate over j >= 20."""
+    """Per-j durations of the basis-streaming kernels and the step SpMV from
+    a rocprofv3 --kernel-trace CSV of bench runs.  The solver launches each
+    of them once per Arnoldi step, j = 1..restart in every cycle (launches
+    after a cycle ended return at once), so dispatch k of a kernel in launch
+    order belongs to step j = k mod restart + 1.  Per kernel and j: the
+    median duration over all cycles and the algorithmic GB/s; per kernel the
+    j-weighted rate over all j and over j >= 20.  Algorithmic bytes: the
+    multi-dot j n b_s + 8 n; the fused update + re-dot and the
+    re-orthogonalising update j n b_s + 16 n; the step SpMV 12 nnz + 4 (n+1)
+    + 16 n + n b_s (the 7-point system: nnz = 7 N^3 - 6 N^2)."""
     import csv
     import statistics
     fmt_id = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "e4m3": 4, "int32": 5, "int16": 6,
               "fp16s": 7}[fmt]
     bs = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2, "e4m3": 1, "int32": 4, "int16": 2,
           "fp16s": 2}[fmt]
-    kname = f"k_multidot<{fmt_id}>"
-    rows = [r for r in csv.DictReader(open(trace_csv)) if kname in r["Kernel_Name"]]
-    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
-    if not rows or len(rows) % restart:
-        raise SystemExit(f"{trace_csv}: {len(rows)} {kname} dispatches, not a multiple of "
-                         f"{restart}")
     n = grid ** 3
-    per_j = {}
-    for k, r in enumerate(rows):
-        per_j.setdefault(k % restart + 1, []).append(
-            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
-    table = []
-    for j in sorted(per_j):
-        med = statistics.median(per_j[j])
-        by = j * n * bs + 8.0 * n
-        table.append({"j": j, "median_us": med * 1e6, "gbps": by / med / 1e9,
-                      "samples": len(per_j[j])})
-    sel = [t for t in table if t["j"] >= 20]
-    tot_b = sum(t["j"] * n * bs + 8.0 * n for t in sel)
-    tot_t = sum(t["median_us"] * 1e-6 for t in sel)
-    return {"kernel": kname, "format": fmt, "grid": grid, "dispatches": len(rows),
-            "j_weighted_gbps_j_ge_20": tot_b / tot_t / 1e9, "per_j": table}
+    nnz = 7 * grid ** 3 - 6 * grid ** 2
+    kernels = {
+        f"k_multidot<{fmt_id}>": lambda j: j * n * bs + 8.0 * n,
+        f"k_update_redot<{fmt_id},": lambda j: j * n * bs + 16.0 * n,
+        f"k_update<{fmt_id}, 2>": lambda j: j * n * bs + 16.0 * n,
+        "k_spmv<256, 2048, 8>": lambda j: 12.0 * nnz + 4.0 * (n + 1) + 16.0 * n + n * bs,
+    }
+    rows = list(csv.DictReader(open(trace_csv)))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    out = {"format": fmt, "grid": grid, "kernels": {}}
+    for key, model in kernels.items():
+        sel = [r for r in rows if key in r["Kernel_Name"]]
+        if not sel or len(sel) % restart:
+            raise SystemExit(f"{trace_csv}: {len(sel)} dispatches of {key}, not a multiple of "
+                             f"{restart}")
+        per_j = {}
+        for k, r in enumerate(sel):
+            per_j.setdefault(k % restart + 1, []).append(
+                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
+        table = [{"j": j, "median_us": statistics.median(v) * 1e6,
+                  "gbps": model(j) / statistics.median(v) / 1e9, "samples": len(v)}
+                 for j, v in sorted(per_j.items())]
+
+        def weighted(tab):
+            return sum(model(t["j"]) for t in tab) / sum(t["median_us"] * 1e-6 for t in tab) / 1e9
+        out["kernels"][key.rstrip(",")] = {
+            "dispatches": len(sel), "j_weighted_gbps": weighted(table),
+            "j_weighted_gbps_j_ge_20": weighted([t for t in table if t["j"] >= 20]),
+            "per_j": table}
+    md = out["kernels"][f"k_multidot<{fmt_id}>"]
+    # the multi-dot's figures at the top level (the roofline kernel)
+    out.update({"kernel": f"k_multidot<{fmt_id}>", "dispatches": md["dispatches"],
+                "j_weighted_gbps_j_ge_20": md["j_weighted_gbps_j_ge_20"], "per_j": md["per_j"]})
+    return out
 
 
 def copy_rate_gbps(torch, dev, nbytes: int = 2 ** 30) -> float:
@@ -170,7 +187,7 @@ def main() -> int:
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the multi-dot traffic record from two counter runs and exit")
     ap.add_argument("--trace-summary", metavar="KERNEL_TRACE_CSV",
-                    help="print the multi-dot's per-j durations from a kernel trace and exit")
+                    help="print per-j rates of the step kernels from a kernel trace and exit")
     args = ap.parse_args()
     if args.trace_summary:
         print(json.dumps(trace_summary(args.trace_summary, args.format, args.grid)))

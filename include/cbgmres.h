@@ -131,7 +131,20 @@ typedef struct {
  * what the sequential projections buy).  Not combinable with the PROFILE
  * flags (CBG_E_UNSUPPORTED). */
 #define CBG_FLAG_MGS 32
-#define CBG_FLAG_ALL 63     /* any other bit is an argument error */
+/* Where steps 13-14 of the previous step run (same bits either way):
+ * NORMALISE_PASS: a pass of their own (v_j = w / t written once, stored
+ * through the accessor, and with Jacobi multiplied by D^-1 there), then
+ * step 3's SpMV reads the result;
+ * NORMALISE_GATHER: inside step 3's SpMV, which divides each gathered
+ * entry by t (one division per nonzero instead of per row) and with Jacobi
+ * reads D^-1 per nonzero.
+ * Neither bit: the pass when the mean row length exceeds 12 nonzeros or the
+ * preconditioner is Jacobi, the gather otherwise.  Both bits: argument
+ * error.  SPMV_VHAT and the block-Jacobi preconditioner always take their
+ * own paths. */
+#define CBG_FLAG_NORMALISE_PASS 64
+#define CBG_FLAG_NORMALISE_GATHER 128
+#define CBG_FLAG_ALL 255    /* any other bit is an argument error */
 
 typedef struct {
     int64_t iterations;        /* Arnoldi steps (SpMVs with A inside cycles) */

@@ -28,6 +28,10 @@ FLAG_PROFILE_DOT = 4
 FLAG_SPMV_VHAT = 8
 FLAG_ALWAYS_REORTH = 16
 FLAG_MGS = 32
+FLAG_NORMALISE_PASS = 64
+FLAG_NORMALISE_GATHER = 128
+# where steps 13-14 run: solve(..., normalise=...)
+NORMALISE = {"auto": 0, "pass": FLAG_NORMALISE_PASS, "gather": FLAG_NORMALISE_GATHER}
 # Arnoldi-step ablations by name (solve(..., variant=...))
 VARIANTS = {"spmv_vhat": FLAG_SPMV_VHAT, "always_reorth": FLAG_ALWAYS_REORTH, "mgs": FLAG_MGS}
 MAX_RESTART = 512
@@ -253,11 +257,14 @@ class SolveResult:
 
 def solve(A: DeviceCSR, b, x0=None, restart=100, fmt="fp64", tol=1e-10, maxiter=10000,
           eta=0.0, precond="none", p_val=None, fallback=False, profile=False, workspace=None,
-          hist=True, fuse=True, pc_block=0, pc_prec=0, variant=()) -> SolveResult:
+          hist=True, fuse=True, pc_block=0, pc_prec=0, variant=(),
+          normalise="auto") -> SolveResult:
     """cbgmres_solve on device tensors; returns the solution and counters.
     profile: False, True (event-time every basis-streaming launch) or "dot"
     (only the multi-dot launches).  variant: names from VARIANTS (ablations
-    of the Arnoldi step).  Raises CbgError on a negative status."""
+    of the Arnoldi step).  normalise: "auto", "pass" or "gather" (where
+    v_j = w / t is formed; the same bits either way).  Raises CbgError on a
+    negative status."""
     torch = _torch()
     x = torch.zeros(A.n, dtype=torch.float64, device=b.device) if x0 is None else x0.clone()
     need = workspace_bytes(A.n, restart, fmt, precond)
@@ -266,7 +273,7 @@ def solve(A: DeviceCSR, b, x0=None, restart=100, fmt="fp64", tol=1e-10, maxiter=
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=b.device)
     flags = {False: 0, True: FLAG_PROFILE, "dot": FLAG_PROFILE_DOT}[profile] \
-        | (0 if fuse else FLAG_NO_FUSE)
+        | (0 if fuse else FLAG_NO_FUSE) | NORMALISE[normalise]
     for name in ((variant,) if isinstance(variant, str) else variant):
         flags |= VARIANTS[name]
     opts = CbgOpts(restart, FORMATS[fmt], tol, maxiter, eta, PRECONDS[precond],

@@ -1411,6 +1411,82 @@ __global__ __launch_bounds__(BLK) void k_normalize(const double *__restrict__ w,
     }
 }
 
+// Steps 13-14 of the previous Arnoldi step as a pass of their own, for
+// matrices whose rows are long enough that dividing each gathered entry by t
+// inside the next SpMV costs more than one extra sweep of v: v = w / t (IEEE
+// division, the bits the gather forms), stored through the accessor, and
+// written out as z = v, or z = dinv .* v for the Jacobi preconditioner (the
+// product the gather forms, so that step 3 runs as the plain SpMV).
+// Each thread owns NP pairs of consecutive entries, BLK pairs apart: every
+// load and store of a wave is contiguous, and all NP loads are issued before
+// the first division.
+template <int F>
+__device__ __forceinline__ void store_pair(uint8_t *__restrict__ Q, int64_t i, double a, double b,
+                                           EncParam p)
+{
+    if constexpr (F == F_FP64) {
+        f64x2 v = {a, b};
+        *(f64x2 *)(Q + i * 8) = v;
+    } else if constexpr (F == F_FP32) {
+        u32x2 v = {__float_as_uint((float)a), __float_as_uint((float)b)};
+        *(u32x2 *)(Q + i * 4) = v;
+    } else if constexpr (F == F_INT32) {
+        u32x2 v = {Fmt<F_INT32>::code(a, p), Fmt<F_INT32>::code(b, p)};
+        *(u32x2 *)(Q + i * 4) = v;
+    } else if constexpr (F == F_E4M3) {
+        *(uint16_t *)(Q + i) = (uint16_t)(Fmt<F>::code(a, p) | (Fmt<F>::code(b, p) << 8));
+    } else {
+        *(uint32_t *)(Q + i * 2) = Fmt<F>::code(a, p) | (Fmt<F>::code(b, p) << 16);
+    }
+}
+
+template <int F>
+__global__ __launch_bounds__(BLK) void k_step_normalize(const double *__restrict__ w, int n,
+                                                        int64_t ld, const double *__restrict__ dinv,
+                                                        double *__restrict__ z,
+                                                        uint8_t *__restrict__ Q,
+                                                        const double *__restrict__ scale_slot,
+                                                        const DevState *st)
+{
+    constexpr int NP = 4;
+    if (st->done)
+        return;
+    const double t = st->t;
+    const EncParam p = param_from_scale(F, *scale_slot);
+    const int64_t npair = ld / 2;                         // ld is a multiple of 16
+    for (int64_t base = blockIdx.x * (int64_t)(BLK * NP); base < npair;
+         base += (int64_t)gridDim.x * BLK * NP) {
+        f64x2 v[NP], d[NP];
+#pragma unroll
+        for (int u = 0; u < NP; ++u) {
+            const int64_t q = base + u * BLK + threadIdx.x;
+            const int64_t i = 2 * q;
+            if (q < npair && i + 1 < n) {
+                v[u] = *(const f64x2 *)(w + i);
+            } else {
+                v[u].x = q < npair && i < n ? w[i] : 0.0;  // entries >= n are 0
+                v[u].y = 0.0;
+            }
+            if (dinv && q < npair)
+                d[u] = *(const f64x2 *)(dinv + i);        // dinv holds 0 beyond n
+        }
+#pragma unroll
+        for (int u = 0; u < NP; ++u) {
+            const int64_t q = base + u * BLK + threadIdx.x;
+            if (q >= npair)
+                continue;
+            const double a = v[u].x / t, b = v[u].y / t;
+            store_pair<F>(Q, 2 * q, a, b, p);
+            f64x2 o = {a, b};
+            if (dinv) {
+                o.x = d[u].x * a;
+                o.y = d[u].y * b;
+            }
+            *(f64x2 *)(z + 2 * q) = o;
+        }
+    }
+}
+
 // The accessor's load for the kernel-level API: v = dec(q) exactly.
 template <int F>
 __global__ __launch_bounds__(BLK) void k_decode(const uint8_t *__restrict__ Q, int n,
@@ -1736,6 +1812,15 @@ void launch_normalize(int fmt, const double *w, int n, int64_t nst, double *v_ou
     CBG_FMT_SWITCH(fmt, (k_normalize<F><<<g, BLK, 0, s>>>(w, n, nst, v_out, (uint8_t *)Q,
                                                            scale_slot, tptr, tval, st,
                                                            check_done, fmt)))
+}
+
+void launch_step_normalize(int fmt, const double *w, int n, int64_t ld, const double *dinv,
+                           double *z, void *Q, const double *scale_slot, const DevState *st,
+                           hipStream_t s)
+{
+    const int g = grid_for((ld / 2 + BLK * 4 - 1) / (BLK * 4), 1);
+    CBG_FMT_SWITCH(fmt, (k_step_normalize<F><<<g, BLK, 0, s>>>(w, n, ld, dinv, z, (uint8_t *)Q,
+                                                                scale_slot, st)))
 }
 
 void launch_decode(int fmt, const void *Q, int n, const double *scale, double *v, hipStream_t s)

@@ -100,6 +100,11 @@ void launch_reduce(const RedWs &ws, int role, int nb_orth, int nb_spmv, int j, D
 void launch_normalize(int fmt, const double *w, int n, int64_t nst, double *v_out, void *Q,
                       const double *scale_slot, const double *tptr, double tval,
                       const DevState *st, int check_done, hipStream_t s);
+// steps 13-14 as a pass: v = w / t stored through the accessor, z = v, or
+// dinv .* v when dinv is given; skipped once the cycle is done
+void launch_step_normalize(int fmt, const double *w, int n, int64_t ld, const double *dinv,
+                           double *z, void *Q, const double *scale_slot, const DevState *st,
+                           hipStream_t s);
 void launch_decode(int fmt, const void *Q, int n, const double *scale, double *v, hipStream_t s);
 int launch_norm(const double *x, int64_t n, const RedWs &ws, hipStream_t s);
 void launch_init_state(DevState *st, int n, int m, int fmt, double tol, double eta,

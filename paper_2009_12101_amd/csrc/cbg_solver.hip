@@ -60,7 +60,7 @@ struct SolveWs {
     size_t v_off, scales_off;   // byte offsets of V and scales in the workspace
     DevState *st;
     uint8_t *V;
-    double *scales, *w0, *w1, *z, *dinv, *xprev;
+    double *scales, *w0, *w1, *z, *v, *dinv, *xprev;
     int8_t *bj_tags;               // block-Jacobi: per-block storage precision
     double *bj64;                  // and the inverted blocks by precision
     float *bj32;
@@ -85,6 +85,7 @@ SolveWs carve_solve(void *ws, int32_t n, int32_t m, int fmt, int pc, size_t *tot
     s.w1 = c.take<double>(ld);   // alternate between these two buffers
     const bool bj = pc == CBG_PC_BLOCK_JACOBI;
     s.z = c.take<double>(pc == CBG_PC_SPARSE || bj ? ld : 1);
+    s.v = c.take<double>(bj ? 1 : ld);   // v_j from the separate normalising pass
     s.dinv = c.take<double>(pc == CBG_PC_JACOBI ? ld : 1);
     s.xprev = c.take<double>(pc == CBG_PC_SPARSE ? ld : 1);
     // sized for the largest block size: ceil(n/bs) bs^2 <= n BJ_MAX + BJ_MAX^2
@@ -255,7 +256,8 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
     if (n < 0 || A->nnz < 0 || m < 1 || m > CBG_MAX_RESTART || !valid_format(fmt) ||
         !(opt->tol >= 0.0) || !isfinite(opt->tol) || opt->maxiter < 0 || pc0 < CBG_PC_NONE ||
         pc0 > CBG_PC_BLOCK_JACOBI || (hist_len > 0 && !hist_out) || hist_len < 0 ||
-        (opt->flags & ~CBG_FLAG_ALL) != 0)
+        (opt->flags & ~CBG_FLAG_ALL) != 0 ||
+        (~opt->flags & (CBG_FLAG_NORMALISE_PASS | CBG_FLAG_NORMALISE_GATHER)) == 0)
         return fail(CBG_E_ARG);
     const int bj_bs = opt->pc_block > 0 ? opt->pc_block : 4;
     const int bj_prec = opt->pc_prec > 0 ? opt->pc_prec : 16;
@@ -292,6 +294,14 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
     const bool mgs = (opt->flags & CBG_FLAG_MGS) != 0;
     if (mgs && prof)
         return fail(CBG_E_UNSUPPORTED);     // event timing covers the CGS kernels only
+    // steps 13-14 in a pass of their own, or inside the next SpMV's gather:
+    // one division per row against one per nonzero, so long rows favour the
+    // pass; with Jacobi the pass also forms dinv .* v once, where the gather
+    // reads dinv per nonzero
+    const bool norm_pass = !vhat && pc0 != CBG_PC_BLOCK_JACOBI &&
+        ((opt->flags & CBG_FLAG_NORMALISE_PASS) != 0 ||
+         ((opt->flags & CBG_FLAG_NORMALISE_GATHER) == 0 &&
+          ((double)A->nnz > 12.0 * n || pc0 == CBG_PC_JACOBI)));
     // steps whose update and re-dot share one basis pass
     auto fused = [&](int j) { return fuse && fused_takes(fmt, basis_ld(n), j); };
     ByteModel bm{(double)n, (double)A->nnz, (double)fmt_bytes(fmt)};
@@ -422,6 +432,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                 if (prev_pc == CBG_PC_JACOBI) b_step += 8.0 * n;
                 if (prev_pc == CBG_PC_SPARSE) b_step += 8.0 * A->nnz + 4.0 * (n + 1) + 16.0 * n;
                 if (prev_pc == CBG_PC_BLOCK_JACOBI) b_step += bj_bytes + 16.0 * n;
+                if (norm_pass) b_step += 16.0 * n;  // v written by the pass, read by the SpMV
                 if (!fused(j) && !mgs)
                     b_step += bm.dot(j);             // the separate re-dot pass
                 if (ro) b_step += mgs ? b_mgs : bm.upd(j);
@@ -491,9 +502,15 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
             } else if (pc == CBG_PC_SPARSE) {
                 SpmvArgs a{};
                 a.n = n; a.ldy = ld; a.rp = A->row_ptr; a.ci = A->col_idx; a.fval = opt->p_val;
-                a.x = cur; a.y = W.z; a.ws = W.red; a.mode = (vhat << 4) | 8 | 3 /*SP_STEP_FLOATVAL*/;
-                a.role = 0 /*SR_NONE*/; a.sg = sg; a.st = W.st;
-                a.Q = slot; a.qscale = W.scales + (j - 1); a.fmt = fmt;
+                a.y = W.z; a.ws = W.red; a.role = 0 /*SR_NONE*/; a.sg = sg; a.st = W.st;
+                if (norm_pass) {
+                    launch_step_normalize(fmt, cur, n, ld, nullptr, W.v, slot, W.scales + (j - 1),
+                                          W.st, s);
+                    a.x = W.v; a.mode = 3 /*SP_FLOATVAL*/;
+                } else {
+                    a.x = cur; a.mode = (vhat << 4) | 8 | 3 /*SP_STEP_FLOATVAL*/;
+                    a.Q = slot; a.qscale = W.scales + (j - 1); a.fmt = fmt;
+                }
                 launch_spmv(a, s);
                 SpmvArgs b2{};
                 b2.n = n; b2.ldy = ld; b2.rp = A->row_ptr; b2.ci = A->col_idx; b2.val = A->val;
@@ -503,10 +520,18 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
             } else {
                 SpmvArgs a{};
                 a.n = n; a.ldy = ld; a.rp = A->row_ptr; a.ci = A->col_idx; a.val = A->val;
-                a.x = cur; a.dinv = W.dinv; a.y = nxt; a.ws = W.red;
-                a.mode = (vhat << 4) | (pc == CBG_PC_JACOBI ? (8 | 1) : (8 | 0));
-                a.role = 1 /*SR_STEP*/;
-                a.sg = sg; a.st = W.st; a.Q = slot; a.qscale = W.scales + (j - 1); a.fmt = fmt;
+                a.dinv = W.dinv; a.y = nxt; a.ws = W.red; a.role = 1 /*SR_STEP*/;
+                a.sg = sg; a.st = W.st;
+                const int base = pc == CBG_PC_JACOBI ? 1 /*SP_JACOBI*/ : 0 /*SP_PLAIN*/;
+                if (norm_pass) {
+                    // z = M^-1 v_j formed by the pass: step 3 is the plain SpMV
+                    launch_step_normalize(fmt, cur, n, ld, pc == CBG_PC_JACOBI ? W.dinv : nullptr,
+                                          W.v, slot, W.scales + (j - 1), W.st, s);
+                    a.x = W.v; a.mode = 0 /*SP_PLAIN*/;
+                } else {
+                    a.x = cur; a.mode = (vhat << 4) | 8 | base;
+                    a.Q = slot; a.qscale = W.scales + (j - 1); a.fmt = fmt;
+                }
                 nb_spmv = launch_spmv(a, s);
             }
             if (mgs) {
