@@ -156,7 +156,7 @@ def test_unknown_flag_bits_are_argument_errors(cbg, dev):
     b = torch.ones(A.n, dtype=torch.float64, device=dev)
     x = torch.zeros_like(b)
     ws = torch.empty(B.workspace_bytes(A.n, 8, "fp64"), dtype=torch.uint8, device=dev)
-    opts = B.CbgOpts(8, 0, 1e-10, 10, 0.0, 0, 0, None, 64, 0, 0, 0)
+    opts = B.CbgOpts(8, 0, 1e-10, 10, 0.0, 0, 0, None, 256, 0, 0, 0)
     res = B.CbgResult()
     csr = Ad.cstruct()
     rc = B.lib().cbgmres_solve(C.byref(csr), B._ptr(b), B._ptr(x), C.byref(opts), B._ptr(ws),
