@@ -563,7 +563,8 @@ int orc_gmres(int32_t n, const int32_t *rp, const int32_t *ci, const double *val
     const int bs = orc_format_bytes(fmt);
     if (n < 0 || m < 1 || bs == 0 || !(opt->tol >= 0.0) || opt->maxiter < 0 ||
         opt->precond < ORC_PC_NONE || opt->precond > ORC_PC_BLOCK_JACOBI ||
-        (opt->variant & ~(ORC_V_SPMV_VHAT | ORC_V_ALWAYS_REORTH | ORC_V_MGS)) != 0 ||
+        (opt->variant & ~(ORC_V_SPMV_VHAT | ORC_V_ALWAYS_REORTH | ORC_V_MGS | ORC_V_GRAM)) != 0 ||
+        ((opt->variant & ORC_V_MGS) && (opt->variant & ORC_V_GRAM)) ||
         (opt->precond == ORC_PC_SPARSE && !opt->p_val) ||
         (n > 0 && (!rp || !ci || !val || !b || !x))) {
         res->status = ORC_E_ARG;
@@ -581,6 +582,7 @@ int orc_gmres(int32_t n, const int32_t *rp, const int32_t *ci, const double *val
     const int spmv_vhat = (opt->variant & ORC_V_SPMV_VHAT) != 0;
     const int always_reorth = (opt->variant & ORC_V_ALWAYS_REORTH) != 0;
     const int mgs = (opt->variant & ORC_V_MGS) != 0;
+    const int gram = (opt->variant & ORC_V_GRAM) != 0;
 
     /* Fig. 1 works with ||b||_2 as the reference of the stop test (R8). */
     const double nb = sqrt(orc_dot(n, b, b));
@@ -647,6 +649,11 @@ int orc_gmres(int32_t n, const int32_t *rp, const int32_t *ci, const double *val
     double *sn = (double *)malloc((size_t)(m + 1) * sizeof(double));
     double *g = (double *)malloc((size_t)(m + 2) * sizeof(double));
     double *y = (double *)malloc((size_t)(m + 1) * sizeof(double));
+    /* ORC_V_GRAM: G ((m+1) x (m+1), row-major, symmetric) and the decoded
+     * newest stored vector */
+    double *G = gram ? (double *)malloc((size_t)(m + 1) * (size_t)(m + 1) * sizeof(double)) : NULL;
+    double *gv = gram ? (double *)malloc((size_t)n * sizeof(double)) : NULL;
+    double *grow = gram ? (double *)malloc((size_t)(m + 1) * sizeof(double)) : NULL;
 #define HH(i, jj) H[(size_t)(jj) * (size_t)(m + 1) + (size_t)(i)]   /* 0-based */
 
     int64_t it = 0;
@@ -735,6 +742,13 @@ int orc_gmres(int32_t n, const int32_t *rp, const int32_t *ci, const double *val
                 for (int32_t i = 0; i < n; ++i)
                     w[i] = w[i] - s[i];
             }
+            if (gram) {
+                /* row jc of G: dec(v^_k)^T dec(v^_jc), k = 0..jc, mirrored */
+                orc_decode(fmt, n, Q[jc], sc[jc], gv);
+                multidot(fmt, j, Q, sc, n, gv, grow, part);
+                for (int32_t k = 0; k < j; ++k)
+                    G[(size_t)jc * (m + 1) + k] = G[(size_t)k * (m + 1) + jc] = grow[k];
+            }
             /* Step 6 */
             double t = sqrt(orc_dot(n, w, w));
             int brk;
@@ -743,7 +757,17 @@ int orc_gmres(int32_t n, const int32_t *rp, const int32_t *ci, const double *val
                 if (mgs) {
                     mgs_pass(fmt, j, Q, sc, n, w, u, s);
                 } else {
-                    multidot(fmt, j, Q, sc, n, w, u, part);
+                    if (gram) {
+                        /* V^T (w - V h) = V^T w - (V^T V) h = h - G h */
+                        for (int32_t k = 0; k < j; ++k) {
+                            double gh = 0.0;
+                            for (int32_t l = 0; l < j; ++l)
+                                gh += G[(size_t)k * (m + 1) + l] * h[l];
+                            u[k] = h[k] - gh;
+                        }
+                    } else {
+                        multidot(fmt, j, Q, sc, n, w, u, part);
+                    }
                     basis_combine(fmt, j, Q, sc, n, u, s);
 #pragma omp parallel for schedule(static)
                     for (int32_t i = 0; i < n; ++i)
@@ -857,6 +881,7 @@ int orc_gmres(int32_t n, const int32_t *rp, const int32_t *ci, const double *val
         free(Q[k]);
     free(Q); free(sc); free(r); free(v); free(z); free(w); free(s); free(xprev);
     free(part); free(H); free(h); free(u); free(cs); free(sn); free(g); free(y);
+    free(G); free(gv); free(grow);
     free(M.dinv);
     free(M.bj);
     return status;

@@ -38,8 +38,14 @@ enum {
  *                       breakdown test of step 12 is unchanged;
  *   ORC_V_MGS           modified Gram-Schmidt: steps 5 and 8 project out
  *                       one stored vector at a time, h_k = dec(v^_k)^T w
- *                       followed by w -= h_k dec(v^_k), k = 1..j in order. */
-enum { ORC_V_SPMV_VHAT = 1, ORC_V_ALWAYS_REORTH = 2, ORC_V_MGS = 4 };
+ *                       followed by w -= h_k dec(v^_k), k = 1..j in order;
+ *   ORC_V_GRAM          step 8's re-dot u = V^T w' (w' = w - V h after
+ *                       step 5) formed from the Gram matrix G = V^T V of the
+ *                       decoded stored vectors: u = h - G h, equal in exact
+ *                       arithmetic.  Row j of G (dec(v^_k)^T dec(v^_j),
+ *                       k <= j) is formed once, at step j.  Not combinable
+ *                       with ORC_V_MGS. */
+enum { ORC_V_SPMV_VHAT = 1, ORC_V_ALWAYS_REORTH = 2, ORC_V_MGS = 4, ORC_V_GRAM = 8 };
 
 enum { ORC_PC_NONE = 0, ORC_PC_JACOBI = 1, ORC_PC_SPARSE = 2, ORC_PC_BLOCK_JACOBI = 3 };
 

@@ -17,6 +17,12 @@ scaled float16 storage format (extensions; the unablated step is Fig. 1).
   sequential projection of A dec(v^_j) against the decoded stored vectors in
   order, which on an fp16 basis differs from the CGS column far above
   rounding; in fp64 storage, exact arithmetic makes MGS and CGS equal.
+* Gram re-dot: with SpMV on the stored vector and a second pass on every
+  step, each Hessenberg column is h + (h - V^T V h), h = V^T A dec(v^_j),
+  recomputed here with numpy from the decoded basis; the explicit re-dot
+  V^T (w - V h) gives the same column to rounding.  h - G h cancels, so on an
+  FP64 basis the Gram form keeps orthogonality to u64 omega / t rather than
+  u64 (1e-13 against 1e-14 on a near-identity matrix).
 """
 import numpy as np
 import pytest
@@ -200,9 +206,81 @@ def test_unknown_variant_bits_are_rejected(orc):
     A = P.poisson2d(4)
     b = np.ones(A.n)
     x = np.zeros(A.n)
-    opts = O._Opts(10, 0, 1e-10, 10, 0.0, 0, None, 0, 0, 0, 8, 0)
+    opts = O._Opts(10, 0, 1e-10, 10, 0.0, 0, None, 0, 0, 0, 16, 0)
     res = O._Result()
     rc = O.lib().orc_gmres(A.n, O._p(A.row_ptr), O._p(A.col_idx), O._p(A.val), O._p(b),
                            O._p(x), C.byref(opts), C.byref(res), None, None, None, None,
                            None, None)
     assert rc == O.E_ARG
+
+
+def gram_columns(orc, A, V, k):
+    """h + u with u = h - G h: the Gram-form second pass, from the decoded
+    stored vectors V (rows) alone."""
+    cols = []
+    for j in range(k - 1):
+        Vj = V[:j + 1]
+        w = orc.spmv(A, V[j])
+        h = Vj @ w
+        G = Vj @ Vj.T
+        u = h - G @ h
+        w2 = w - Vj.T @ h - Vj.T @ u
+        cols.append(np.concatenate([h + u, [np.linalg.norm(w2)]]))
+    return cols
+
+
+@pytest.mark.parametrize("fmt", ["fp16", "int16", "e4m3"])
+def test_gram_columns_are_h_plus_h_minus_gh(orc, fmt):
+    A = P.convdiff7(9)
+    b = P.rhs_uniform(A.n, 3)
+    kw = dict(restart=16, fmt=fmt, tol=0.0, maxiter=16, debug=True)
+    rg = orc.gmres(A, b, variant=("gram", "spmv_vhat", "always_reorth"), **kw)
+    re = orc.gmres(A, b, variant=("spmv_vhat", "always_reorth"), **kw)
+    assert rg["reorths"] == rg["iterations"] == 16
+    worst = 0.0
+    for j, h in enumerate(gram_columns(orc, A, rg["V"], rg["steps"])):
+        worst = max(worst, np.max(np.abs(rg["H"][:j + 2, j] - h)) / np.linalg.norm(h))
+    assert worst <= 1e-12
+    # the explicit re-dot reaches the same columns to rounding, by other bits
+    k = rg["steps"]
+    assert np.allclose(rg["H"][:, :k - 1], re["H"][:, :k - 1], rtol=0,
+                       atol=1e-12 * np.abs(re["H"]).max())
+    assert not np.array_equal(rg["H"], re["H"])
+
+
+def test_gram_keeps_the_fp64_basis_orthogonal_to_a_cancellation_bound(orc):
+    """h - G h cancels: its FP64 error is about u64 ||h||, against a result
+    of size t = h_{j+1,j}, so the second pass leaves a component of relative
+    size u64 omega / t along the basis (the explicit re-dot measures it
+    instead).  On this near-identity matrix omega / t is about 20: the Gram
+    form keeps the basis orthogonal to 1e-13, the explicit re-dot to 1e-14."""
+    n = 120
+    rng = np.random.default_rng(0)
+    A = csr_from_dense(np.eye(n) + 0.05 * rng.standard_normal((n, n)) / np.sqrt(n))
+    b = rng.standard_normal(n)
+    kw = dict(restart=40, fmt="fp64", tol=0.0, maxiter=40, debug=True)
+    rg = orc.gmres(A, b, variant=("gram", "always_reorth"), **kw)
+    re = orc.gmres(A, b, variant="always_reorth", **kw)
+    assert rg["reorths"] == 40
+    k = rg["V"].shape[0]
+    lg = np.linalg.norm(np.eye(k) - rg["V"] @ rg["V"].T)
+    le = np.linalg.norm(np.eye(k) - re["V"] @ re["V"].T)
+    assert lg <= 1e-13 and le <= 1e-14
+
+
+@pytest.mark.parametrize("fmt", ["fp64", "fp16", "bf16"])
+def test_gram_solves_like_the_explicit_re_dot(orc, fmt):
+    A = P.lognormal27(8, 1)
+    b = P.rhs_uniform(A.n, 1)
+    kw = dict(restart=25, fmt=fmt, tol=1e-10, maxiter=5000)
+    rg = orc.gmres(A, b, variant="gram", **kw)
+    re = orc.gmres(A, b, **kw)
+    assert rg["status"] == re["status"] == 0
+    assert abs(rg["iterations"] - re["iterations"]) <= 0.02 * re["iterations"] + 1
+    assert np.allclose(rg["hist"][:10], re["hist"][:10], rtol=1e-10, atol=0)
+
+
+def test_gram_with_mgs_is_rejected(orc):
+    A = P.poisson2d(4)
+    r = orc.gmres(A, np.ones(A.n), restart=5, variant=("gram", "mgs"))
+    assert r["status"] == -1
