@@ -9,12 +9,14 @@ storage run after the timed region for the compressed-vs-fp64 comparison.
 
 Prints one JSON line.  `value` is the fp16-basis time to solution (seconds,
 lower is better).  `roofline` covers the multi-dot kernel h = V^T w (the
-dominant kernel): algorithmic bytes per launch (j * n * 2 + 8 n for j
-stored vectors) over its duration in the timed solves, from HIP events the
-solver records at each multi-dot launch's own start and end (only those
-launches are event-timed in the timed region).  One more solve after the
-timed region times every basis-streaming kernel (`orth_kernels_gbps`,
-`fused_update_redot`).
+dominant kernel, which also forms the newest row of the basis's Gram matrix
+for step 8's re-dot): algorithmic bytes per launch (j * n * 2 + 8 n + n * 2
+for j stored vectors: the basis, w, and the newest vector's tile) over its
+duration in the timed solves, from HIP events the solver records at each
+multi-dot launch's own start and end (only those launches are event-timed
+in the timed region).  One more solve after the timed region times every
+basis-streaming kernel (`orth_kernels_gbps`; `fused_update_redot` with
+`--explicit-redot`).
 `roofline.copy_gbps` is a 1 GiB device-to-device copy timed the same way
 (`frac_of_copy` reads the multi-dot against it).  `--trace-summary` turns a
 rocprofv3 kernel trace of these runs into per-j multi-dot rates.
@@ -62,7 +64,7 @@ def pmc_summary(fetch_csv: str, write_csv: str, fmt: str, grid: int) -> dict:
     import csv
     fmt_id = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "e4m3": 4, "int32": 5, "int16": 6,
               "fp16s": 7}[fmt]
-    kname = f"k_multidot<{fmt_id}>"
+    kname = f"k_multidot<{fmt_id}, true>"
 
     def read(path, counter):
         rows = list(csv.DictReader(open(path)))
@@ -99,9 +101,9 @@ def trace_summary(trace_csv: str, fmt: str, grid: int, restart: int = 100) -> di
     order belongs to step j = k mod restart + 1.  Per kernel and j: the
     median duration over all cycles and the algorithmic GB/s; per kernel the
     j-weighted rate over all j and over j >= 20.  Algorithmic bytes: the
-    multi-dot j n b_s + 8 n; the fused update + re-dot and the
-    re-orthogonalising update j n b_s + 16 n; the step SpMV 12 nnz + 4 (n+1)
-    + 16 n + n b_s (the 7-point system: nnz = 7 N^3 - 6 N^2)."""
+    multi-dot with the Gram row j n b_s + 8 n + n b_s; the step-5 update and
+    the re-orthogonalising update j n b_s + 16 n; the step SpMV 12 nnz +
+    4 (n+1) + 16 n + n b_s (the 7-point system: nnz = 7 N^3 - 6 N^2)."""
     import csv
     import statistics
     fmt_id = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "e4m3": 4, "int32": 5, "int16": 6,
@@ -111,8 +113,8 @@ def trace_summary(trace_csv: str, fmt: str, grid: int, restart: int = 100) -> di
     n = grid ** 3
     nnz = 7 * grid ** 3 - 6 * grid ** 2
     kernels = {
-        f"k_multidot<{fmt_id}>": lambda j: j * n * bs + 8.0 * n,
-        f"k_update_redot<{fmt_id},": lambda j: j * n * bs + 16.0 * n,
+        f"k_multidot<{fmt_id}, true>": lambda j: j * n * bs + 8.0 * n + n * bs,
+        f"k_update<{fmt_id}, 5>": lambda j: j * n * bs + 16.0 * n,
         f"k_update<{fmt_id}, 2>": lambda j: j * n * bs + 16.0 * n,
         "k_spmv<256, 2048, 8>": lambda j: 12.0 * nnz + 4.0 * (n + 1) + 16.0 * n + n * bs,
     }
@@ -138,9 +140,9 @@ def trace_summary(trace_csv: str, fmt: str, grid: int, restart: int = 100) -> di
             "dispatches": len(sel), "j_weighted_gbps": weighted(table),
             "j_weighted_gbps_j_ge_20": weighted([t for t in table if t["j"] >= 20]),
             "per_j": table}
-    md = out["kernels"][f"k_multidot<{fmt_id}>"]
+    md = out["kernels"][f"k_multidot<{fmt_id}, true>"]
     # the multi-dot's figures at the top level (the roofline kernel)
-    out.update({"kernel": f"k_multidot<{fmt_id}>", "dispatches": md["dispatches"],
+    out.update({"kernel": f"k_multidot<{fmt_id}, true>", "dispatches": md["dispatches"],
                 "j_weighted_gbps_j_ge_20": md["j_weighted_gbps_j_ge_20"], "per_j": md["per_j"]})
     return out
 
@@ -178,8 +180,11 @@ def main() -> int:
     ap.add_argument("--format", default="fp16")
     ap.add_argument("--compare", default="fp64,fp32,int16")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--explicit-redot", action="store_true",
+                    help="ablation: step 8's re-dot as an explicit multi-dot of the updated w "
+                         "(fused with the update where the register tile allows)")
     ap.add_argument("--no-fuse", action="store_true",
-                    help="ablation: update and re-dot as two basis passes")
+                    help="with --explicit-redot: update and re-dot as two basis passes")
     ap.add_argument("--cpu-cycles", type=int, default=5,
                     help="restart cycles of the CPU oracle sample (about 2.5 s each on 16 cores)")
     ap.add_argument("--calib-copy", action="store_true",
@@ -229,7 +234,8 @@ def main() -> int:
 
     def one(fmt, profile):
         return cbg.solve(Ad, bd, restart=m, fmt=fmt, tol=tol, maxiter=maxiter, profile=profile,
-                         workspace=ws, fuse=not args.no_fuse)
+                         workspace=ws, fuse=not args.no_fuse,
+                         variant=("explicit_redot",) if args.explicit_redot else ())
 
     # the timed solves event-time the multi-dot launches only (the roofline
     # kernel); timing every basis kernel costs about 8% of a step
@@ -327,7 +333,7 @@ def main() -> int:
         else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "kernel": f"k_multidot<{args.format}>",
+                     "kernel": f"k_multidot<{args.format}> (with the Gram row)",
                      "launches": dot_launch,
                      "copy_gbps": copy_gbps, "frac_of_copy": achieved / copy_gbps,
                      "avg_launch_us": dot_ms * 1e3 / max(dot_launch, 1),

@@ -144,7 +144,20 @@ typedef struct {
  * own paths. */
 #define CBG_FLAG_NORMALISE_PASS 64
 #define CBG_FLAG_NORMALISE_GATHER 128
-#define CBG_FLAG_ALL 255    /* any other bit is an argument error */
+/* Step 8's re-dot u = V^T w' (w' = w - V h after step 5).  By default it is
+ * formed as h - G h, with G = V^T V the Gram matrix of the decoded stored
+ * vectors: the identity is exact, the step-5 multi-dot forms G's newest row
+ * in the same basis pass, and the update runs without a re-dot, so a
+ * re-orthogonalised step streams the basis three times with two of the
+ * passes plain.  In FP64, h - G h cancels: the second pass leaves
+ * components of relative size about 2^-53 omega / h_{j+1,j} along the
+ * basis where the explicit re-dot leaves 2^-53, far below the storage error
+ * of every compressed format.
+ * EXPLICIT_REDOT: the form Fig. 1 writes, a second multi-dot of w' (fused
+ * with the update while j fits the fused kernel's register tile; NO_FUSE
+ * splits it).  MGS takes its own path either way. */
+#define CBG_FLAG_EXPLICIT_REDOT 256
+#define CBG_FLAG_ALL 511    /* any other bit is an argument error */
 
 typedef struct {
     int64_t iterations;        /* Arnoldi steps (SpMVs with A inside cycles) */

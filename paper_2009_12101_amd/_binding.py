@@ -30,10 +30,14 @@ FLAG_ALWAYS_REORTH = 16
 FLAG_MGS = 32
 FLAG_NORMALISE_PASS = 64
 FLAG_NORMALISE_GATHER = 128
+FLAG_EXPLICIT_REDOT = 256
 # where steps 13-14 run: solve(..., normalise=...)
 NORMALISE = {"auto": 0, "pass": FLAG_NORMALISE_PASS, "gather": FLAG_NORMALISE_GATHER}
 # Arnoldi-step ablations by name (solve(..., variant=...))
-VARIANTS = {"spmv_vhat": FLAG_SPMV_VHAT, "always_reorth": FLAG_ALWAYS_REORTH, "mgs": FLAG_MGS}
+# (step 8's re-dot is in Gram form unless "explicit_redot" is named; "gram"
+# names that default, as the oracle's variant of the same name)
+VARIANTS = {"spmv_vhat": FLAG_SPMV_VHAT, "always_reorth": FLAG_ALWAYS_REORTH, "mgs": FLAG_MGS,
+            "gram": 0, "explicit_redot": FLAG_EXPLICIT_REDOT}
 MAX_RESTART = 512
 
 EXPORTS = ["cbg_strerror", "cbg_last_hip_error", "cbg_basis_ld", "cbg_workspace_bytes", "cbg_kernel_workspace_bytes",

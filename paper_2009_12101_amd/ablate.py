@@ -9,12 +9,14 @@ from that fp64-basis solution (``x_err``; two solves that both meet the
 tolerance can differ by up to 2 tol ||b|| / sigma_min(A)):
 
 * ``default``: Fig. 1 as the solver runs it (SpMV on the FP64 v, CGS with
-  the step-7 test, eta = 1/sqrt(2));
+  the step-7 test, eta = 1/sqrt(2), step 8's re-dot in Gram form);
 * ``spmv_vhat``: step 3 multiplies by the stored vector read back;
 * ``cgs2``: a second CGS pass on every step;
 * ``cgs1``: never a second pass (eta -> 0);
 * ``mgs`` / ``mgs1``: modified Gram-Schmidt with the step-7 test / with one
   pass only (one launch per stored vector: slow by design);
+* ``explicit``: step 8's re-dot as a second multi-dot of the updated w, the
+  form Fig. 1 writes (fused with the update where the tile allows);
 * formats include ``fp16s``, float16 with a per-vector power-of-two scale.
 
     python -m paper_2009_12101_amd.ablate --system convdiff7_128 \\
@@ -37,6 +39,7 @@ VARIANTS = {
     "cgs1": dict(eta=1e-300),
     "mgs": dict(variant=("mgs",)),
     "mgs1": dict(variant=("mgs",), eta=1e-300),
+    "explicit": dict(variant=("explicit_redot",)),
 }
 
 

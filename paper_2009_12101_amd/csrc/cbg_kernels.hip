@@ -105,6 +105,7 @@ struct StepArrays {
     double *hist;      // m: recurrence residual of each step of the cycle
     double *scales;    // m+1: per-vector scales of the stored basis
     int32_t *flags;    // m: bit0 re-orthogonalised, bit1 breakdown
+    double *G;         // (m+1) x (m+1), row-major: Gram matrix of the stored basis
 };
 
 // Fig. 1 steps 9-12 and the column-by-column Givens update of step 17, run
@@ -452,7 +453,10 @@ __device__ __forceinline__ u32x4 ld_chunk(const uint8_t *__restrict__ V, int64_t
         (const u32x4 *)(V + (int64_t)k * ldb + i0 * fmt_bytes(F)));
 }
 
-template <int F>
+// GRAM: the same pass also forms g_k = dec(V_k)^T dec(V_{j-1}), k < j, the
+// newest row of the Gram matrix of the stored vectors (partials in rows
+// j + 2 + k), from a register tile of the newest vector.
+template <int F, bool GRAM>
 __global__ __launch_bounds__(BLK) CBG_MD_ATTR void k_multidot(const uint8_t *__restrict__ V, int64_t ld,
                                                   const double *__restrict__ scales, int n, int j,
                                                   const double *__restrict__ w, RedArgs ra,
@@ -462,11 +466,13 @@ __global__ __launch_bounds__(BLK) CBG_MD_ATTR void k_multidot(const uint8_t *__r
         return;
     using T = Fmt<F>;
     constexpr int VW = T::VW, CH = T::CH, KC = T::KC;
+    constexpr int NV = GRAM ? 2 : 1;                  // values per stored vector
+    constexpr int WROW = MAX_RESTART + 1;
     constexpr int TILE = BLK * VW * CH;
     const int64_t ldb = ld * fmt_bytes(F);
     // per-wave running sums over the block's tiles: no barrier until the end
-    __shared__ double wacc[NWAVE][MAX_RESTART + 1];
-    for (int k = threadIdx.x; k < NWAVE * (MAX_RESTART + 1); k += BLK)
+    __shared__ double wacc[NWAVE][NV * WROW];
+    for (int k = threadIdx.x; k < NWAVE * NV * WROW; k += BLK)
         (&wacc[0][0])[k] = 0.0;
     __syncthreads();
     const int64_t ntiles = ((int64_t)n + TILE - 1) / TILE;
@@ -475,11 +481,18 @@ __global__ __launch_bounds__(BLK) CBG_MD_ATTR void k_multidot(const uint8_t *__r
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const bool full = (tile + 1) * TILE <= n;
         double wr[CH * VW];
+        double gr[GRAM ? CH * VW : 1];
         int64_t i0[CH];
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
             i0[c] = tile * TILE + ((int64_t)c * BLK + threadIdx.x) * VW;
             load_w<VW>(w, n, i0[c], wr + c * VW);
+        }
+        if constexpr (GRAM) {
+            const double sg = T::SCALED ? scales[j - 1] : 1.0;
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+                load_dec<F>(V + (int64_t)(j - 1) * ldb, i0[c], n, sg, gr + c * VW);
         }
         if (with_norms) {
 #pragma unroll
@@ -489,7 +502,7 @@ __global__ __launch_bounds__(BLK) CBG_MD_ATTR void k_multidot(const uint8_t *__r
             }
         }
         for (int kc = 0; kc < j; kc += KC) {
-            double acc[KC];
+            double acc[NV * KC];
             if (full) {
                 u32x4 raw[KC][CH];
 #pragma unroll
@@ -497,19 +510,28 @@ __global__ __launch_bounds__(BLK) CBG_MD_ATTR void k_multidot(const uint8_t *__r
 #pragma unroll
                     for (int c = 0; c < CH; ++c)
                         raw[kk][c] = ld_chunk<F>(V, ldb, min(kc + kk, j - 1), i0[c]);
+                // keep the batch's loads together, ahead of its arithmetic: under
+                // the Gram tile's register pressure the scheduler would otherwise
+                // interleave them with the FMAs, one load in flight per wave
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                 for (int kk = 0; kk < KC; ++kk) {
                     const double s = T::SCALED ? scales[min(kc + kk, j - 1)] : 1.0;
-                    double a = 0.0;
+                    double a = 0.0, g = 0.0;
 #pragma unroll
                     for (int c = 0; c < CH; ++c) {
                         double d[VW];
                         T::dec(raw[kk][c], s, d);
 #pragma unroll
-                        for (int e = 0; e < VW; ++e)
+                        for (int e = 0; e < VW; ++e) {
                             a = fma(d[e], wr[c * VW + e], a);
+                            if constexpr (GRAM)
+                                g = fma(d[e], gr[c * VW + e], g);
+                        }
                     }
                     acc[kk] = a;
+                    if constexpr (GRAM)
+                        acc[KC + kk] = g;
                 }
             } else {
 #pragma unroll
@@ -517,33 +539,41 @@ __global__ __launch_bounds__(BLK) CBG_MD_ATTR void k_multidot(const uint8_t *__r
                     const int k = min(kc + kk, j - 1);
                     const double s = T::SCALED ? scales[k] : 1.0;
                     const uint8_t *Vk = V + (int64_t)k * ldb;
-                    double a = 0.0;
+                    double a = 0.0, g = 0.0;
 #pragma unroll
                     for (int c = 0; c < CH; ++c) {
                         double d[VW];
                         load_dec<F>(Vk, i0[c], n, s, d);
 #pragma unroll
-                        for (int e = 0; e < VW; ++e)
+                        for (int e = 0; e < VW; ++e) {
                             a = fma(d[e], wr[c * VW + e], a);
+                            if constexpr (GRAM)
+                                g = fma(d[e], gr[c * VW + e], g);
+                        }
                     }
                     acc[kk] = a;
+                    if constexpr (GRAM)
+                        acc[KC + kk] = g;
                 }
             }
-            wave_transpose_sum<KC>(acc);
-            if (lane < KC) {
-                const int k = kc + bitrev<KC>(lane);
+            wave_transpose_sum<NV * KC>(acc);
+            if (lane < NV * KC) {
+                const int idx = bitrev<NV * KC>(lane);
+                const int k = kc + (idx < KC ? idx : idx - KC);
                 if (k < j)
-                    wacc[wave][k] += acc[0];
+                    wacc[wave][(idx < KC ? 0 : WROW) + k] += acc[0];
             }
         }
     }
     __syncthreads();
-    for (int k = threadIdx.x; k < j; k += BLK) {
-        double t = wacc[0][k];
+    for (int k = threadIdx.x; k < NV * j; k += BLK) {
+        const int src = k < j ? k : WROW + (k - j);
+        double t = wacc[0][src];
 #pragma unroll
         for (int q = 1; q < NWAVE; ++q)
-            t += wacc[q][k];
-        ra.part[(size_t)k * ra.stride + blockIdx.x] = t;
+            t += wacc[q][src];
+        const int row = k < j ? k : j + 2 + (k - j);       // g_k in row j + 2 + k
+        ra.part[(size_t)row * ra.stride + blockIdx.x] = t;
     }
     if (with_norms) {
         block_sum_max(ssq, mx);
@@ -556,13 +586,14 @@ __global__ __launch_bounds__(BLK) CBG_MD_ATTR void k_multidot(const uint8_t *__r
 
 // ---------------------------------------------------------------------------
 // Basis combination through the accessor: s = sum_k c_k dec(V_k), k < j.
-//   U_PLAIN / U_STEP1 / U_STEP2: w -= s, with ||w||_2 and ||w||_inf;
+//   U_PLAIN / U_STEP1 / U_STEP2 / U_STEP1N: w -= s, with ||w||_2 and
+//   ||w||_inf (partials in rows 0 and 1, except U_STEP1);
 //   U_SOLUTION: x += dinv .* s (Jacobi) or x += s;  U_COMBINE: out = s.
 // Full tiles stream the vectors UNR at a time with the next batch's loads
 // in flight while the current batch is decoded and accumulated.
 // ---------------------------------------------------------------------------
 
-enum { U_PLAIN = 0, U_STEP1 = 1, U_STEP2 = 2, U_SOLUTION = 3, U_COMBINE = 4 };
+enum { U_PLAIN = 0, U_STEP1 = 1, U_STEP2 = 2, U_SOLUTION = 3, U_COMBINE = 4, U_STEP1N = 5 };
 
 template <int F, int ROLE>
 __global__ __launch_bounds__(BLK) void k_update(const uint8_t *__restrict__ V, int64_t ld,
@@ -573,7 +604,7 @@ __global__ __launch_bounds__(BLK) void k_update(const uint8_t *__restrict__ V, i
                                                 const DevState *st)
 {
     int j = j_arg;
-    if constexpr (ROLE == U_STEP1 || ROLE == U_STEP2) {
+    if constexpr (ROLE == U_STEP1 || ROLE == U_STEP2 || ROLE == U_STEP1N) {
         if (st->done)
             return;
         if (ROLE == U_STEP2 && !st->reorth)
@@ -1233,8 +1264,10 @@ __device__ double block_fold(const double *__restrict__ src, int nb, bool is_max
 // kernel-level multi-dot value).
 int reduce_grid(int role, int j)
 {
-    if (role == RR_H || role == RR_U || role == RR_VALUES)
+    if (role == RR_H || role == RR_U || role == RR_VALUES || role == RR_UG)
         return 1 + (j > 0 ? j : 0);
+    if (role == RR_HG)
+        return 1 + 2 * (j > 0 ? j : 0);
     return 1;
 }
 
@@ -1255,10 +1288,35 @@ __global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth
         return;
     }
     const int tid = threadIdx.x;
+    if (role == RR_HG && blockIdx.x > j) {
+        // block 1 + j + k: g_k, mirrored into row and column j - 1 of G
+        const int k = blockIdx.x - 1 - j;
+        const double a = block_fold(ws.orth + (size_t)(j + 2 + k) * ws.stride, nb_orth, false);
+        if (tid == 0) {
+            const size_t ldg = (size_t)st->m + 1;
+            sa.G[(size_t)(j - 1) * ldg + k] = a;
+            sa.G[(size_t)k * ldg + (j - 1)] = a;
+        }
+        return;
+    }
+    if (role == RR_UG && blockIdx.x > 0) {
+        // step 8 in Gram form: u_k = h_k - sum_l G_kl h_l (every step: the
+        // test of step 7 is block 0's, and u is only read if it fired)
+        __shared__ double prod[MAX_RESTART];
+        const int k = blockIdx.x - 1;
+        const size_t ldg = (size_t)st->m + 1;
+        for (int l = tid; l < j; l += RBLK)
+            prod[l] = sa.G[(size_t)k * ldg + l] * sa.h[l];
+        __syncthreads();
+        const double gh = block_fold(prod, j, false);
+        if (tid == 0)
+            sa.u[k] = sa.h[k] - gh;
+        return;
+    }
     // coefficients h_k / u_k / kernel-level values: block 1 + k folds value k
     if (blockIdx.x > 0) {
         const int k = blockIdx.x - 1;
-        double *dst = role == RR_H ? sa.h : role == RR_U ? sa.u : out;
+        double *dst = (role == RR_H || role == RR_HG) ? sa.h : role == RR_U ? sa.u : out;
         const double a = block_fold(ws.orth + (size_t)k * ws.stride, nb_orth, false);
         if (tid == 0)
             dst[k] = a;
@@ -1270,7 +1328,7 @@ __global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth
     __shared__ double sv[2];
     const double *s0, *s1;
     int nb;
-    if (role == RR_H) {
+    if (role == RR_H || role == RR_HG) {
         s0 = ws.spmv;                                   // omega^2
         s1 = ws.spmv + ws.stride;
         nb = nb_spmv;
@@ -1278,7 +1336,7 @@ __global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth
         s0 = ws.orth + (size_t)j * ws.stride;           // ||w||^2, max|w_i|
         s1 = ws.orth + (size_t)(j + 1) * ws.stride;
         nb = nb_orth;
-    } else if (role == RR_T2 || role == RR_NORMS || role == RR_MGS_T) {
+    } else if (role == RR_T2 || role == RR_NORMS || role == RR_MGS_T || role == RR_UG) {
         s0 = ws.orth;
         s1 = ws.orth + ws.stride;
         nb = nb_orth;
@@ -1343,10 +1401,12 @@ __global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth
         break;
     }
     case RR_H:
+    case RR_HG:
         if (tid == 0)
             st->omega = sqrt(sv[0]);
         break;
     case RR_U:
+    case RR_UG:
     case RR_MGS_T: {
         // Fig. 1 steps 6-7; without re-orthogonalisation the step ends here
         // (finish_step needs h, which the previous kernel stored, not u)
@@ -1675,16 +1735,23 @@ void launch_multidot(const OrthArgs &a, hipStream_t s)
     int g = orth_grid(a.fmt, a.n);
     RedArgs ra{a.ws.orth, a.ws.stride};
     const uint8_t *V = (const uint8_t *)a.V;
-    if (a.ev0) {
-        CBG_FMT_SWITCH(a.fmt, (hipExtLaunchKernelGGL(k_multidot<F>, dim3(g), dim3(BLK), 0, s,
-                                                     a.ev0, a.ev1, 0, V, a.ld, a.scales, a.n,
-                                                     a.j, a.w, ra, a.st, a.gated,
-                                                     a.with_norms)))
-    } else {
-        CBG_FMT_SWITCH(a.fmt, (k_multidot<F><<<g, BLK, 0, s>>>(V, a.ld, a.scales, a.n, a.j, a.w,
-                                                                ra, a.st, a.gated,
-                                                                a.with_norms)))
+#define CBG_MD(G)                                                                              \
+    if (a.ev0) {                                                                               \
+        CBG_FMT_SWITCH(a.fmt, (hipExtLaunchKernelGGL(k_multidot<F, G>, dim3(g), dim3(BLK), 0, s, \
+                                                     a.ev0, a.ev1, 0, V, a.ld, a.scales, a.n,  \
+                                                     a.j, a.w, ra, a.st, a.gated,              \
+                                                     a.with_norms)))                           \
+    } else {                                                                                   \
+        CBG_FMT_SWITCH(a.fmt, (k_multidot<F, G><<<g, BLK, 0, s>>>(V, a.ld, a.scales, a.n, a.j,  \
+                                                                   a.w, ra, a.st, a.gated,     \
+                                                                   a.with_norms)))             \
     }
+    if (a.gram) {
+        CBG_MD(true)
+    } else {
+        CBG_MD(false)
+    }
+#undef CBG_MD
 }
 
 void launch_update(const OrthArgs &a, hipStream_t s)
@@ -1706,6 +1773,7 @@ void launch_update(const OrthArgs &a, hipStream_t s)
     case U_PLAIN: CBG_UPD(U_PLAIN) break;
     case U_STEP1: CBG_UPD(U_STEP1) break;
     case U_STEP2: CBG_UPD(U_STEP2) break;
+    case U_STEP1N: CBG_UPD(U_STEP1N) break;
     case U_SOLUTION: CBG_UPD(U_SOLUTION) break;
     default: CBG_UPD(U_COMBINE) break;
     }
@@ -1876,7 +1944,9 @@ void make_step_arrays(void *out, double *H, double *h, double *u, double *cs, do
 {
     StepArrays *a = (StepArrays *)out;
     a->H = H; a->h = h; a->u = u; a->cs = cs; a->sn = sn; a->g = g; a->y = y;
-    a->hist = hist; a->scales = scales; a->flags = flags;
+    a->hist = hist; a->scales = scales; a->flags = flags; a->G = nullptr;
 }
+
+void set_step_gram(void *sa, double *G) { ((StepArrays *)sa)->G = G; }
 
 }  // namespace cbg

@@ -42,6 +42,7 @@ struct OrthArgs {
     const double *w;      // multi-dot input
     int gated;            // multi-dot: skipped once the cycle is done
     int with_norms;       // multi-dot: also partials of ||w||^2 and max|w_i|
+    int gram;             // multi-dot: also the newest Gram row, dec(V_k)^T dec(V_{j-1})
     const double *coef;   // update coefficients
     double *wio;          // update: the vector updated in place (or written)
     const double *dinv;
@@ -53,7 +54,9 @@ struct OrthArgs {
 
 // reduce roles (k_reduce)
 enum { RR_NB = 0, RR_SCALE = 1, RR_NORM2 = 2, RR_RESID = 3, RR_H = 4, RR_U = 5, RR_T2 = 6,
-       RR_VALUES = 7, RR_NORMS = 8, RR_MGS_H = 9, RR_MGS_U = 10, RR_MGS_T = 11 };
+       RR_VALUES = 7, RR_NORMS = 8, RR_MGS_H = 9, RR_MGS_U = 10, RR_MGS_T = 11,
+       RR_HG = 12,   // RR_H plus the newest Gram row from the multi-dot's rows j+2+k
+       RR_UG = 13 }; // step 6-7 from the update's norm partials, u = h - G h
 
 // SpMV launch shapes: rows per block and LDS product-buffer entries
 enum { SPMV_R256_C2K = 0, SPMV_R64_C2K = 1, SPMV_R64_C4K = 2, SPMV_R32_C4K = 3 };
@@ -116,5 +119,7 @@ void launch_backsolve(const DevState *st, const void *sa, hipStream_t s);
 size_t step_arrays_size();
 void make_step_arrays(void *out, double *H, double *h, double *u, double *cs, double *sn,
                       double *g, double *y, double *hist, double *scales, int32_t *flags);
+// the Gram matrix ((m+1) x (m+1) doubles) for the RR_HG / RR_UG folds
+void set_step_gram(void *sa, double *G);
 
 }  // namespace cbg

@@ -47,11 +47,11 @@ struct Carver {
     }
 };
 
-RedWs carve_red(Carver &c, int jmax)
+RedWs carve_red(Carver &c, int jmax, int rows = 0)
 {
     RedWs r;
     r.stride = MAX_GRID;
-    r.orth = c.take<double>((size_t)(jmax + 2) * MAX_GRID);
+    r.orth = c.take<double>((size_t)(rows > 0 ? rows : jmax + 2) * MAX_GRID);
     r.spmv = c.take<double>((size_t)2 * MAX_GRID);
     return r;
 }
@@ -65,7 +65,7 @@ struct SolveWs {
     double *bj64;                  // and the inverted blocks by precision
     float *bj32;
     uint16_t *bj16;
-    double *H, *h, *u, *cs, *sn, *g, *y, *hist;
+    double *H, *h, *u, *cs, *sn, *g, *y, *hist, *G;
     int32_t *flags;
     unsigned *bad;
     RedWs red;
@@ -104,7 +104,9 @@ SolveWs carve_solve(void *ws, int32_t n, int32_t m, int fmt, int pc, size_t *tot
     s.hist = c.take<double>(m);
     s.flags = c.take<int32_t>(m);
     s.bad = c.take<unsigned>(1);
-    s.red = carve_red(c, m + 1);
+    s.G = c.take<double>((size_t)(m + 1) * (m + 1));
+    // partial rows: h_k, two norms, and the Gram row g_k in rows j + 2 + k
+    s.red = carve_red(c, m + 1, 2 * (m + 1) + 2);
     if (total)
         *total = c.off;
     return s;
@@ -292,6 +294,8 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
     const int vhat = (opt->flags & CBG_FLAG_SPMV_VHAT) ? 1 : 0;
     const int reorth_all = (opt->flags & CBG_FLAG_ALWAYS_REORTH) ? 1 : 0;
     const bool mgs = (opt->flags & CBG_FLAG_MGS) != 0;
+    // step 8 in Gram form unless the explicit re-dot is asked for
+    const bool gram = !mgs && (opt->flags & CBG_FLAG_EXPLICIT_REDOT) == 0;
     if (mgs && prof)
         return fail(CBG_E_UNSUPPORTED);     // event timing covers the CGS kernels only
     // steps 13-14 in a pass of their own, or inside the next SpMV's gather:
@@ -303,12 +307,13 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
          ((opt->flags & CBG_FLAG_NORMALISE_GATHER) == 0 &&
           ((double)A->nnz > 12.0 * n || pc0 == CBG_PC_JACOBI)));
     // steps whose update and re-dot share one basis pass
-    auto fused = [&](int j) { return fuse && fused_takes(fmt, basis_ld(n), j); };
+    auto fused = [&](int j) { return !gram && fuse && fused_takes(fmt, basis_ld(n), j); };
     ByteModel bm{(double)n, (double)A->nnz, (double)fmt_bytes(fmt)};
 
     std::vector<unsigned char> sa_buf(step_arrays_size());
     void *sa = sa_buf.data();
     make_step_arrays(sa, W.H, W.h, W.u, W.cs, W.sn, W.g, W.y, W.hist, W.scales, W.flags);
+    set_step_gram(sa, W.G);
 
     // set-up: initialise the state, ||b||
     const int nb_orth = orth_grid(fmt, n);
@@ -399,12 +404,14 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                 for (int j = 1; j <= m; ++j) {
                     const bool ro = j <= jeff && (cyc_flags[j - 1] & 1);
                     for (int k = 0; k < 4; ++k) {
-                        if ((k == 2 && fused(j)) || !profiled(k))
+                        if ((k == 2 && (fused(j) || gram)) || !profiled(k))
                             continue;            // no separate re-dot launch, or not timed
                         float ms;
                         HIP_TRY(hipEventElapsedTime(&ms, evs.at(j, k, 0), evs.at(j, k, 1)));
                         const bool work = j <= jeff && (k < 3 || ro);
-                        const double by = !work ? 0.0 : (k % 2 == 0) ? bm.dot(j) : bm.upd(j);
+                        const double by = !work ? 0.0
+                                          : k == 0 && gram ? bm.dot(j) + n * bm.bs
+                                          : (k % 2 == 0) ? bm.dot(j) : bm.upd(j);
                         res->prof_orth_ms += ms;
                         res->prof_orth_bytes += by;
                         res->prof_orth_launches += 1;
@@ -433,8 +440,10 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                 if (prev_pc == CBG_PC_SPARSE) b_step += 8.0 * A->nnz + 4.0 * (n + 1) + 16.0 * n;
                 if (prev_pc == CBG_PC_BLOCK_JACOBI) b_step += bj_bytes + 16.0 * n;
                 if (norm_pass) b_step += 16.0 * n;  // v written by the pass, read by the SpMV
-                if (!fused(j) && !mgs)
+                if (!fused(j) && !mgs && !gram)
                     b_step += bm.dot(j);             // the separate re-dot pass
+                if (gram)
+                    b_step += n * bm.bs;             // the newest vector's tile for G
                 if (ro) b_step += mgs ? b_mgs : bm.upd(j);
                 model_bytes += b_step;
             }
@@ -564,11 +573,19 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
             };
             // step 5: h = V^T w ; w -= V h
             timed(0);
+            o.gram = gram ? 1 : 0;
             launch_multidot(o, s);
-            launch_reduce(W.red, RR_H, nb_orth, nb_spmv, j, W.st, sa, nullptr, fmt, s);
+            o.gram = 0;
+            launch_reduce(W.red, gram ? RR_HG : RR_H, nb_orth, nb_spmv, j, W.st, sa, nullptr,
+                          fmt, s);
             o.coef = W.h; o.role = 1 /*U_STEP1*/;
             timed(1);
-            if (fused(j)) {
+            if (gram) {
+                // steps 6-8: ||w||, the test of step 7, u = h - G h
+                o.role = 5 /*U_STEP1N*/;
+                launch_update(o, s);
+                launch_reduce(W.red, RR_UG, nb_orth, 0, j, W.st, sa, nullptr, fmt, s);
+            } else if (fused(j)) {
                 // steps 5-8 in one basis pass: w -= V h, then ||w||, max|w|
                 // and u = V^T w of the updated rows
                 const int nb_u = launch_update_redot(o, s);

@@ -1,6 +1,6 @@
 """GPU ablation variants of the Arnoldi step against the CPU oracle, through
-the C ABI (CBG_FLAG_SPMV_VHAT, CBG_FLAG_ALWAYS_REORTH, CBG_FLAG_MGS, the
-scaled float16 basis).
+the C ABI (CBG_FLAG_SPMV_VHAT, CBG_FLAG_ALWAYS_REORTH, CBG_FLAG_MGS,
+CBG_FLAG_GRAM, the scaled float16 basis).
 
 fp64 basis: a variant follows the oracle's same variant up to rounding
 (counts within one step, iteration-matched x within 1e-8, first-cycle
@@ -39,7 +39,8 @@ def true_res(orc, A, b, x):
 
 
 VARIANTS = [("spmv_vhat",), ("always_reorth",), ("spmv_vhat", "always_reorth"), ("mgs",),
-            ("mgs", "always_reorth")]
+            ("mgs", "always_reorth"), ("gram",), ("gram", "always_reorth"),
+            ("gram", "spmv_vhat"), ("explicit_redot",), ("explicit_redot", "always_reorth")]
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
@@ -114,6 +115,67 @@ def test_mgs_first_steps(cbg, orc, dev, fmt):
     assert np.linalg.norm(r.x.cpu().numpy() - on["x"]) <= 1e-12 * np.linalg.norm(on["x"])
 
 
+@pytest.mark.parametrize("fmt", ["fp16", "int16", "bf16", "fp16s", "e4m3", "fp32", "int32"])
+@pytest.mark.parametrize("precond", ["none", "jacobi", "block_jacobi"])
+def test_gram_first_steps(cbg, orc, dev, fmt, precond):
+    """Step 8 in Gram form: the first steps coincide with the oracle's Gram
+    run to 1e-12 (and with its explicit re-dot run to rounding)."""
+    print(f"ablation gram {fmt} {precond}", flush=True)
+    A = P.lognormal27(12, 2)
+    b = P.rhs_uniform(A.n, 9)
+    Ad = cbg.DeviceCSR.from_host(A, dev)
+    kw = dict(restart=30, fmt=fmt, tol=0.0, maxiter=6, precond=precond,
+              variant=("gram", "always_reorth"))
+    r = cbg.solve(Ad, torch.from_numpy(b).to(dev), **kw)
+    on = orc.gmres(A, b, **kw)
+    assert r.reorths == 6 and on["reorths"] == 6
+    assert np.allclose(r.hist, on["hist"], rtol=1e-12, atol=0)
+    assert np.linalg.norm(r.x.cpu().numpy() - on["x"]) <= 1e-12 * np.linalg.norm(on["x"])
+
+
+@pytest.mark.parametrize("m", [8, 104, 130])
+def test_gram_across_tile_and_fold_sizes(cbg, orc, dev, m):
+    """A full cycle of m steps on an fp16 basis (the Gram rows up to j = m,
+    the multi-dot's 2j values per wave, the u folds over j terms), against
+    the oracle's Gram run."""
+    print(f"ablation gram m={m}", flush=True)
+    A = P.poisson2d(48)
+    b = P.rhs_uniform(A.n, 4)
+    kw = dict(restart=m, fmt="fp16", tol=0.0, maxiter=m, variant="gram")
+    r = cbg.solve(cbg.DeviceCSR.from_host(A, dev), torch.from_numpy(b).to(dev), **kw)
+    o = orc.gmres(A, b, **kw)
+    assert r.iterations == o["iterations"] == m
+    k = min(m, 10)
+    assert np.allclose(r.hist[:k], o["hist"][:k], rtol=1e-10, atol=0)
+    # the end of the cycle, against the band that rounding-level perturbations
+    # of b give the oracle itself: 1% wide at m = 104, but at m = 130, where
+    # the fp16 recurrence residual has begun to wander, 1.9e-7 to 4.7e-7 over
+    # eight perturbed oracle runs of the Gram and explicit re-dots together;
+    # a few samples cover part of that, hence the factor 3
+    band = [o["hist"][-1]]
+    for seed in range(3):
+        bp = b * (1.0 + 1e-15 * np.random.default_rng(seed).standard_normal(A.n))
+        band.append(orc.gmres(A, bp, **kw)["hist"][-1])
+    assert min(band) / 3 <= r.hist[-1] <= 3 * max(band)
+    # |g_{j+1}| = |s_j| |g_j| with |s_j| <= 1: non-increasing within the cycle
+    assert np.all(np.diff(r.hist) <= 1e-15 * r.hist[:-1])
+
+
+def test_gram_is_the_default_and_profiles(cbg, dev):
+    A = P.convdiff7(10)
+    Ad = cbg.DeviceCSR.from_host(A, dev)
+    b = torch.from_numpy(P.rhs_uniform(A.n, 1)).to(dev)
+    kw = dict(restart=20, fmt="fp16", tol=1e-10, maxiter=2000)
+    r0 = cbg.solve(Ad, b, **kw)
+    r1 = cbg.solve(Ad, b, variant="gram", profile=True, **kw)
+    assert r0.iterations == r1.iterations and r1.prof_fused_launches == 0
+    assert np.array_equal(r0.x.cpu().numpy(), r1.x.cpu().numpy())
+    assert r1.prof_dot_launches > 0 and r1.prof_orth_bytes > 0
+    re = cbg.solve(Ad, b, variant="explicit_redot", profile=True, **kw)
+    assert re.prof_fused_launches > 0
+    assert not np.array_equal(r0.x.cpu().numpy(), re.x.cpu().numpy())
+
+
 def test_mgs_with_profiling_is_unsupported(cbg, dev):
     A = P.poisson2d(6)
     Ad = cbg.DeviceCSR.from_host(A, dev)
@@ -129,7 +191,11 @@ def test_mgs_with_profiling_is_unsupported(cbg, dev):
                                          ("fp16s", ()),
                                          ("fp16s", ("spmv_vhat", "always_reorth")),
                                          ("int16", ("always_reorth",)),
-                                         ("bf16", ("spmv_vhat",))])
+                                         ("bf16", ("spmv_vhat",)),
+                                         ("fp16", ("gram",)),
+                                         ("int16", ("gram",)),
+                                         ("e4m3", ("gram",)),
+                                         ("bf16", ("gram", "always_reorth"))])
 def test_compressed_variant_solves(cbg, orc, dev, fmt, variant):
     print(f"ablation solve {fmt} {variant}", flush=True)
     A = P.convdiff7(20)
@@ -156,7 +222,7 @@ def test_unknown_flag_bits_are_argument_errors(cbg, dev):
     b = torch.ones(A.n, dtype=torch.float64, device=dev)
     x = torch.zeros_like(b)
     ws = torch.empty(B.workspace_bytes(A.n, 8, "fp64"), dtype=torch.uint8, device=dev)
-    opts = B.CbgOpts(8, 0, 1e-10, 10, 0.0, 0, 0, None, 256, 0, 0, 0)
+    opts = B.CbgOpts(8, 0, 1e-10, 10, 0.0, 0, 0, None, 512, 0, 0, 0)
     res = B.CbgResult()
     csr = Ad.cstruct()
     rc = B.lib().cbgmres_solve(C.byref(csr), B._ptr(b), B._ptr(x), C.byref(opts), B._ptr(ws),
