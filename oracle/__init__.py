@@ -28,7 +28,8 @@ STORAGE_DTYPE = {"fp64": np.float64, "fp32": np.float32, "fp16": np.uint16, "bf1
                  "e4m3": np.uint8, "int32": np.int32, "int16": np.int16, "fp16s": np.uint16}
 # Arnoldi-step variants for ablations (bits of the options' `variant`)
 # ("explicit_redot" names the default, the re-dot Fig. 1 writes)
-VARIANTS = {"spmv_vhat": 1, "always_reorth": 2, "mgs": 4, "gram": 8, "explicit_redot": 0}
+VARIANTS = {"spmv_vhat": 1, "always_reorth": 2, "mgs": 4, "gram": 8, "explicit_redot": 0,
+            "onepass": 16}
 PRECONDS = {"none": 0, "jacobi": 1, "sparse": 2, "block_jacobi": 3}
 OK, NOT_CONVERGED, E_ARG, E_NONFINITE = 0, 1, -1, -4
 

@@ -563,8 +563,10 @@ int orc_gmres(int32_t n, const int32_t *rp, const int32_t *ci, const double *val
     const int bs = orc_format_bytes(fmt);
     if (n < 0 || m < 1 || bs == 0 || !(opt->tol >= 0.0) || opt->maxiter < 0 ||
         opt->precond < ORC_PC_NONE || opt->precond > ORC_PC_BLOCK_JACOBI ||
-        (opt->variant & ~(ORC_V_SPMV_VHAT | ORC_V_ALWAYS_REORTH | ORC_V_MGS | ORC_V_GRAM)) != 0 ||
+        (opt->variant & ~(ORC_V_SPMV_VHAT | ORC_V_ALWAYS_REORTH | ORC_V_MGS | ORC_V_GRAM |
+                          ORC_V_ONEPASS)) != 0 ||
         ((opt->variant & ORC_V_MGS) && (opt->variant & ORC_V_GRAM)) ||
+        ((opt->variant & ORC_V_ONEPASS) && !(opt->variant & ORC_V_GRAM)) ||
         (opt->precond == ORC_PC_SPARSE && !opt->p_val) ||
         (n > 0 && (!rp || !ci || !val || !b || !x))) {
         res->status = ORC_E_ARG;
@@ -583,6 +585,7 @@ int orc_gmres(int32_t n, const int32_t *rp, const int32_t *ci, const double *val
     const int always_reorth = (opt->variant & ORC_V_ALWAYS_REORTH) != 0;
     const int mgs = (opt->variant & ORC_V_MGS) != 0;
     const int gram = (opt->variant & ORC_V_GRAM) != 0;
+    const int onepass = (opt->variant & ORC_V_ONEPASS) != 0;
 
     /* Fig. 1 works with ||b||_2 as the reference of the stop test (R8). */
     const double nb = sqrt(orc_dot(n, b, b));
@@ -733,6 +736,47 @@ int orc_gmres(int32_t n, const int32_t *rp, const int32_t *ci, const double *val
             /* Step 4 */
             double omega = sqrt(orc_dot(n, w, w));
             /* Step 5: h = V_j^T w; w = w - V_j h, V_j widened from storage. */
+            int brk;
+            double t;
+            if (onepass) {
+                /* h and row jc of G, then u = h - G h and t1 by Pythagoras */
+                multidot(fmt, j, Q, sc, n, w, h, part);
+                orc_decode(fmt, n, Q[jc], sc[jc], gv);
+                multidot(fmt, j, Q, sc, n, gv, grow, part);
+                for (int32_t k = 0; k < j; ++k)
+                    G[(size_t)jc * (m + 1) + k] = G[(size_t)k * (m + 1) + jc] = grow[k];
+                double hh = 0.0, hu = 0.0;
+                for (int32_t k = 0; k < j; ++k) {
+                    double gh = 0.0;
+                    for (int32_t l = 0; l < j; ++l)
+                        gh += G[(size_t)k * (m + 1) + l] * h[l];
+                    u[k] = h[k] - gh;
+                }
+                for (int32_t k = 0; k < j; ++k) {
+                    hh += h[k] * h[k];
+                    hu += h[k] * u[k];
+                }
+                const double t1sq = omega * omega - hh - hu;
+                const double t1 = t1sq > 0.0 ? sqrt(t1sq) : 0.0;
+                const int ro = always_reorth || t1 < eta * omega;
+                for (int32_t k = 0; k < j; ++k)
+                    grow[k] = ro ? h[k] + u[k] : h[k];
+                basis_combine(fmt, j, Q, sc, n, grow, s);
+#pragma omp parallel for schedule(static)
+                for (int32_t i = 0; i < n; ++i)
+                    w[i] = w[i] - s[i];
+                const double t2 = sqrt(orc_dot(n, w, w));
+                if (ro) {
+                    for (int32_t k = 0; k < j; ++k)
+                        h[k] = h[k] + u[k];
+                    res->reorths += 1;
+                    brk = (t2 == 0.0) || (t2 < eta * t1);
+                } else {
+                    brk = (t2 == 0.0);
+                }
+                t = t2;
+                goto column;
+            }
             if (mgs) {
                 mgs_pass(fmt, j, Q, sc, n, w, h, s);
             } else {
@@ -750,8 +794,7 @@ int orc_gmres(int32_t n, const int32_t *rp, const int32_t *ci, const double *val
                     G[(size_t)jc * (m + 1) + k] = G[(size_t)k * (m + 1) + jc] = grow[k];
             }
             /* Step 6 */
-            double t = sqrt(orc_dot(n, w, w));
-            int brk;
+            t = sqrt(orc_dot(n, w, w));
             if (always_reorth || t < eta * omega) {
                 /* Steps 8-10: one more CGS (or MGS) pass. */
                 if (mgs) {
@@ -786,6 +829,7 @@ int orc_gmres(int32_t n, const int32_t *rp, const int32_t *ci, const double *val
             } else {
                 brk = (t == 0.0);
             }
+        column:
             for (int32_t k = 0; k < j; ++k)
                 HH(k, jc) = h[k];
             HH(j, jc) = t;

@@ -44,8 +44,15 @@ enum {
  *                       decoded stored vectors: u = h - G h, equal in exact
  *                       arithmetic.  Row j of G (dec(v^_k)^T dec(v^_j),
  *                       k <= j) is formed once, at step j.  Not combinable
- *                       with ORC_V_MGS. */
-enum { ORC_V_SPMV_VHAT = 1, ORC_V_ALWAYS_REORTH = 2, ORC_V_MGS = 4, ORC_V_GRAM = 8 };
+ *                       with ORC_V_MGS;
+ *   ORC_V_ONEPASS       with ORC_V_GRAM: steps 5-10 as one update.  u = h - G h
+ *                       and t1^2 = ||w - V h||^2 = omega^2 - h^T h - h^T u
+ *                       (Pythagoras, exact) are known before any update, so
+ *                       step 7 decides first and w -= V (h + u) (or V h)
+ *                       runs once; t1 = 0 where rounding makes t1^2 <= 0.
+ *                       Step 12's test compares the final norm with t1. */
+enum { ORC_V_SPMV_VHAT = 1, ORC_V_ALWAYS_REORTH = 2, ORC_V_MGS = 4, ORC_V_GRAM = 8,
+       ORC_V_ONEPASS = 16 };
 
 enum { ORC_PC_NONE = 0, ORC_PC_JACOBI = 1, ORC_PC_SPARSE = 2, ORC_PC_BLOCK_JACOBI = 3 };
 

@@ -206,7 +206,7 @@ def test_unknown_variant_bits_are_rejected(orc):
     A = P.poisson2d(4)
     b = np.ones(A.n)
     x = np.zeros(A.n)
-    opts = O._Opts(10, 0, 1e-10, 10, 0.0, 0, None, 0, 0, 0, 16, 0)
+    opts = O._Opts(10, 0, 1e-10, 10, 0.0, 0, None, 0, 0, 0, 32, 0)
     res = O._Result()
     rc = O.lib().orc_gmres(A.n, O._p(A.row_ptr), O._p(A.col_idx), O._p(A.val), O._p(b),
                            O._p(x), C.byref(opts), C.byref(res), None, None, None, None,
@@ -284,3 +284,58 @@ def test_gram_with_mgs_is_rejected(orc):
     A = P.poisson2d(4)
     r = orc.gmres(A, np.ones(A.n), restart=5, variant=("gram", "mgs"))
     assert r["status"] == -1
+
+
+# One-pass CGS2: u = h - G h and t1^2 = omega^2 - h^T h - h^T u known before
+# any update, so the step-7 decision comes first and one update applies
+# h + u (or h).  Pins: the columns against numpy, the decisions and counts
+# against the two-pass Gram form, the textbook breakdowns against Fig. 1.
+
+@pytest.mark.parametrize("fmt", ["fp16", "int16", "e4m3"])
+def test_onepass_columns_are_h_plus_u_with_one_update(orc, fmt):
+    A = P.convdiff7(9)
+    b = P.rhs_uniform(A.n, 3)
+    kw = dict(restart=16, fmt=fmt, tol=0.0, maxiter=16, debug=True)
+    r = orc.gmres(A, b, variant=("gram", "onepass", "spmv_vhat", "always_reorth"), **kw)
+    assert r["reorths"] == r["iterations"] == 16
+    worst = 0.0
+    for j, h in enumerate(gram_columns(orc, A, r["V"], r["steps"])):
+        worst = max(worst, np.max(np.abs(r["H"][:j + 2, j] - h)) / np.linalg.norm(h))
+    assert worst <= 1e-12
+
+
+@pytest.mark.parametrize("fmt", ["fp64", "fp16", "bf16", "int16"])
+@pytest.mark.parametrize("system", ["convdiff7", "lognormal27"])
+def test_onepass_decides_like_the_two_pass_gram_form(orc, fmt, system):
+    A = P.convdiff7(10) if system == "convdiff7" else P.lognormal27(8, 1)
+    b = P.rhs_uniform(A.n, 2)
+    kw = dict(restart=25, fmt=fmt, tol=1e-10, maxiter=5000)
+    r1 = orc.gmres(A, b, variant=("gram", "onepass"), **kw)
+    r2 = orc.gmres(A, b, variant="gram", **kw)
+    assert r1["status"] == r2["status"] == 0
+    # counts to within the spread that 1e-15 perturbations of b give either
+    # form (int16 on convdiff7(10): 66 to 71 steps over twelve of them)
+    assert abs(r1["iterations"] - r2["iterations"]) <= 0.08 * r2["iterations"] + 1
+    assert abs(r1["reorths"] - r2["reorths"]) <= 0.08 * r2["reorths"] + 1
+    assert np.allclose(r1["hist"][:10], r2["hist"][:10], rtol=1e-10, atol=0)
+
+
+@pytest.mark.parametrize("fmt", ["fp64", "fp16"])
+def test_onepass_textbook_breakdowns(orc, fmt):
+    """A = I breaks down after one step; a diagonal with five distinct
+    eigenvalues after five (fp64): the same counts and breakdowns as Fig. 1."""
+    cases = [(np.eye(50), np.random.default_rng(0).standard_normal(50)),
+             (np.diag(np.tile([1.0, 2, 3, 4, 5], 10)), np.ones(50))]
+    for M, b in cases:
+        A = csr_from_dense(M)
+        kw = dict(restart=20, fmt=fmt, tol=1e-12, maxiter=40)
+        r1 = orc.gmres(A, b, variant=("gram", "onepass"), **kw)
+        r0 = orc.gmres(A, b, **kw)
+        assert r1["status"] == r0["status"] == 0
+        assert (r1["iterations"], r1["breakdowns"]) == (r0["iterations"], r0["breakdowns"])
+        assert r1["breakdowns"] >= 1
+
+
+def test_onepass_needs_the_gram_form(orc):
+    A = P.poisson2d(4)
+    assert orc.gmres(A, np.ones(A.n), restart=5, variant="onepass")["status"] == -1
