@@ -101,8 +101,8 @@ def trace_summary(trace_csv: str, fmt: str, grid: int, restart: int = 100) -> di
     order belongs to step j = k mod restart + 1.  Per kernel and j: the
     median duration over all cycles and the algorithmic GB/s; per kernel the
     j-weighted rate over all j and over j >= 20.  Algorithmic bytes: the
-    multi-dot with the Gram row j n b_s + 8 n + n b_s; the step-5 update and
-    the re-orthogonalising update j n b_s + 16 n; the step SpMV 12 nnz +
+    multi-dot with the Gram row j n b_s + 8 n + n b_s; the one update of
+    steps 5-10 j n b_s + 16 n; the step SpMV 12 nnz +
     4 (n+1) + 16 n + n b_s (the 7-point system: nnz = 7 N^3 - 6 N^2)."""
     import csv
     import statistics
@@ -114,8 +114,7 @@ def trace_summary(trace_csv: str, fmt: str, grid: int, restart: int = 100) -> di
     nnz = 7 * grid ** 3 - 6 * grid ** 2
     kernels = {
         f"k_multidot<{fmt_id}, true>": lambda j: j * n * bs + 8.0 * n + n * bs,
-        f"k_update<{fmt_id}, 5>": lambda j: j * n * bs + 16.0 * n,
-        f"k_update<{fmt_id}, 2>": lambda j: j * n * bs + 16.0 * n,
+        f"k_update<{fmt_id}, 6>": lambda j: j * n * bs + 16.0 * n,
         "k_spmv<256, 2048, 8>": lambda j: 12.0 * nnz + 4.0 * (n + 1) + 16.0 * n + n * bs,
     }
     rows = list(csv.DictReader(open(trace_csv)))

@@ -144,20 +144,28 @@ typedef struct {
  * own paths. */
 #define CBG_FLAG_NORMALISE_PASS 64
 #define CBG_FLAG_NORMALISE_GATHER 128
-/* Step 8's re-dot u = V^T w' (w' = w - V h after step 5).  By default it is
- * formed as h - G h, with G = V^T V the Gram matrix of the decoded stored
- * vectors: the identity is exact, the step-5 multi-dot forms G's newest row
- * in the same basis pass, and the update runs without a re-dot, so a
- * re-orthogonalised step streams the basis three times with two of the
- * passes plain.  In FP64, h - G h cancels: the second pass leaves
- * components of relative size about 2^-53 omega / h_{j+1,j} along the
- * basis where the explicit re-dot leaves 2^-53, far below the storage error
- * of every compressed format.
- * EXPLICIT_REDOT: the form Fig. 1 writes, a second multi-dot of w' (fused
- * with the update while j fits the fused kernel's register tile; NO_FUSE
- * splits it).  MGS takes its own path either way. */
+/* Steps 5-10 (CGS with the conditional second pass).  By default:
+ * the step-5 multi-dot h = V^T w also forms the newest row of G = V^T V,
+ * the Gram matrix of the decoded stored vectors; then u = h - G h (step 8's
+ * re-dot, since V^T (w - V h) = h - G h) and t1^2 = ||w - V h||^2 =
+ * omega^2 - h^T h - h^T u (step 6, by Pythagoras) are known before any
+ * update, so step 7 decides first and one update w -= V (h + u) (or V h)
+ * does steps 5 and 9.  A re-orthogonalised step reads the basis twice (the
+ * multi-dot and the update) instead of four times.  Both identities are
+ * exact; in FP64 they cancel, leaving components of relative size about
+ * 2^-53 omega / h_{j+1,j} along the basis where the explicit passes leave
+ * 2^-53, far below the storage error of every compressed format.  Step 12
+ * compares the final norm with t1, floored at sqrt(4 (j+1) 2^-53) omega,
+ * below which t1^2 is rounding alone.
+ * EXPLICIT_REDOT: the form Fig. 1 writes: update, norm, and a second
+ * multi-dot of the updated w (fused with the update while j fits the fused
+ * kernel's register tile; NO_FUSE splits it), then the second update.
+ * TWO_PASS: the Gram-form re-dot with the update of step 5, the norm of
+ * step 6 and the second update as separate passes.  With EXPLICIT_REDOT or
+ * MGS: argument error.  MGS takes its own path. */
 #define CBG_FLAG_EXPLICIT_REDOT 256
-#define CBG_FLAG_ALL 511    /* any other bit is an argument error */
+#define CBG_FLAG_TWO_PASS 512
+#define CBG_FLAG_ALL 1023   /* any other bit is an argument error */
 
 typedef struct {
     int64_t iterations;        /* Arnoldi steps (SpMVs with A inside cycles) */

@@ -756,8 +756,12 @@ int orc_gmres(int32_t n, const int32_t *rp, const int32_t *ci, const double *val
                     hh += h[k] * h[k];
                     hu += h[k] * u[k];
                 }
+                /* below about (j+1) u64 omega^2 the difference is rounding
+                 * alone: t1 is floored there, so that step 12 sees a w that
+                 * lies numerically in span(V) as the breakdown it is */
                 const double t1sq = omega * omega - hh - hu;
-                const double t1 = t1sq > 0.0 ? sqrt(t1sq) : 0.0;
+                const double floor2 = 4.0 * (j + 1) * 0x1p-53 * omega * omega;
+                const double t1 = sqrt(t1sq > floor2 ? t1sq : floor2);
                 const int ro = always_reorth || t1 < eta * omega;
                 for (int32_t k = 0; k < j; ++k)
                     grow[k] = ro ? h[k] + u[k] : h[k];

@@ -49,7 +49,8 @@ enum {
  *                       and t1^2 = ||w - V h||^2 = omega^2 - h^T h - h^T u
  *                       (Pythagoras, exact) are known before any update, so
  *                       step 7 decides first and w -= V (h + u) (or V h)
- *                       runs once; t1 = 0 where rounding makes t1^2 <= 0.
+ *                       runs once; t1^2 is floored at 4 (j+1) u64 omega^2,
+ *                       below which it is rounding alone.
  *                       Step 12's test compares the final norm with t1. */
 enum { ORC_V_SPMV_VHAT = 1, ORC_V_ALWAYS_REORTH = 2, ORC_V_MGS = 4, ORC_V_GRAM = 8,
        ORC_V_ONEPASS = 16 };

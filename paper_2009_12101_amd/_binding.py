@@ -31,14 +31,30 @@ FLAG_MGS = 32
 FLAG_NORMALISE_PASS = 64
 FLAG_NORMALISE_GATHER = 128
 FLAG_EXPLICIT_REDOT = 256
+FLAG_TWO_PASS = 512
 # where steps 13-14 run: solve(..., normalise=...)
 NORMALISE = {"auto": 0, "pass": FLAG_NORMALISE_PASS, "gather": FLAG_NORMALISE_GATHER}
-# Arnoldi-step ablations by name (solve(..., variant=...))
-# (step 8's re-dot is in Gram form unless "explicit_redot" is named; "gram"
-# names that default, as the oracle's variant of the same name)
-VARIANTS = {"spmv_vhat": FLAG_SPMV_VHAT, "always_reorth": FLAG_ALWAYS_REORTH, "mgs": FLAG_MGS,
-            "gram": 0, "explicit_redot": FLAG_EXPLICIT_REDOT}
-MAX_RESTART = 512
+# Arnoldi-step variants by name, the names the oracle uses: "gram" is the
+# Gram-form re-dot with separate passes, ("gram", "onepass") steps 5-10 in
+# one update (the library's default), "explicit_redot" the form Fig. 1
+# writes; an empty variant is the library's default.
+VARIANTS = ("spmv_vhat", "always_reorth", "mgs", "gram", "onepass", "explicit_redot")
+
+
+def variant_flags(names) -> int:
+    names = set((names,) if isinstance(names, str) else names)
+    unknown = names - set(VARIANTS)
+    if unknown:
+        raise KeyError(f"unknown variant(s) {sorted(unknown)}")
+    if "onepass" in names and "gram" not in names:
+        raise KeyError("onepass needs gram")
+    f = 0
+    f |= FLAG_SPMV_VHAT if "spmv_vhat" in names else 0
+    f |= FLAG_ALWAYS_REORTH if "always_reorth" in names else 0
+    f |= FLAG_MGS if "mgs" in names else 0
+    f |= FLAG_EXPLICIT_REDOT if "explicit_redot" in names else 0
+    f |= FLAG_TWO_PASS if "gram" in names and "onepass" not in names else 0
+    return f
 
 EXPORTS = ["cbg_strerror", "cbg_last_hip_error", "cbg_basis_ld", "cbg_workspace_bytes", "cbg_kernel_workspace_bytes",
            "cbg_workspace_basis", "cbgmres_solve", "cbg_encode", "cbg_decode", "cbg_spmv",
@@ -278,8 +294,7 @@ def solve(A: DeviceCSR, b, x0=None, restart=100, fmt="fp64", tol=1e-10, maxiter=
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=b.device)
     flags = {False: 0, True: FLAG_PROFILE, "dot": FLAG_PROFILE_DOT}[profile] \
         | (0 if fuse else FLAG_NO_FUSE) | NORMALISE[normalise]
-    for name in ((variant,) if isinstance(variant, str) else variant):
-        flags |= VARIANTS[name]
+    flags |= variant_flags(variant)
     opts = CbgOpts(restart, FORMATS[fmt], tol, maxiter, eta, PRECONDS[precond],
                    int(bool(fallback)), None if p_val is None else p_val.data_ptr(),
                    flags, 0, pc_block, pc_prec)

@@ -9,7 +9,10 @@ from that fp64-basis solution (``x_err``; two solves that both meet the
 tolerance can differ by up to 2 tol ||b|| / sigma_min(A)):
 
 * ``default``: Fig. 1 as the solver runs it (SpMV on the FP64 v, CGS with
-  the step-7 test, eta = 1/sqrt(2), step 8's re-dot in Gram form);
+  the step-7 test, eta = 1/sqrt(2); the re-dot and the norm of step 6 from
+  the Gram row the multi-dot forms, steps 5-10 in one update);
+* ``twopass``: the Gram-form re-dot with the update, the norm and the second
+  update as separate passes;
 * ``spmv_vhat``: step 3 multiplies by the stored vector read back;
 * ``cgs2``: a second CGS pass on every step;
 * ``cgs1``: never a second pass (eta -> 0);
@@ -39,6 +42,7 @@ VARIANTS = {
     "cgs1": dict(eta=1e-300),
     "mgs": dict(variant=("mgs",)),
     "mgs1": dict(variant=("mgs",), eta=1e-300),
+    "twopass": dict(variant=("gram",)),
     "explicit": dict(variant=("explicit_redot",)),
 }
 

@@ -588,12 +588,14 @@ __global__ __launch_bounds__(BLK) CBG_MD_ATTR void k_multidot(const uint8_t *__r
 // Basis combination through the accessor: s = sum_k c_k dec(V_k), k < j.
 //   U_PLAIN / U_STEP1 / U_STEP2 / U_STEP1N: w -= s, with ||w||_2 and
 //   ||w||_inf (partials in rows 0 and 1, except U_STEP1);
+//   U_CGS2: steps 5-10 in one update (coef = h; see below).
 //   U_SOLUTION: x += dinv .* s (Jacobi) or x += s;  U_COMBINE: out = s.
 // Full tiles stream the vectors UNR at a time with the next batch's loads
 // in flight while the current batch is decoded and accumulated.
 // ---------------------------------------------------------------------------
 
-enum { U_PLAIN = 0, U_STEP1 = 1, U_STEP2 = 2, U_SOLUTION = 3, U_COMBINE = 4, U_STEP1N = 5 };
+enum { U_PLAIN = 0, U_STEP1 = 1, U_STEP2 = 2, U_SOLUTION = 3, U_COMBINE = 4, U_STEP1N = 5,
+       U_CGS2 = 6 };
 
 template <int F, int ROLE>
 __global__ __launch_bounds__(BLK) void k_update(const uint8_t *__restrict__ V, int64_t ld,
@@ -601,10 +603,11 @@ __global__ __launch_bounds__(BLK) void k_update(const uint8_t *__restrict__ V, i
                                                 const double *__restrict__ coef,
                                                 double *__restrict__ w,
                                                 const double *__restrict__ dinv, RedArgs ra,
-                                                const DevState *st)
+                                                const DevState *st,
+                                                const double *__restrict__ uin, DevState *stw)
 {
     int j = j_arg;
-    if constexpr (ROLE == U_STEP1 || ROLE == U_STEP2 || ROLE == U_STEP1N) {
+    if constexpr (ROLE == U_STEP1 || ROLE == U_STEP2 || ROLE == U_STEP1N || ROLE == U_CGS2) {
         if (st->done)
             return;
         if (ROLE == U_STEP2 && !st->reorth)
@@ -618,6 +621,49 @@ __global__ __launch_bounds__(BLK) void k_update(const uint8_t *__restrict__ V, i
     const int64_t ldb = ld * fmt_bytes(F);
     const int64_t ntiles = ((int64_t)n + TILE - 1) / TILE;
     double ssq = 0.0, mx = 0.0;
+    if constexpr (ROLE == U_CGS2) {
+        // u = h - G h comes from the fold before (uin).  Every block forms
+        // the same t1^2 = ||w - V h||^2 = omega^2 - h^T h - h^T u, decides
+        // step 7, and updates with h + u (re-orthogonalising) or h.  Block 0
+        // publishes the decision and t1 for the closing fold.
+        __shared__ double lc[MAX_RESTART], lpart[2][NWAVE];
+        double phh = 0.0, phu = 0.0;
+        for (int k = threadIdx.x; k < j; k += BLK) {
+            const double hk = coef[k], uk = uin[k];
+            lc[k] = uk;
+            phh += hk * hk;
+            phu += hk * uk;
+        }
+        phh = wave_sum(phh);
+        phu = wave_sum(phu);
+        if ((threadIdx.x & 63) == 0) {
+            lpart[0][threadIdx.x >> 6] = phh;
+            lpart[1][threadIdx.x >> 6] = phu;
+        }
+        __syncthreads();
+        double hh = lpart[0][0], hu = lpart[1][0];
+#pragma unroll
+        for (int q = 1; q < NWAVE; ++q) {
+            hh += lpart[0][q];
+            hu += lpart[1][q];
+        }
+        // below about (j+1) u64 omega^2 the difference is rounding alone:
+        // t1 is floored there, so that step 12 sees a w that lies
+        // numerically in span(V) as the breakdown it is
+        const double omega = st->omega;
+        const double t1sq = omega * omega - hh - hu;
+        const double floor2 = 4.0 * (j + 1) * 0x1p-53 * omega * omega;
+        const double t1 = sqrt(t1sq > floor2 ? t1sq : floor2);
+        const bool ro = st->reorth_all || t1 < st->eta * omega;
+        for (int k = threadIdx.x; k < j; k += BLK)
+            lc[k] = ro ? coef[k] + lc[k] : coef[k];
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            stw->reorth = ro ? 1 : 0;
+            stw->t = t1;
+        }
+        __syncthreads();
+        coef = lc;
+    }
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const bool full = (tile + 1) * TILE <= n;
         double s[CH * VW];
@@ -1264,7 +1310,7 @@ __device__ double block_fold(const double *__restrict__ src, int nb, bool is_max
 // kernel-level multi-dot value).
 int reduce_grid(int role, int j)
 {
-    if (role == RR_H || role == RR_U || role == RR_VALUES || role == RR_UG)
+    if (role == RR_H || role == RR_U || role == RR_VALUES || role == RR_UG || role == RR_GU)
         return 1 + (j > 0 ? j : 0);
     if (role == RR_HG)
         return 1 + 2 * (j > 0 ? j : 0);
@@ -1299,7 +1345,9 @@ __global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth
         }
         return;
     }
-    if (role == RR_UG && blockIdx.x > 0) {
+    if (role == RR_GU && blockIdx.x == 0)
+        return;                                         // u only
+    if ((role == RR_UG || role == RR_GU) && blockIdx.x > 0) {
         // step 8 in Gram form: u_k = h_k - sum_l G_kl h_l (every step: the
         // test of step 7 is block 0's, and u is only read if it fired)
         __shared__ double prod[MAX_RESTART];
@@ -1336,7 +1384,8 @@ __global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth
         s0 = ws.orth + (size_t)j * ws.stride;           // ||w||^2, max|w_i|
         s1 = ws.orth + (size_t)(j + 1) * ws.stride;
         nb = nb_orth;
-    } else if (role == RR_T2 || role == RR_NORMS || role == RR_MGS_T || role == RR_UG) {
+    } else if (role == RR_T2 || role == RR_NORMS || role == RR_MGS_T || role == RR_UG ||
+               role == RR_C2) {
         s0 = ws.orth;
         s1 = ws.orth + ws.stride;
         nb = nb_orth;
@@ -1425,6 +1474,21 @@ __global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth
     }
     case RR_T2:
         finish_step(st, sa, j, true, sqrt(sv[0]), sv[1]);
+        break;
+    case RR_C2:
+        // the one-pass update's norms: with re-orthogonalisation the closing
+        // norm against t1 (which the update stored), else the step's t
+        if (st->reorth) {
+            finish_step(st, sa, j, true, sqrt(sv[0]), sv[1]);
+        } else {
+            __syncthreads();
+            if (tid == 0) {
+                st->t = sqrt(sv[0]);
+                st->wmax = sv[1];
+            }
+            __syncthreads();
+            finish_step(st, sa, j, false, 0.0, 0.0);
+        }
         break;
     }
 }
@@ -1763,17 +1827,19 @@ void launch_update(const OrthArgs &a, hipStream_t s)
     if (a.ev0) {                                                                              \
         CBG_FMT_SWITCH(a.fmt, (hipExtLaunchKernelGGL(k_update<F, R>, dim3(g), dim3(BLK), 0, s, \
                                                      a.ev0, a.ev1, 0, V, a.ld, a.scales, a.n, \
-                                                     a.j, a.coef, a.wio, a.dinv, ra, a.st)))  \
+                                                     a.j, a.coef, a.wio, a.dinv, ra, a.st,    \
+                                                     a.u, a.stw)))                            \
     } else {                                                                                  \
         CBG_FMT_SWITCH(a.fmt, (k_update<F, R><<<g, BLK, 0, s>>>(V, a.ld, a.scales, a.n, a.j,   \
                                                                  a.coef, a.wio, a.dinv, ra,   \
-                                                                 a.st)))                      \
+                                                                 a.st, a.u, a.stw)))          \
     }
     switch (a.role) {
     case U_PLAIN: CBG_UPD(U_PLAIN) break;
     case U_STEP1: CBG_UPD(U_STEP1) break;
     case U_STEP2: CBG_UPD(U_STEP2) break;
     case U_STEP1N: CBG_UPD(U_STEP1N) break;
+    case U_CGS2: CBG_UPD(U_CGS2) break;
     case U_SOLUTION: CBG_UPD(U_SOLUTION) break;
     default: CBG_UPD(U_COMBINE) break;
     }

@@ -43,6 +43,8 @@ struct OrthArgs {
     int gated;            // multi-dot: skipped once the cycle is done
     int with_norms;       // multi-dot: also partials of ||w||^2 and max|w_i|
     int gram;             // multi-dot: also the newest Gram row, dec(V_k)^T dec(V_{j-1})
+    const double *u;      // one-pass update: u = h - G h (from the RR_GU fold)
+    DevState *stw;        // one-pass update: the step-7 decision and t1
     const double *coef;   // update coefficients
     double *wio;          // update: the vector updated in place (or written)
     const double *dinv;
@@ -56,7 +58,9 @@ struct OrthArgs {
 enum { RR_NB = 0, RR_SCALE = 1, RR_NORM2 = 2, RR_RESID = 3, RR_H = 4, RR_U = 5, RR_T2 = 6,
        RR_VALUES = 7, RR_NORMS = 8, RR_MGS_H = 9, RR_MGS_U = 10, RR_MGS_T = 11,
        RR_HG = 12,   // RR_H plus the newest Gram row from the multi-dot's rows j+2+k
-       RR_UG = 13 }; // step 6-7 from the update's norm partials, u = h - G h
+       RR_UG = 13,   // step 6-7 from the update's norm partials, u = h - G h
+       RR_C2 = 14,   // close of the one-pass update (rows 0 and 1)
+       RR_GU = 15 }; // u = h - G h only (blocks 1..j), for the one-pass update
 
 // SpMV launch shapes: rows per block and LDS product-buffer entries
 enum { SPMV_R256_C2K = 0, SPMV_R64_C2K = 1, SPMV_R64_C4K = 2, SPMV_R32_C4K = 3 };

@@ -259,7 +259,10 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
         !(opt->tol >= 0.0) || !isfinite(opt->tol) || opt->maxiter < 0 || pc0 < CBG_PC_NONE ||
         pc0 > CBG_PC_BLOCK_JACOBI || (hist_len > 0 && !hist_out) || hist_len < 0 ||
         (opt->flags & ~CBG_FLAG_ALL) != 0 ||
-        (~opt->flags & (CBG_FLAG_NORMALISE_PASS | CBG_FLAG_NORMALISE_GATHER)) == 0)
+        (~opt->flags & (CBG_FLAG_NORMALISE_PASS | CBG_FLAG_NORMALISE_GATHER)) == 0 ||
+        // the two-pass Gram form excludes the other forms of steps 5-10
+        ((opt->flags & CBG_FLAG_TWO_PASS) &&
+         (opt->flags & (CBG_FLAG_EXPLICIT_REDOT | CBG_FLAG_MGS))))
         return fail(CBG_E_ARG);
     const int bj_bs = opt->pc_block > 0 ? opt->pc_block : 4;
     const int bj_prec = opt->pc_prec > 0 ? opt->pc_prec : 16;
@@ -296,6 +299,8 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
     const bool mgs = (opt->flags & CBG_FLAG_MGS) != 0;
     // step 8 in Gram form unless the explicit re-dot is asked for
     const bool gram = !mgs && (opt->flags & CBG_FLAG_EXPLICIT_REDOT) == 0;
+    // steps 5-10 in one update unless the two-pass Gram form is asked for
+    const bool onepass = gram && (opt->flags & CBG_FLAG_TWO_PASS) == 0;
     if (mgs && prof)
         return fail(CBG_E_UNSUPPORTED);     // event timing covers the CGS kernels only
     // steps 13-14 in a pass of their own, or inside the next SpMV's gather:
@@ -404,7 +409,8 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                 for (int j = 1; j <= m; ++j) {
                     const bool ro = j <= jeff && (cyc_flags[j - 1] & 1);
                     for (int k = 0; k < 4; ++k) {
-                        if ((k == 2 && (fused(j) || gram)) || !profiled(k))
+                        if ((k == 2 && (fused(j) || gram)) || (k == 3 && onepass) ||
+                            !profiled(k))
                             continue;            // no separate re-dot launch, or not timed
                         float ms;
                         HIP_TRY(hipEventElapsedTime(&ms, evs.at(j, k, 0), evs.at(j, k, 1)));
@@ -444,7 +450,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                     b_step += bm.dot(j);             // the separate re-dot pass
                 if (gram)
                     b_step += n * bm.bs;             // the newest vector's tile for G
-                if (ro) b_step += mgs ? b_mgs : bm.upd(j);
+                if (ro && !onepass) b_step += mgs ? b_mgs : bm.upd(j);
                 model_bytes += b_step;
             }
             model_bytes += jeff * n * bm.bs + 16.0 * n;     // solution update
@@ -580,6 +586,18 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                           fmt, s);
             o.coef = W.h; o.role = 1 /*U_STEP1*/;
             timed(1);
+            if (onepass) {
+                // u = h - G h, then steps 5-10 in one update with h + u or h,
+                // then the close
+                launch_reduce(W.red, RR_GU, 0, 0, j, W.st, sa, nullptr, fmt, s);
+                o.role = 6 /*U_CGS2*/; o.u = W.u; o.stw = W.st;
+                launch_update(o, s);
+                launch_reduce(W.red, RR_C2, nb_orth, 0, j, W.st, sa, nullptr, fmt, s);
+                double *t = cur;
+                cur = nxt;
+                nxt = t;
+                continue;
+            }
             if (gram) {
                 // steps 6-8: ||w||, the test of step 7, u = h - G h
                 o.role = 5 /*U_STEP1N*/;

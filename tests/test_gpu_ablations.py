@@ -40,7 +40,8 @@ def true_res(orc, A, b, x):
 
 VARIANTS = [("spmv_vhat",), ("always_reorth",), ("spmv_vhat", "always_reorth"), ("mgs",),
             ("mgs", "always_reorth"), ("gram",), ("gram", "always_reorth"),
-            ("gram", "spmv_vhat"), ("explicit_redot",), ("explicit_redot", "always_reorth")]
+            ("gram", "spmv_vhat"), ("explicit_redot",), ("explicit_redot", "always_reorth"),
+            ("gram", "onepass"), ("gram", "onepass", "always_reorth")]
 
 
 @pytest.mark.parametrize("variant", VARIANTS)
@@ -133,15 +134,49 @@ def test_gram_first_steps(cbg, orc, dev, fmt, precond):
     assert np.linalg.norm(r.x.cpu().numpy() - on["x"]) <= 1e-12 * np.linalg.norm(on["x"])
 
 
+@pytest.mark.parametrize("fmt", ["fp16", "int16", "bf16", "fp16s", "e4m3", "fp32", "fp64"])
+@pytest.mark.parametrize("precond", ["none", "jacobi", "block_jacobi"])
+def test_onepass_first_steps(cbg, orc, dev, fmt, precond):
+    """Steps 5-10 in one update: the first steps coincide with the oracle's
+    one-pass run to 1e-12, with step 7's decision taken from t1 by
+    Pythagoras (eta = 1/sqrt(2): the test fires on most steps here)."""
+    print(f"ablation onepass {fmt} {precond}", flush=True)
+    A = P.lognormal27(12, 2)
+    b = P.rhs_uniform(A.n, 9)
+    Ad = cbg.DeviceCSR.from_host(A, dev)
+    kw = dict(restart=30, fmt=fmt, tol=0.0, maxiter=8, precond=precond,
+              variant=("gram", "onepass"))
+    r = cbg.solve(Ad, torch.from_numpy(b).to(dev), **kw)
+    on = orc.gmres(A, b, **kw)
+    assert r.reorths == on["reorths"]
+    assert np.allclose(r.hist, on["hist"], rtol=1e-12, atol=0)
+    assert np.linalg.norm(r.x.cpu().numpy() - on["x"]) <= 1e-12 * np.linalg.norm(on["x"])
+
+
+@pytest.mark.parametrize("fmt", ["fp64", "fp16"])
+def test_onepass_textbook_breakdowns(cbg, orc, dev, fmt):
+    from tests._helpers import csr_from_dense
+    cases = [(np.eye(50), np.random.default_rng(0).standard_normal(50)),
+             (np.diag(np.tile([1.0, 2, 3, 4, 5], 10)), np.ones(50))]
+    for M, b in cases:
+        A = csr_from_dense(M)
+        kw = dict(restart=20, fmt=fmt, tol=1e-12, maxiter=40, variant=("gram", "onepass"))
+        r = cbg.solve(cbg.DeviceCSR.from_host(A, dev), torch.from_numpy(b).to(dev), **kw)
+        o = orc.gmres(A, b, **kw)
+        assert r.status == o["status"] == 0
+        assert (r.iterations, r.breakdowns) == (o["iterations"], o["breakdowns"])
+
+
+@pytest.mark.parametrize("variant", [("gram",), ("gram", "onepass")])
 @pytest.mark.parametrize("m", [8, 104, 130])
-def test_gram_across_tile_and_fold_sizes(cbg, orc, dev, m):
+def test_gram_across_tile_and_fold_sizes(cbg, orc, dev, m, variant):
     """A full cycle of m steps on an fp16 basis (the Gram rows up to j = m,
     the multi-dot's 2j values per wave, the u folds over j terms), against
     the oracle's Gram run."""
-    print(f"ablation gram m={m}", flush=True)
+    print(f"ablation {variant} m={m}", flush=True)
     A = P.poisson2d(48)
     b = P.rhs_uniform(A.n, 4)
-    kw = dict(restart=m, fmt="fp16", tol=0.0, maxiter=m, variant="gram")
+    kw = dict(restart=m, fmt="fp16", tol=0.0, maxiter=m, variant=variant)
     r = cbg.solve(cbg.DeviceCSR.from_host(A, dev), torch.from_numpy(b).to(dev), **kw)
     o = orc.gmres(A, b, **kw)
     assert r.iterations == o["iterations"] == m
@@ -161,19 +196,24 @@ def test_gram_across_tile_and_fold_sizes(cbg, orc, dev, m):
     assert np.all(np.diff(r.hist) <= 1e-15 * r.hist[:-1])
 
 
-def test_gram_is_the_default_and_profiles(cbg, dev):
+def test_onepass_gram_is_the_default_and_profiles(cbg, dev):
     A = P.convdiff7(10)
     Ad = cbg.DeviceCSR.from_host(A, dev)
     b = torch.from_numpy(P.rhs_uniform(A.n, 1)).to(dev)
     kw = dict(restart=20, fmt="fp16", tol=1e-10, maxiter=2000)
     r0 = cbg.solve(Ad, b, **kw)
-    r1 = cbg.solve(Ad, b, variant="gram", profile=True, **kw)
+    r1 = cbg.solve(Ad, b, variant=("gram", "onepass"), profile=True, **kw)
     assert r0.iterations == r1.iterations and r1.prof_fused_launches == 0
     assert np.array_equal(r0.x.cpu().numpy(), r1.x.cpu().numpy())
     assert r1.prof_dot_launches > 0 and r1.prof_orth_bytes > 0
-    re = cbg.solve(Ad, b, variant="explicit_redot", profile=True, **kw)
-    assert re.prof_fused_launches > 0
-    assert not np.array_equal(r0.x.cpu().numpy(), re.x.cpu().numpy())
+    # the one-pass step: a multi-dot and one update per step, both timed
+    assert r1.prof_orth_launches == 2 * r1.prof_dot_launches
+    for var in ("gram", "explicit_redot"):
+        re = cbg.solve(Ad, b, variant=var, profile=True, **kw)
+        assert (re.prof_fused_launches > 0) == (var == "explicit_redot")
+        assert not np.array_equal(r0.x.cpu().numpy(), re.x.cpu().numpy())
+    with pytest.raises(KeyError):
+        cbg.solve(Ad, b, variant="onepass", **kw)
 
 
 def test_mgs_with_profiling_is_unsupported(cbg, dev):
@@ -195,7 +235,10 @@ def test_mgs_with_profiling_is_unsupported(cbg, dev):
                                          ("fp16", ("gram",)),
                                          ("int16", ("gram",)),
                                          ("e4m3", ("gram",)),
-                                         ("bf16", ("gram", "always_reorth"))])
+                                         ("bf16", ("gram", "always_reorth")),
+                                         ("fp16", ("gram", "onepass")),
+                                         ("int16", ("gram", "onepass")),
+                                         ("e4m3", ("gram", "onepass"))])
 def test_compressed_variant_solves(cbg, orc, dev, fmt, variant):
     print(f"ablation solve {fmt} {variant}", flush=True)
     A = P.convdiff7(20)
@@ -222,7 +265,7 @@ def test_unknown_flag_bits_are_argument_errors(cbg, dev):
     b = torch.ones(A.n, dtype=torch.float64, device=dev)
     x = torch.zeros_like(b)
     ws = torch.empty(B.workspace_bytes(A.n, 8, "fp64"), dtype=torch.uint8, device=dev)
-    opts = B.CbgOpts(8, 0, 1e-10, 10, 0.0, 0, 0, None, 512, 0, 0, 0)
+    opts = B.CbgOpts(8, 0, 1e-10, 10, 0.0, 0, 0, None, 1024, 0, 0, 0)
     res = B.CbgResult()
     csr = Ad.cstruct()
     rc = B.lib().cbgmres_solve(C.byref(csr), B._ptr(b), B._ptr(x), C.byref(opts), B._ptr(ws),
