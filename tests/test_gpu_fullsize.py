@@ -27,6 +27,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from paper_2009_12101_amd import problems as P
+from tests._helpers import LIB_DEFAULT
 
 U = 2.0 ** -53
 M, TOL = 100, 1e-10
@@ -119,7 +120,7 @@ def test_multidot_update_full(cbg, orc, dev, system):
 @pytest.mark.timeout(300)
 def test_fp64_solve_full(cbg, orc, dev, system):
     A, b, Ad, bd, ws = system
-    ref = orc.gmres(A, b, restart=M, fmt="fp64", tol=TOL, maxiter=20000)
+    ref = orc.gmres(A, b, restart=M, fmt="fp64", tol=TOL, maxiter=20000, variant=LIB_DEFAULT)
     assert ref["status"] == 0
     r = cbg.solve(Ad, bd, restart=M, fmt="fp64", tol=TOL, maxiter=20000, workspace=ws)
     assert r.status == 0
@@ -135,12 +136,12 @@ def test_fp64_solve_full(cbg, orc, dev, system):
 @pytest.mark.timeout(300)
 def test_fp16_solve_full(cbg, orc, dev, system):
     A, b, Ad, bd, ws = system
-    one = orc.gmres(A, b, restart=M, fmt="fp16", tol=TOL, maxiter=M)
+    one = orc.gmres(A, b, restart=M, fmt="fp16", tol=TOL, maxiter=M, variant=LIB_DEFAULT)
     r1 = cbg.solve(Ad, bd, restart=M, fmt="fp16", tol=TOL, maxiter=M, workspace=ws)
     assert r1.iterations == one["iterations"] == M
     assert np.allclose(r1.hist[:3], one["hist"][:3], rtol=1e-12, atol=0)
     assert abs(r1.hist[M - 1] / one["hist"][M - 1] - 1.0) <= 1e-2
-    ref = orc.gmres(A, b, restart=M, fmt="fp16", tol=TOL, maxiter=20000)
+    ref = orc.gmres(A, b, restart=M, fmt="fp16", tol=TOL, maxiter=20000, variant=LIB_DEFAULT)
     assert ref["status"] == 0
     r = cbg.solve(Ad, bd, restart=M, fmt="fp16", tol=TOL, maxiter=20000, workspace=ws)
     assert r.status == 0

@@ -20,6 +20,8 @@ meet the tolerance can differ by).
 import numpy as np
 import pytest
 
+from tests._helpers import LIB_DEFAULT
+
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
@@ -44,7 +46,7 @@ def cbg():
 
 
 def run_pair(cbg, orc, dev, A, b, **kw):
-    ref = orc.gmres(A, b, **kw)
+    ref = orc.gmres(A, b, variant=LIB_DEFAULT, **kw)
     Ad = cbg.DeviceCSR.from_host(A, dev)
     bd = torch.from_numpy(b).to(dev)
     kw2 = dict(kw)
@@ -82,7 +84,7 @@ def test_solve_parity_fp64(cbg, orc, dev, name, m):
     assert abs(r.true_rel_res - true_res(orc, A, b, x)) <= 1e-3 * TOL
     it = ref["iterations"]
     rm = cbg.solve(Ad, bd, restart=m, fmt="fp64", tol=0.0, maxiter=it)
-    refm = orc.gmres(A, b, restart=m, fmt="fp64", tol=0.0, maxiter=it)
+    refm = orc.gmres(A, b, restart=m, fmt="fp64", tol=0.0, maxiter=it, variant=LIB_DEFAULT)
     assert rm.iterations == refm["iterations"] == it
     xm = rm.x.cpu().numpy()
     # same iteration, different rounding: the gap grows like kappa * steps * u
@@ -104,7 +106,7 @@ def test_solve_parity_compressed(cbg, orc, dev, fmt, name, m):
     it_g, it_o = [], []
     for s in range(NPERT):
         bp = perturbed(b, s)
-        o = orc.gmres(A, bp, restart=m, fmt=fmt, tol=TOL, maxiter=20000)
+        o = orc.gmres(A, bp, restart=m, fmt=fmt, tol=TOL, maxiter=20000, variant=LIB_DEFAULT)
         r = cbg.solve(Ad, torch.from_numpy(bp).to(dev), restart=m, fmt=fmt, tol=TOL,
                       maxiter=20000)
         assert o["status"] == 0 and r.status == 0
@@ -118,7 +120,7 @@ def test_solve_parity_compressed(cbg, orc, dev, fmt, name, m):
     assert abs(mg - mo) <= 0.05 * mo + 0.5 * spread + 2, (sorted(it_g), sorted(it_o))
     # before the stored entries can round differently, the runs coincide
     r = cbg.solve(Ad, torch.from_numpy(b).to(dev), restart=m, fmt=fmt, tol=0.0, maxiter=3)
-    o = orc.gmres(A, b, restart=m, fmt=fmt, tol=0.0, maxiter=3)
+    o = orc.gmres(A, b, restart=m, fmt=fmt, tol=0.0, maxiter=3, variant=LIB_DEFAULT)
     xg = r.x.cpu().numpy()
     assert np.linalg.norm(xg - o["x"]) <= 1e-12 * np.linalg.norm(o["x"])
     assert np.allclose(r.hist, o["hist"], rtol=1e-12, atol=0)
@@ -155,6 +157,7 @@ def test_sparse_preconditioner_equal_to_jacobi(cbg, orc, dev):
     pv = np.zeros(A.nnz, np.float32)
     pv[diag] = (1.0 / A.val[diag]).astype(np.float32)
     ref = orc.gmres(A, b, restart=30, fmt="fp16", tol=1e-10, maxiter=5000, precond="sparse",
+                    variant=LIB_DEFAULT,
                     p_val=pv)
     Ad = cbg.DeviceCSR.from_host(A, dev)
     r = cbg.solve(Ad, torch.from_numpy(b).to(dev), restart=30, fmt="fp16", tol=1e-10,

@@ -21,6 +21,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from paper_2009_12101_amd import problems as P
+from tests._helpers import LIB_DEFAULT
 from paper_2009_12101_amd._binding import SPAI_NPARAM as NPARAM
 
 
@@ -344,7 +345,8 @@ def test_solver_basis_in_workspace(cbg, orc, dev):
     A = P.lognormal27(10, 3)
     b = P.rhs_uniform(A.n, 3)
     m = 30
-    ref = orc.gmres(A, b, restart=m, fmt="fp64", tol=1e-14, maxiter=m, debug=True)
+    ref = orc.gmres(A, b, restart=m, fmt="fp64", tol=1e-14, maxiter=m, debug=True,
+                    variant=LIB_DEFAULT)
     Ad = cbg.DeviceCSR.from_host(A, dev)
     ws = torch.empty(cbg.workspace_bytes(A.n, m, "fp64"), dtype=torch.uint8, device=dev)
     r = cbg.solve(Ad, torch.from_numpy(b).to(dev), restart=m, fmt="fp64", tol=1e-14, maxiter=m,
