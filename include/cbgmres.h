@@ -109,12 +109,13 @@ typedef struct {
 #define CBG_MAX_RESTART 512
 /* time the orthogonalisation kernels with HIP events (cbg_result.prof_*) */
 #define CBG_FLAG_PROFILE 1
-/* run the update of step 5 and the re-dot of step 8 as two basis passes
- * (by default they share one pass while j fits the fused kernel's register
- * tile; the arithmetic is the same, the summation order of u differs) */
+/* with CBG_FLAG_EXPLICIT_REDOT: run the update of step 5 and the re-dot of
+ * step 8 as two basis passes (otherwise they share one pass while j fits
+ * the fused kernel's register tile; the arithmetic is the same, the
+ * summation order of u differs); no effect on the default form */
 #define CBG_FLAG_NO_FUSE 2
 /* time only the multi-dot launches with HIP events (cbg_result.prof_dot_*;
- * one event pair per launch instead of four per step) */
+ * one event pair per step instead of one per basis-streaming launch) */
 #define CBG_FLAG_PROFILE_DOT 4
 /* Ablations of the Arnoldi step (numerical studies; off by default).
  * SPMV_VHAT: step 3 multiplies by the stored vector read back, dec(v^_j),
@@ -190,10 +191,10 @@ typedef struct {
     double prof_orth_ms;
     double prof_orth_bytes;
     int64_t prof_orth_launches;
-    double prof_dot_ms;        /* the multi-dot kernel alone (both passes) */
+    double prof_dot_ms;        /* the multi-dot kernel alone (every multi-dot launch) */
     double prof_dot_bytes;
     int64_t prof_dot_launches;
-    double prof_fused_ms;      /* the fused update + re-dot kernel alone */
+    double prof_fused_ms;      /* the fused update + re-dot kernel alone (explicit form) */
     double prof_fused_bytes;
     int64_t prof_fused_launches;
 } cbg_result;
