@@ -359,7 +359,10 @@ __global__ __launch_bounds__(BLK) void k_spmv(int n, int64_t ldy, const int32_t 
         ep = param_from_scale(fmt, *qscale);
     }
     constexpr int TPR = BLK / RPB;          // threads per row in the sum phase
-    constexpr int UNR = 4;                  // products per thread per batch
+    // products per thread per batch: eight on the short-row shape (one batch
+    // covers the block's 256 rows of a 7-point matrix: 36.1 against 38.1 us
+    // at 128^3), four on the long-row shapes (27-point rows: 165 against 167)
+    constexpr int UNR = RPB >= 256 ? 8 : 4;
     __shared__ double prod[CAP];
     __shared__ int lrp[RPB + 1];
     const int tid = threadIdx.x;
