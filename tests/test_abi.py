@@ -120,3 +120,19 @@ def test_kernel_calls_reject_bad_arguments_on_host(L):
                         1 << 20, None) == B.E_ARG
     bad = B.CbgCsr(-1, 0, 0, None, None, None)
     assert L.cbg_spmv(C.byref(bad), vp(16), vp(32), None, None, 0, None) == B.E_ARG
+
+
+def test_variant_names_map_to_flags():
+    """Variant names mean what the oracle's names mean; an empty variant is
+    the library default (the Gram-form re-dot with steps 5-10 in one
+    update), so "gram" alone asks for the two-pass form."""
+    from paper_2009_12101_amd import _binding as B
+    assert B.variant_flags(()) == 0
+    assert B.variant_flags(("gram", "onepass")) == 0
+    assert B.variant_flags("gram") == B.FLAG_TWO_PASS
+    assert B.variant_flags("explicit_redot") == B.FLAG_EXPLICIT_REDOT
+    assert B.variant_flags(("mgs", "always_reorth")) == B.FLAG_MGS | B.FLAG_ALWAYS_REORTH
+    assert B.variant_flags(("gram", "spmv_vhat")) == B.FLAG_TWO_PASS | B.FLAG_SPMV_VHAT
+    for bad in ("onepass", "cgs3", ("gram", "nope")):
+        with pytest.raises(KeyError):
+            B.variant_flags(bad)
