@@ -210,6 +210,35 @@ def _stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def _need(t, name: str, dtype, numel: int, device=None, exact: bool = False, gpu: bool = True):
+    """Raise ValueError unless t is a contiguous tensor of `dtype` holding at
+    least `numel` elements (exactly `numel` with exact=True) on a GPU
+    (`device`, if given).  The C ABI takes bare pointers and cannot check
+    lengths, so a short or mistyped tensor would let the kernels read or
+    write past its allocation."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if (t.numel() != numel) if exact else (t.numel() < numel):
+        raise ValueError(f"{name}: {t.numel()} elements, expected "
+                         f"{'' if exact else 'at least '}{numel}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor is not contiguous")
+    if not gpu:
+        return t
+    if t.device.type != "cuda":
+        raise ValueError(f"{name}: tensor on {t.device}, expected a GPU tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name}: tensor on {t.device}, expected {device}")
+    return t
+
+
+def _dev_of(A):
+    return A.val.device
+
+
 def last_hip_error():
     """(hipError_t, library source line, error name) of the last failing HIP
     call on this thread (0 if none)."""
@@ -245,7 +274,23 @@ class DeviceCSR:
         va = torch.from_numpy(np.ascontiguousarray(A.val, dtype=np.float64)).to(device)
         return cls(int(A.n), int(A.nnz), rp, ci, va)
 
+    def check(self):
+        """Raise ValueError unless the arrays match n and nnz (int32 indices,
+        fp64 values, contiguous, one GPU)."""
+        torch = _torch()
+        if self.n < 0 or self.nnz < 0:
+            raise ValueError(f"CSR: n = {self.n}, nnz = {self.nnz}")
+        dev = self.val.device
+        arrays = ((self.row_ptr, "A.row_ptr", torch.int32, self.n + 1),
+                  (self.col_idx, "A.col_idx", torch.int32, self.nnz),
+                  (self.val, "A.val", torch.float64, self.nnz))
+        for gpu in (False, True):           # shapes first, then the device
+            for t, nm, dt, cnt in arrays:
+                _need(t, nm, dt, cnt, dev, exact=True, gpu=gpu)
+        return self
+
     def cstruct(self) -> CbgCsr:
+        self.check()
         return CbgCsr(self.n, 0, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(),
                       self.val.data_ptr())
 
@@ -286,10 +331,21 @@ def solve(A: DeviceCSR, b, x0=None, restart=100, fmt="fp64", tol=1e-10, maxiter=
     v_j = w / t is formed; the same bits either way).  Raises CbgError on a
     negative status."""
     torch = _torch()
+    A.check()
+    dev = _dev_of(A)
+    _need(b, "b", torch.float64, A.n, dev, exact=True)
+    if x0 is not None:
+        _need(x0, "x0", torch.float64, A.n, dev, exact=True)
+    if precond == "sparse" or p_val is not None:
+        if p_val is None:
+            raise ValueError("p_val: the sparse preconditioner needs its values")
+        _need(p_val, "p_val", torch.float32, A.nnz, dev, exact=True)
     x = torch.zeros(A.n, dtype=torch.float64, device=b.device) if x0 is None else x0.clone()
     need = workspace_bytes(A.n, restart, fmt, precond)
     if need == 0 and A.n > 0:
         raise CbgError(E_ARG, "cbg_workspace_bytes")
+    if workspace is not None:
+        _need(workspace, "workspace", torch.uint8, 0, dev)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=b.device)
     flags = {False: 0, True: FLAG_PROFILE, "dot": FLAG_PROFILE_DOT}[profile] \
@@ -328,12 +384,16 @@ def encode(fmt: str, v, out=None, scale=None, ws=None):
     """The accessor's store: returns (q, scale) on the device."""
     torch = _torch()
     n = v.numel()
+    _need(v, "v", torch.float64, n)
     dt = {"fp64": torch.float64, "fp32": torch.float32, "fp16": torch.int16, "bf16": torch.int16,
           "e4m3": torch.uint8, "int32": torch.int32, "int16": torch.int16,
           "fp16s": torch.int16}[fmt]
     q = torch.empty(n, dtype=dt, device=v.device) if out is None else out
     sc = torch.empty(1, dtype=torch.float64, device=v.device) if scale is None else scale
     ws = _kws(n, 0, v.device) if ws is None else ws
+    _need(q, "q", dt, n, v.device)
+    _need(sc, "scale", torch.float64, 1, v.device)
+    _need(ws, "ws", torch.uint8, kernel_workspace_bytes(n, 0), v.device)
     _check(lib().cbg_encode(FORMATS[fmt], _ptr(v), n, _ptr(q), _ptr(sc), _ptr(ws), ws.numel(),
                             _stream()), "cbg_encode")
     return q, sc
@@ -342,6 +402,11 @@ def encode(fmt: str, v, out=None, scale=None, ws=None):
 def decode(fmt: str, q, scale, n=None):
     torch = _torch()
     n = q.numel() if n is None else n
+    if q.dtype not in (torch.float64, torch.float32, torch.int16, torch.uint8, torch.int32) or \
+            q.element_size() != FORMAT_BYTES[fmt]:
+        raise ValueError(f"q: dtype {q.dtype} does not hold {fmt} codes")
+    _need(q, "q", q.dtype, n)
+    _need(scale, "scale", torch.float64, 1, q.device)
     v = torch.empty(n, dtype=torch.float64, device=q.device)
     _check(lib().cbg_decode(FORMATS[fmt], _ptr(q), _ptr(scale), n, _ptr(v), _stream()),
            "cbg_decode")
@@ -350,7 +415,10 @@ def decode(fmt: str, q, scale, n=None):
 
 def spmv(A: DeviceCSR, x, y=None, want_norm=False):
     torch = _torch()
+    A.check()
+    _need(x, "x", torch.float64, A.n, _dev_of(A))
     y = torch.empty(A.n, dtype=torch.float64, device=x.device) if y is None else y
+    _need(y, "y", torch.float64, A.n, _dev_of(A))
     nrm = torch.empty(1, dtype=torch.float64, device=x.device) if want_norm else None
     ws = _kws(A.n, 0, x.device) if want_norm else None
     csr = A.cstruct()
@@ -359,10 +427,29 @@ def spmv(A: DeviceCSR, x, y=None, want_norm=False):
     return (y, nrm) if want_norm else y
 
 
+def _check_basis(fmt, V, ld, scales, n, j, device):
+    """The stored basis: j vectors of ld entries (ld >= n) in `fmt`, one fp64
+    scale each."""
+    torch = _torch()
+    if ld < n:
+        raise ValueError(f"ld = {ld} < n = {n}")
+    if j > 0:
+        if not isinstance(V, torch.Tensor) or V.device != device or not V.is_contiguous():
+            raise ValueError("V: expected a contiguous tensor on the GPU of w")
+        if V.numel() * V.element_size() < j * ld * FORMAT_BYTES[fmt]:
+            raise ValueError(f"V: {V.numel() * V.element_size()} bytes, expected at least "
+                             f"{j * ld * FORMAT_BYTES[fmt]} ({j} vectors of {ld} {fmt} entries)")
+        _need(scales, "scales", torch.float64, j, device)
+
+
 def multidot(fmt: str, V, ld: int, scales, n: int, j: int, w, h=None, ws=None):
     torch = _torch()
+    _need(w, "w", torch.float64, n)
+    _check_basis(fmt, V, ld, scales, n, j, w.device)
     h = torch.empty(max(j, 1), dtype=torch.float64, device=w.device) if h is None else h
     ws = _kws(n, j, w.device) if ws is None else ws
+    _need(h, "h", torch.float64, j, w.device)
+    _need(ws, "ws", torch.uint8, kernel_workspace_bytes(n, j), w.device)
     _check(lib().cbg_multidot(FORMATS[fmt], _ptr(V), ld, _ptr(scales), n, j, _ptr(w), _ptr(h),
                               _ptr(ws), ws.numel(), _stream()), "cbg_multidot")
     return h[:j]
@@ -370,8 +457,13 @@ def multidot(fmt: str, V, ld: int, scales, n: int, j: int, w, h=None, ws=None):
 
 def update(fmt: str, V, ld: int, scales, n: int, j: int, h, w, norms=None, ws=None):
     torch = _torch()
+    _need(w, "w", torch.float64, n)
+    _check_basis(fmt, V, ld, scales, n, j, w.device)
+    _need(h, "h", torch.float64, j, w.device)
     norms = torch.empty(2, dtype=torch.float64, device=w.device) if norms is None else norms
     ws = _kws(n, 0, w.device) if ws is None else ws
+    _need(norms, "norms", torch.float64, 2, w.device)
+    _need(ws, "ws", torch.uint8, kernel_workspace_bytes(n, 0), w.device)
     _check(lib().cbg_update(FORMATS[fmt], _ptr(V), ld, _ptr(scales), n, j, _ptr(h), _ptr(w),
                             _ptr(norms), _ptr(ws), ws.numel(), _stream()), "cbg_update")
     return norms
@@ -380,9 +472,13 @@ def update(fmt: str, V, ld: int, scales, n: int, j: int, h, w, norms=None, ws=No
 def update_redot(fmt: str, V, ld: int, scales, n: int, j: int, h, w, ws=None):
     """w -= V h, then (u = V^T w, norms = [||w||_2, ||w||_inf]) in one pass."""
     torch = _torch()
+    _need(w, "w", torch.float64, n)
+    _check_basis(fmt, V, ld, scales, n, j, w.device)
+    _need(h, "h", torch.float64, j, w.device)
     u = torch.empty(max(j, 1), dtype=torch.float64, device=w.device)
     norms = torch.empty(2, dtype=torch.float64, device=w.device)
     ws = _kws(n, j, w.device) if ws is None else ws
+    _need(ws, "ws", torch.uint8, kernel_workspace_bytes(n, j), w.device)
     _check(lib().cbg_update_redot(FORMATS[fmt], _ptr(V), ld, _ptr(scales), n, j, _ptr(h),
                                   _ptr(w), _ptr(u), _ptr(norms), _ptr(ws), ws.numel(),
                                   _stream()), "cbg_update_redot")
@@ -410,7 +506,14 @@ def block_jacobi_setup(A: DeviceCSR, bs=4, prec_min=16):
 def block_jacobi_apply(n, bs, blocks, v, z=None):
     torch = _torch()
     tags, x64, x32, x16 = blocks
+    nblk = (n + bs - 1) // bs
+    _need(v, "v", torch.float64, n)
+    _need(tags, "tags", torch.int8, nblk, v.device)
+    for t, nm, dt in ((x64, "x64", torch.float64), (x32, "x32", torch.float32),
+                      (x16, "x16", torch.int16)):
+        _need(t, nm, dt, nblk * bs * bs, v.device)
     z = torch.empty(n, dtype=torch.float64, device=v.device) if z is None else z
+    _need(z, "z", torch.float64, n, v.device)
     _check(lib().cbg_block_jacobi_apply(n, bs, _ptr(tags), _ptr(x64), _ptr(x32), _ptr(x16),
                                         _ptr(v), _ptr(z), _stream()), "cbg_block_jacobi_apply")
     return z
@@ -418,8 +521,11 @@ def block_jacobi_apply(n, bs, blocks, v, z=None):
 
 # ------------------------------------------------ learned preconditioner
 
-def _grid3(grid):
-    return (C.c_int32 * 3)(*[int(g) for g in grid])
+def _grid3(grid, n=None):
+    g = [int(v) for v in grid]
+    if len(g) != 3 or min(g) < 1 or (n is not None and g[0] * g[1] * g[2] != n):
+        raise ValueError(f"grid {tuple(grid)} does not number the {n} rows")
+    return (C.c_int32 * 3)(*g)
 
 
 def _sws(n, nnz, K, device):
@@ -434,8 +540,10 @@ def spai_features(A: DeviceCSR, grid, feat=None, ws=None):
     dev = A.val.device
     feat = torch.empty((A.n, SPAI_NFEAT), dtype=torch.int16, device=dev) if feat is None else feat
     ws = _sws(A.n, A.nnz, 0, dev) if ws is None else ws
+    _need(feat, "feat", torch.int16, A.n * SPAI_NFEAT, dev)
+    _need(ws, "ws", torch.uint8, spai_workspace_bytes(A.n, A.nnz, 0), dev)
     csr = A.cstruct()
-    _check(lib().cbg_spai_features(C.byref(csr), _grid3(grid), _ptr(feat), _ptr(ws), ws.numel(),
+    _check(lib().cbg_spai_features(C.byref(csr), _grid3(grid, A.n), _ptr(feat), _ptr(ws), ws.numel(),
                                    _stream()), "cbg_spai_features")
     return feat
 
@@ -444,6 +552,9 @@ def mlp_forward(feat, weights, params, keep_activations=False):
     """Returns O (n, 32) fp32, and (H1, H2) bf16 bit patterns if asked."""
     torch = _torch()
     n, dev = feat.shape[0], feat.device
+    _need(feat, "feat", torch.int16, n * SPAI_NFEAT)
+    _need(weights, "weights", torch.int16, SPAI_NWEIGHT, dev)
+    _need(params, "params", torch.float32, SPAI_NPARAM, dev)
     O = torch.empty((n, SPAI_NOUT), dtype=torch.float32, device=dev)
     h1 = h2 = None
     if keep_activations:
@@ -457,8 +568,10 @@ def mlp_forward(feat, weights, params, keep_activations=False):
 def spai_assemble(A: DeviceCSR, grid, O, p_val=None):
     torch = _torch()
     p_val = torch.empty(A.nnz, dtype=torch.float32, device=O.device) if p_val is None else p_val
+    _need(O, "O", torch.float32, A.n * SPAI_NOUT, _dev_of(A))
+    _need(p_val, "p_val", torch.float32, A.nnz, _dev_of(A))
     csr = A.cstruct()
-    _check(lib().cbg_spai_assemble(C.byref(csr), _grid3(grid), _ptr(O), _ptr(p_val), _stream()),
+    _check(lib().cbg_spai_assemble(C.byref(csr), _grid3(grid, A.n), _ptr(O), _ptr(p_val), _stream()),
            "cbg_spai_assemble")
     return p_val
 
@@ -469,8 +582,12 @@ def learned_build(A: DeviceCSR, grid, weights, params, p_val=None, ws=None):
     dev = A.val.device
     p_val = torch.empty(A.nnz, dtype=torch.float32, device=dev) if p_val is None else p_val
     ws = _sws(A.n, A.nnz, 0, dev) if ws is None else ws
+    _need(weights, "weights", torch.int16, SPAI_NWEIGHT, dev)
+    _need(params, "params", torch.float32, SPAI_NPARAM, dev)
+    _need(p_val, "p_val", torch.float32, A.nnz, dev)
+    _need(ws, "ws", torch.uint8, spai_workspace_bytes(A.n, A.nnz, 0), dev)
     csr = A.cstruct()
-    _check(lib().cbg_learned_build(C.byref(csr), _grid3(grid), _ptr(weights), _ptr(params),
+    _check(lib().cbg_learned_build(C.byref(csr), _grid3(grid, A.n), _ptr(weights), _ptr(params),
                                    _ptr(p_val), _ptr(ws), ws.numel(), _stream()),
            "cbg_learned_build")
     return p_val
@@ -481,6 +598,7 @@ def csr_transpose_values(A: DeviceCSR, ws=None):
     dev = A.val.device
     t = torch.empty(A.nnz, dtype=torch.float64, device=dev)
     ws = _sws(A.n, A.nnz, 0, dev) if ws is None else ws
+    _need(ws, "ws", torch.uint8, spai_workspace_bytes(A.n, A.nnz, 0), dev)
     csr = A.cstruct()
     _check(lib().cbg_csr_transpose_values(C.byref(csr), _ptr(t), _ptr(ws), ws.numel(),
                                           _stream()), "cbg_csr_transpose_values")
@@ -490,7 +608,11 @@ def csr_transpose_values(A: DeviceCSR, ws=None):
 def spai_pack(V, ld: int, n: int, K: int, first: int = 0, stride: int = 1, out=None):
     """(n, K) int16 tensor of fp16 bit patterns from K FP64 vectors in V."""
     torch = _torch()
+    if K < 1 or K > SPAI_MAX_K or first < 0 or stride < 1 or ld < n:
+        raise ValueError(f"spai_pack: K = {K}, first = {first}, stride = {stride}, ld = {ld}")
+    _need(V, "V", torch.float64, (first + (K - 1) * stride) * ld + n)
     out = torch.empty((n, K), dtype=torch.int16, device=V.device) if out is None else out
+    _need(out, "out", torch.int16, n * K, V.device)
     _check(lib().cbg_spai_pack(_ptr(V), int(ld), int(n), int(K), int(first), int(stride),
                                _ptr(out), _stream()), "cbg_spai_pack")
     return out
@@ -501,9 +623,13 @@ def spai_grad_p(A: DeviceCSR, t_val, p_val, V, scale, ws=None):
     torch = _torch()
     dev = A.val.device
     K = V.shape[1]
+    _need(t_val, "t_val", torch.float64, A.nnz, dev)
+    _need(p_val, "p_val", torch.float32, A.nnz, dev)
+    _need(V, "V", torch.int16, A.n * K, dev)
     loss = torch.empty(1, dtype=torch.float64, device=dev)
     dP = torch.empty(A.nnz, dtype=torch.float64, device=dev)
     ws = _sws(A.n, A.nnz, K, dev) if ws is None else ws
+    _need(ws, "ws", torch.uint8, spai_workspace_bytes(A.n, A.nnz, K), dev)
     csr = A.cstruct()
     _check(lib().cbg_spai_grad_p(C.byref(csr), _ptr(t_val), _ptr(p_val), K, _ptr(V),
                                  float(scale), _ptr(loss), 0, _ptr(dP), _ptr(ws), ws.numel(),
@@ -513,9 +639,10 @@ def spai_grad_p(A: DeviceCSR, t_val, p_val, V, scale, ws=None):
 
 def spai_grad_o(A: DeviceCSR, grid, dP):
     torch = _torch()
+    _need(dP, "dP", torch.float64, A.nnz, _dev_of(A))
     dO = torch.empty((A.n, SPAI_NOUT), dtype=torch.int16, device=dP.device)
     csr = A.cstruct()
-    _check(lib().cbg_spai_grad_o(C.byref(csr), _grid3(grid), _ptr(dP), _ptr(dO), _stream()),
+    _check(lib().cbg_spai_grad_o(C.byref(csr), _grid3(grid, A.n), _ptr(dP), _ptr(dO), _stream()),
            "cbg_spai_grad_o")
     return dO
 
@@ -525,6 +652,13 @@ def mlp_backward(feat, h1, h2, dO, weights, grad=None, accumulate=False, ws=None
     n, dev = feat.shape[0], feat.device
     grad = torch.empty(SPAI_NPARAM, dtype=torch.float64, device=dev) if grad is None else grad
     ws = _sws(n, 0, 0, dev) if ws is None else ws
+    _need(feat, "feat", torch.int16, n * SPAI_NFEAT, dev)
+    _need(h1, "h1", torch.int16, n * SPAI_NHID, dev)
+    _need(h2, "h2", torch.int16, n * SPAI_NHID, dev)
+    _need(dO, "dO", torch.int16, n * SPAI_NOUT, dev)
+    _need(weights, "weights", torch.int16, SPAI_NWEIGHT, dev)
+    _need(grad, "grad", torch.float64, SPAI_NPARAM, dev)
+    _need(ws, "ws", torch.uint8, spai_workspace_bytes(n, 0, 0), dev)
     _check(lib().cbg_mlp_backward(n, _ptr(feat), _ptr(h1), _ptr(h2), _ptr(dO), _ptr(weights),
                                   _ptr(grad), int(bool(accumulate)), _ptr(ws), ws.numel(),
                                   _stream()), "cbg_mlp_backward")
@@ -534,23 +668,41 @@ def mlp_backward(feat, h1, h2, dO, weights, grad=None, accumulate=False, ws=None
 def spai_loss_grad(A: DeviceCSR, t_val, grid, feat, weights, params, V, scale, loss, grad,
                    accumulate=False, ws=None):
     """loss[1], grad[NPARAM] (+)= one matrix's loss and parameter gradient."""
+    torch = _torch()
     dev = A.val.device
     K = V.shape[1]
     ws = _sws(A.n, A.nnz, K, dev) if ws is None else ws
+    _need(t_val, "t_val", torch.float64, A.nnz, dev)
+    _need(feat, "feat", torch.int16, A.n * SPAI_NFEAT, dev)
+    _need(weights, "weights", torch.int16, SPAI_NWEIGHT, dev)
+    _need(params, "params", torch.float32, SPAI_NPARAM, dev)
+    _need(V, "V", torch.int16, A.n * K, dev)
+    _need(loss, "loss", torch.float64, 1, dev)
+    _need(grad, "grad", torch.float64, SPAI_NPARAM, dev)
+    _need(ws, "ws", torch.uint8, spai_workspace_bytes(A.n, A.nnz, K), dev)
     csr = A.cstruct()
-    _check(lib().cbg_spai_loss_grad(C.byref(csr), _ptr(t_val), _grid3(grid), _ptr(feat),
+    _check(lib().cbg_spai_loss_grad(C.byref(csr), _ptr(t_val), _grid3(grid, A.n), _ptr(feat),
                                     _ptr(weights), _ptr(params), K, _ptr(V), float(scale),
                                     _ptr(loss), _ptr(grad), int(bool(accumulate)), _ptr(ws),
                                     ws.numel(), _stream()), "cbg_spai_loss_grad")
 
 
 def spai_round_weights(params, weights):
+    torch = _torch()
+    _need(params, "params", torch.float32, SPAI_NPARAM)
+    _need(weights, "weights", torch.int16, SPAI_NWEIGHT, params.device)
     _check(lib().cbg_spai_round_weights(_ptr(params), _ptr(weights), _stream()),
            "cbg_spai_round_weights")
     return weights
 
 
 def adam_step(params, m1, m2, weights, grad, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    torch = _torch()
+    _need(params, "params", torch.float32, SPAI_NPARAM)
+    for tt, nm in ((m1, "m1"), (m2, "m2")):
+        _need(tt, nm, torch.float32, SPAI_NPARAM, params.device)
+    _need(weights, "weights", torch.int16, SPAI_NWEIGHT, params.device)
+    _need(grad, "grad", torch.float64, SPAI_NPARAM, params.device)
     _check(lib().cbg_adam_step(_ptr(params), _ptr(m1), _ptr(m2), _ptr(weights), _ptr(grad),
                                int(t), float(lr), float(beta1), float(beta2), float(eps),
                                _stream()), "cbg_adam_step")

@@ -136,3 +136,45 @@ def test_variant_names_map_to_flags():
     for bad in ("onepass", "cgs3", ("gram", "nope")):
         with pytest.raises(KeyError):
             B.variant_flags(bad)
+
+
+def test_binding_checks_tensors_before_the_call():
+    """The C ABI takes bare pointers, so the binding checks dtype, length,
+    contiguity and device of every tensor it passes; a mismatch is a
+    ValueError raised before the library is called."""
+    import numpy as np
+    torch = pytest.importorskip("torch")
+    from paper_2009_12101_amd import _binding as B
+    from paper_2009_12101_amd import problems as P
+    f64 = torch.zeros(8, dtype=torch.float64)
+    with pytest.raises(ValueError, match="dtype"):
+        B._need(f64.float(), "b", torch.float64, 8)
+    with pytest.raises(ValueError, match="at least 9"):
+        B._need(f64, "b", torch.float64, 9)
+    with pytest.raises(ValueError, match="expected 7"):
+        B._need(f64, "b", torch.float64, 7, exact=True)
+    with pytest.raises(ValueError, match="contiguous"):
+        B._need(torch.zeros(16, dtype=torch.float64)[::2], "b", torch.float64, 8)
+    with pytest.raises(ValueError, match="GPU"):
+        B._need(f64, "b", torch.float64, 8)
+    with pytest.raises(ValueError, match="torch tensor"):
+        B._need(np.zeros(8), "b", torch.float64, 8)
+    # a CSR whose arrays do not match n and nnz
+    A = P.poisson2d(4)
+    D = B.DeviceCSR.from_host(A, "cpu")
+    bad = B.DeviceCSR(D.n, D.nnz, D.row_ptr, D.col_idx, D.val.float())
+    with pytest.raises(ValueError, match="A.val: dtype"):
+        bad.check()
+    short = B.DeviceCSR(D.n, D.nnz, D.row_ptr[:-1].clone(), D.col_idx, D.val)
+    with pytest.raises(ValueError, match="A.row_ptr"):
+        short.check()
+    # every wrapper checks before it calls: CPU tensors never reach the ABI
+    b = torch.from_numpy(P.rhs_uniform(A.n, 0))
+    with pytest.raises(ValueError):
+        B.solve(D, b, restart=5)
+    with pytest.raises(ValueError):
+        B.spmv(D, b)
+    with pytest.raises(ValueError):
+        B.multidot("fp16", torch.zeros(256, dtype=torch.int16), 256, torch.ones(1), A.n, 1, b)
+    with pytest.raises(ValueError, match="grid"):
+        B._grid3((4, 4, 2), A.n)
