@@ -30,7 +30,7 @@ STORAGE_DTYPE = {"fp64": np.float64, "fp32": np.float32, "fp16": np.uint16, "bf1
 # ("explicit_redot" names the default, the re-dot Fig. 1 writes)
 VARIANTS = {"spmv_vhat": 1, "always_reorth": 2, "mgs": 4, "gram": 8, "explicit_redot": 0,
             "onepass": 16}
-PRECONDS = {"none": 0, "jacobi": 1, "sparse": 2, "block_jacobi": 3}
+PRECONDS = {"none": 0, "jacobi": 1, "sparse": 2, "block_jacobi": 3, "stencil": 4}
 OK, NOT_CONVERGED, E_ARG, E_NONFINITE = 0, 1, -1, -4
 
 
@@ -49,7 +49,8 @@ class _Opts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("format", C.c_int32), ("tol", C.c_double),
                 ("maxiter", C.c_int64), ("eta", C.c_double), ("precond", C.c_int32),
                 ("p_val", C.c_void_p), ("fallback", C.c_int32), ("pc_block", C.c_int32),
-                ("pc_prec", C.c_int32), ("variant", C.c_int32), ("pad", C.c_int32)]
+                ("pc_prec", C.c_int32), ("variant", C.c_int32), ("pad", C.c_int32),
+                ("p_stencil", C.c_void_p), ("grid", C.c_int32 * 3), ("st_ld", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -80,6 +81,8 @@ def lib():
                                 vp, vp, vp, vp, vp, C.POINTER(i32)]
         L.orc_block_jacobi.argtypes = [i32, vp, vp, vp, i32, i32, vp, vp]
         L.orc_block_jacobi.restype = C.c_int
+        L.orc_stencil_apply.argtypes = [i32, vp, vp, vp, C.POINTER(i32), vp, i64, vp, vp]
+        L.orc_stencil_apply.restype = C.c_int
         L.orc_set_threads.argtypes = [C.c_int]
         L.orc_set_threads.restype = None
         L.orc_get_threads.argtypes = []
@@ -149,9 +152,23 @@ def block_jacobi(A, bs=4, prec_min=16):
     return vals.reshape(nblk, bs, bs), prec
 
 
+def stencil_apply(A, grid, codes, v):
+    """z = M^-1 v for the stencil preconditioner (orc_opts, ORC_PC_STENCIL):
+    codes (27, ld) uint16 float16 codes, slot-major."""
+    codes = np.ascontiguousarray(codes, dtype=np.uint16)
+    v = _f64(v)
+    z = np.empty(A.n, dtype=np.float64)
+    g = (C.c_int32 * 3)(*[int(t) for t in grid])
+    rc = lib().orc_stencil_apply(A.n, _p(A.row_ptr), _p(A.col_idx), _p(A.val), g, _p(codes),
+                                 codes.shape[1], _p(v), _p(z))
+    if rc != 0:
+        raise ValueError(f"orc_stencil_apply: {rc}")
+    return z
+
+
 def gmres(A, b, x0=None, restart=100, fmt="fp64", tol=1e-10, maxiter=10000, eta=0.0,
           precond="none", p_val=None, fallback=False, debug=False, pc_block=0, pc_prec=0,
-          variant=()):
+          variant=(), p_stencil=None, grid=(0, 0, 0)):
     """Run the oracle solver. Returns a dict with x, status, counts, the
     recurrence-residual history and the explicit residual per cycle; with
     ``debug`` also the first cycle's decoded basis V (k x n) and its
@@ -163,12 +180,16 @@ def gmres(A, b, x0=None, restart=100, fmt="fp64", tol=1e-10, maxiter=10000, eta=
     pv = None
     if precond == "sparse":
         pv = np.ascontiguousarray(p_val, dtype=np.float32)
+    st = None
+    if precond == "stencil":
+        st = np.ascontiguousarray(p_stencil, dtype=np.uint16)
     vbits = 0
     for name in ((variant,) if isinstance(variant, str) else variant):
         vbits |= VARIANTS[name]
     opts = _Opts(restart, FORMATS[fmt], tol, maxiter, eta, PRECONDS[precond],
                  None if pv is None else pv.ctypes.data, int(bool(fallback)), pc_block, pc_prec,
-                 vbits, 0)
+                 vbits, 0, None if st is None else st.ctypes.data,
+                 (C.c_int32 * 3)(*[int(t) for t in grid]), 0 if st is None else st.shape[1])
     res = _Result()
     hist = np.full(max(maxiter, 1), np.nan)
     cyc = np.full(max(maxiter, 1) + 2, np.nan)

@@ -508,11 +508,38 @@ int orc_block_jacobi(int32_t n, const int32_t *rp, const int32_t *ci, const doub
 
 typedef struct {
     int kind;                 /* ORC_PC_* currently in force */
-    double *dinv;             /* Jacobi: 1 / a_ii */
+    double *dinv;             /* Jacobi, stencil: 1 / a_ii */
     const float *pv;          /* sparse: P values on A's pattern */
     int bs;                   /* block-Jacobi: block size */
     double *bj;               /* block-Jacobi: stored inverse values */
+    const uint16_t *st;       /* stencil: float16 codes, slot-major */
+    int32_t nx, ny, nz;       /* stencil: grid */
+    int64_t st_ld;            /* stencil: slot stride */
 } precond;
+
+/* The stencil preconditioner of orc_opts (ORC_PC_STENCIL): row i at grid
+ * point (x, y, z) sums its existing neighbours in slot order. */
+static void apply_stencil(const precond *M, int32_t n, const double *v, double *z)
+{
+    const int64_t nx = M->nx, ny = M->ny, nz = M->nz;
+#pragma omp parallel for schedule(static)
+    for (int32_t i = 0; i < n; ++i) {
+        const int64_t x = i % nx, y = (i / nx) % ny, zz = i / (nx * ny);
+        double s = 0.0;
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    if (x + dx < 0 || x + dx >= nx || y + dy < 0 || y + dy >= ny ||
+                        zz + dz < 0 || zz + dz >= nz)
+                        continue;
+                    const int p = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1);
+                    const double c = (p == 13 ? 1.0 : 0.0) +
+                                     tab_f16[M->st[(int64_t)p * M->st_ld + i]];
+                    s = s + c * v[i + dz * nx * ny + dy * nx + dx];
+                }
+        z[i] = M->dinv[i] * s;
+    }
+}
 
 /* z = M^{-1} v (Fig. 1 step 3 and step 17). */
 static void apply_precond(const precond *M, int32_t n, const int32_t *rp, const int32_t *ci,
@@ -524,6 +551,8 @@ static void apply_precond(const precond *M, int32_t n, const int32_t *rp, const 
             z[i] = M->dinv[i] * v[i];
     } else if (M->kind == ORC_PC_SPARSE) {
         spmv_f32vals(n, rp, ci, M->pv, v, z);
+    } else if (M->kind == ORC_PC_STENCIL) {
+        apply_stencil(M, n, v, z);
     } else if (M->kind == ORC_PC_BLOCK_JACOBI) {
         const int bs = M->bs;
 #pragma omp parallel for schedule(static)
@@ -562,12 +591,15 @@ int orc_gmres(int32_t n, const int32_t *rp, const int32_t *ci, const double *val
     const int fmt = opt->format;
     const int bs = orc_format_bytes(fmt);
     if (n < 0 || m < 1 || bs == 0 || !(opt->tol >= 0.0) || opt->maxiter < 0 ||
-        opt->precond < ORC_PC_NONE || opt->precond > ORC_PC_BLOCK_JACOBI ||
+        opt->precond < ORC_PC_NONE || opt->precond > ORC_PC_STENCIL ||
         (opt->variant & ~(ORC_V_SPMV_VHAT | ORC_V_ALWAYS_REORTH | ORC_V_MGS | ORC_V_GRAM |
                           ORC_V_ONEPASS)) != 0 ||
         ((opt->variant & ORC_V_MGS) && (opt->variant & ORC_V_GRAM)) ||
         ((opt->variant & ORC_V_ONEPASS) && !(opt->variant & ORC_V_GRAM)) ||
         (opt->precond == ORC_PC_SPARSE && !opt->p_val) ||
+        (opt->precond == ORC_PC_STENCIL &&
+         (!opt->p_stencil || opt->grid[0] < 1 || opt->grid[1] < 1 || opt->grid[2] < 1 ||
+          (int64_t)opt->grid[0] * opt->grid[1] * opt->grid[2] != n || opt->st_ld < n)) ||
         (n > 0 && (!rp || !ci || !val || !b || !x))) {
         res->status = ORC_E_ARG;
         return ORC_E_ARG;
@@ -599,7 +631,8 @@ int orc_gmres(int32_t n, const int32_t *rp, const int32_t *ci, const double *val
         return ORC_OK;
     }
 
-    precond M = {opt->precond, NULL, opt->p_val, 0, NULL};
+    precond M = {opt->precond, NULL, opt->p_val, 0, NULL, opt->p_stencil, opt->grid[0],
+                 opt->grid[1], opt->grid[2], opt->st_ld};
     if (M.kind == ORC_PC_BLOCK_JACOBI) {
         M.bs = opt->pc_block > 0 ? opt->pc_block : 4;
         const int pmin = opt->pc_prec > 0 ? opt->pc_prec : 16;
@@ -614,7 +647,7 @@ int orc_gmres(int32_t n, const int32_t *rp, const int32_t *ci, const double *val
             return ORC_E_ARG;
         }
     }
-    if (M.kind == ORC_PC_JACOBI) {
+    if (M.kind == ORC_PC_JACOBI || M.kind == ORC_PC_STENCIL) {
         M.dinv = (double *)malloc((size_t)n * sizeof(double));
         int bad = 0;
         for (int32_t i = 0; i < n; ++i) {
@@ -677,7 +710,8 @@ int orc_gmres(int32_t n, const int32_t *rp, const int32_t *ci, const double *val
             cycle_res[cycle] = rho / nb;
 
         if (!isfinite(rho)) {
-            if (M.kind == ORC_PC_SPARSE && opt->fallback && cycle > 0) {
+            if ((M.kind == ORC_PC_SPARSE || M.kind == ORC_PC_STENCIL) && opt->fallback &&
+                cycle > 0) {
                 /* plain CB-GMRES takes over from the last finite iterate */
                 memcpy(x, xprev, (size_t)n * sizeof(double));
                 M.kind = ORC_PC_NONE;
@@ -697,7 +731,7 @@ int orc_gmres(int32_t n, const int32_t *rp, const int32_t *ci, const double *val
             status = ORC_NOT_CONVERGED;
             break;
         }
-        if (M.kind == ORC_PC_SPARSE && opt->fallback) {
+        if ((M.kind == ORC_PC_SPARSE || M.kind == ORC_PC_STENCIL) && opt->fallback) {
             /* stagnation: explicit residual not below 0.99x its previous
              * value in two consecutive cycles */
             stagnant = rho > 0.99 * rho_prev ? stagnant + 1 : 0;
@@ -952,4 +986,30 @@ int orc_get_threads(void)
 #else
     return 1;
 #endif
+}
+
+int orc_stencil_apply(int32_t n, const int32_t *rp, const int32_t *ci, const double *val,
+                      const int32_t grid[3], const uint16_t *codes, int64_t st_ld,
+                      const double *v, double *z)
+{
+    if (n < 0 || !grid || grid[0] < 1 || grid[1] < 1 || grid[2] < 1 ||
+        (int64_t)grid[0] * grid[1] * grid[2] != n || st_ld < n ||
+        (n > 0 && (!rp || !ci || !val || !codes || !v || !z)))
+        return ORC_E_ARG;
+    precond M = {ORC_PC_STENCIL, NULL, NULL, 0, NULL, codes, grid[0], grid[1], grid[2], st_ld};
+    M.dinv = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    int bad = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        double d = 0.0;
+        for (int32_t p = rp[i]; p < rp[i + 1]; ++p)
+            if (ci[p] == i)
+                d = val[p];
+        if (d == 0.0)
+            bad = 1;
+        M.dinv[i] = 1.0 / d;
+    }
+    if (!bad)
+        apply_stencil(&M, n, v, z);
+    free(M.dinv);
+    return bad ? ORC_E_ARG : 0;
 }

@@ -55,7 +55,23 @@ enum {
 enum { ORC_V_SPMV_VHAT = 1, ORC_V_ALWAYS_REORTH = 2, ORC_V_MGS = 4, ORC_V_GRAM = 8,
        ORC_V_ONEPASS = 16 };
 
-enum { ORC_PC_NONE = 0, ORC_PC_JACOBI = 1, ORC_PC_SPARSE = 2, ORC_PC_BLOCK_JACOBI = 3 };
+/* Right preconditioners M^-1 (Fig. 1 step 3; step 17):
+ *   ORC_PC_JACOBI       z_i = d_i v_i, d_i = fl(1 / a_ii) (Section 6 uses it);
+ *   ORC_PC_SPARSE       z = P v, P with float values on A's pattern;
+ *   ORC_PC_BLOCK_JACOBI see orc_block_jacobi;
+ *   ORC_PC_STENCIL      the learned preconditioner in its stored form (this
+ *                       project's definition): on an nx x ny x nz grid
+ *                       (x fastest), row i's 27 stencil slots p = 9(dz+1) +
+ *                       3(dy+1) + (dx+1) carry float16 codes o_{p,i}
+ *                       (slot-major: code of slot p of row i at p ld + i,
+ *                       ld = the row stride given), and
+ *                         z_i = d_i * sum_p c_{p,i} v_{i + dz nx ny + dy nx + dx}
+ *                       over the slots whose grid point exists, in slot
+ *                       order, with c_{p,i} = [p = 13] + dec16(o_{p,i})
+ *                       (exact in FP64) and d_i = fl(1 / a_ii).  All codes
+ *                       0 gives Jacobi bit for bit. */
+enum { ORC_PC_NONE = 0, ORC_PC_JACOBI = 1, ORC_PC_SPARSE = 2, ORC_PC_BLOCK_JACOBI = 3,
+       ORC_PC_STENCIL = 4 };
 
 enum { ORC_OK = 0, ORC_NOT_CONVERGED = 1, ORC_E_ARG = -1, ORC_E_NONFINITE = -4 };
 
@@ -90,6 +106,9 @@ typedef struct {
                                  or 64 bits (0: 16) */
     int32_t variant;          /* ORC_V_* bits (0: Fig. 1 as written) */
     int32_t pad;
+    const uint16_t *p_stencil; /* ORC_PC_STENCIL: 27 x st_ld float16 codes, slot-major */
+    int32_t grid[3];          /* ORC_PC_STENCIL: nx, ny, nz with nx ny nz = n */
+    int32_t st_ld;            /* ORC_PC_STENCIL: slot stride (>= n) */
 } orc_opts;
 
 typedef struct {
@@ -143,6 +162,13 @@ int orc_gmres(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
 
 void orc_set_threads(int nthreads);
 int  orc_get_threads(void);
+
+/* z = M^-1 v for ORC_PC_STENCIL alone (the definition above); returns
+ * ORC_E_ARG if a diagonal entry is missing or zero or the grid does not
+ * number the n rows. */
+int orc_stencil_apply(int32_t n, const int32_t *rp, const int32_t *ci, const double *val,
+                      const int32_t grid[3], const uint16_t *codes, int64_t st_ld,
+                      const double *v, double *z);
 
 #ifdef __cplusplus
 }

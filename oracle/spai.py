@@ -36,6 +36,13 @@ rounding points.
   bf16 matrix units).
 * Adam (Kingma and Ba, 2015) on fp32 master weights; the bf16 weights are
   the round-to-nearest-even of the masters.
+* Stored form for the solve: the corrections O_{i,p} of the slots present
+  in row i, rounded once to float16 (round to nearest even from the fp32
+  network output; 0 for absent slots), slot-major (27 rows of ld codes).
+  The solve applies z_i = fl(1/a_ii) * sum_p ([p = 13] + o_{p,i}) v at the
+  slot's grid neighbour (ORC_PC_STENCIL of the oracle's options): the same
+  operator as D^-1 (I + O) up to the float16 rounding of O, with zero
+  codes giving Jacobi bit for bit.
 """
 from __future__ import annotations
 
@@ -118,6 +125,21 @@ def p_values(A, grid, O, rounding=True) -> np.ndarray:
     val = (delta + np.where(slots >= 0, o, 0.0)) / d[rows]
     val = np.where(slots >= 0, val, 0.0)
     return fl32(val) if rounding else val
+
+
+def stencil_codes(A, grid, O, ld=None) -> np.ndarray:
+    """(27, ld) uint16 float16 codes of the stored form: slot p of row i holds
+    fp16(O_{i,p}) if row i stores that slot, else 0.  O (n, >= 27) holds
+    fp32 values; numpy's float32 -> float16 cast rounds once to nearest
+    even."""
+    ld = A.n if ld is None else ld
+    slots = entry_slots(A, grid)
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    good = slots >= 0
+    codes = np.zeros((NSLOT, ld), dtype=np.uint16)
+    o16 = np.asarray(O, dtype=np.float32)[rows[good], slots[good]].astype(np.float16)
+    codes[slots[good], rows[good]] = o16.view(np.uint16)
+    return codes
 
 
 def _csr_matvec(A, vals, X):

@@ -137,3 +137,128 @@ def test_adam_first_step_is_lr_sign(S):
     for k in prm:
         expect = -1e-3 * g[k].astype(np.float32) / (np.abs(g[k].astype(np.float32)) + 1e-8)
         assert np.allclose(prm[k], expect, rtol=1e-6, atol=0)
+
+
+# ---------------------------------------------------------------- stored form
+
+def _stencil_csr(A, grid, codes):
+    """The stored form assembled independently as a scipy CSR matrix:
+    M = diag(1/a_ii) (I + O16) with O16 the decoded codes at the grid
+    neighbour of each slot (numpy's float16 decode)."""
+    import scipy.sparse as sp
+    nx, ny, nz = grid
+    n = A.n
+    rows, cols, vals = [], [], []
+    dinv = 1.0 / np.array([A.val[A.row_ptr[i]:A.row_ptr[i + 1]][
+        A.col_idx[A.row_ptr[i]:A.row_ptr[i + 1]] == i][-1] for i in range(n)])
+    o = codes.view(np.float16).astype(np.float64)
+    for i in range(n):
+        x, y, z = i % nx, (i // nx) % ny, i // (nx * ny)
+        for p in range(27):
+            dz, dy, dx = p // 9 - 1, (p // 3) % 3 - 1, p % 3 - 1
+            if 0 <= x + dx < nx and 0 <= y + dy < ny and 0 <= z + dz < nz:
+                c = (1.0 if p == 13 else 0.0) + o[p, i]
+                if c != 0.0:
+                    rows.append(i)
+                    cols.append(i + dz * nx * ny + dy * nx + dx)
+                    vals.append(dinv[i] * c)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(n, n)), dinv
+
+
+def test_stencil_codes_are_fp16_of_the_present_slots(S):
+    """Codes: fp16(O) on the slots row i stores, 0 on the others (a 7-point
+    matrix leaves 20 of the 27 grid slots of an interior row empty), at
+    stride ld; checked entry by entry against the CSR pattern."""
+    A = P.convdiff7(4)
+    O = np.random.default_rng(1).standard_normal((A.n, 32)).astype(np.float32)
+    ld = A.n + 5
+    codes = S.stencil_codes(A, A.grid, O, ld)
+    assert codes.shape == (27, ld) and np.all(codes[:, A.n:] == 0)
+    nx, ny, _ = A.grid
+    for i in range(A.n):
+        present = {}
+        for q in range(A.row_ptr[i], A.row_ptr[i + 1]):
+            d = int(A.col_idx[q]) - i
+            dz = 1 if d >= nx * ny - nx - 1 else (-1 if d <= -(nx * ny - nx - 1) else 0)
+            rem = d - dz * nx * ny
+            dy = 1 if rem >= nx - 1 else (-1 if rem <= -(nx - 1) else 0)
+            dx = rem - dy * nx
+            present[9 * (dz + 1) + 3 * (dy + 1) + dx + 1] = True
+        for p in range(27):
+            want = np.float16(O[i, p]).view(np.uint16) if p in present else 0
+            assert codes[p, i] == want, (i, p)
+    assert sum(1 for p in range(27) if codes[p, 21 + 16] != 0) <= 7
+
+
+def test_stencil_apply_against_assembled_matrix(S):
+    import oracle as orc
+    A = P.lognormal27(5, 4)
+    O = (0.3 * np.random.default_rng(2).standard_normal((A.n, 32))).astype(np.float32)
+    codes = S.stencil_codes(A, A.grid, O)
+    M, dinv = _stencil_csr(A, A.grid, codes)
+    v = np.random.default_rng(3).standard_normal(A.n)
+    z = orc.stencil_apply(A, A.grid, codes, v)
+    bound = 30 * 2.0 ** -53 * (abs(M) @ np.abs(v))
+    assert np.all(np.abs(z - M @ v) <= bound)
+    # a hand-computed row: the interior row (1,1,1) of a 3^3 grid sees all 27
+    A3 = P.lognormal27(3, 5)
+    O3 = np.zeros((A3.n, 32), np.float32)
+    O3[13, 12], O3[13, 14], O3[13, 13], O3[13, 4] = 0.5, -0.25, 0.125, 2.0
+    c3 = S.stencil_codes(A3, A3.grid, O3)
+    v3 = np.arange(1.0, 28.0)
+    d13 = A3.val[A3.row_ptr[13]:A3.row_ptr[14]][A3.col_idx[A3.row_ptr[13]:A3.row_ptr[14]] == 13]
+    want = (1.0 / d13[0]) * (0.5 * v3[12] + 1.125 * v3[13] - 0.25 * v3[14] + 2.0 * v3[4])
+    assert orc.stencil_apply(A3, A3.grid, c3, v3)[13] == want
+
+
+def test_stencil_zero_codes_are_jacobi_bit_for_bit(S):
+    import oracle as orc
+    A = P.lognormal27(6, 1)
+    codes = np.zeros((27, A.n), np.uint16)
+    v = np.random.default_rng(0).standard_normal(A.n)
+    assert np.array_equal(orc.stencil_apply(A, A.grid, codes, v), (1.0 / S.diagonal(A)) * v)
+    b = P.rhs_uniform(A.n, 1)
+    for fmt in ("fp64", "fp16"):
+        rj = orc.gmres(A, b, restart=20, fmt=fmt, tol=1e-10, maxiter=500, precond="jacobi")
+        rs = orc.gmres(A, b, restart=20, fmt=fmt, tol=1e-10, maxiter=500, precond="stencil",
+                       p_stencil=codes, grid=A.grid)
+        assert rj["iterations"] == rs["iterations"]
+        assert np.array_equal(rj["x"], rs["x"])
+
+
+def test_stencil_solve_equals_change_of_variables(S):
+    """Right preconditioning with the stored form: GMRES on A M^-1 y = b,
+    x = M^-1 y, against a plain run on the explicitly assembled A M."""
+    import oracle as orc
+    from tests._helpers import csr_from_scipy
+    A = P.lognormal27(5, 3)
+    b = P.rhs_uniform(A.n, 3)
+    O = (0.02 * np.random.default_rng(4).standard_normal((A.n, 32))).astype(np.float32)
+    codes = S.stencil_codes(A, A.grid, O)
+    M, _ = _stencil_csr(A, A.grid, codes)
+    AM = csr_from_scipy(A.to_scipy() @ M)
+    rs = orc.gmres(A, b, restart=20, fmt="fp64", tol=1e-10, maxiter=2000, precond="stencil",
+                   p_stencil=codes, grid=A.grid)
+    rp = orc.gmres(AM, b, restart=20, fmt="fp64", tol=1e-10, maxiter=2000)
+    assert rs["status"] == 0 and rp["status"] == 0
+    assert abs(rs["iterations"] - rp["iterations"]) <= 1
+    x = M @ rp["x"]
+    assert np.linalg.norm(rs["x"] - x) <= 1e-7 * np.linalg.norm(x)
+
+
+def test_stencil_fallback_and_argument_checks(S):
+    import oracle as orc
+    A = P.lognormal27(4, 2)
+    b = P.rhs_uniform(A.n, 2)
+    # codes of -1 on the diagonal slot make M^-1 = 0 on every row: non-finite
+    # values in the first cycle, so the solver drops M and finishes with M = I
+    codes = np.zeros((27, A.n), np.uint16)
+    codes[13, :] = np.float16(-1.0).view(np.uint16)
+    r = orc.gmres(A, b, restart=20, fmt="fp64", tol=1e-10, maxiter=3000, precond="stencil",
+                  p_stencil=codes, grid=A.grid, fallback=True)
+    assert r["status"] == 0 and r["fell_back"] == 1 and r["true_rel_res"] <= 1e-10
+    r = orc.gmres(A, b, restart=20, fmt="fp64", tol=1e-10, maxiter=3000, precond="stencil",
+                  p_stencil=codes, grid=(4, 4, 3))
+    assert r["status"] == -1                      # the grid does not number the rows
+    with pytest.raises(ValueError):
+        orc.stencil_apply(A, (4, 4, 3), codes, b)
