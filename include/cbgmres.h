@@ -55,8 +55,11 @@ typedef enum {
     CBG_PC_NONE = 0,     /* M = I */
     CBG_PC_JACOBI = 1,   /* M^{-1} = diag(1 / a_ii), the paper's default (Section 6) */
     CBG_PC_SPARSE = 2,   /* M^{-1} = P, single-precision values on A's pattern */
-    CBG_PC_BLOCK_JACOBI = 3 /* M^{-1} = blockdiag(D_b^{-1}), adaptive-precision storage
+    CBG_PC_BLOCK_JACOBI = 3, /* M^{-1} = blockdiag(D_b^{-1}), adaptive-precision storage
                                (cbg_block_jacobi_setup; Section 6 discusses block-Jacobi) */
+    CBG_PC_STENCIL = 4   /* M^{-1} = D^{-1} (I + O) on a grid's 27-point stencil, O in
+                            float16 (the learned preconditioner's stored form, see
+                            cbg_learned_build_stencil) */
 } cbg_precond_kind;
 
 enum {
@@ -84,7 +87,7 @@ typedef struct {
  * the stop test ||b - A x||_2 <= tau ||b||_2 (Section 3).  maxiter: limit on
  * Arnoldi steps over all cycles.  eta: re-orthogonalisation threshold of
  * Fig. 1 step 7; <= 0 selects 1/sqrt(2).  p_val [dev]: CBG_PC_SPARSE values
- * (nnz floats on A's pattern).  fallback: with CBG_PC_SPARSE, drop P and
+ * (nnz floats on A's pattern).  fallback: with CBG_PC_SPARSE or CBG_PC_STENCIL, drop M and
  * continue with M = I when the explicit residual fails to fall below 0.99x
  * its previous value in two consecutive cycles or a non-finite value
  * appears.  flags: CBG_FLAG_* bits.  A singular diagonal block with
@@ -104,6 +107,10 @@ typedef struct {
     int32_t pc_block;    /* CBG_PC_BLOCK_JACOBI: block size 1..8 (0 selects 4) */
     int32_t pc_prec;     /* CBG_PC_BLOCK_JACOBI: lowest storage precision of the
                             inverted blocks, 16, 32 or 64 bits (0 selects 16) */
+    const uint16_t *p_stencil; /* CBG_PC_STENCIL [dev]: 27 x cbg_basis_ld(n) float16
+                            codes, slot-major (see cbg_learned_build_stencil) */
+    int32_t grid[3];     /* CBG_PC_STENCIL: nx, ny, nz with nx ny nz = n */
+    int32_t reserved2;
 } cbg_opts;
 
 #define CBG_MAX_RESTART 512
@@ -154,10 +161,14 @@ typedef struct {
  * does steps 5 and 9.  A re-orthogonalised step reads the basis twice (the
  * multi-dot and the update) instead of four times.  Both identities are
  * exact; in FP64 they cancel, leaving components of relative size about
- * 2^-53 omega / h_{j+1,j} along the basis where the explicit passes leave
- * 2^-53, far below the storage error of every compressed format.  Step 12
- * compares the final norm with t1, floored at sqrt(4 (j+1) 2^-53) omega,
- * below which t1^2 is rounding alone.
+ * 2^-53 omega / t1 along the basis where the explicit passes leave 2^-53.
+ * So a step whose t1^2 falls below 10^-4 omega^2 (t1 < omega / 100: a
+ * near-breakdown, as on clustered spectra) takes Fig. 1's explicit form
+ * instead: w1 = w - V h, t1 = ||w1||, u = V^T w1 (in the same basis pass),
+ * then w1 -= V u and its norm; cbg_result.explicit_steps counts them.  The
+ * loss of orthogonality of an FP64 basis then stays near 10^2 2^-53, and
+ * step 12 always compares the final norm with a t1 that was summed, not
+ * cancelled.
  * EXPLICIT_REDOT: the form Fig. 1 writes: update, norm, and a second
  * multi-dot of the updated w (fused with the update while j fits the fused
  * kernel's register tile; NO_FUSE splits it), then the second update.
@@ -166,7 +177,10 @@ typedef struct {
  * MGS: argument error.  MGS takes its own path. */
 #define CBG_FLAG_EXPLICIT_REDOT 256
 #define CBG_FLAG_TWO_PASS 512
-#define CBG_FLAG_ALL 1023   /* any other bit is an argument error */
+/* time the Arnoldi steps' SpMV with A (w = A M^-1 v, Fig. 1 step 3) with HIP
+ * events at each launch's own start and end (cbg_result.prof_spmv_*) */
+#define CBG_FLAG_PROFILE_SPMV 1024
+#define CBG_FLAG_ALL 2047   /* any other bit is an argument error */
 
 typedef struct {
     int64_t iterations;        /* Arnoldi steps (SpMVs with A inside cycles) */
@@ -197,6 +211,11 @@ typedef struct {
     double prof_fused_ms;      /* the fused update + re-dot kernel alone (explicit form) */
     double prof_fused_bytes;
     int64_t prof_fused_launches;
+    int64_t explicit_steps;    /* default form: steps that took Fig. 1's explicit form
+                                  because t1 < omega / 100 (see CBG_FLAG_TWO_PASS) */
+    double prof_spmv_ms;       /* with CBG_FLAG_PROFILE_SPMV: the steps' SpMV with A */
+    double prof_spmv_bytes;
+    int64_t prof_spmv_launches;
 } cbg_result;
 
 /* Device workspace bytes cbgmres_solve needs for this problem shape
@@ -375,6 +394,27 @@ int cbg_spai_assemble(const cbg_csr *A, const int32_t grid[3], const float *out,
  * CBG_E_NONFINITE as cbg_spai_features. */
 int cbg_learned_build(const cbg_csr *A, const int32_t grid[3], const uint16_t *weights,
                       const float *params, float *p_val, void *ws, size_t ws_bytes, void *stream);
+
+/* Stored form of the learned preconditioner for CBG_PC_STENCIL: the network's
+ * corrections O_ip of the slots row i stores, each rounded once to float16
+ * (round to nearest even from fp32; 0 for slots the row does not store),
+ * slot-major: the code of slot p of row i at p_stencil[p * ld + i], ld =
+ * cbg_basis_ld(n), rows [n, ld) 0.  The solve applies
+ *   z_i = fl(1 / a_ii) * sum_p ([p = 13] + o_ip) v_(grid neighbour p of i)
+ * over the slots whose grid point exists: the operator P above up to the
+ * float16 rounding of O (instead of P's fp32 rounding), read as 54 bytes per
+ * row with no column indices.  All codes 0 (W3 = 0, b3 = 0) is Jacobi.
+ * p_stencil [dev] 27 * ld uint16.  Synchronises; CBG_E_NONFINITE as
+ * cbg_spai_features. */
+int cbg_learned_build_stencil(const cbg_csr *A, const int32_t grid[3], const uint16_t *weights,
+                              const float *params, uint16_t *p_stencil, void *ws,
+                              size_t ws_bytes, void *stream);
+
+/* z = M^-1 v for CBG_PC_STENCIL (v, z [dev] n doubles; p_stencil as above;
+ * ws of cbg_spai_workspace_bytes(n, nnz, 0)).  Synchronises; CBG_E_ARG if a
+ * diagonal entry is zero or missing. */
+int cbg_stencil_apply(const cbg_csr *A, const int32_t grid[3], const uint16_t *p_stencil,
+                      const double *v, double *z, void *ws, size_t ws_bytes, void *stream);
 
 /* Values of A^T on A's pattern: t_val[p] = a_ci for entry p = (i, c).  A
  * must be structurally symmetric; synchronises and returns

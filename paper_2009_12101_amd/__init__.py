@@ -12,7 +12,8 @@ from . import problems
 from ._binding import (FORMATS, FORMAT_BYTES, PRECONDS, CbgError, DeviceCSR, SolveResult,
                        adam_step, basis_ld, block_jacobi_apply, block_jacobi_setup,
                        csr_transpose_values, decode, encode,
-                       kernel_workspace_bytes, learned_build, lib, mlp_backward, mlp_forward,
+                       kernel_workspace_bytes, learned_build, learned_build_stencil, lib,
+                       mlp_backward, mlp_forward, stencil_apply,
                        multidot, solve, spai_assemble, spai_features, spai_grad_o, spai_grad_p,
                        spai_loss_grad, spai_pack, spai_round_weights, spai_workspace_bytes, spmv,
                        strerror, update, update_redot, workspace_basis, workspace_bytes)
@@ -20,7 +21,8 @@ from ._binding import (FORMATS, FORMAT_BYTES, PRECONDS, CbgError, DeviceCSR, Sol
 __all__ = ["problems", "FORMATS", "FORMAT_BYTES", "PRECONDS", "CbgError", "DeviceCSR",
            "SolveResult", "adam_step", "basis_ld", "block_jacobi_apply", "block_jacobi_setup",
            "csr_transpose_values", "decode", "encode",
-           "kernel_workspace_bytes", "learned_build", "lib", "mlp_backward", "mlp_forward",
+           "kernel_workspace_bytes", "learned_build", "learned_build_stencil", "lib",
+           "mlp_backward", "mlp_forward", "stencil_apply",
            "multidot", "solve", "spai_assemble", "spai_features", "spai_grad_o", "spai_grad_p",
            "spai_loss_grad", "spai_pack", "spai_round_weights", "spai_workspace_bytes", "spmv",
            "strerror", "update", "update_redot", "workspace_basis", "workspace_bytes"]

@@ -19,7 +19,7 @@ FORMATS = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "e4m3": 4, "int32": 5, "i
            "fp16s": 7}
 FORMAT_BYTES = {"fp64": 8, "fp32": 4, "fp16": 2, "bf16": 2, "e4m3": 1, "int32": 4, "int16": 2,
                 "fp16s": 2}
-PRECONDS = {"none": 0, "jacobi": 1, "sparse": 2, "block_jacobi": 3}
+PRECONDS = {"none": 0, "jacobi": 1, "sparse": 2, "block_jacobi": 3, "stencil": 4}
 OK, NOT_CONVERGED = 0, 1
 E_ARG, E_WORKSPACE, E_HIP, E_NONFINITE, E_UNSUPPORTED = -1, -2, -3, -4, -5
 FLAG_PROFILE = 1
@@ -32,6 +32,7 @@ FLAG_NORMALISE_PASS = 64
 FLAG_NORMALISE_GATHER = 128
 FLAG_EXPLICIT_REDOT = 256
 FLAG_TWO_PASS = 512
+FLAG_PROFILE_SPMV = 1024
 # where steps 13-14 run: solve(..., normalise=...)
 NORMALISE = {"auto": 0, "pass": FLAG_NORMALISE_PASS, "gather": FLAG_NORMALISE_GATHER}
 # Arnoldi-step variants by name, the names the oracle uses: "gram" is the
@@ -58,10 +59,11 @@ def variant_flags(names) -> int:
 
 EXPORTS = ["cbg_strerror", "cbg_last_hip_error", "cbg_basis_ld", "cbg_workspace_bytes", "cbg_kernel_workspace_bytes",
            "cbg_workspace_basis", "cbgmres_solve", "cbg_encode", "cbg_decode", "cbg_spmv",
-           "cbg_multidot", "cbg_update", "cbg_update_redot", "cbg_block_jacobi_setup",
+           "cbg_multidot", "cbg_update", "cbg_update_redot",
+           "cbg_block_jacobi_setup",
            "cbg_block_jacobi_apply", "cbg_spai_workspace_bytes", "cbg_spai_features", "cbg_mlp_forward",
-           "cbg_spai_assemble", "cbg_learned_build", "cbg_csr_transpose_values",
-           "cbg_spai_pack", "cbg_spai_grad_p", "cbg_spai_grad_o", "cbg_mlp_backward",
+           "cbg_spai_assemble", "cbg_learned_build", "cbg_learned_build_stencil",
+           "cbg_stencil_apply", "cbg_csr_transpose_values", "cbg_spai_pack", "cbg_spai_grad_p", "cbg_spai_grad_o", "cbg_mlp_backward",
            "cbg_spai_loss_grad", "cbg_spai_round_weights", "cbg_adam_step"]
 
 SPAI_NFEAT, SPAI_NHID, SPAI_NOUT = 64, 64, 32
@@ -77,7 +79,8 @@ class CbgOpts(C.Structure):
     _fields_ = [("restart", C.c_int32), ("format", C.c_int32), ("tol", C.c_double),
                 ("maxiter", C.c_int64), ("eta", C.c_double), ("precond", C.c_int32),
                 ("fallback", C.c_int32), ("p_val", C.c_void_p), ("flags", C.c_int32),
-                ("reserved", C.c_int32), ("pc_block", C.c_int32), ("pc_prec", C.c_int32)]
+                ("reserved", C.c_int32), ("pc_block", C.c_int32), ("pc_prec", C.c_int32),
+                ("p_stencil", C.c_void_p), ("grid", C.c_int32 * 3), ("reserved2", C.c_int32)]
 
 
 class CbgResult(C.Structure):
@@ -89,7 +92,9 @@ class CbgResult(C.Structure):
                 ("prof_orth_bytes", C.c_double), ("prof_orth_launches", C.c_int64),
                 ("prof_dot_ms", C.c_double), ("prof_dot_bytes", C.c_double),
                 ("prof_dot_launches", C.c_int64), ("prof_fused_ms", C.c_double),
-                ("prof_fused_bytes", C.c_double), ("prof_fused_launches", C.c_int64)]
+                ("prof_fused_bytes", C.c_double), ("prof_fused_launches", C.c_int64),
+                ("explicit_steps", C.c_int64), ("prof_spmv_ms", C.c_double),
+                ("prof_spmv_bytes", C.c_double), ("prof_spmv_launches", C.c_int64)]
 
 
 class CbgError(RuntimeError):
@@ -146,6 +151,8 @@ def lib():
         L.cbg_mlp_forward.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp]
         L.cbg_spai_assemble.argtypes = [pcsr, vp, vp, vp, vp]
         L.cbg_learned_build.argtypes = [pcsr, vp, vp, vp, vp, vp, sz, vp]
+        L.cbg_learned_build_stencil.argtypes = [pcsr, vp, vp, vp, vp, vp, sz, vp]
+        L.cbg_stencil_apply.argtypes = [pcsr, vp, vp, vp, vp, vp, sz, vp]
         L.cbg_csr_transpose_values.argtypes = [pcsr, vp, vp, sz, vp]
         L.cbg_spai_pack.argtypes = [vp, i64, i32, i32, i32, i32, vp, vp]
         L.cbg_spai_grad_p.argtypes = [pcsr, vp, vp, i32, vp, f64, vp, i32, vp, vp, sz, vp]
@@ -158,7 +165,8 @@ def lib():
         for f in ("cbgmres_solve", "cbg_encode", "cbg_decode", "cbg_spmv", "cbg_multidot",
                   "cbg_update", "cbg_update_redot", "cbg_block_jacobi_setup",
                   "cbg_block_jacobi_apply", "cbg_workspace_basis", "cbg_spai_features", "cbg_mlp_forward",
-                  "cbg_spai_assemble", "cbg_learned_build", "cbg_csr_transpose_values",
+                  "cbg_spai_assemble", "cbg_learned_build", "cbg_learned_build_stencil",
+                  "cbg_stencil_apply", "cbg_csr_transpose_values",
                   "cbg_spai_pack", "cbg_spai_grad_p", "cbg_spai_grad_o", "cbg_mlp_backward",
                   "cbg_spai_loss_grad", "cbg_spai_round_weights", "cbg_adam_step"):
             getattr(L, f).restype = C.c_int
@@ -318,15 +326,22 @@ class SolveResult:
     prof_fused_ms: float = 0.0
     prof_fused_bytes: float = 0.0
     prof_fused_launches: int = 0
+    explicit_steps: int = 0
+    prof_spmv_ms: float = 0.0
+    prof_spmv_bytes: float = 0.0
+    prof_spmv_launches: int = 0
 
 
 def solve(A: DeviceCSR, b, x0=None, restart=100, fmt="fp64", tol=1e-10, maxiter=10000,
           eta=0.0, precond="none", p_val=None, fallback=False, profile=False, workspace=None,
           hist=True, fuse=True, pc_block=0, pc_prec=0, variant=(),
-          normalise="auto") -> SolveResult:
+          normalise="auto", p_stencil=None, grid=None) -> SolveResult:
     """cbgmres_solve on device tensors; returns the solution and counters.
-    profile: False, True (event-time every basis-streaming launch) or "dot"
-    (only the multi-dot launches).  variant: names from VARIANTS (ablations
+    precond "stencil" takes p_stencil (27 * basis_ld(n) int16 float16 codes,
+    from learned_build_stencil) and grid (nx, ny, nz).
+    profile: False, True (event-time every basis-streaming launch), "dot"
+    (only the multi-dot launches), "spmv" (only the steps' SpMV with A) or
+    "all" (both kinds).  variant: names from VARIANTS (ablations
     of the Arnoldi step).  normalise: "auto", "pass" or "gather" (where
     v_j = w / t is formed; the same bits either way).  Raises CbgError on a
     negative status."""
@@ -340,6 +355,12 @@ def solve(A: DeviceCSR, b, x0=None, restart=100, fmt="fp64", tol=1e-10, maxiter=
         if p_val is None:
             raise ValueError("p_val: the sparse preconditioner needs its values")
         _need(p_val, "p_val", torch.float32, A.nnz, dev, exact=True)
+    g3 = (0, 0, 0)
+    if precond == "stencil" or p_stencil is not None:
+        if p_stencil is None or grid is None:
+            raise ValueError("the stencil preconditioner needs p_stencil and grid")
+        _need(p_stencil, "p_stencil", torch.int16, 27 * basis_ld(A.n), dev, exact=True)
+        g3 = tuple(_grid3(grid, A.n))
     x = torch.zeros(A.n, dtype=torch.float64, device=b.device) if x0 is None else x0.clone()
     need = workspace_bytes(A.n, restart, fmt, precond)
     if need == 0 and A.n > 0:
@@ -348,12 +369,15 @@ def solve(A: DeviceCSR, b, x0=None, restart=100, fmt="fp64", tol=1e-10, maxiter=
         _need(workspace, "workspace", torch.uint8, 0, dev)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=b.device)
-    flags = {False: 0, True: FLAG_PROFILE, "dot": FLAG_PROFILE_DOT}[profile] \
+    flags = {False: 0, True: FLAG_PROFILE, "dot": FLAG_PROFILE_DOT,
+             "spmv": FLAG_PROFILE_SPMV, "all": FLAG_PROFILE | FLAG_PROFILE_SPMV}[profile] \
         | (0 if fuse else FLAG_NO_FUSE) | NORMALISE[normalise]
     flags |= variant_flags(variant)
     opts = CbgOpts(restart, FORMATS[fmt], tol, maxiter, eta, PRECONDS[precond],
                    int(bool(fallback)), None if p_val is None else p_val.data_ptr(),
-                   flags, 0, pc_block, pc_prec)
+                   flags, 0, pc_block, pc_prec,
+                   None if p_stencil is None else p_stencil.data_ptr(),
+                   (C.c_int32 * 3)(*g3), 0)
     res = CbgResult()
     hl = int(maxiter) if hist else 0
     h = np.zeros(max(hl, 1))
@@ -372,7 +396,10 @@ def solve(A: DeviceCSR, b, x0=None, restart=100, fmt="fp64", tol=1e-10, maxiter=
                        prof_dot_bytes=res.prof_dot_bytes,
                        prof_dot_launches=res.prof_dot_launches,
                        prof_fused_ms=res.prof_fused_ms, prof_fused_bytes=res.prof_fused_bytes,
-                       prof_fused_launches=res.prof_fused_launches)
+                       prof_fused_launches=res.prof_fused_launches,
+                       explicit_steps=res.explicit_steps, prof_spmv_ms=res.prof_spmv_ms,
+                       prof_spmv_bytes=res.prof_spmv_bytes,
+                       prof_spmv_launches=res.prof_spmv_launches)
 
 
 def _kws(n, j, device):
@@ -591,6 +618,43 @@ def learned_build(A: DeviceCSR, grid, weights, params, p_val=None, ws=None):
                                    _ptr(p_val), _ptr(ws), ws.numel(), _stream()),
            "cbg_learned_build")
     return p_val
+
+
+def learned_build_stencil(A: DeviceCSR, grid, weights, params, p_stencil=None, ws=None):
+    """The stored form for precond "stencil": (27 * basis_ld(n),) int16
+    float16 codes, slot-major (features, forward pass, packing)."""
+    torch = _torch()
+    dev = A.val.device
+    n_codes = 27 * basis_ld(A.n)
+    p_stencil = torch.empty(n_codes, dtype=torch.int16, device=dev) if p_stencil is None \
+        else p_stencil
+    ws = _sws(A.n, A.nnz, 0, dev) if ws is None else ws
+    _need(weights, "weights", torch.int16, SPAI_NWEIGHT, dev)
+    _need(params, "params", torch.float32, SPAI_NPARAM, dev)
+    _need(p_stencil, "p_stencil", torch.int16, n_codes, dev)
+    _need(ws, "ws", torch.uint8, spai_workspace_bytes(A.n, A.nnz, 0), dev)
+    csr = A.cstruct()
+    _check(lib().cbg_learned_build_stencil(C.byref(csr), _grid3(grid, A.n), _ptr(weights),
+                                           _ptr(params), _ptr(p_stencil), _ptr(ws), ws.numel(),
+                                           _stream()), "cbg_learned_build_stencil")
+    return p_stencil
+
+
+def stencil_apply(A: DeviceCSR, grid, p_stencil, v, z=None, ws=None):
+    """z = M^-1 v for the stencil preconditioner's stored form."""
+    torch = _torch()
+    dev = A.val.device
+    _need(p_stencil, "p_stencil", torch.int16, 27 * basis_ld(A.n), dev)
+    _need(v, "v", torch.float64, A.n, dev)
+    z = torch.empty(A.n, dtype=torch.float64, device=dev) if z is None else z
+    _need(z, "z", torch.float64, A.n, dev)
+    ws = _sws(A.n, A.nnz, 0, dev) if ws is None else ws
+    _need(ws, "ws", torch.uint8, spai_workspace_bytes(A.n, A.nnz, 0), dev)
+    csr = A.cstruct()
+    _check(lib().cbg_stencil_apply(C.byref(csr), _grid3(grid, A.n), _ptr(p_stencil), _ptr(v),
+                                   _ptr(z), _ptr(ws), ws.numel(), _stream()),
+           "cbg_stencil_apply")
+    return z
 
 
 def csr_transpose_values(A: DeviceCSR, ws=None):

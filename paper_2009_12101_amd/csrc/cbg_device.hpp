@@ -401,6 +401,8 @@ struct DevState {
     int32_t reorth_all; // re-orthogonalise on every step (CGS2 ablation)
     int32_t reorth;     // the current step re-orthogonalises
     int32_t conv;       // recurrence residual met the tolerance
+    int32_t hard;       // the current step took the explicit form (t1 << omega)
+    int32_t pad1;
     double beta;        // ||r||_2 at the cycle start
     double rmax;        // max |r_i| at the cycle start
     double omega;       // ||A M^-1 v||_2 (step 4)

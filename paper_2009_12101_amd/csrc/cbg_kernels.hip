@@ -112,24 +112,57 @@ struct StepArrays {
 // by every thread of a one-block kernel.  Reading of step 12 (the literal
 // test would end every re-orthogonalised cycle): breakdown iff
 // h_{j+1,j} = 0, or the second pass again lost more than a factor eta.
-// The column (h, plus u after a re-orthogonalisation) and the stored
-// rotations are staged in LDS; one thread then runs the rotation chain with
-// the carried entry in a register.
+// The new column (h, plus u after a re-orthogonalisation) meets the j-1
+// stored rotations: rotation i maps the carried entry x to -s_i x + c_i
+// h_{i+1} and writes H_i = c_i x + s_i h_{i+1}.  The carries are the prefix
+// compositions of these affine maps, formed by a block-wide scan (log2 j
+// rounds) instead of a serial chain of j-1 rotations; thread 0 then forms
+// the new rotation and updates g.
 __device__ void finish_step(DevState *st, const StepArrays &a, int j, bool reorth, double t2,
                             double wmax2)
 {
     __shared__ double lh[MAX_RESTART + 1], lc[MAX_RESTART], ls[MAX_RESTART];
+    __shared__ double pa[2][MAX_RESTART], pb[2][MAX_RESTART];
     const int tid = threadIdx.x, nth = blockDim.x;
+    const int jc = j - 1;
     for (int k = tid; k < j; k += nth)
         lh[k] = reorth ? a.h[k] + a.u[k] : a.h[k];
-    for (int k = tid; k < j - 1; k += nth) {
+    for (int k = tid; k < jc; k += nth) {
         lc[k] = a.cs[k];
         ls[k] = a.sn[k];
     }
     __syncthreads();
+    // rotation i as the affine map x -> pa x + pb
+    for (int i = tid; i < jc; i += nth) {
+        pa[0][i] = -ls[i];
+        pb[0][i] = lc[i] * lh[i + 1];
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int d = 1; d < jc; d <<= 1) {
+        // inclusive scan: map i composed after map i - d (Hillis-Steele)
+        for (int i = tid; i < jc; i += nth) {
+            double A = pa[cur][i], B = pb[cur][i];
+            if (i >= d) {
+                B = fma(A, pb[cur][i - d], B);
+                A = A * pa[cur][i - d];
+            }
+            pa[cur ^ 1][i] = A;
+            pb[cur ^ 1][i] = B;
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    const int m = st->m;
+    double *Hc = a.H + (size_t)jc * (m + 1);
+    for (int i = tid; i < jc; i += nth) {
+        const double x = i == 0 ? lh[0] : fma(pa[cur][i - 1], lh[0], pb[cur][i - 1]);
+        Hc[i] = lc[i] * x + ls[i] * lh[i + 1];
+    }
+    const double carry = jc == 0 ? lh[0] : fma(pa[cur][jc - 1], lh[0], pb[cur][jc - 1]);
+    __syncthreads();
     if (tid != 0)
         return;
-    const int m = st->m;
     double t = st->t;
     bool brk;
     if (reorth) {
@@ -141,14 +174,6 @@ __device__ void finish_step(DevState *st, const StepArrays &a, int j, bool reort
         brk = (t == 0.0);
     }
     st->t = t;
-    const int jc = j - 1;
-    double *Hc = a.H + (size_t)jc * (m + 1);
-    double carry = lh[0];
-    for (int i = 0; i < jc; ++i) {
-        const double a1 = lh[i + 1];
-        Hc[i] = lc[i] * carry + ls[i] * a1;
-        carry = -ls[i] * carry + lc[i] * a1;
-    }
     const double rr = sqrt(carry * carry + t * t);
     double c = 1.0, sn = 0.0;
     if (rr > 0.0) {
@@ -171,7 +196,7 @@ __device__ void finish_step(DevState *st, const StepArrays &a, int j, bool reort
     const bool conv = fabs(gnew) <= st->tau_nb;
     if (brk)
         st->breakdowns += 1;
-    a.flags[jc] = (reorth ? 1 : 0) | (brk ? 2 : 0);
+    a.flags[jc] = (reorth ? 1 : 0) | (brk ? 2 : 0) | (st->hard ? 4 : 0);
     st->jeff = j;
     if (!finite)
         st->nonfinite = 1;
@@ -438,6 +463,154 @@ __global__ __launch_bounds__(BLK) void k_spmv(int n, int64_t ldy, const int32_t 
 }
 
 // ---------------------------------------------------------------------------
+// CSR SpMV with a row-parallel gather, for long rows: a block owns RPB
+// consecutive rows.  Phase 1 loads the block's values and column indices
+// with unit stride across the threads (coalesced) into LDS.  Phase 2 gives
+// wave p the entries p, p + NPART, ... of every row, lane r for row r: one
+// gather instruction reads x at the same stencil offset for RPB consecutive
+// rows, i.e. contiguous addresses on a structured matrix, where gathering in
+// entry order (CSR-stream) touches about three times as many cache lines per
+// instruction on 27-point rows and is bound by them.  The NPART partial sums
+// of a row are added in wave order.  A block whose rows hold more than CAP
+// entries reads them from memory in phase 2.  Same modes, padding rows and
+// partials as k_spmv.
+// ---------------------------------------------------------------------------
+
+template <int MODE>
+__device__ __forceinline__ double spmv_x(int c, const double *__restrict__ x,
+                                         const double *__restrict__ dinv, double tdiv, int fmt,
+                                         EncParam ep)
+{
+    double xv = x[c];
+    if constexpr (sp_step(MODE))
+        xv = xv / tdiv;
+    if constexpr (sp_quant(MODE))
+        xv = quantize(fmt, xv, ep);
+    if constexpr ((MODE & 7) == SP_JACOBI)
+        xv = dinv[c] * xv;
+    return xv;
+}
+
+template <int RPB, int CAP, int MODE>
+__global__ __launch_bounds__(BLK) void k_spmv_rp(int n, int64_t ldy,
+                                                 const int32_t *__restrict__ rp,
+                                                 const int32_t *__restrict__ ci,
+                                                 const double *__restrict__ val,
+                                                 const float *__restrict__ fval,
+                                                 const double *__restrict__ x,
+                                                 const double *__restrict__ dinv,
+                                                 const double *__restrict__ b,
+                                                 double *__restrict__ y, RedArgs ra, int role,
+                                                 const DevState *st, uint8_t *__restrict__ Q,
+                                                 const double *__restrict__ qscale, int fmt)
+{
+    constexpr int NPART = BLK / RPB;
+    constexpr int UNR = 4;
+    constexpr bool FLT = (MODE & 7) == SP_FLOATVAL || (MODE & 7) == SP_ACCUM;
+    if (st && role != SR_FREE && st->done)
+        return;
+    double tdiv = 1.0;
+    EncParam ep{1.0, 0};
+    if constexpr (sp_step(MODE)) {
+        tdiv = st->t;
+        ep = param_from_scale(fmt, *qscale);
+    }
+    __shared__ double lv[CAP];
+    __shared__ int lc[CAP];
+    __shared__ int lrp[RPB + 1];
+    __shared__ double ls[NPART][RPB];
+    const int tid = threadIdx.x;
+    const int r = tid % RPB, part = tid / RPB;
+    double ssq = 0.0, mx = 0.0;
+    const int64_t nblk = (ldy + RPB - 1) / RPB;
+    for (int64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const int64_t r0 = blk * RPB;
+        const int nr = r0 < n ? (int)min((int64_t)RPB, (int64_t)n - r0) : 0;   // rows with entries
+        __syncthreads();                    // LDS reuse across iterations
+        for (int t = tid; t <= nr && nr > 0; t += BLK)
+            lrp[t] = rp[r0 + t];
+        __syncthreads();
+        const int p0 = nr > 0 ? lrp[0] : 0;
+        const int cnt = nr > 0 ? lrp[nr] - p0 : 0;
+        const bool staged = cnt <= CAP;
+        if (staged && cnt > 0) {
+            for (int q = tid; q < cnt; q += BLK * UNR) {
+                double v[UNR];
+                int c[UNR];
+#pragma unroll
+                for (int u = 0; u < UNR; ++u) {
+                    const int qq = min(q + u * BLK, cnt - 1);   // clamped: loads stay in bounds
+                    v[u] = FLT ? (double)fval[p0 + qq] : val[p0 + qq];
+                    c[u] = ci[p0 + qq];
+                }
+#pragma unroll
+                for (int u = 0; u < UNR; ++u)
+                    if (q + u * BLK < cnt) {
+                        lv[q + u * BLK] = v[u];
+                        lc[q + u * BLK] = c[u];
+                    }
+            }
+        }
+        __syncthreads();
+        double s = 0.0;
+        if (r < nr) {
+            const int a0 = lrp[r] - p0, a1 = lrp[r + 1] - p0;
+            if (staged) {
+                int k = a0 + part;
+                for (; k + 3 * NPART < a1; k += 4 * NPART) {
+                    const double x0 = spmv_x<MODE>(lc[k], x, dinv, tdiv, fmt, ep);
+                    const double x1 = spmv_x<MODE>(lc[k + NPART], x, dinv, tdiv, fmt, ep);
+                    const double x2 = spmv_x<MODE>(lc[k + 2 * NPART], x, dinv, tdiv, fmt, ep);
+                    const double x3 = spmv_x<MODE>(lc[k + 3 * NPART], x, dinv, tdiv, fmt, ep);
+                    s += lv[k] * x0;
+                    s += lv[k + NPART] * x1;
+                    s += lv[k + 2 * NPART] * x2;
+                    s += lv[k + 3 * NPART] * x3;
+                }
+                for (; k < a1; k += NPART)
+                    s += lv[k] * spmv_x<MODE>(lc[k], x, dinv, tdiv, fmt, ep);
+            } else {
+                for (int k = a0 + part; k < a1; k += NPART)
+                    s += spmv_term<MODE>(p0 + k, ci, val, fval, x, dinv, tdiv, fmt, ep);
+            }
+        }
+        ls[part][r] = s;
+        __syncthreads();
+        if (tid < RPB) {
+            const int64_t row = r0 + tid;
+            double t = ls[0][tid];
+#pragma unroll
+            for (int q = 1; q < NPART; ++q)
+                t += ls[q][tid];
+            if (row < ldy) {
+                if constexpr (sp_step(MODE)) {
+                    // steps 13-14 for this block's rows: v = w / t, stored
+                    // through the accessor (rows in [n, ldy) hold w = 0)
+                    store_entry(fmt, Q, row, x[row] / tdiv, ep);
+                }
+                double yv;
+                if constexpr ((MODE & 7) == SP_RESID)
+                    yv = row < n ? b[row] - t : 0.0;
+                else if constexpr ((MODE & 7) == SP_ACCUM)
+                    yv = y[row] + t;
+                else
+                    yv = row < n ? t : 0.0;
+                y[row] = yv;
+                ssq += yv * yv;
+                mx = fmax(mx, fabs(yv));
+            }
+        }
+    }
+    if (role == SR_NONE)
+        return;
+    block_sum_max(ssq, mx);
+    if (threadIdx.x == 0) {
+        ra.part[blockIdx.x] = ssq;
+        ra.part[(size_t)ra.stride + blockIdx.x] = mx;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Multi-dot through the accessor: h_k = sum_i dec(V_k)_i w_i, k < j.
 // Each block keeps a tile of w in registers and streams the stored vectors
 // KC at a time.  In full tiles every load of a batch is issued before any
@@ -597,8 +770,74 @@ __global__ __launch_bounds__(BLK) CBG_MD_ATTR void k_multidot(const uint8_t *__r
 // in flight while the current batch is decoded and accumulated.
 // ---------------------------------------------------------------------------
 
+// Fixed-order folds of block partials (used by the reduce kernel and by
+// the second pass of a hard step).
+constexpr int RBLK = 256;
+constexpr int RWAVES = RBLK / 64;
+
+// One wave folds block partials src[0 .. nb) (16 independent loads in flight
+// per lane, fixed order); every lane returns the total.  nb = 0 gives 0.
+__device__ __forceinline__ double wave_fold(const double *__restrict__ src, int nb, bool is_max)
+{
+    constexpr int U = 16;
+    const int lane = threadIdx.x & 63;
+    double acc[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        acc[u] = 0.0;
+    for (int b0 = lane; b0 < nb; b0 += 64 * U) {
+        double x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            x[u] = src[min(b0 + 64 * u, nb - 1)];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double xv = (b0 + 64 * u < nb) ? x[u] : 0.0;
+            acc[u] = is_max ? fmax(acc[u], xv) : acc[u] + xv;
+        }
+    }
+    double a = acc[0];
+#pragma unroll
+    for (int u = 1; u < U; ++u)
+        a = is_max ? fmax(a, acc[u]) : a + acc[u];
+    return is_max ? wave_max(a) : wave_sum(a);
+}
+
+// The whole block folds src[0 .. nb): wave w takes the contiguous quarter
+// starting at w * ceil(nb / 4), and the four wave totals are combined in
+// wave order (so the result depends on nb only, not on timing).  Every
+// thread returns the total; block-uniform call.
+__device__ double block_fold(const double *__restrict__ src, int nb, bool is_max)
+{
+    __shared__ double part[RWAVES];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int q = (nb + RWAVES - 1) / RWAVES;
+    const int lo = min(wave * q, nb), hi = min(lo + q, nb);
+    const double a = wave_fold(src + lo, hi - lo, is_max);
+    if (lane == 0)
+        part[wave] = a;
+    __syncthreads();
+    double t = part[0];
+#pragma unroll
+    for (int w = 1; w < RWAVES; ++w)
+        t = is_max ? fmax(t, part[w]) : t + part[w];
+    __syncthreads();
+    return t;
+}
+
 enum { U_PLAIN = 0, U_STEP1 = 1, U_STEP2 = 2, U_SOLUTION = 3, U_COMBINE = 4, U_STEP1N = 5,
-       U_CGS2 = 6 };
+       U_CGS2 = 6, U_HARD = 7 };
+
+// A step of the one-pass update is "hard" when t1^2 = omega^2 - h^T h -
+// h^T u falls below HARD_RATIO omega^2 (t1 < omega / 100).  There the
+// cancellation in t1^2 and the Gram-form re-dot (which cannot see the
+// rounding of the first update, an error of about u64 omega / t1 in the
+// orthogonality of the new vector) are no longer negligible, so the step
+// takes Fig. 1's explicit form instead: w1 = w - V h, t1 = ||w1||,
+// u = V^T w1, w2 = w1 - V u, t2 = ||w2||.  On the stencil systems here
+// t / omega stays above 0.3, so the explicit form is a safeguard for
+// near-breakdowns (clustered spectra), not the common path.
+constexpr double HARD_RATIO = 1e-4;
 
 template <int F, int ROLE>
 __global__ __launch_bounds__(BLK) void k_update(const uint8_t *__restrict__ V, int64_t ld,
@@ -607,13 +846,17 @@ __global__ __launch_bounds__(BLK) void k_update(const uint8_t *__restrict__ V, i
                                                 double *__restrict__ w,
                                                 const double *__restrict__ dinv, RedArgs ra,
                                                 const DevState *st,
-                                                const double *__restrict__ uin, DevState *stw)
+                                                double *__restrict__ uio, DevState *stw,
+                                                const double *__restrict__ G)
 {
     int j = j_arg;
-    if constexpr (ROLE == U_STEP1 || ROLE == U_STEP2 || ROLE == U_STEP1N || ROLE == U_CGS2) {
+    if constexpr (ROLE == U_STEP1 || ROLE == U_STEP2 || ROLE == U_STEP1N || ROLE == U_CGS2 ||
+                  ROLE == U_HARD) {
         if (st->done)
             return;
         if (ROLE == U_STEP2 && !st->reorth)
+            return;
+        if (ROLE == U_HARD && !st->hard)
             return;
     }
     if constexpr (ROLE == U_SOLUTION || ROLE == U_COMBINE)
@@ -624,47 +867,118 @@ __global__ __launch_bounds__(BLK) void k_update(const uint8_t *__restrict__ V, i
     const int64_t ldb = ld * fmt_bytes(F);
     const int64_t ntiles = ((int64_t)n + TILE - 1) / TILE;
     double ssq = 0.0, mx = 0.0;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // U_CGS2: Gram-form re-dot u = h - G h, then steps 5-10 in one update;
+    // U_HARD: the explicit second pass of a hard step.  lp holds partial sums
+    // of G h in the prologue and, on a hard step, the per-wave re-dot sums.
+    __shared__ double lc[(ROLE == U_CGS2 || ROLE == U_HARD) ? MAX_RESTART : 1];
+    __shared__ double lh[ROLE == U_CGS2 ? MAX_RESTART : 1];
+    __shared__ double lp[ROLE == U_CGS2 ? NWAVE * MAX_RESTART : 1];
+    __shared__ double lr[2][NWAVE];
+    bool hard = false;
     if constexpr (ROLE == U_CGS2) {
-        // u = h - G h comes from the fold before (uin).  Every block forms
-        // the same t1^2 = ||w - V h||^2 = omega^2 - h^T h - h^T u, decides
-        // step 7, and updates with h + u (re-orthogonalising) or h.  Block 0
-        // publishes the decision and t1 for the closing fold.
-        __shared__ double lc[MAX_RESTART], lpart[2][NWAVE];
+        // Every block forms the same u = h - G h (G symmetric: wave wv sums
+        // G[l][k] h_l over its quarter of l for k = lane, lane + 64, ...,
+        // reading rows of G, contiguous in k), then the same t1^2 =
+        // ||w - V h||^2 = omega^2 - h^T h - h^T u, decides step 7, and updates
+        // with h + u (re-orthogonalising) or h.  Block 0 publishes u, the
+        // decision and t1 for the closing fold.  A hard step updates with h
+        // only and adds the explicit re-dot of the result.
+        for (int k = tid; k < j; k += BLK)
+            lh[k] = coef[k];
+        __syncthreads();
+        const size_t ldg = (size_t)st->m + 1;
+        const int q = (j + NWAVE - 1) / NWAVE;
+        const int l0 = min(wv * q, j), l1 = min(l0 + q, j);
+        for (int k = lane; k < j; k += 64) {
+            double acc = 0.0;
+#pragma unroll 4
+            for (int l = l0; l < l1; ++l)
+                acc = fma(G[(size_t)l * ldg + k], lh[l], acc);
+            lp[wv * MAX_RESTART + k] = acc;
+        }
+        __syncthreads();
         double phh = 0.0, phu = 0.0;
-        for (int k = threadIdx.x; k < j; k += BLK) {
-            const double hk = coef[k], uk = uin[k];
+        for (int k = tid; k < j; k += BLK) {
+            double gh = lp[k];
+#pragma unroll
+            for (int w2 = 1; w2 < NWAVE; ++w2)
+                gh += lp[w2 * MAX_RESTART + k];
+            const double hk = lh[k], uk = hk - gh;
             lc[k] = uk;
             phh += hk * hk;
             phu += hk * uk;
         }
         phh = wave_sum(phh);
         phu = wave_sum(phu);
-        if ((threadIdx.x & 63) == 0) {
-            lpart[0][threadIdx.x >> 6] = phh;
-            lpart[1][threadIdx.x >> 6] = phu;
+        if (lane == 0) {
+            lr[0][wv] = phh;
+            lr[1][wv] = phu;
         }
         __syncthreads();
-        double hh = lpart[0][0], hu = lpart[1][0];
+        double hh = lr[0][0], hu = lr[1][0];
 #pragma unroll
-        for (int q = 1; q < NWAVE; ++q) {
-            hh += lpart[0][q];
-            hu += lpart[1][q];
+        for (int w2 = 1; w2 < NWAVE; ++w2) {
+            hh += lr[0][w2];
+            hu += lr[1][w2];
         }
-        // below about (j+1) u64 omega^2 the difference is rounding alone:
-        // t1 is floored there, so that step 12 sees a w that lies
-        // numerically in span(V) as the breakdown it is
         const double omega = st->omega;
         const double t1sq = omega * omega - hh - hu;
-        const double floor2 = 4.0 * (j + 1) * 0x1p-53 * omega * omega;
-        const double t1 = sqrt(t1sq > floor2 ? t1sq : floor2);
-        const bool ro = st->reorth_all || t1 < st->eta * omega;
-        for (int k = threadIdx.x; k < j; k += BLK)
-            lc[k] = ro ? coef[k] + lc[k] : coef[k];
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            stw->reorth = ro ? 1 : 0;
-            stw->t = t1;
+        hard = !(t1sq >= HARD_RATIO * omega * omega);       // also when not finite
+        const double t1 = hard ? 0.0 : sqrt(t1sq);
+        const bool ro = !hard && (st->reorth_all || t1 < st->eta * omega);
+        for (int k = tid; k < j; k += BLK) {
+            const double uk = lc[k];
+            if (blockIdx.x == 0)
+                uio[k] = uk;
+            lc[k] = ro ? lh[k] + uk : lh[k];
+        }
+        if (blockIdx.x == 0 && tid == 0) {
+            stw->hard = hard ? 1 : 0;
+            if (!hard) {
+                stw->reorth = ro ? 1 : 0;
+                stw->t = t1;
+            }
+        }
+        if (hard) {
+            // per-wave re-dot sums, accumulated over the block's tiles
+            for (int k = tid; k < NWAVE * j; k += BLK)
+                lp[k] = 0.0;
         }
         __syncthreads();
+        coef = lc;
+    }
+    if constexpr (ROLE == U_HARD) {
+        // The hard step's explicit second pass.  Every block folds, from the
+        // first pass's partials (rows 0..j-1: u = V^T w1; rows j, j+1:
+        // ||w1||^2, max|w1|), u and t1, decides step 7 against t1, and
+        // updates w1 -= V u.  Block 0 publishes u, t1, max|w1| and the
+        // decision; the norms go to rows j+2, j+3 for the closing fold.
+        const int nb = gridDim.x;            // the first pass ran on the same grid
+        for (int k = wv; k < j; k += NWAVE) {
+            const double a = wave_fold(ra.part + (size_t)k * ra.stride, nb, false);
+            if (lane == 0)
+                lc[k] = a;
+        }
+        if (wv < 2) {
+            const double a = wave_fold(ra.part + (size_t)(j + wv) * ra.stride, nb, wv == 1);
+            if (lane == 0)
+                lr[0][wv] = a;
+        }
+        __syncthreads();
+        const double t1 = sqrt(lr[0][0]);
+        const bool ro = st->reorth_all || t1 < st->eta * st->omega;
+        if (blockIdx.x == 0) {
+            for (int k = tid; k < j; k += BLK)
+                uio[k] = lc[k];
+            if (tid == 0) {
+                stw->t = t1;
+                stw->wmax = lr[0][1];
+                stw->reorth = ro ? 1 : 0;
+            }
+        }
+        if (!ro)
+            return;
         coef = lc;
     }
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -741,7 +1055,7 @@ __global__ __launch_bounds__(BLK) void k_update(const uint8_t *__restrict__ V, i
                     load_w<VW>(dinv, n, i0[c], dv);
 #pragma unroll
                     for (int e = 0; e < VW; ++e)
-                        o[e] = o[e] + dv[e] * s[c * VW + e];
+                        o[e] = fma(dv[e], s[c * VW + e], o[e]);
                 } else {
 #pragma unroll
                     for (int e = 0; e < VW; ++e)
@@ -754,17 +1068,60 @@ __global__ __launch_bounds__(BLK) void k_update(const uint8_t *__restrict__ V, i
                     o[e] = o[e] - s[c * VW + e];
                     ssq += o[e] * o[e];
                     mx = fmax(mx, fabs(o[e]));
+                    s[c * VW + e] = o[e];        // kept for a hard step's re-dot
                 }
             }
             store_w<VW>(w, n, i0[c], o);
         }
+        if constexpr (ROLE == U_CGS2) {
+            if (hard) {
+                // Fig. 1 step 8 for this tile's rows: u_k += dec(V_k)^T w1
+                // (rows >= n hold w1 = 0); one wave sum per vector, added
+                // into the wave's slot in tile order
+                for (int k = 0; k < j; ++k) {
+                    const double sk = T::SCALED ? scales[k] : 1.0;
+                    const uint8_t *Vk = V + (int64_t)k * ldb;
+                    double acc = 0.0;
+#pragma unroll
+                    for (int c = 0; c < CH; ++c) {
+                        double d[VW];
+                        load_dec<F>(Vk, i0[c], n, sk, d);
+#pragma unroll
+                        for (int e = 0; e < VW; ++e)
+                            acc = fma(d[e], s[c * VW + e], acc);
+                    }
+                    acc = wave_sum(acc);
+                    if (lane == 0)
+                        lp[k * NWAVE + wv] += acc;
+                }
+            }
+        }
     }
     if constexpr (ROLE == U_SOLUTION || ROLE == U_COMBINE || ROLE == U_STEP1)
         return;
+    // partial rows: the norms in rows 0 and 1; a hard step's first pass puts
+    // the re-dot in rows 0..j-1 and the norms in rows j, j+1, its second
+    // pass the norms in rows j+2, j+3
+    int row = 0;
+    if constexpr (ROLE == U_CGS2) {
+        if (hard) {
+            __syncthreads();
+            for (int k = tid; k < j; k += BLK) {
+                double a = lp[k * NWAVE];
+#pragma unroll
+                for (int w2 = 1; w2 < NWAVE; ++w2)
+                    a += lp[k * NWAVE + w2];
+                ra.part[(size_t)k * ra.stride + blockIdx.x] = a;
+            }
+            row = j;
+        }
+    }
+    if constexpr (ROLE == U_HARD)
+        row = j + 2;
     block_sum_max(ssq, mx);
     if (threadIdx.x == 0) {
-        ra.part[blockIdx.x] = ssq;
-        ra.part[(size_t)ra.stride + blockIdx.x] = mx;
+        ra.part[(size_t)row * ra.stride + blockIdx.x] = ssq;
+        ra.part[(size_t)(row + 1) * ra.stride + blockIdx.x] = mx;
     }
 }
 
@@ -1256,64 +1613,11 @@ __global__ __launch_bounds__(BLK) void k_mgs(const uint8_t *__restrict__ V, int6
 //   RR_MGS_U   MGS pass 2: one coefficient u_k into *out
 //   RR_MGS_T   end of MGS pass 1: as RR_U's scalars, from partials 0 and 1
 
-constexpr int RBLK = 256;
-constexpr int RWAVES = RBLK / 64;
-
-// One wave folds block partials src[0 .. nb) (16 independent loads in flight
-// per lane, fixed order); every lane returns the total.  nb = 0 gives 0.
-__device__ __forceinline__ double wave_fold(const double *__restrict__ src, int nb, bool is_max)
-{
-    constexpr int U = 16;
-    const int lane = threadIdx.x & 63;
-    double acc[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-        acc[u] = 0.0;
-    for (int b0 = lane; b0 < nb; b0 += 64 * U) {
-        double x[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-            x[u] = src[min(b0 + 64 * u, nb - 1)];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const double xv = (b0 + 64 * u < nb) ? x[u] : 0.0;
-            acc[u] = is_max ? fmax(acc[u], xv) : acc[u] + xv;
-        }
-    }
-    double a = acc[0];
-#pragma unroll
-    for (int u = 1; u < U; ++u)
-        a = is_max ? fmax(a, acc[u]) : a + acc[u];
-    return is_max ? wave_max(a) : wave_sum(a);
-}
-
-// The whole block folds src[0 .. nb): wave w takes the contiguous quarter
-// starting at w * ceil(nb / 4), and the four wave totals are combined in
-// wave order (so the result depends on nb only, not on timing).  Every
-// thread returns the total; block-uniform call.
-__device__ double block_fold(const double *__restrict__ src, int nb, bool is_max)
-{
-    __shared__ double part[RWAVES];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int q = (nb + RWAVES - 1) / RWAVES;
-    const int lo = min(wave * q, nb), hi = min(lo + q, nb);
-    const double a = wave_fold(src + lo, hi - lo, is_max);
-    if (lane == 0)
-        part[wave] = a;
-    __syncthreads();
-    double t = part[0];
-#pragma unroll
-    for (int w = 1; w < RWAVES; ++w)
-        t = is_max ? fmax(t, part[w]) : t + part[w];
-    __syncthreads();
-    return t;
-}
-
 // Block 0 does the scalars; block 1 + k folds value k (h_k, u_k or a
 // kernel-level multi-dot value).
 int reduce_grid(int role, int j)
 {
-    if (role == RR_H || role == RR_U || role == RR_VALUES || role == RR_UG || role == RR_GU)
+    if (role == RR_H || role == RR_U || role == RR_VALUES || role == RR_UG)
         return 1 + (j > 0 ? j : 0);
     if (role == RR_HG)
         return 1 + 2 * (j > 0 ? j : 0);
@@ -1348,9 +1652,7 @@ __global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth
         }
         return;
     }
-    if (role == RR_GU && blockIdx.x == 0)
-        return;                                         // u only
-    if ((role == RR_UG || role == RR_GU) && blockIdx.x > 0) {
+    if (role == RR_UG && blockIdx.x > 0) {
         // step 8 in Gram form: u_k = h_k - sum_l G_kl h_l (every step: the
         // test of step 7 is block 0's, and u is only read if it fired)
         __shared__ double prod[MAX_RESTART];
@@ -1387,8 +1689,14 @@ __global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth
         s0 = ws.orth + (size_t)j * ws.stride;           // ||w||^2, max|w_i|
         s1 = ws.orth + (size_t)(j + 1) * ws.stride;
         nb = nb_orth;
-    } else if (role == RR_T2 || role == RR_NORMS || role == RR_MGS_T || role == RR_UG ||
-               role == RR_C2) {
+    } else if (role == RR_C2) {
+        // the one-pass update's norms (rows 0, 1), or a hard step's second
+        // pass (rows j+2, j+3)
+        const int row = st->hard ? j + 2 : 0;
+        s0 = ws.orth + (size_t)row * ws.stride;
+        s1 = ws.orth + (size_t)(row + 1) * ws.stride;
+        nb = nb_orth;
+    } else if (role == RR_T2 || role == RR_NORMS || role == RR_MGS_T || role == RR_UG) {
         s0 = ws.orth;
         s1 = ws.orth + ws.stride;
         nb = nb_orth;
@@ -1480,12 +1788,14 @@ __global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth
         break;
     case RR_C2:
         // the one-pass update's norms: with re-orthogonalisation the closing
-        // norm against t1 (which the update stored), else the step's t
+        // norm against t1 (which the update stored), else the step's t.  A
+        // hard step without re-orthogonalisation has its t and max|w| from
+        // the second-pass kernel already.
         if (st->reorth) {
             finish_step(st, sa, j, true, sqrt(sv[0]), sv[1]);
         } else {
             __syncthreads();
-            if (tid == 0) {
+            if (tid == 0 && !st->hard) {
                 st->t = sqrt(sv[0]);
                 st->wmax = sv[1];
             }
@@ -1614,6 +1924,95 @@ __global__ __launch_bounds__(BLK) void k_step_normalize(const double *__restrict
     }
 }
 
+// The learned preconditioner in its stored form (CBG_PC_STENCIL): on an
+// nx x ny x nz grid, row i's 27 slots carry float16 codes o (slot-major, row
+// stride ld) and
+//   z_i = dinv_i * (sum_p c_p w_(i + off_p)) / t,   c_p = [p = 13] + o_p,
+// over the slots whose grid point exists, in slot order.  ST_STEP: w is the
+// step's orthogonalised vector and t = h_{j+1,j}, so z = M^-1 v with v = w / t
+// (one division per row instead of one per term; with all codes 0 this is
+// the Jacobi pass's z bit for bit), and v_j = w / t is stored through the
+// accessor for rows [0, ld) as in k_step_normalize (z written for all ld
+// rows, 0 beyond n).  ST_PLAIN: z = M^-1 w and ST_ACC: z += M^-1 w (the
+// solution update), both for rows < n only.  A thread takes
+// two consecutive rows: one 4-byte load per slot for both rows' codes.
+enum { ST_STEP = 0, ST_PLAIN = 1, ST_ACC = 2 };
+
+template <int F, int MODE>
+__global__ __launch_bounds__(BLK) void k_stencil(const double *__restrict__ w, int n, int64_t ld,
+                                                 int nx, int ny, int nz,
+                                                 const uint16_t *__restrict__ codes,
+                                                 const double *__restrict__ dinv,
+                                                 double *__restrict__ z, uint8_t *__restrict__ Q,
+                                                 const double *__restrict__ scale_slot,
+                                                 const DevState *st)
+{
+    double t = 1.0;
+    EncParam ep{1.0, 0};
+    if constexpr (MODE == ST_STEP) {
+        if (st->done)
+            return;
+        t = st->t;
+        ep = param_from_scale(F, *scale_slot);
+    }
+    const int64_t npair = ld / 2;                     // ld is a multiple of 16
+    const int64_t S = (int64_t)nx * ny;
+    for (int64_t q = blockIdx.x * (int64_t)BLK + threadIdx.x; q < npair;
+         q += (int64_t)gridDim.x * BLK) {
+        const int64_t i0 = 2 * q;
+        int gx[2], gy[2], gz[2];
+        bool live[2];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const int64_t i = i0 + r;
+            live[r] = i < n;
+            const uint32_t u = live[r] ? (uint32_t)i : 0u, row = u / (uint32_t)nx;
+            gx[r] = (int)(u - row * (uint32_t)nx);
+            gy[r] = (int)(row % (uint32_t)ny);
+            gz[r] = (int)(row / (uint32_t)ny);
+        }
+        double s[2] = {0.0, 0.0};
+#pragma unroll
+        for (int slot = 0; slot < 27; ++slot) {
+            const int dz = slot / 9 - 1, dy = (slot / 3) % 3 - 1, dx = slot % 3 - 1;
+            const uint32_t cc = *(const uint32_t *)(codes + slot * ld + i0);
+            const int64_t off = dz * S + dy * nx + dx;
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const bool in = live[r] && gx[r] + dx >= 0 && gx[r] + dx < nx &&
+                                gy[r] + dy >= 0 && gy[r] + dy < ny && gz[r] + dz >= 0 &&
+                                gz[r] + dz < nz;
+                if (in) {
+                    const double c = (slot == 13 ? 1.0 : 0.0) + dec_f16((cc >> (16 * r)) & 0xFFFFu);
+                    s[r] = fma(c, w[i0 + r + off], s[r]);
+                }
+            }
+        }
+        if constexpr (MODE == ST_ACC) {
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+                if (live[r])
+                    z[i0 + r] = fma(dinv[i0 + r], s[r], z[i0 + r]);   // as x += dinv .* s
+        } else if constexpr (MODE == ST_PLAIN) {
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+                if (live[r])
+                    z[i0 + r] = dinv[i0 + r] * s[r];
+        } else {
+            const f64x2 d = *(const f64x2 *)(dinv + i0);      // dinv holds 0 beyond n
+            f64x2 o;
+            o.x = live[0] ? d.x * (s[0] / t) : 0.0;
+            o.y = live[1] ? d.y * (s[1] / t) : 0.0;
+            *(f64x2 *)(z + i0) = o;
+            if constexpr (MODE == ST_STEP) {
+                const double a = live[0] ? w[i0] / t : 0.0;
+                const double b = live[1] ? w[i0 + 1] / t : 0.0;
+                store_pair<F>(Q, i0, a, b, ep);
+            }
+        }
+    }
+}
+
 // The accessor's load for the kernel-level API: v = dec(q) exactly.
 template <int F>
 __global__ __launch_bounds__(BLK) void k_decode(const uint8_t *__restrict__ Q, int n,
@@ -1696,7 +2095,11 @@ int spmv_shape_of(int n, int64_t nnz)
 
 int spmv_rows(int shape)
 {
-    return shape == SPMV_R256_C2K ? 256 : shape == SPMV_R32_C4K ? 32 : 64;
+    switch (shape) {
+    case SPMV_R256_C2K: return 256;
+    case SPMV_R32_C4K: return 32;
+    default: return 64;
+    }
 }
 
 template <int RPB, int CAP>
@@ -1706,9 +2109,48 @@ static int spmv_shape(const SpmvArgs &a, hipStream_t s)
     RedArgs ra{a.ws.spmv, a.ws.stride};
 #define CBG_SPMV_CASE(M)                                                                      \
     case M:                                                                                   \
-        k_spmv<RPB, CAP, M><<<g, BLK, 0, s>>>(a.n, a.ldy, a.rp, a.ci, a.val, a.fval, a.x,     \
-                                               a.dinv, a.b, a.y, ra, a.role, a.st,            \
-                                               (uint8_t *)a.Q, a.qscale, a.fmt);              \
+        if (a.ev0)                                                                            \
+            hipExtLaunchKernelGGL(k_spmv<RPB, CAP, M>, dim3(g), dim3(BLK), 0, s, a.ev0, a.ev1, \
+                                  0, a.n, a.ldy, a.rp, a.ci, a.val, a.fval, a.x, a.dinv, a.b, \
+                                  a.y, ra, a.role, a.st, (uint8_t *)a.Q, a.qscale, a.fmt);    \
+        else                                                                                  \
+            k_spmv<RPB, CAP, M><<<g, BLK, 0, s>>>(a.n, a.ldy, a.rp, a.ci, a.val, a.fval, a.x, \
+                                                   a.dinv, a.b, a.y, ra, a.role, a.st,        \
+                                                   (uint8_t *)a.Q, a.qscale, a.fmt);          \
+        break;
+    switch (a.mode) {
+        CBG_SPMV_CASE(SP_PLAIN)
+        CBG_SPMV_CASE(SP_JACOBI)
+        CBG_SPMV_CASE(SP_RESID)
+        CBG_SPMV_CASE(SP_FLOATVAL)
+        CBG_SPMV_CASE(SP_ACCUM)
+        CBG_SPMV_CASE(SP_STEP_PLAIN)
+        CBG_SPMV_CASE(SP_STEP_JACOBI)
+        CBG_SPMV_CASE(SP_STEP_FLOATVAL)
+        CBG_SPMV_CASE(SP_STEP_PLAIN_Q)
+        CBG_SPMV_CASE(SP_STEP_JACOBI_Q)
+        CBG_SPMV_CASE(SP_STEP_FLOATVAL_Q)
+    }
+#undef CBG_SPMV_CASE
+    return g;
+}
+
+template <int RPB, int CAP>
+static int spmv_rp_shape(const SpmvArgs &a, hipStream_t s)
+{
+    int g = grid_for((a.ldy + RPB - 1) / RPB, 1);
+    RedArgs ra{a.ws.spmv, a.ws.stride};
+#define CBG_SPMV_CASE(M)                                                                      \
+    case M:                                                                                   \
+        if (a.ev0)                                                                            \
+            hipExtLaunchKernelGGL(k_spmv_rp<RPB, CAP, M>, dim3(g), dim3(BLK), 0, s, a.ev0,     \
+                                  a.ev1, 0, a.n, a.ldy, a.rp, a.ci, a.val, a.fval, a.x,       \
+                                  a.dinv, a.b, a.y, ra, a.role, a.st, (uint8_t *)a.Q,         \
+                                  a.qscale, a.fmt);                                           \
+        else                                                                                  \
+            k_spmv_rp<RPB, CAP, M><<<g, BLK, 0, s>>>(a.n, a.ldy, a.rp, a.ci, a.val, a.fval,   \
+                                                      a.x, a.dinv, a.b, a.y, ra, a.role, a.st, \
+                                                      (uint8_t *)a.Q, a.qscale, a.fmt);        \
         break;
     switch (a.mode) {
         CBG_SPMV_CASE(SP_PLAIN)
@@ -1733,6 +2175,7 @@ int launch_spmv(const SpmvArgs &a, hipStream_t s)
     case SPMV_R256_C2K: return spmv_shape<256, 2048>(a, s);
     case SPMV_R64_C2K: return spmv_shape<64, 2048>(a, s);
     case SPMV_R64_C4K: return spmv_shape<64, 4096>(a, s);
+    case SPMV_RP64_C2K: return spmv_rp_shape<64, 2048>(a, s);
     default: return spmv_shape<32, 4096>(a, s);
     }
 }
@@ -1831,11 +2274,11 @@ void launch_update(const OrthArgs &a, hipStream_t s)
         CBG_FMT_SWITCH(a.fmt, (hipExtLaunchKernelGGL(k_update<F, R>, dim3(g), dim3(BLK), 0, s, \
                                                      a.ev0, a.ev1, 0, V, a.ld, a.scales, a.n, \
                                                      a.j, a.coef, a.wio, a.dinv, ra, a.st,    \
-                                                     a.u, a.stw)))                            \
+                                                     a.u, a.stw, a.G)))                       \
     } else {                                                                                  \
         CBG_FMT_SWITCH(a.fmt, (k_update<F, R><<<g, BLK, 0, s>>>(V, a.ld, a.scales, a.n, a.j,   \
                                                                  a.coef, a.wio, a.dinv, ra,   \
-                                                                 a.st, a.u, a.stw)))          \
+                                                                 a.st, a.u, a.stw, a.G)))     \
     }
     switch (a.role) {
     case U_PLAIN: CBG_UPD(U_PLAIN) break;
@@ -1843,6 +2286,7 @@ void launch_update(const OrthArgs &a, hipStream_t s)
     case U_STEP2: CBG_UPD(U_STEP2) break;
     case U_STEP1N: CBG_UPD(U_STEP1N) break;
     case U_CGS2: CBG_UPD(U_CGS2) break;
+    case U_HARD: CBG_UPD(U_HARD) break;
     case U_SOLUTION: CBG_UPD(U_SOLUTION) break;
     default: CBG_UPD(U_COMBINE) break;
     }
@@ -1958,6 +2402,24 @@ void launch_step_normalize(int fmt, const double *w, int n, int64_t ld, const do
     const int g = grid_for((ld / 2 + BLK * 4 - 1) / (BLK * 4), 1);
     CBG_FMT_SWITCH(fmt, (k_step_normalize<F><<<g, BLK, 0, s>>>(w, n, ld, dinv, z, (uint8_t *)Q,
                                                                 scale_slot, st)))
+}
+
+void launch_stencil(int fmt, int mode, const double *w, int n, int64_t ld, const int32_t grid[3],
+                    const uint16_t *codes, const double *dinv, double *z, void *Q,
+                    const double *scale_slot, const DevState *st, hipStream_t s)
+{
+    const int g = grid_for((ld / 2 + BLK - 1) / BLK, 1);
+    if (mode == ST_STEP) {
+        CBG_FMT_SWITCH(fmt, (k_stencil<F, ST_STEP><<<g, BLK, 0, s>>>(
+                                w, n, ld, grid[0], grid[1], grid[2], codes, dinv, z,
+                                (uint8_t *)Q, scale_slot, st)))
+    } else if (mode == ST_PLAIN) {
+        k_stencil<F_FP64, ST_PLAIN><<<g, BLK, 0, s>>>(w, n, ld, grid[0], grid[1], grid[2], codes,
+                                                      dinv, z, nullptr, nullptr, nullptr);
+    } else {
+        k_stencil<F_FP64, ST_ACC><<<g, BLK, 0, s>>>(w, n, ld, grid[0], grid[1], grid[2], codes,
+                                                    dinv, z, nullptr, nullptr, nullptr);
+    }
 }
 
 void launch_decode(int fmt, const void *Q, int n, const double *scale, double *v, hipStream_t s)

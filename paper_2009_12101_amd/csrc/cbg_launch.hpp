@@ -31,6 +31,7 @@ struct SpmvArgs {
     void *Q;              // step variants: basis slot receiving enc(x / t)
     const double *qscale; // step variants: that slot's scale
     int fmt;              // step variants: storage format
+    hipEvent_t ev0, ev1;  // optional: recorded at the kernel's own start and end
 };
 
 struct OrthArgs {
@@ -43,8 +44,9 @@ struct OrthArgs {
     int gated;            // multi-dot: skipped once the cycle is done
     int with_norms;       // multi-dot: also partials of ||w||^2 and max|w_i|
     int gram;             // multi-dot: also the newest Gram row, dec(V_k)^T dec(V_{j-1})
-    const double *u;      // one-pass update: u = h - G h (from the RR_GU fold)
+    double *u;            // one-pass update: receives u (Gram form, or a hard step's explicit re-dot)
     DevState *stw;        // one-pass update: the step-7 decision and t1
+    const double *G;      // one-pass update: the Gram matrix of the stored basis
     const double *coef;   // update coefficients
     double *wio;          // update: the vector updated in place (or written)
     const double *dinv;
@@ -59,11 +61,11 @@ enum { RR_NB = 0, RR_SCALE = 1, RR_NORM2 = 2, RR_RESID = 3, RR_H = 4, RR_U = 5, 
        RR_VALUES = 7, RR_NORMS = 8, RR_MGS_H = 9, RR_MGS_U = 10, RR_MGS_T = 11,
        RR_HG = 12,   // RR_H plus the newest Gram row from the multi-dot's rows j+2+k
        RR_UG = 13,   // step 6-7 from the update's norm partials, u = h - G h
-       RR_C2 = 14,   // close of the one-pass update (rows 0 and 1)
-       RR_GU = 15 }; // u = h - G h only (blocks 1..j), for the one-pass update
+       RR_C2 = 14 }; // close of the one-pass update (rows 0 and 1; a hard step's rows j+2, j+3)
 
 // SpMV launch shapes: rows per block and LDS product-buffer entries
-enum { SPMV_R256_C2K = 0, SPMV_R64_C2K = 1, SPMV_R64_C4K = 2, SPMV_R32_C4K = 3 };
+enum { SPMV_R256_C2K = 0, SPMV_R64_C2K = 1, SPMV_R64_C4K = 2, SPMV_R32_C4K = 3,
+       SPMV_RP64_C2K = 4 };   // row-parallel gather (k_spmv_rp)
 int spmv_shape_of(int n, int64_t nnz);     // from the mean row length
 int spmv_rows(int shape);
 int spmv_grid(int shape, int64_t ldy);
@@ -113,6 +115,13 @@ void launch_step_normalize(int fmt, const double *w, int n, int64_t ld, const do
                            double *z, void *Q, const double *scale_slot, const DevState *st,
                            hipStream_t s);
 void launch_decode(int fmt, const void *Q, int n, const double *scale, double *v, hipStream_t s);
+// The stencil preconditioner's stored form (CBG_PC_STENCIL) on ld rows (a
+// multiple of 16; w, dinv and z hold ld entries, z in ACC mode n):
+// mode 0 (step): z = M^-1 (w / t) and v_j = w / t stored (skipped once the
+// cycle is done); 1: z = M^-1 w; 2: z += M^-1 w.
+void launch_stencil(int fmt, int mode, const double *w, int n, int64_t ld, const int32_t grid[3],
+                    const uint16_t *codes, const double *dinv, double *z, void *Q,
+                    const double *scale_slot, const DevState *st, hipStream_t s);
 int launch_norm(const double *x, int64_t n, const RedWs &ws, hipStream_t s);
 void launch_init_state(DevState *st, int n, int m, int fmt, double tol, double eta,
                        int64_t maxiter, int reorth_all, hipStream_t s);

@@ -26,6 +26,9 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
 bool valid_format(int f) { return f >= CBG_FP64 && f <= CBG_FP16S; }
 
+// the preconditioners whose explicit-residual checks may drop them (M = I)
+bool droppable(int pc) { return pc == CBG_PC_SPARSE || pc == CBG_PC_STENCIL; }
+
 int64_t basis_ld(int32_t n) { return ((int64_t)n + 255) / 256 * 256; }
 
 size_t red_bytes(int jmax)
@@ -83,11 +86,11 @@ SolveWs carve_solve(void *ws, int32_t n, int32_t m, int fmt, int pc, size_t *tot
     s.scales = c.take<double>(m + 1);
     s.w0 = c.take<double>(ld);   // the step's w and the previous step's w
     s.w1 = c.take<double>(ld);   // alternate between these two buffers
-    const bool bj = pc == CBG_PC_BLOCK_JACOBI;
-    s.z = c.take<double>(pc == CBG_PC_SPARSE || bj ? ld : 1);
-    s.v = c.take<double>(bj ? 1 : ld);   // v_j from the separate normalising pass
-    s.dinv = c.take<double>(pc == CBG_PC_JACOBI ? ld : 1);
-    s.xprev = c.take<double>(pc == CBG_PC_SPARSE ? ld : 1);
+    const bool bj = pc == CBG_PC_BLOCK_JACOBI, stc = pc == CBG_PC_STENCIL;
+    s.z = c.take<double>(pc == CBG_PC_SPARSE || bj || stc ? ld : 1);
+    s.v = c.take<double>(bj || stc ? 1 : ld);   // v_j from the separate normalising pass
+    s.dinv = c.take<double>(pc == CBG_PC_JACOBI || stc ? ld : 1);
+    s.xprev = c.take<double>(pc == CBG_PC_SPARSE || stc ? ld : 1);
     // sized for the largest block size: ceil(n/bs) bs^2 <= n BJ_MAX + BJ_MAX^2
     const size_t bjv = bj ? (size_t)n * BJ_MAX + BJ_MAX * BJ_MAX : 1;
     s.bj_tags = c.take<int8_t>(bj ? (size_t)n + 1 : 1);
@@ -143,8 +146,9 @@ struct ByteModel {
 };
 
 // Profiling events of one cycle: per step, start/end of the four
-// basis-streaming launches (dot, update, re-dot, re-update), recorded by
-// hipExtLaunchKernelGGL at each kernel's own start and end.
+// basis-streaming launches (dot, update, re-dot, re-update) and of the SpMV
+// with A, recorded by hipExtLaunchKernelGGL at each kernel's own start and
+// end.
 struct CycleEvents {
     std::vector<hipEvent_t> ev;
     int m = 0;
@@ -152,14 +156,14 @@ struct CycleEvents {
     int create(int mm)
     {
         m = mm;
-        ev.assign((size_t)m * 8, nullptr);
+        ev.assign((size_t)m * 10, nullptr);
         for (auto &e : ev)
             if (hipEventCreate(&e) != hipSuccess)
                 return CBG_E_HIP;
         ok = true;
         return 0;
     }
-    hipEvent_t at(int j, int k, int edge) { return ev[((size_t)(j - 1) * 4 + k) * 2 + edge]; }
+    hipEvent_t at(int j, int k, int edge) { return ev[((size_t)(j - 1) * 5 + k) * 2 + edge]; }
     ~CycleEvents()
     {
         for (auto &e : ev)
@@ -211,7 +215,7 @@ int64_t cbg_basis_ld(int32_t n) { return n < 0 ? 0 : basis_ld(n); }
 size_t cbg_workspace_bytes(int32_t n, int32_t restart, int32_t format, int32_t precond)
 {
     if (n < 0 || restart < 1 || restart > CBG_MAX_RESTART || !valid_format(format) ||
-        precond < CBG_PC_NONE || precond > CBG_PC_BLOCK_JACOBI)
+        precond < CBG_PC_NONE || precond > CBG_PC_STENCIL)
         return 0;
     size_t total = 0;
     carve_solve(nullptr, n, restart, format, precond, &total);
@@ -222,7 +226,7 @@ int cbg_workspace_basis(int32_t n, int32_t restart, int32_t format, int32_t prec
                         size_t *basis_offset, size_t *scales_offset)
 {
     if (n < 0 || restart < 1 || restart > CBG_MAX_RESTART || !valid_format(format) ||
-        precond < CBG_PC_NONE || precond > CBG_PC_BLOCK_JACOBI || !basis_offset ||
+        precond < CBG_PC_NONE || precond > CBG_PC_STENCIL || !basis_offset ||
         !scales_offset)
         return CBG_E_ARG;
     const SolveWs w = carve_solve(nullptr, n, restart, format, precond, nullptr);
@@ -257,7 +261,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
     const int fmt = opt->format, pc0 = opt->precond;
     if (n < 0 || A->nnz < 0 || m < 1 || m > CBG_MAX_RESTART || !valid_format(fmt) ||
         !(opt->tol >= 0.0) || !isfinite(opt->tol) || opt->maxiter < 0 || pc0 < CBG_PC_NONE ||
-        pc0 > CBG_PC_BLOCK_JACOBI || (hist_len > 0 && !hist_out) || hist_len < 0 ||
+        pc0 > CBG_PC_STENCIL || (hist_len > 0 && !hist_out) || hist_len < 0 ||
         (opt->flags & ~CBG_FLAG_ALL) != 0 ||
         (~opt->flags & (CBG_FLAG_NORMALISE_PASS | CBG_FLAG_NORMALISE_GATHER)) == 0 ||
         // the two-pass Gram form excludes the other forms of steps 5-10
@@ -274,6 +278,11 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
         return fail(CBG_E_ARG);
     if (pc0 == CBG_PC_SPARSE && n > 0 && !opt->p_val)
         return fail(CBG_E_ARG);
+    if (pc0 == CBG_PC_STENCIL &&
+        (opt->grid[0] < 1 || opt->grid[1] < 1 || opt->grid[2] < 1 ||
+         (int64_t)opt->grid[0] * opt->grid[1] * opt->grid[2] != n ||
+         (n > 0 && (!opt->p_stencil || !aligned16(opt->p_stencil)))))
+        return fail(CBG_E_ARG);
     if (n == 0)
         return fail(CBG_OK);
     size_t need = 0;
@@ -289,6 +298,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
     const int sg = spmv_shape_of(n, A->nnz);
     const bool prof_all = (opt->flags & CBG_FLAG_PROFILE) != 0;
     const bool prof = prof_all || (opt->flags & CBG_FLAG_PROFILE_DOT) != 0;
+    const bool prof_spmv = (opt->flags & CBG_FLAG_PROFILE_SPMV) != 0;
     // launch slots k of a step: 0 multi-dot, 1 update (or fused update +
     // re-dot), 2 re-dot multi-dot, 3 re-orthogonalising update
     auto profiled = [&](int k) { return prof_all || k % 2 == 0; };
@@ -301,8 +311,10 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
     const bool gram = !mgs && (opt->flags & CBG_FLAG_EXPLICIT_REDOT) == 0;
     // steps 5-10 in one update unless the two-pass Gram form is asked for
     const bool onepass = gram && (opt->flags & CBG_FLAG_TWO_PASS) == 0;
-    if (mgs && prof)
+    if (mgs && (prof || prof_spmv))
         return fail(CBG_E_UNSUPPORTED);     // event timing covers the CGS kernels only
+    if (vhat && pc0 == CBG_PC_STENCIL)
+        return fail(CBG_E_UNSUPPORTED);     // the stencil pass reads the FP64 v only
     // steps 13-14 in a pass of their own, or inside the next SpMV's gather:
     // one division per row against one per nonzero, so long rows favour the
     // pass; with Jacobi the pass also forms dinv .* v once, where the gather
@@ -329,7 +341,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
         launch_reduce(W.red, RR_NB, 0, g, 0, W.st, sa, nullptr, fmt, s);
     }
     int pc = pc0;
-    if (pc == CBG_PC_JACOBI)
+    if (pc == CBG_PC_JACOBI || pc == CBG_PC_STENCIL)
         launch_jacobi_setup(n, ld, A->row_ptr, A->col_idx, A->val, W.dinv, W.bad, s);
     const int bj_nblk = (n + bj_bs - 1) / bj_bs;
     std::vector<int8_t> bj_tags;
@@ -364,7 +376,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
     const double nb = hs.nb;
 
     CycleEvents evs;
-    if (prof && evs.create(m) != 0)
+    if ((prof || prof_spmv) && evs.create(m) != 0)
         return fail(CBG_E_HIP);
 
     std::vector<double> cyc_hist(m);
@@ -433,8 +445,24 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                     }
                 }
             }
+            if (prof_spmv) {
+                // the step SpMV: the plain product when a pass formed M^-1 v,
+                // else the gather variant, which also stores v_j
+                const bool gather = !norm_pass && prev_pc != CBG_PC_STENCIL &&
+                                    prev_pc != CBG_PC_SPARSE && prev_pc != CBG_PC_BLOCK_JACOBI;
+                for (int j = 1; j <= m; ++j) {
+                    float ms;
+                    HIP_TRY(hipEventElapsedTime(&ms, evs.at(j, 4, 0), evs.at(j, 4, 1)));
+                    res->prof_spmv_ms += ms;
+                    res->prof_spmv_bytes +=
+                        j <= jeff ? (gather ? bm.spmv_step() : bm.spmv()) : 0.0;
+                    res->prof_spmv_launches += 1;
+                }
+            }
             for (int j = 1; j <= jeff; ++j) {
                 const bool ro = cyc_flags[j - 1] & 1;
+                if (cyc_flags[j - 1] & 4)
+                    res->explicit_steps += 1;
                 if (hist_n < hist_len)
                     hist_out[hist_n] = cyc_hist[j - 1];
                 ++hist_n;
@@ -444,13 +472,21 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                 double b_step = bm.spmv_step() + (mgs ? b_mgs : bm.dot(j) + bm.upd(j));
                 if (prev_pc == CBG_PC_JACOBI) b_step += 8.0 * n;
                 if (prev_pc == CBG_PC_SPARSE) b_step += 8.0 * A->nnz + 4.0 * (n + 1) + 16.0 * n;
+                // the stencil pass in place of the normalising one: codes
+                // (27 x 2 bytes), dinv, and z written and read
+                if (prev_pc == CBG_PC_STENCIL) b_step += 62.0 * n + 16.0 * n;
                 if (prev_pc == CBG_PC_BLOCK_JACOBI) b_step += bj_bytes + 16.0 * n;
-                if (norm_pass) b_step += 16.0 * n;  // v written by the pass, read by the SpMV
+                if (norm_pass && prev_pc != CBG_PC_STENCIL)
+                    b_step += 16.0 * n;  // v written by the pass, read by the SpMV
                 if (!fused(j) && !mgs && !gram)
                     b_step += bm.dot(j);             // the separate re-dot pass
                 if (gram)
                     b_step += n * bm.bs;             // the newest vector's tile for G
                 if (ro && !onepass) b_step += mgs ? b_mgs : bm.upd(j);
+                // a hard step of the one-pass form: the re-dot pass, and the
+                // second update if it re-orthogonalised
+                if (onepass && (cyc_flags[j - 1] & 4))
+                    b_step += j * n * bm.bs + (ro ? bm.upd(j) : 0.0);
                 model_bytes += b_step;
             }
             model_bytes += jeff * n * bm.bs + 16.0 * n;     // solution update
@@ -458,7 +494,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
 
         rho = hs.beta;
         if (hs.nonfinite || !isfinite(rho)) {
-            if (pc == CBG_PC_SPARSE && opt->fallback && cycles > 0) {
+            if (droppable(pc) && opt->fallback && cycles > 0) {
                 // plain CB-GMRES takes over from the last finite iterate
                 HIP_TRY(hipMemcpyAsync(x, W.xprev, (size_t)n * sizeof(double),
                                        hipMemcpyDeviceToDevice, s));
@@ -481,7 +517,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
             status = CBG_NOT_CONVERGED;
             break;
         }
-        if (pc == CBG_PC_SPARSE && opt->fallback) {
+        if (droppable(pc) && opt->fallback) {
             stagnant = rho > 0.99 * rho_prev ? stagnant + 1 : 0;
             if (stagnant >= 2) {
                 pc = CBG_PC_NONE;
@@ -490,7 +526,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
             }
         }
         rho_prev = rho;
-        if (pc == CBG_PC_SPARSE && opt->fallback)
+        if (droppable(pc) && opt->fallback)
             HIP_TRY(hipMemcpyAsync(W.xprev, x, (size_t)n * sizeof(double),
                                    hipMemcpyDeviceToDevice, s));
         cycles += 1;
@@ -505,7 +541,19 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
             // vector j) fused with steps 3-4: w = A M^-1 v_j, omega
             void *slot = W.V + (size_t)(j - 1) * vbytes;
             int nb_spmv;
-            if (pc == CBG_PC_BLOCK_JACOBI) {
+            hipEvent_t sev0 = prof_spmv ? evs.at(j, 4, 0) : nullptr;
+            hipEvent_t sev1 = prof_spmv ? evs.at(j, 4, 1) : nullptr;
+            if (pc == CBG_PC_STENCIL) {
+                // v_j = w / t stored, z = M^-1 v_j in one pass; then w = A z
+                launch_stencil(fmt, 0, cur, n, ld, opt->grid, opt->p_stencil, W.dinv, W.z, slot,
+                               W.scales + (j - 1), W.st, s);
+                SpmvArgs b2{};
+                b2.n = n; b2.ldy = ld; b2.rp = A->row_ptr; b2.ci = A->col_idx; b2.val = A->val;
+                b2.x = W.z; b2.y = nxt; b2.ws = W.red; b2.mode = 0 /*SP_PLAIN*/;
+                b2.role = 1 /*SR_STEP*/; b2.sg = sg; b2.st = W.st;
+                b2.ev0 = sev0; b2.ev1 = sev1;
+                nb_spmv = launch_spmv(b2, s);
+            } else if (pc == CBG_PC_BLOCK_JACOBI) {
                 // v_j = w / t stored, z = M^-1 v_j; then w = A z, omega
                 launch_bj_apply(n, ld, bj_bs, W.bj_tags, W.bj64, W.bj32, W.bj16, cur, W.z, 0,
                                 W.st, slot, W.scales + (j - 1), fmt, vhat, s);
@@ -513,6 +561,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                 b2.n = n; b2.ldy = ld; b2.rp = A->row_ptr; b2.ci = A->col_idx; b2.val = A->val;
                 b2.x = W.z; b2.y = nxt; b2.ws = W.red; b2.mode = 0 /*SP_PLAIN*/;
                 b2.role = 1 /*SR_STEP*/; b2.sg = sg; b2.st = W.st;
+                b2.ev0 = sev0; b2.ev1 = sev1;
                 nb_spmv = launch_spmv(b2, s);
             } else if (pc == CBG_PC_SPARSE) {
                 SpmvArgs a{};
@@ -531,6 +580,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                 b2.n = n; b2.ldy = ld; b2.rp = A->row_ptr; b2.ci = A->col_idx; b2.val = A->val;
                 b2.x = W.z; b2.y = nxt; b2.ws = W.red; b2.mode = 0 /*SP_PLAIN*/;
                 b2.role = 1 /*SR_STEP*/; b2.sg = sg; b2.st = W.st;
+                b2.ev0 = sev0; b2.ev1 = sev1;
                 nb_spmv = launch_spmv(b2, s);
             } else {
                 SpmvArgs a{};
@@ -547,6 +597,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                     a.x = cur; a.mode = (vhat << 4) | 8 | base;
                     a.Q = slot; a.qscale = W.scales + (j - 1); a.fmt = fmt;
                 }
+                a.ev0 = sev0; a.ev1 = sev1;
                 nb_spmv = launch_spmv(a, s);
             }
             if (mgs) {
@@ -587,10 +638,12 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
             o.coef = W.h; o.role = 1 /*U_STEP1*/;
             timed(1);
             if (onepass) {
-                // u = h - G h, then steps 5-10 in one update with h + u or h,
-                // then the close
-                launch_reduce(W.red, RR_GU, 0, 0, j, W.st, sa, nullptr, fmt, s);
-                o.role = 6 /*U_CGS2*/; o.u = W.u; o.stw = W.st;
+                // u = h - G h and steps 5-10 in one update with h + u or h;
+                // a hard step's explicit second pass (nothing otherwise);
+                // the close
+                o.role = 6 /*U_CGS2*/; o.u = W.u; o.stw = W.st; o.G = W.G;
+                launch_update(o, s);
+                o.role = 7 /*U_HARD*/;
                 launch_update(o, s);
                 launch_reduce(W.red, RR_C2, nb_orth, 0, j, W.st, sa, nullptr, fmt, s);
                 double *t = cur;
@@ -638,6 +691,12 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                 launch_update(o, s);
                 launch_bj_apply(n, ld, bj_bs, W.bj_tags, W.bj64, W.bj32, W.bj16, W.z, x, 1,
                                 nullptr, nullptr, nullptr, fmt, 0, s);   // x += M^-1 z
+            } else if (pc == CBG_PC_STENCIL) {
+                o.role = 4 /*U_COMBINE*/;       // z = V y
+                o.wio = W.z;
+                launch_update(o, s);
+                launch_stencil(fmt, 2, W.z, n, ld, opt->grid, opt->p_stencil, W.dinv, x, nullptr,
+                               nullptr, nullptr, s);   // x += M^-1 z
             } else if (pc == CBG_PC_SPARSE) {
                 o.role = 4 /*U_COMBINE*/;       // z = V y
                 o.wio = W.z;

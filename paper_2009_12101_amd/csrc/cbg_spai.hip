@@ -388,6 +388,51 @@ __global__ __launch_bounds__(256) void k_assemble(int n, const int32_t *__restri
     }
 }
 
+// float16 code of an fp32 value: one rounding to nearest even; magnitudes
+// from 65520 up become infinity, NaN the quiet NaN.
+__device__ __forceinline__ uint16_t f16_code(float f)
+{
+    const double v = (double)f;
+    if (!(fabs(v) < 65520.0))
+        return (uint16_t)(v != v ? 0x7E00u : (0x7C00u | (sign_of(v) << 15)));
+    return (uint16_t)(rne_code<10, -14, 15>(v) | (sign_of(v) << 15));
+}
+
+// The stored form of the learned preconditioner (CBG_PC_STENCIL): codes[p
+// ld + i] = f16(O_{i,p}) for the slots p row i stores, 0 for the other
+// slots and for rows [n, ld) (a half-wave per row; the row's 27 codes are
+// assembled in LDS, then written one per lane).
+__global__ __launch_bounds__(256) void k_stencil_pack(int n, int64_t ld,
+                                                      const int32_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ ci, int nx,
+                                                      int ny, const float *__restrict__ O,
+                                                      uint16_t *__restrict__ codes)
+{
+    __shared__ uint16_t lc[HWR][NO];
+    const int g = threadIdx.x >> 5, lane = threadIdx.x & 31;
+    for (int64_t base = (int64_t)blockIdx.x * HWR; base < ld; base += (int64_t)gridDim.x * HWR) {
+        const int64_t i = base + g;
+        const bool live = i < n;
+        const int beg = live ? rp[i] : 0, end = live ? rp[i + 1] : 0;
+        const int chunks = block_chunks((end - beg + 31) / 32);
+        const RowPos rpos = row_pos(live ? i : 0, nx, ny);
+        lc[g][lane] = 0;
+        __syncthreads();
+        for (int q = 0; q < chunks; ++q) {
+            const int p = beg + q * 32 + lane;
+            if (p < end) {
+                const int sl = slot_at(rpos, i, ci[p], nx, ny);
+                if (sl >= 0)
+                    lc[g][sl] = f16_code(O[i * NO + sl]);
+            }
+        }
+        __syncthreads();
+        if (i < ld && lane < NSLOT)
+            codes[(int64_t)lane * ld + i] = lc[g][lane];
+        __syncthreads();
+    }
+}
+
 // dL/dO (bf16, n x 32) from dL/dP: dO_{i,p} = dP_{i,c(p)} / a_ii (a
 // half-wave per row; the row's 32 slots assembled in LDS).
 __global__ __launch_bounds__(256) void k_grad_o(int n, const int32_t *__restrict__ rp,
@@ -845,6 +890,7 @@ size_t salign(size_t x) { return (x + SALIGN - 1) / SALIGN * SALIGN; }
 struct SpaiWs {
     unsigned *bad;
     double *diag;
+    double *dinv;          // 1 / a_ii on cbg_basis_ld(n) rows (stencil apply)
     double *lpart;
     float *gpart;
     uint16_t *feat, *h1, *h2, *dO;
@@ -864,6 +910,7 @@ SpaiWs carve_spai(void *ws, int64_t n, int64_t nnz, int64_t K, size_t *total)
     SpaiWs s;
     s.bad = (unsigned *)take(sizeof(unsigned));
     s.diag = (double *)take(8 * (size_t)n);
+    s.dinv = (double *)take(8 * (size_t)((n + 255) / 256 * 256));
     s.lpart = (double *)take(sizeof(double) * MAXB_ROW);
     s.gpart = (float *)take(sizeof(float) * (size_t)MAXB_BACK * NPARAM);
     s.feat = (uint16_t *)take(2 * (size_t)n * NF);
@@ -1061,6 +1108,62 @@ int cbg_learned_build(const cbg_csr *A, const int32_t grid[3], const uint16_t *w
     if ((e = read_flag(W.bad, s, &bad)))
         return e;
     return bad ? CBG_E_NONFINITE : CBG_OK;
+}
+
+int cbg_learned_build_stencil(const cbg_csr *A, const int32_t grid[3], const uint16_t *weights,
+                              const float *params, uint16_t *p_stencil, void *ws,
+                              size_t ws_bytes, void *stream)
+{
+    if (!csr_ok(A) || !grid_ok(A, grid) || (A->n > 0 && (!weights || !params || !p_stencil)) ||
+        !a16(weights) || !a16(params) || !a16(p_stencil))
+        return CBG_E_ARG;
+    int e = ws_check(ws, ws_bytes, A->n, A->nnz, 0);
+    if (e)
+        return e;
+    if (A->n == 0)
+        return CBG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    SpaiWs W = carve_spai(ws, A->n, A->nnz, 0, nullptr);
+    const int64_t ld = cbg_basis_ld(A->n);
+    SP_TRY(hipMemsetAsync(W.bad, 0, sizeof(unsigned), s));
+    hipLaunchKernelGGL(k_diag, dim3(group_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
+                       A->col_idx, A->val, W.diag);
+    hipLaunchKernelGGL(k_features, dim3(group_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
+                       A->col_idx, A->val, grid[0], grid[1], (const double *)W.diag, W.feat,
+                       W.bad);
+    enqueue_forward(A->n, W.feat, weights, params, W.O, nullptr, nullptr, s);
+    hipLaunchKernelGGL(k_stencil_pack, dim3(group_grid(ld)), dim3(256), 0, s, A->n, ld,
+                       A->row_ptr, A->col_idx, grid[0], grid[1], (const float *)W.O, p_stencil);
+    SP_TRY(hipGetLastError());
+    unsigned bad = 0;
+    if ((e = read_flag(W.bad, s, &bad)))
+        return e;
+    return bad ? CBG_E_NONFINITE : CBG_OK;
+}
+
+int cbg_stencil_apply(const cbg_csr *A, const int32_t grid[3], const uint16_t *p_stencil,
+                      const double *v, double *z, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!csr_ok(A) || !grid_ok(A, grid) || (A->n > 0 && (!p_stencil || !v || !z)) ||
+        !a16(p_stencil))
+        return CBG_E_ARG;
+    int e = ws_check(ws, ws_bytes, A->n, A->nnz, 0);
+    if (e)
+        return e;
+    if (A->n == 0)
+        return CBG_OK;
+    hipStream_t s = (hipStream_t)stream;
+    SpaiWs W = carve_spai(ws, A->n, A->nnz, 0, nullptr);
+    const int64_t ld = cbg_basis_ld(A->n);
+    SP_TRY(hipMemsetAsync(W.bad, 0, sizeof(unsigned), s));
+    launch_jacobi_setup(A->n, ld, A->row_ptr, A->col_idx, A->val, W.dinv, W.bad, s);
+    launch_stencil(F_FP64, 1, v, A->n, ld, grid, p_stencil, W.dinv, z, nullptr, nullptr, nullptr,
+                   s);
+    SP_TRY(hipGetLastError());
+    unsigned bad = 0;
+    if ((e = read_flag(W.bad, s, &bad)))
+        return e;
+    return bad ? CBG_E_ARG : CBG_OK;
 }
 
 int cbg_csr_transpose_values(const cbg_csr *A, double *t_val, void *ws, size_t ws_bytes,

@@ -110,6 +110,11 @@ class LearnedSPAI:
         """P values (nnz fp32) for CBG_PC_SPARSE."""
         return B.learned_build(A, grid, self.weights, self.params, ws=ws)
 
+    def build_stencil(self, A: "B.DeviceCSR", grid, ws=None, out=None):
+        """The stored form for CBG_PC_STENCIL: float16 corrections on the
+        27-point slots (27 * basis_ld(n) codes, slot-major)."""
+        return B.learned_build_stencil(A, grid, self.weights, self.params, p_stencil=out, ws=ws)
+
     # ----------------------------------------------------------- storage
     def save(self, path: str):
         np.savez(path, params=self.params.cpu().numpy(), m1=self.m1.cpu().numpy(),
@@ -127,7 +132,7 @@ class LearnedSPAI:
 
 
 def init_params(seed: int) -> np.ndarray:
-    """He-normal W1 (32x64) and W2 (64x64) from the seeded counter-based
+    """He-normal W1 (64x64) and W2 (64x64) from the seeded counter-based
     normal stream, stored fp32; W3, b1, b2, b3 zero (so P starts as Jacobi)."""
     nf, nh, no = B.SPAI_NFEAT, B.SPAI_NHID, B.SPAI_NOUT
     z = P.normal(seed, P.STREAM_WEIGHTS, nf * nh + nh * nh)
@@ -184,27 +189,37 @@ def make_instances(seeds, N: int, device, pool=None, log=None):
 def compare(model: LearnedSPAI, A, b, fmt="fp16", restart=100, tol=1e-10, maxiter=20000,
             repeats=1, device="cuda", plain_fp64=False):
     """Time to solution of CB-GMRES with M = I, Jacobi, block-Jacobi (4 x 4
-    blocks, adaptive or fp64 storage) and the learned P (its build, features
-    to P values, included in the time), all with the `fmt` basis; with
-    plain_fp64 also plain GMRES (fp64 basis, M = I).  Block-Jacobi's set-up
-    (inverting the blocks) is part of its solve."""
+    blocks, adaptive or fp64 storage), the learned P in its stored form
+    ("learned": float16 corrections on the 27-point slots, applied in the
+    normalising pass) and as fp32 values on A's pattern ("learned_csr", one
+    more CSR pass per step), each build (features to stored values)
+    included in the time, all with the `fmt` basis; with plain_fp64 also
+    plain GMRES (fp64 basis, M = I).  Block-Jacobi's set-up (inverting the
+    blocks) is part of its solve."""
     torch = _torch()
     Ad = B.DeviceCSR.from_host(A, device)
     bd = torch.from_numpy(b).to(device)
     need = max(B.workspace_bytes(A.n, restart, fmt, "sparse"),
+               B.workspace_bytes(A.n, restart, fmt, "stencil"),
                B.workspace_bytes(A.n, restart, fmt, "block_jacobi"),
                B.workspace_bytes(A.n, restart, "fp64", "none") if plain_fp64 else 0)
     ws = torch.empty(need, dtype=torch.uint8, device=device)
     sws = torch.empty(B.spai_workspace_bytes(A.n, A.nnz, 0), dtype=torch.uint8, device=device)
     rows = {}
-    kinds = ["none", "jacobi", "block_jacobi", "block_jacobi_fp64", "learned"] + \
+    kinds = ["none", "jacobi", "block_jacobi", "block_jacobi_fp64", "learned", "learned_csr"] + \
         (["plain_fp64"] if plain_fp64 else [])
+    codes = torch.empty(27 * B.basis_ld(A.n), dtype=torch.int16, device=device)
     for kind in kinds:
         best = None
         for _ in range(repeats + 1):            # the first run warms up
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             if kind == "learned":
+                model.build_stencil(Ad, A.grid, ws=sws, out=codes)
+                r = B.solve(Ad, bd, restart=restart, fmt=fmt, tol=tol, maxiter=maxiter,
+                            precond="stencil", p_stencil=codes, grid=A.grid, fallback=True,
+                            workspace=ws, hist=False)
+            elif kind == "learned_csr":
                 pv = model.build(Ad, A.grid, ws=sws)
                 r = B.solve(Ad, bd, restart=restart, fmt=fmt, tol=tol, maxiter=maxiter,
                             precond="sparse", p_val=pv, fallback=True, workspace=ws,

@@ -1,0 +1,70 @@
+"""Writes cycle_spread.json: how far the oracle's own end-of-cycle recurrence
+residual moves under rounding-level perturbations of b, on the full-size
+workloads that tests/test_gpu_configs.py (27-point lognormal diffusion) and
+tests/test_gpu_fullsize.py (7-point convection-diffusion) run for one
+restart cycle.
+
+For each case (system, grid N, restart m, storage format) the oracle (Fig. 1
+as written) runs one cycle on b ~ U[-1, 1] (seed 0) and on NPERT copies
+b_p = b (1 + 1e-15 z_p), z_p ~ N(0, 1) (numpy seed 1000 + p).  Two correct
+implementations of the same iteration differ by rounding only, like these
+runs, so the largest relative deviation max_p |r_p / r_0 - 1| of the
+end-of-cycle residual r is the scale of the GPU-vs-oracle band.  Only the
+oracle runs here.
+
+    python tests/golden/make_cycle_spread.py      # about 40 min on 8 cores
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle as orc                                   # noqa: E402
+from paper_2009_12101_amd import problems as P         # noqa: E402
+
+CASES = [("convdiff7", 128, 100, "fp16"),
+         ("lognormal27", 128, 100, "bf16"), ("lognormal27", 128, 100, "e4m3"),
+         ("lognormal27", 160, 200, "fp16"), ("lognormal27", 160, 200, "int16"),
+         ("lognormal27", 160, 200, "fp64")]
+NPERT = 8
+
+
+def perturbed(b, p):
+    return b * (1.0 + 1e-15 * np.random.default_rng(1000 + p).standard_normal(b.size))
+
+
+def main():
+    out = {"npert": NPERT, "perturbation": "b (1 + 1e-15 z), z ~ N(0,1), numpy seed 1000 + p",
+           "threads": orc.get_threads(), "cases": {}}
+    systems = {}
+    for name, N, m, fmt in CASES:
+        if (name, N) not in systems:
+            systems.clear()
+            A = P.lognormal27(N, 0) if name == "lognormal27" else P.convdiff7(N)
+            systems[(name, N)] = (A, P.rhs_uniform(A.n, 0))
+        A, b = systems[(name, N)]
+        t0 = time.time()
+        res = []
+        for p in range(-1, NPERT):
+            bp = b if p < 0 else perturbed(b, p)
+            r = orc.gmres(A, bp, restart=m, fmt=fmt, tol=1e-10, maxiter=m)
+            res.append(float(r["hist"][m - 1]))
+        r0 = res[0]
+        dev = [abs(r / r0 - 1.0) for r in res[1:]]
+        key = f"{name}_{N}_{m}_{fmt}"
+        out["cases"][key] = {"end_of_cycle_residual": r0, "perturbed": res[1:],
+                             "max_rel_deviation": max(dev)}
+        print(f"{key}: r0 = {r0:.4e}, max deviation {max(dev):.3e} "
+              f"({time.time() - t0:.0f} s)", flush=True)
+    with open(os.path.join(HERE, "cycle_spread.json"), "w") as f:
+        json.dump(out, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -137,9 +137,11 @@ def test_gram_first_steps(cbg, orc, dev, fmt, precond):
 @pytest.mark.parametrize("fmt", ["fp16", "int16", "bf16", "fp16s", "e4m3", "fp32", "fp64"])
 @pytest.mark.parametrize("precond", ["none", "jacobi", "block_jacobi"])
 def test_onepass_first_steps(cbg, orc, dev, fmt, precond):
-    """Steps 5-10 in one update: the first steps coincide with the oracle's
-    one-pass run to 1e-12, with step 7's decision taken from t1 by
-    Pythagoras (eta = 1/sqrt(2): the test fires on most steps here)."""
+    """Cross-check of the default arrangement of steps 5-10 (one update,
+    step 7 decided from t1 by Pythagoras) against the oracle's one-pass
+    variant, which restates it: the first steps coincide to 1e-12 (eta =
+    1/sqrt(2): the test fires on most steps here).  Parity with Fig. 1 is
+    tested in test_gpu_solve.py."""
     print(f"ablation onepass {fmt} {precond}", flush=True)
     A = P.lognormal27(12, 2)
     b = P.rhs_uniform(A.n, 9)
@@ -154,13 +156,16 @@ def test_onepass_first_steps(cbg, orc, dev, fmt, precond):
 
 
 @pytest.mark.parametrize("fmt", ["fp64", "fp16"])
-def test_onepass_textbook_breakdowns(cbg, orc, dev, fmt):
+def test_default_textbook_breakdowns(cbg, orc, dev, fmt):
+    """A = I and a diagonal with five eigenvalues: the default form (whose
+    near-breakdown steps take Fig. 1's explicit form) breaks down where
+    Fig. 1 does."""
     from tests._helpers import csr_from_dense
     cases = [(np.eye(50), np.random.default_rng(0).standard_normal(50)),
              (np.diag(np.tile([1.0, 2, 3, 4, 5], 10)), np.ones(50))]
     for M, b in cases:
         A = csr_from_dense(M)
-        kw = dict(restart=20, fmt=fmt, tol=1e-12, maxiter=40, variant=("gram", "onepass"))
+        kw = dict(restart=20, fmt=fmt, tol=1e-12, maxiter=40)
         r = cbg.solve(cbg.DeviceCSR.from_host(A, dev), torch.from_numpy(b).to(dev), **kw)
         o = orc.gmres(A, b, **kw)
         assert r.status == o["status"] == 0
@@ -265,7 +270,7 @@ def test_unknown_flag_bits_are_argument_errors(cbg, dev):
     b = torch.ones(A.n, dtype=torch.float64, device=dev)
     x = torch.zeros_like(b)
     ws = torch.empty(B.workspace_bytes(A.n, 8, "fp64"), dtype=torch.uint8, device=dev)
-    opts = B.CbgOpts(8, 0, 1e-10, 10, 0.0, 0, 0, None, 1024, 0, 0, 0)
+    opts = B.CbgOpts(8, 0, 1e-10, 10, 0.0, 0, 0, None, 2048, 0, 0, 0)
     res = B.CbgResult()
     csr = Ad.cstruct()
     rc = B.lib().cbgmres_solve(C.byref(csr), B._ptr(b), B._ptr(x), C.byref(opts), B._ptr(ws),

@@ -16,7 +16,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from paper_2009_12101_amd import problems as P
-from tests._helpers import LIB_DEFAULT
+from tests._helpers import FIG1
 from tests._helpers import csr_from_dense
 
 U = 2.0 ** -53
@@ -125,7 +125,7 @@ def test_apply_within_fp64_bound(cbg, orc, dev, bs):
 def test_fp64_solve_parity(cbg, orc, dev, name, bs):
     A = SYSTEMS[name]()
     b = P.rhs_uniform(A.n, 5)
-    ref = orc.gmres(A, b, restart=30, fmt="fp64", tol=1e-10, maxiter=3000, variant=LIB_DEFAULT,
+    ref = orc.gmres(A, b, restart=30, fmt="fp64", tol=1e-10, maxiter=3000, variant=FIG1,
                     precond="block_jacobi", pc_block=bs)
     Ad = cbg.DeviceCSR.from_host(A, dev)
     bd = torch.from_numpy(b).to(dev)
@@ -144,7 +144,7 @@ def test_fp64_solve_parity(cbg, orc, dev, name, bs):
 def test_fp16_solve_reaches_tolerance(cbg, orc, dev):
     A = P.convdiff7(16)
     b = P.rhs_uniform(A.n, 6)
-    ref = orc.gmres(A, b, restart=30, fmt="fp16", tol=1e-10, maxiter=3000, variant=LIB_DEFAULT,
+    ref = orc.gmres(A, b, restart=30, fmt="fp16", tol=1e-10, maxiter=3000, variant=FIG1,
                     precond="block_jacobi", pc_block=4)
     Ad = cbg.DeviceCSR.from_host(A, dev)
     r = cbg.solve(Ad, torch.from_numpy(b).to(dev), restart=30, fmt="fp16", tol=1e-10,

@@ -5,15 +5,22 @@
 * The same generator on 160^3 (n = 4,096,000, nnz = 109,215,352), restart
   200, bases fp16 and int16.
 
-b ~ U[-1, 1] seed 0, x0 = 0.  Both sides run one full cycle (maxiter = m).
-The first steps agree to rounding; after that the stored bases drift apart
-at storage precision, so the recurrence residual at the end of the cycle
-is compared to max(5e-2, u) relative, u the format's unit roundoff (e4m3:
-2^-4; measured differences up to 3.4e-2).  The first stored basis vector, read from
+b ~ U[-1, 1] seed 0, x0 = 0.  Both sides run one full cycle (maxiter = m);
+the oracle runs Fig. 1 as written.  The first steps agree to rounding; after
+that the stored bases drift apart at storage precision, so the recurrence
+residual at the end of the cycle agrees only as closely as two runs of one
+iteration that differ by rounding: the band is max(1e-2, 1.5 d), d the
+largest relative change of the oracle's own end-of-cycle residual under
+eight rounding-level perturbations of b at the same configuration
+(tests/golden/cycle_spread.json, written by
+tests/golden/make_cycle_spread.py).  The first stored basis vector, read from
 the solver workspace, is enc(r0 / ||r0||) on both sides; ||r0|| is summed
 in different orders, so a code may differ by one step where r0_i / ||r0||
 lies within an ulp of a rounding boundary (a tiny fraction of entries).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -21,7 +28,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from paper_2009_12101_amd import problems as P
-from tests._helpers import LIB_DEFAULT
+from tests._helpers import FIG1
 
 # (160, 200, fp64): its basis (6.6 GB) is past the fused pass's 32-bit
 # offsets, so every step runs the two-pass form (a regression case: the
@@ -45,6 +52,14 @@ def cbg():
 
 
 _cache = {}
+SPREAD_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                           "cycle_spread.json")
+
+
+def cycle_band(name, N, m, fmt):
+    """max(1e-2, 1.5 x the oracle's own spread) for one configuration."""
+    spread = json.load(open(SPREAD_FILE))
+    return max(1e-2, 1.5 * spread["cases"][f"{name}_{N}_{m}_{fmt}"]["max_rel_deviation"])
 
 
 def system(cbg, dev, N):
@@ -61,20 +76,19 @@ def system(cbg, dev, N):
 @pytest.mark.parametrize("N,m,fmt", CASES)
 def test_one_cycle(cbg, orc, dev, N, m, fmt):
     A, b, Ad, bd = system(cbg, dev, N)
-    ref = orc.gmres(A, b, restart=m, fmt=fmt, tol=1e-10, maxiter=m, variant=LIB_DEFAULT)
+    ref = orc.gmres(A, b, restart=m, fmt=fmt, tol=1e-10, maxiter=m, variant=FIG1)
     ws = torch.empty(cbg.workspace_bytes(A.n, m, fmt), dtype=torch.uint8, device=dev)
     r = cbg.solve(Ad, bd, restart=m, fmt=fmt, tol=1e-10, maxiter=m, workspace=ws)
     assert r.iterations == ref["iterations"] == m
     assert np.allclose(r.hist[:3], ref["hist"][:3], rtol=1e-12, atol=0)
     # two correct runs drift apart at storage precision; after a cycle their
-    # residuals agree to a few percent, and never better than one rounding
-    # of a stored entry (unit roundoff 2^-4 for e4m3).  Measured at 160^3,
-    # m = 200, int16: 6.08e-4 on the GPU, 5.94e-4 (Fig. 1's form) and
-    # 5.88e-4 (the one-pass form) on the oracle, whose two forms alone differ
-    # by 1.1%
-    u_fmt = {"fp64": 2.0 ** -53, "fp16": 2.0 ** -11, "bf16": 2.0 ** -8, "e4m3": 2.0 ** -4,
-             "int16": 2.0 ** -16}[fmt]
-    assert abs(r.hist[m - 1] / ref["hist"][m - 1] - 1.0) <= max(5e-2, u_fmt)
+    # residuals agree as closely as rounding-level perturbations of b move
+    # the oracle's own
+    band = cycle_band("lognormal27", N, m, fmt)
+    dev_rel = abs(r.hist[m - 1] / ref["hist"][m - 1] - 1.0)
+    print(f"  end of cycle: GPU {r.hist[m - 1]:.4e}, oracle {ref['hist'][m - 1]:.4e}, "
+          f"relative {dev_rel:.2e}, band {band:.2e}", flush=True)
+    assert dev_rel <= band
     # the first stored basis vector: enc(r0 / ||r0||)
     off, soff = cbg.workspace_basis(A.n, m, fmt)
     dt = {"fp64": np.float64, "fp16": np.uint16, "bf16": np.uint16, "e4m3": np.uint8,

@@ -13,12 +13,14 @@ compared whole rather than sampled.
 * fp64-basis solve: both sides follow the same iteration up to rounding;
   counts within one step; in iteration-matched mode (the GPU capped at the
   oracle's count) x within 1e-8 relative of the oracle's.
-* fp16-basis solve (the bench step): the first steps agree to rounding,
-  the recurrence residual after one full cycle agrees to 1e-2 relative
-  (the two bases drift apart at storage precision; on this system even the
-  fp64 and fp16 runs differ by 2e-4 there), and the full solve reaches the
-  tolerance with a count within 10% of the oracle's (one sample of a count
-  that moves by up to 8% under rounding-level changes of b).
+* fp16-basis solve: the first steps agree to rounding, the recurrence
+  residual after one full cycle agrees within the band that rounding-level
+  perturbations of b give the oracle itself (max(1e-2, 1.5 x that spread),
+  tests/golden/cycle_spread.json), and the full solve reaches the tolerance
+  with a count within 10% of the oracle's (one sample of a count that moves
+  by up to 8% under rounding-level changes of b).
+
+The oracle runs Fig. 1 as written throughout.
 """
 import numpy as np
 import pytest
@@ -27,7 +29,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from paper_2009_12101_amd import problems as P
-from tests._helpers import LIB_DEFAULT
+from tests._helpers import FIG1
 
 U = 2.0 ** -53
 M, TOL = 100, 1e-10
@@ -120,7 +122,7 @@ def test_multidot_update_full(cbg, orc, dev, system):
 @pytest.mark.timeout(300)
 def test_fp64_solve_full(cbg, orc, dev, system):
     A, b, Ad, bd, ws = system
-    ref = orc.gmres(A, b, restart=M, fmt="fp64", tol=TOL, maxiter=20000, variant=LIB_DEFAULT)
+    ref = orc.gmres(A, b, restart=M, fmt="fp64", tol=TOL, maxiter=20000, variant=FIG1)
     assert ref["status"] == 0
     r = cbg.solve(Ad, bd, restart=M, fmt="fp64", tol=TOL, maxiter=20000, workspace=ws)
     assert r.status == 0
@@ -136,12 +138,16 @@ def test_fp64_solve_full(cbg, orc, dev, system):
 @pytest.mark.timeout(300)
 def test_fp16_solve_full(cbg, orc, dev, system):
     A, b, Ad, bd, ws = system
-    one = orc.gmres(A, b, restart=M, fmt="fp16", tol=TOL, maxiter=M, variant=LIB_DEFAULT)
+    one = orc.gmres(A, b, restart=M, fmt="fp16", tol=TOL, maxiter=M, variant=FIG1)
     r1 = cbg.solve(Ad, bd, restart=M, fmt="fp16", tol=TOL, maxiter=M, workspace=ws)
     assert r1.iterations == one["iterations"] == M
     assert np.allclose(r1.hist[:3], one["hist"][:3], rtol=1e-12, atol=0)
-    assert abs(r1.hist[M - 1] / one["hist"][M - 1] - 1.0) <= 1e-2
-    ref = orc.gmres(A, b, restart=M, fmt="fp16", tol=TOL, maxiter=20000, variant=LIB_DEFAULT)
+    # after a cycle: as closely as rounding-level perturbations of b move the
+    # oracle's own residual (tests/golden/cycle_spread.json), at least 1e-2
+    from tests.test_gpu_configs import cycle_band
+    band = cycle_band("convdiff7", 128, M, "fp16")
+    assert abs(r1.hist[M - 1] / one["hist"][M - 1] - 1.0) <= band
+    ref = orc.gmres(A, b, restart=M, fmt="fp16", tol=TOL, maxiter=20000, variant=FIG1)
     assert ref["status"] == 0
     r = cbg.solve(Ad, bd, restart=M, fmt="fp16", tol=TOL, maxiter=20000, workspace=ws)
     assert r.status == 0

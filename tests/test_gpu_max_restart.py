@@ -14,7 +14,7 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from paper_2009_12101_amd import problems as P
-from tests._helpers import LIB_DEFAULT
+from tests._helpers import FIG1
 
 M = 512
 
@@ -44,7 +44,7 @@ def test_fp64_full_cycle_at_max_restart(cbg, orc, dev, system):
     print("max restart fp64", flush=True)
     A, b = system
     kw = dict(restart=M, fmt="fp64", tol=0.0, maxiter=M)
-    o = orc.gmres(A, b, variant=LIB_DEFAULT, **kw)
+    o = orc.gmres(A, b, variant=FIG1, **kw)
     r = cbg.solve(cbg.DeviceCSR.from_host(A, dev), torch.from_numpy(b).to(dev), **kw)
     assert o["iterations"] == r.iterations == M
     assert o["cycle_len"][0] == M
@@ -58,7 +58,7 @@ def test_compressed_full_cycle_at_max_restart(cbg, orc, dev, system, fmt):
     print(f"max restart {fmt}", flush=True)
     A, b = system
     kw = dict(restart=M, fmt=fmt, tol=0.0, maxiter=M)
-    o = orc.gmres(A, b, variant=LIB_DEFAULT, **kw)
+    o = orc.gmres(A, b, variant=FIG1, **kw)
     r = cbg.solve(cbg.DeviceCSR.from_host(A, dev), torch.from_numpy(b).to(dev), **kw)
     assert o["iterations"] == r.iterations == M
     # the first steps coincide; after 512 steps the two runs, which round

@@ -1,9 +1,13 @@
 """GPU CB-GMRES solves against the CPU oracle, through the C ABI.
 
+The reference is the oracle's default: Fig. 1 as written (explicit re-dot,
+two updates).  The library's default arranges steps 5-10 differently (the
+Gram-form re-dot and one update, with Fig. 1's explicit form on steps where
+t1 < omega / 100); the two agree up to FP64 rounding.
+
 fp64 basis: the GPU and the oracle follow the same iteration up to rounding,
 so in iteration-matched mode (both capped at the oracle's step count) the
-iterates agree to 1e-8 relative (observed: 1e-14 to 4e-11) and the counts
-to within one step.
+iterates agree to 1e-8 relative and the counts to within one step.
 
 Compressed bases: which way a stored entry rounds is decided by its last
 fp64 bits, so two correct implementations whose fp64 arithmetic differs in
@@ -11,16 +15,24 @@ summation order drift apart at the storage precision after a few steps
 (the first steps still agree to rounding).  The iteration count is then a
 random variable of the problem: a 1e-15 relative change of b moves it by up
 to +-8% on these systems (measured on the oracle).  Parity is therefore
-stated over 11 seeded rounding-level perturbations of b run on both sides:
-median counts within 5% (plus half the oracle's 10-90% spread), every GPU
-solve at true residual <= tol, and every GPU solution within
-2 tol ||b|| / sigma_min(A) of the oracle's (the bound two solves that both
-meet the tolerance can differ by).
+stated over 21 seeded rounding-level perturbations of b run on both sides:
+mean counts within 5%, the two samples of counts not distinguishable by a
+two-sided Mann-Whitney rank test (p >= 1e-3), every GPU solve at true
+residual <= tol, and every GPU solution within 2 tol ||b|| / sigma_min(A)
+of the oracle's (the bound two solves that both meet the tolerance can
+differ by).  The median is not the statistic: on the 7-point system the
+fp16 and scaled-fp16 counts are bimodal (clusters near 126 and 138 steps,
+restart 30), so the median of 21 runs falls in either cluster.  Measured on
+the CPU (tests/golden/count_spread.json, written by
+tests/golden/make_count_spread.py), the oracle's Fig. 1 form against its
+one-pass arrangement of steps 5-10, two correct implementations of one
+iteration: means within 2.0%, medians up to 3.7% apart, rank-test p >= 0.097
+(the GPU against the oracle: medians 6.6% apart on convdiff7_20 with fp16s).
 """
 import numpy as np
 import pytest
 
-from tests._helpers import LIB_DEFAULT
+from tests._helpers import FIG1
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -28,7 +40,7 @@ pytestmark = pytest.mark.gpu
 FORMATS = ["fp64", "fp32", "fp16", "bf16", "e4m3", "int32", "int16", "fp16s"]
 PROBLEMS = [("poisson2d_64", 100), ("convdiff7_20", 30), ("lognormal27_12", 40)]
 TOL = 1e-10
-NPERT = 11
+NPERT = 21
 
 
 @pytest.fixture(scope="module")
@@ -46,7 +58,7 @@ def cbg():
 
 
 def run_pair(cbg, orc, dev, A, b, **kw):
-    ref = orc.gmres(A, b, variant=LIB_DEFAULT, **kw)
+    ref = orc.gmres(A, b, variant=FIG1, **kw)
     Ad = cbg.DeviceCSR.from_host(A, dev)
     bd = torch.from_numpy(b).to(dev)
     kw2 = dict(kw)
@@ -84,7 +96,7 @@ def test_solve_parity_fp64(cbg, orc, dev, name, m):
     assert abs(r.true_rel_res - true_res(orc, A, b, x)) <= 1e-3 * TOL
     it = ref["iterations"]
     rm = cbg.solve(Ad, bd, restart=m, fmt="fp64", tol=0.0, maxiter=it)
-    refm = orc.gmres(A, b, restart=m, fmt="fp64", tol=0.0, maxiter=it, variant=LIB_DEFAULT)
+    refm = orc.gmres(A, b, restart=m, fmt="fp64", tol=0.0, maxiter=it, variant=FIG1)
     assert rm.iterations == refm["iterations"] == it
     xm = rm.x.cpu().numpy()
     # same iteration, different rounding: the gap grows like kappa * steps * u
@@ -106,7 +118,7 @@ def test_solve_parity_compressed(cbg, orc, dev, fmt, name, m):
     it_g, it_o = [], []
     for s in range(NPERT):
         bp = perturbed(b, s)
-        o = orc.gmres(A, bp, restart=m, fmt=fmt, tol=TOL, maxiter=20000, variant=LIB_DEFAULT)
+        o = orc.gmres(A, bp, restart=m, fmt=fmt, tol=TOL, maxiter=20000, variant=FIG1)
         r = cbg.solve(Ad, torch.from_numpy(bp).to(dev), restart=m, fmt=fmt, tol=TOL,
                       maxiter=20000)
         assert o["status"] == 0 and r.status == 0
@@ -115,12 +127,14 @@ def test_solve_parity_compressed(cbg, orc, dev, fmt, name, m):
         assert np.linalg.norm(x - o["x"]) <= 2.05 * TOL * np.linalg.norm(bp) / smin
         it_g.append(r.iterations)
         it_o.append(o["iterations"])
-    mo, mg = np.median(it_o), np.median(it_g)
-    spread = np.percentile(it_o, 90) - np.percentile(it_o, 10)
-    assert abs(mg - mo) <= 0.05 * mo + 0.5 * spread + 2, (sorted(it_g), sorted(it_o))
+    from scipy.stats import mannwhitneyu
+    print(f"  counts GPU {sorted(it_g)}\n  counts oracle {sorted(it_o)}", flush=True)
+    assert abs(np.mean(it_g) - np.mean(it_o)) <= 0.05 * np.mean(it_o)
+    if len(set(it_g + it_o)) > 1:
+        assert mannwhitneyu(it_g, it_o).pvalue >= 1e-3
     # before the stored entries can round differently, the runs coincide
     r = cbg.solve(Ad, torch.from_numpy(b).to(dev), restart=m, fmt=fmt, tol=0.0, maxiter=3)
-    o = orc.gmres(A, b, restart=m, fmt=fmt, tol=0.0, maxiter=3, variant=LIB_DEFAULT)
+    o = orc.gmres(A, b, restart=m, fmt=fmt, tol=0.0, maxiter=3, variant=FIG1)
     xg = r.x.cpu().numpy()
     assert np.linalg.norm(xg - o["x"]) <= 1e-12 * np.linalg.norm(o["x"])
     assert np.allclose(r.hist, o["hist"], rtol=1e-12, atol=0)
@@ -156,15 +170,26 @@ def test_sparse_preconditioner_equal_to_jacobi(cbg, orc, dev):
     diag = A.col_idx == rows
     pv = np.zeros(A.nnz, np.float32)
     pv[diag] = (1.0 / A.val[diag]).astype(np.float32)
-    ref = orc.gmres(A, b, restart=30, fmt="fp16", tol=1e-10, maxiter=5000, precond="sparse",
-                    variant=LIB_DEFAULT,
-                    p_val=pv)
+    ref = orc.gmres(A, b, restart=30, fmt="fp64", tol=1e-10, maxiter=5000, precond="sparse",
+                    variant=FIG1, p_val=pv)
     Ad = cbg.DeviceCSR.from_host(A, dev)
-    r = cbg.solve(Ad, torch.from_numpy(b).to(dev), restart=30, fmt="fp16", tol=1e-10,
-                  maxiter=5000, precond="sparse", p_val=torch.from_numpy(pv).to(dev))
+    pd = torch.from_numpy(pv).to(dev)
+    r = cbg.solve(Ad, torch.from_numpy(b).to(dev), restart=30, fmt="fp64", tol=1e-10,
+                  maxiter=5000, precond="sparse", p_val=pd)
     assert r.status == 0 and ref["status"] == 0
-    assert abs(r.iterations - ref["iterations"]) <= 0.05 * ref["iterations"] + 2
+    assert abs(r.iterations - ref["iterations"]) <= 1
     assert true_res(orc, A, b, r.x.cpu().numpy()) <= 1e-10
+    it = ref["iterations"]
+    rm = cbg.solve(Ad, torch.from_numpy(b).to(dev), restart=30, fmt="fp64", tol=0.0,
+                   maxiter=it, precond="sparse", p_val=pd)
+    om = orc.gmres(A, b, restart=30, fmt="fp64", tol=0.0, maxiter=it, precond="sparse",
+                   variant=FIG1, p_val=pv)
+    xo = om["x"]
+    assert np.linalg.norm(rm.x.cpu().numpy() - xo) <= 1e-8 * np.linalg.norm(xo)
+    # an fp16 basis with the same P reaches the tolerance
+    r16 = cbg.solve(Ad, torch.from_numpy(b).to(dev), restart=30, fmt="fp16", tol=1e-10,
+                    maxiter=5000, precond="sparse", p_val=pd)
+    assert r16.status == 0 and true_res(orc, A, b, r16.x.cpu().numpy()) <= 1e-10
 
 
 def test_sparse_fallback_on_nonfinite(cbg, orc, dev):
