@@ -1960,16 +1960,22 @@ __global__ __launch_bounds__(BLK) void k_stencil(const double *__restrict__ w, i
     for (int64_t q = blockIdx.x * (int64_t)BLK + threadIdx.x; q < npair;
          q += (int64_t)gridDim.x * BLK) {
         const int64_t i0 = 2 * q;
-        int gx[2], gy[2], gz[2];
+        // per row, which of the three offsets along each axis exist; a slot
+        // whose grid point does not exist (or a row >= n) contributes
+        // nothing, and its gather reads an address clamped into [0, n) (no
+        // branch per slot)
         bool live[2];
+        uint32_t mx[2], my[2], mz[2];
 #pragma unroll
         for (int r = 0; r < 2; ++r) {
             const int64_t i = i0 + r;
             live[r] = i < n;
             const uint32_t u = live[r] ? (uint32_t)i : 0u, row = u / (uint32_t)nx;
-            gx[r] = (int)(u - row * (uint32_t)nx);
-            gy[r] = (int)(row % (uint32_t)ny);
-            gz[r] = (int)(row / (uint32_t)ny);
+            const int gx = (int)(u - row * (uint32_t)nx), gy = (int)(row % (uint32_t)ny),
+                      gz = (int)(row / (uint32_t)ny);
+            mx[r] = 2u | (gx > 0 ? 1u : 0u) | (gx < nx - 1 ? 4u : 0u);
+            my[r] = 2u | (gy > 0 ? 1u : 0u) | (gy < ny - 1 ? 4u : 0u);
+            mz[r] = 2u | (gz > 0 ? 1u : 0u) | (gz < nz - 1 ? 4u : 0u);
         }
         double s[2] = {0.0, 0.0};
 #pragma unroll
@@ -1979,13 +1985,11 @@ __global__ __launch_bounds__(BLK) void k_stencil(const double *__restrict__ w, i
             const int64_t off = dz * S + dy * nx + dx;
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
-                const bool in = live[r] && gx[r] + dx >= 0 && gx[r] + dx < nx &&
-                                gy[r] + dy >= 0 && gy[r] + dy < ny && gz[r] + dz >= 0 &&
-                                gz[r] + dz < nz;
-                if (in) {
-                    const double c = (slot == 13 ? 1.0 : 0.0) + dec_f16((cc >> (16 * r)) & 0xFFFFu);
-                    s[r] = fma(c, w[i0 + r + off], s[r]);
-                }
+                const bool in = live[r] && ((mx[r] >> (dx + 1)) & (my[r] >> (dy + 1)) &
+                                            (mz[r] >> (dz + 1)) & 1u);
+                const int64_t idx = min(max(i0 + r + off, (int64_t)0), (int64_t)n - 1);
+                const double c = (slot == 13 ? 1.0 : 0.0) + dec_f16((cc >> (16 * r)) & 0xFFFFu);
+                s[r] = fma(in ? c : 0.0, w[idx], s[r]);
             }
         }
         if constexpr (MODE == ST_ACC) {

@@ -172,6 +172,66 @@ struct CycleEvents {
     }
 };
 
+// Steps of a cycle are enqueued in chunks; after each chunk the cycle's done
+// flag is copied to pinned host memory behind an event. The host reads the
+// flag of the chunk before the one just enqueued, so one chunk always stays
+// queued and the device never waits on the host, while a cycle that ends
+// early (recurrence residual met, breakdown) leaves at most two chunks of
+// launches that find the cycle finished and return at once.
+constexpr int STEP_CHUNK = 16;
+
+struct DoneWatch {
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    int32_t *flag = nullptr;        // pinned: one slot per chunk of a cycle
+    bool ok = false;
+    int pending = -1;               // chunk whose event and flag are unread
+    int create()
+    {
+        // the pinned slots are per host thread and live until the process ends
+        static thread_local int32_t *slots = nullptr;
+        if (!slots && hipHostMalloc((void **)&slots, sizeof(int32_t) * 2,
+                                    hipHostMallocDefault) != hipSuccess) {
+            slots = nullptr;
+            (void)hipGetLastError();
+            return 0;               // no pinned memory: every step is enqueued
+        }
+        for (auto &e : ev)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess)
+                return CBG_E_HIP;
+        flag = slots;
+        ok = true;
+        return 0;
+    }
+    // Called before the step that opens chunk k (k >= 1). Returns 1 when the
+    // cycle was already finished by the end of chunk k - 2, so the caller
+    // stops enqueueing; a negative value is a HIP error.
+    int boundary(int k, const int32_t *done_dev, hipStream_t s)
+    {
+        if (!ok)
+            return 0;
+        const int slot = k & 1;
+        if (hipMemcpyAsync(flag + slot, done_dev, sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
+                hipSuccess ||
+            hipEventRecord(ev[slot], s) != hipSuccess)
+            return -1;
+        int stop = 0;
+        if (pending >= 0) {
+            if (hipEventSynchronize(ev[pending & 1]) != hipSuccess)
+                return -1;
+            stop = flag[pending & 1] != 0;
+        }
+        pending = k;
+        return stop;
+    }
+    void reset() { pending = -1; }
+    ~DoneWatch()
+    {
+        for (auto &e : ev)
+            if (e)
+                (void)hipEventDestroy(e);
+    }
+};
+
 }  // namespace
 
 // The failing HIP call's error code and source line, per host thread, for
@@ -378,6 +438,10 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
     CycleEvents evs;
     if ((prof || prof_spmv) && evs.create(m) != 0)
         return fail(CBG_E_HIP);
+    DoneWatch watch;
+    if (watch.create() != 0)
+        return fail(CBG_E_HIP);
+    int jl = m;                         // steps enqueued in the cycle that ran last
 
     std::vector<double> cyc_hist(m);
     std::vector<int32_t> cyc_flags(m);
@@ -418,7 +482,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
             if (prof) {
                 // every launch of the cycle is timed, including the ones that
                 // found the cycle finished (they move no bytes)
-                for (int j = 1; j <= m; ++j) {
+                for (int j = 1; j <= jl; ++j) {
                     const bool ro = j <= jeff && (cyc_flags[j - 1] & 1);
                     for (int k = 0; k < 4; ++k) {
                         if ((k == 2 && (fused(j) || gram)) || (k == 3 && onepass) ||
@@ -450,7 +514,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                 // else the gather variant, which also stores v_j
                 const bool gather = !norm_pass && prev_pc != CBG_PC_STENCIL &&
                                     prev_pc != CBG_PC_SPARSE && prev_pc != CBG_PC_BLOCK_JACOBI;
-                for (int j = 1; j <= m; ++j) {
+                for (int j = 1; j <= jl; ++j) {
                     float ms;
                     HIP_TRY(hipEventElapsedTime(&ms, evs.at(j, 4, 0), evs.at(j, 4, 1)));
                     res->prof_spmv_ms += ms;
@@ -536,7 +600,18 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
         // The residual r sits in w0 with t = beta; step 1's SpMV forms
         // v_1 = r / beta and stores it as basis vector 1.
         double *cur = W.w0, *nxt = W.w1;
+        watch.reset();
+        jl = m;
         for (int j = 1; j <= m; ++j) {
+            if (j > 1 && (j - 1) % STEP_CHUNK == 0) {
+                const int w = watch.boundary((j - 1) / STEP_CHUNK, &W.st->done, s);
+                if (w < 0)
+                    return fail(CBG_E_HIP);
+                if (w > 0) {
+                    jl = j - 1;
+                    break;
+                }
+            }
             // steps 13-14 of the previous step (v_j = w / t, stored as basis
             // vector j) fused with steps 3-4: w = A M^-1 v_j, omega
             void *slot = W.V + (size_t)(j - 1) * vbytes;
@@ -644,6 +719,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                 o.role = 6 /*U_CGS2*/; o.u = W.u; o.stw = W.st; o.G = W.G;
                 launch_update(o, s);
                 o.role = 7 /*U_HARD*/;
+                o.ev0 = o.ev1 = nullptr;        // the events belong to the update above
                 launch_update(o, s);
                 launch_reduce(W.red, RR_C2, nb_orth, 0, j, W.st, sa, nullptr, fmt, s);
                 double *t = cur;
