@@ -292,6 +292,20 @@ int cbg_multidot(int32_t format, const void *V, int64_t ld, const double *scales
                  int32_t n, int32_t j, const double *w, double *h, void *ws,
                  size_t ws_bytes, void *stream);
 
+/* cbg_multidot for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and results, with the block partials in a fixed array of this
+ * library on each GPU (CBG_NOALLOC_MAX_J + 4 rows of 4096 doubles, about
+ * 4.3 MB per GPU, held until the process ends, located once per device)
+ * instead of a workspace argument.  Allocates nothing and records no memset.
+ * j > CBG_NOALLOC_MAX_J returns CBG_E_UNSUPPORTED before any HIP call.  All
+ * calls on one GPU share its array: calls that overlap in time on one GPU
+ * (different streams, or host threads without ordering) race and must not
+ * be issued. */
+#define CBG_NOALLOC_MAX_J 128
+int cbg_multidot_noalloc(int32_t format, const void *V, int64_t ld, const double *scales,
+                         int32_t n, int32_t j, const double *w, double *h, void *stream);
+
 /* Update of step 5: w -= sum_k h_k dec(V_k), then norms[0] = ||w||_2 and
  * norms[1] = ||w||_inf (Section 5.2: both norms in one pass).
  * norms [dev, nullable] 2 doubles. */

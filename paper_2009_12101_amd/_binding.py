@@ -59,7 +59,7 @@ def variant_flags(names) -> int:
 
 EXPORTS = ["cbg_strerror", "cbg_last_hip_error", "cbg_basis_ld", "cbg_workspace_bytes", "cbg_kernel_workspace_bytes",
            "cbg_workspace_basis", "cbgmres_solve", "cbg_encode", "cbg_decode", "cbg_spmv",
-           "cbg_multidot", "cbg_update", "cbg_update_redot",
+           "cbg_multidot", "cbg_multidot_noalloc", "cbg_update", "cbg_update_redot",
            "cbg_block_jacobi_setup",
            "cbg_block_jacobi_apply", "cbg_spai_workspace_bytes", "cbg_spai_features", "cbg_mlp_forward",
            "cbg_spai_assemble", "cbg_learned_build", "cbg_learned_build_stencil",
@@ -138,6 +138,7 @@ def lib():
         L.cbg_decode.argtypes = [i32, vp, vp, i32, vp, vp]
         L.cbg_spmv.argtypes = [C.POINTER(CbgCsr), vp, vp, vp, vp, sz, vp]
         L.cbg_multidot.argtypes = [i32, vp, i64, vp, i32, i32, vp, vp, vp, sz, vp]
+        L.cbg_multidot_noalloc.argtypes = [i32, vp, i64, vp, i32, i32, vp, vp, vp]
         L.cbg_update.argtypes = [i32, vp, i64, vp, i32, i32, vp, vp, vp, vp, sz, vp]
         L.cbg_update_redot.argtypes = [i32, vp, i64, vp, i32, i32, vp, vp, vp, vp, vp, sz, vp]
         L.cbg_block_jacobi_setup.argtypes = [C.POINTER(CbgCsr), i32, i32, vp, vp, vp, vp, vp, sz,
@@ -163,6 +164,7 @@ def lib():
         L.cbg_spai_round_weights.argtypes = [vp, vp, vp]
         L.cbg_adam_step.argtypes = [vp, vp, vp, vp, vp, i64, f64, f64, f64, f64, vp]
         for f in ("cbgmres_solve", "cbg_encode", "cbg_decode", "cbg_spmv", "cbg_multidot",
+                  "cbg_multidot_noalloc",
                   "cbg_update", "cbg_update_redot", "cbg_block_jacobi_setup",
                   "cbg_block_jacobi_apply", "cbg_workspace_basis", "cbg_spai_features", "cbg_mlp_forward",
                   "cbg_spai_assemble", "cbg_learned_build", "cbg_learned_build_stencil",
@@ -479,6 +481,21 @@ def multidot(fmt: str, V, ld: int, scales, n: int, j: int, w, h=None, ws=None):
     _need(ws, "ws", torch.uint8, kernel_workspace_bytes(n, j), w.device)
     _check(lib().cbg_multidot(FORMATS[fmt], _ptr(V), ld, _ptr(scales), n, j, _ptr(w), _ptr(h),
                               _ptr(ws), ws.numel(), _stream()), "cbg_multidot")
+    return h[:j]
+
+
+NOALLOC_MAX_J = 128
+
+
+def multidot_noalloc(fmt: str, V, ld: int, scales, n: int, j: int, w, h):
+    """cbg_multidot_noalloc: h[:j] = V^T w with the library's own per-GPU
+    scratch array (no workspace argument; h is the caller's)."""
+    torch = _torch()
+    _need(w, "w", torch.float64, n)
+    _check_basis(fmt, V, ld, scales, n, j, w.device)
+    _need(h, "h", torch.float64, j, w.device)
+    _check(lib().cbg_multidot_noalloc(FORMATS[fmt], _ptr(V), ld, _ptr(scales), n, j, _ptr(w),
+                                      _ptr(h), _stream()), "cbg_multidot_noalloc")
     return h[:j]
 
 

@@ -2467,6 +2467,19 @@ void launch_clear_flags(DevState *st, unsigned *bad, hipStream_t s)
     k_clear_flags<<<1, 64, 0, s>>>(st, bad);
 }
 
+// p[0 .. count) = 0 with a kernel (no memset node where a caller captures)
+__global__ void k_fill_zero(double *p, int count)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+void launch_fill_zero(double *p, int count, hipStream_t s)
+{
+    if (count > 0)
+        k_fill_zero<<<grid_for(count, 256), 256, 0, s>>>(p, count);
+}
+
 void launch_backsolve(const DevState *st, const void *sa, hipStream_t s)
 {
     k_backsolve<<<1, 64, 0, s>>>(st, *(const StepArrays *)sa);

@@ -128,6 +128,7 @@ void launch_init_state(DevState *st, int n, int m, int fmt, double tol, double e
 void launch_jacobi_setup(int n, int64_t ld, const int32_t *rp, const int32_t *ci,
                          const double *val, double *dinv, unsigned *bad, hipStream_t s);
 void launch_clear_flags(DevState *st, unsigned *bad, hipStream_t s);
+void launch_fill_zero(double *p, int count, hipStream_t s);
 void launch_backsolve(const DevState *st, const void *sa, hipStream_t s);
 size_t step_arrays_size();
 void make_step_arrays(void *out, double *H, double *h, double *u, double *cs, double *sn,

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <vector>
 
 #include "../../include/cbgmres.h"
@@ -901,6 +902,81 @@ int cbg_multidot(int32_t format, const void *V, int64_t ld, const double *scales
     OrthArgs o{};
     o.fmt = format; o.V = V; o.ld = ld; o.scales = scales; o.n = n; o.j = j; o.w = w;
     o.ws = kernel_red(ws, j);
+    launch_multidot(o, s);
+    launch_reduce(o.ws, RR_VALUES, orth_grid(format, n), 0, j, nullptr, nullptr, h, format, s);
+    HIP_TRY(hipGetLastError());
+    return CBG_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------
+// The multi-dot without a workspace argument: its block partials live in a
+// fixed device array of this library, one per GPU (each device holds its own
+// copy at its own address, found once per device with hipGetSymbolAddress).
+// ------------------------------------------------------------------------
+
+namespace {
+
+// the workspace layout of the kernel-level calls at the largest j: j + 2
+// rows of multi-dot partials, then the SpMV's two rows
+constexpr int NOALLOC_ROWS = CBG_NOALLOC_MAX_J + 4;
+constexpr size_t NOALLOC_DOUBLES = (size_t)NOALLOC_ROWS * MAX_GRID;
+__device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+double *g_scratch_ptr[NOALLOC_MAX_DEVICES];
+std::mutex g_scratch_mu;
+
+// This device's copy of `scratch` (a device address; the array's name in
+// host code is only a host-side stand-in), or nullptr after a HIP error.
+double *scratch_on_current_device()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) {
+            note_hip_error(e, __LINE__);
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+int cbg_multidot_noalloc(int32_t format, const void *V, int64_t ld, const double *scales,
+                         int32_t n, int32_t j, const double *w, double *h, void *stream)
+{
+    if (!basis_args_ok(format, V, ld, scales, n, j) || (j > 0 && !h) ||
+        (n > 0 && (!w || !aligned16(w))))
+        return CBG_E_ARG;
+    if (j > CBG_NOALLOC_MAX_J)
+        return CBG_E_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    if (j == 0)
+        return CBG_OK;
+    if (n == 0) {
+        launch_fill_zero(h, j, s);
+        HIP_TRY(hipGetLastError());
+        return CBG_OK;
+    }
+    double *base = scratch_on_current_device();
+    if (!base)
+        return CBG_E_HIP;
+    OrthArgs o{};
+    o.fmt = format; o.V = V; o.ld = ld; o.scales = scales; o.n = n; o.j = j; o.w = w;
+    o.ws.orth = base;          // rows 0 .. j-1: the block partials of h
+    o.ws.spmv = base + (size_t)(j + 2) * MAX_GRID;
+    o.ws.stride = MAX_GRID;
     launch_multidot(o, s);
     launch_reduce(o.ws, RR_VALUES, orth_grid(format, n), 0, j, nullptr, nullptr, h, format, s);
     HIP_TRY(hipGetLastError());
