@@ -27,9 +27,10 @@ Prints one JSON line.  `value` is the headline solve's time to solution
 (seconds, lower is better).  `roofline` covers the dominant kernel of the
 configuration, HIP events recorded at each launch's own start and end in
 the timed solves: the multi-dot h = V^T w with the Gram row on D1/D2 (bytes
-j n b_s + 8 n + n b_s per launch), the step SpMV with A on D3-D5 (12 nnz +
-4 (n+1) + 16 n: values, column indices, row pointers, the gathered input
-and the output).  `cpu_baseline` times the CPU oracle (Fig. 1 as written, on
+j n b_s + 8 n + n b_s per launch), the step SpMV with A on D3-D5, which
+reads the sliced-ELL copy of A (12 e + 8 (n/64 + 1) + 16 n: values and
+columns of the e stored entries, slice offsets, the gathered input and the
+output; 12 nnz + 4 (n+1) + 16 n on the CSR arrays).  `cpu_baseline` times the CPU oracle (Fig. 1 as written, on
 the host cores) on the same system: the whole solve where it fits the
 sample budget, else a stated number of steps scaled to the GPU's count.
 `--trace-summary` and `--pmc-summary` turn rocprofv3 outputs of these runs
@@ -117,7 +118,7 @@ def kernel_pattern(cfg: Config) -> str:
     """Substring of the roofline kernel's name in rocprofv3 outputs."""
     if cfg.kernel == "multidot":
         return f"k_multidot<{FMT_ID[cfg.fmt]}, true>"
-    return "k_spmv"                 # the step SpMV (the only SpMV of a D3-D5 step)
+    return "k_spmv_sell<0, true>"   # the step SpMV on the sliced-ELL copy (27-point rows)
 
 
 def pmc_summary(fetch_csv: str, write_csv: str, cfg: Config) -> dict:
@@ -182,8 +183,20 @@ def trace_summary(trace_csv: str, cfg: Config) -> dict:
             spmv[r["Kernel_Name"]] = spmv.get(r["Kernel_Name"], 0) + 1
     step_spmv = max(spmv, key=spmv.get)
     targs = step_spmv.split("<", 1)[1].split(">", 1)[0].split(",")
-    gather = (int(targs[-1]) & 8) != 0           # an Arnoldi-step mode: stores v_j too
-    sp_bytes = 12.0 * nnz + 4.0 * (n + 1) + 16.0 * n + (n * bs if gather else 0.0)
+    sell = "k_spmv_sell" in step_spmv
+    # the mode is the first template argument of the sliced-ELL kernel, the
+    # last of the CSR ones
+    mode = int(targs[0] if sell else targs[-1])
+    gather = (mode & 8) != 0                     # an Arnoldi-step mode: stores v_j too
+    if sell:
+        import numpy as np
+        lens = np.zeros(-(-n // 64) * 64, dtype=np.int64)
+        lens[:n] = np.diff(A.row_ptr)
+        entries = 64 * int(lens.reshape(-1, 64).max(axis=1).sum())
+        sp_bytes = 12.0 * entries + 8.0 * (len(lens) // 64 + 1) + 16.0 * n
+    else:
+        sp_bytes = 12.0 * nnz + 4.0 * (n + 1) + 16.0 * n
+    sp_bytes += n * bs if gather else 0.0
     kernels[step_spmv] = lambda j: sp_bytes
     out = {"config": cfg.key, "format": cfg.fmt, "kernels": {}}
     for key, model in kernels.items():
@@ -268,6 +281,8 @@ def main() -> int:
                     help="host processes generating the training matrices")
     ap.add_argument("--explicit-redot", action="store_true",
                     help="ablation: steps 5-10 in Fig. 1's explicit form")
+    ap.add_argument("--csr", action="store_true",
+                    help="ablation: the SpMV on A's CSR arrays (no sliced-ELL copy)")
     ap.add_argument("--no-compare", action="store_true",
                     help="time the headline solves only (no all-kernel solve, no comparison "
                          "solves): the command a kernel-trace profile of the roofline kernel "
@@ -350,7 +365,7 @@ def main() -> int:
     t0 = time.time()
     A, b = build_system(cfg, P)
     log(f"generated {cfg.system} {cfg.grid}: n={A.n} nnz={A.nnz} in {time.time() - t0:.1f}s")
-    Ad = cbg.DeviceCSR.from_host(A, dev)
+    Ad = cbg.DeviceCSR.from_host(A, dev, sell=False if args.csr else "auto")
     bd = torch.from_numpy(b).to(dev)
     m, tol, maxiter = cfg.restart, 1e-10, 20000
     pcs = {("stencil" if pc == "learned" else pc) for _, pc in cfg.compare + [(cfg.fmt,
@@ -399,7 +414,8 @@ def main() -> int:
         k_ms = sum(r.prof_spmv_ms for r in results)
         k_bytes = sum(r.prof_spmv_bytes for r in results)
         k_launch = sum(r.prof_spmv_launches for r in results)
-        k_name = "k_spmv (the Arnoldi step's SpMV with A)"
+        k_name = ("k_spmv_sell (the Arnoldi step's SpMV with A, sliced-ELL copy)"
+                  if Ad.sell_col is not None else "k_spmv (the Arnoldi step's SpMV with A)")
     achieved = k_bytes / (k_ms * 1e-3) / 1e9 if k_ms > 0 else 0.0
     x = r0.x.cpu().numpy()
     S = A.to_scipy()
@@ -491,6 +507,8 @@ def main() -> int:
                    "preconditioner": ("learned, stored form (float16 corrections on the "
                                       "27-point slots), build included" if cfg.precond ==
                                       "learned" else cfg.precond),
+                   "matrix_storage": ("sliced ELL (SELL-64) beside CSR"
+                                      if Ad.sell_col is not None else "CSR"),
                    "arithmetic": "fp64", "parallelism": "single GPU"},
         "iterations": r0.iterations, "restarts": r0.restarts, "reorths": r0.reorths,
         "true_rel_res": res_check,

@@ -73,7 +73,23 @@ enum {
 };
 
 /* CSR matrix, 0-based, column indices sorted within each row.
- * row_ptr [dev] n+1 int32; col_idx [dev] nnz int32; val [dev] nnz double. */
+ * row_ptr [dev] n+1 int32; col_idx [dev] nnz int32; val [dev] nnz double.
+ *
+ * Optional sliced-ELL copy of the same matrix (SELL-64; built by
+ * cbg_sell_ptr + cbg_sell_fill), used by the SpMV with A (Fig. 1 steps 1, 3
+ * and 18) when sell_ptr, sell_col and sell_val are all non-NULL; NULL
+ * selects the CSR kernels.  Rows are grouped in slices of CBG_SELL_SLICE = 64
+ * consecutive rows; slice s stores width_s entries per row, width_s the
+ * longest row of the slice, column-major: entry k of row 64 s + r (k-th
+ * nonzero in CSR order) sits at sell_ptr[s] + 64 k + r.  Entries beyond a
+ * row's length, and the rows >= n of the last slice, hold value 0 and
+ * column min(row, n - 1).  sell_ptr [dev] (n + 63) / 64 + 1 int64 (offsets,
+ * sell_ptr[0] = 0); sell_col [dev] int32 and sell_val [dev] double, each
+ * sell_entries = sell_ptr[last] long.  Each row's products are summed in
+ * CSR order with separately rounded products and sums, so y = A x equals
+ * the row-sequential CSR sum bit for bit (for finite x; a padding entry
+ * multiplies x at the row's own index by 0).  The CSR arrays stay required:
+ * the preconditioner set-ups and the sparse-P products read them. */
 typedef struct {
     int32_t n;
     int32_t reserved;
@@ -81,7 +97,13 @@ typedef struct {
     const int32_t *row_ptr;
     const int32_t *col_idx;
     const double *val;
+    const int64_t *sell_ptr;
+    const int32_t *sell_col;
+    const double *sell_val;
+    int64_t sell_entries;
 } cbg_csr;
+
+#define CBG_SELL_SLICE 64
 
 /* Solver options.  restart: m of Fig. 1 (1 .. CBG_MAX_RESTART).  tol: tau of
  * the stop test ||b - A x||_2 <= tau ||b||_2 (Section 3).  maxiter: limit on
@@ -279,8 +301,22 @@ int cbg_encode(int32_t format, const double *v, int32_t n, void *q, double *scal
 int cbg_decode(int32_t format, const void *q, const double *scale, int32_t n, double *v,
                void *stream);
 
+/* Sliced-ELL copy of A (see cbg_csr), first half: sell_ptr [dev]
+ * (n + 63) / 64 + 1 int64 receives the slice offsets and *entries [host] the
+ * total number of entries (sell_ptr's last value; the call synchronises the
+ * stream).  Reads A's CSR arrays only.  The caller sizes sell_col and
+ * sell_val from *entries (entries / nnz - 1 is the padding; the caller may
+ * keep the CSR kernels when it is large). */
+int cbg_sell_ptr(const cbg_csr *A, int64_t *sell_ptr, int64_t *entries, void *stream);
+
+/* Second half: fills sell_col [dev] and sell_val [dev] (entries long, from
+ * cbg_sell_ptr) from A's CSR arrays and sell_ptr. */
+int cbg_sell_fill(const cbg_csr *A, const int64_t *sell_ptr, int32_t *sell_col,
+                  double *sell_val, void *stream);
+
 /* y = A x (step 3); if norm2 [dev, nullable] is given, *norm2 = ||y||_2
- * (step 4).  x [dev] n doubles, y [dev] n doubles. */
+ * (step 4).  x [dev] n doubles, y [dev] n doubles.  With A's sliced-ELL
+ * copy present, y equals the row-sequential CSR sum bit for bit. */
 int cbg_spmv(const cbg_csr *A, const double *x, double *y, double *norm2, void *ws,
              size_t ws_bytes, void *stream);
 

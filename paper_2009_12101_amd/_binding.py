@@ -60,6 +60,7 @@ def variant_flags(names) -> int:
 EXPORTS = ["cbg_strerror", "cbg_last_hip_error", "cbg_basis_ld", "cbg_workspace_bytes", "cbg_kernel_workspace_bytes",
            "cbg_workspace_basis", "cbgmres_solve", "cbg_encode", "cbg_decode", "cbg_spmv",
            "cbg_multidot", "cbg_multidot_noalloc", "cbg_update", "cbg_update_redot",
+           "cbg_sell_ptr", "cbg_sell_fill",
            "cbg_block_jacobi_setup",
            "cbg_block_jacobi_apply", "cbg_spai_workspace_bytes", "cbg_spai_features", "cbg_mlp_forward",
            "cbg_spai_assemble", "cbg_learned_build", "cbg_learned_build_stencil",
@@ -72,7 +73,9 @@ SPAI_NPARAM, SPAI_NWEIGHT, SPAI_MAX_K = 10400, 10240, 32
 
 class CbgCsr(C.Structure):
     _fields_ = [("n", C.c_int32), ("reserved", C.c_int32), ("nnz", C.c_int64),
-                ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("val", C.c_void_p)]
+                ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("val", C.c_void_p),
+                ("sell_ptr", C.c_void_p), ("sell_col", C.c_void_p), ("sell_val", C.c_void_p),
+                ("sell_entries", C.c_int64)]
 
 
 class CbgOpts(C.Structure):
@@ -137,6 +140,8 @@ def lib():
         L.cbg_encode.argtypes = [i32, vp, i32, vp, vp, vp, sz, vp]
         L.cbg_decode.argtypes = [i32, vp, vp, i32, vp, vp]
         L.cbg_spmv.argtypes = [C.POINTER(CbgCsr), vp, vp, vp, vp, sz, vp]
+        L.cbg_sell_ptr.argtypes = [C.POINTER(CbgCsr), vp, C.POINTER(i64), vp]
+        L.cbg_sell_fill.argtypes = [C.POINTER(CbgCsr), vp, vp, vp, vp]
         L.cbg_multidot.argtypes = [i32, vp, i64, vp, i32, i32, vp, vp, vp, sz, vp]
         L.cbg_multidot_noalloc.argtypes = [i32, vp, i64, vp, i32, i32, vp, vp, vp]
         L.cbg_update.argtypes = [i32, vp, i64, vp, i32, i32, vp, vp, vp, vp, sz, vp]
@@ -164,7 +169,7 @@ def lib():
         L.cbg_spai_round_weights.argtypes = [vp, vp, vp]
         L.cbg_adam_step.argtypes = [vp, vp, vp, vp, vp, i64, f64, f64, f64, f64, vp]
         for f in ("cbgmres_solve", "cbg_encode", "cbg_decode", "cbg_spmv", "cbg_multidot",
-                  "cbg_multidot_noalloc",
+                  "cbg_multidot_noalloc", "cbg_sell_ptr", "cbg_sell_fill",
                   "cbg_update", "cbg_update_redot", "cbg_block_jacobi_setup",
                   "cbg_block_jacobi_apply", "cbg_workspace_basis", "cbg_spai_features", "cbg_mlp_forward",
                   "cbg_spai_assemble", "cbg_learned_build", "cbg_learned_build_stencil",
@@ -267,33 +272,92 @@ def _check(rc: int, where: str):
     return rc
 
 
+SELL_SLICE = 64
+# the sliced-ELL copy is kept when its padding is at most this fraction of nnz
+SELL_MAX_PADDING = 0.25
+
+
 @dataclasses.dataclass
 class DeviceCSR:
-    """A CSR matrix resident in device memory (int32 indices, fp64 values)."""
+    """A CSR matrix resident in device memory (int32 indices, fp64 values),
+    with an optional sliced-ELL copy (SELL-64, cbg_sell_ptr / cbg_sell_fill)
+    that the SpMV with A reads when present."""
     n: int
     nnz: int
     row_ptr: "object"
     col_idx: "object"
     val: "object"
+    sell_ptr: "object" = None
+    sell_col: "object" = None
+    sell_val: "object" = None
 
     @classmethod
-    def from_host(cls, A, device="cuda"):
+    def from_host(cls, A, device="cuda", sell="auto"):
+        """Copy a host CSR matrix to the GPU.  sell: "auto" builds the
+        sliced-ELL copy unless its padding exceeds SELL_MAX_PADDING of nnz;
+        True builds it regardless; False keeps the CSR kernels."""
         torch = _torch()
         rp = torch.from_numpy(np.ascontiguousarray(A.row_ptr, dtype=np.int32)).to(device)
         ci = torch.from_numpy(np.ascontiguousarray(A.col_idx, dtype=np.int32)).to(device)
         va = torch.from_numpy(np.ascontiguousarray(A.val, dtype=np.float64)).to(device)
-        return cls(int(A.n), int(A.nnz), rp, ci, va)
+        D = cls(int(A.n), int(A.nnz), rp, ci, va)
+        if sell and D.n > 0 and (sell is True or D.val.device.type == "cuda"):
+            D.build_sell(max_padding=None if sell is True else SELL_MAX_PADDING)
+        return D
+
+    def build_sell(self, max_padding=None):
+        """Build the sliced-ELL copy on the GPU (kept only if its padding is
+        at most max_padding of nnz, when given).  Returns self."""
+        torch = _torch()
+        self.drop_sell()
+        dev = self.val.device
+        nslice = (self.n + SELL_SLICE - 1) // SELL_SLICE
+        sp = torch.empty(nslice + 1, dtype=torch.int64, device=dev)
+        ent = C.c_int64(0)
+        csr = self.cstruct()
+        _check(lib().cbg_sell_ptr(C.byref(csr), _ptr(sp), C.byref(ent), _stream()),
+               "cbg_sell_ptr")
+        entries = int(ent.value)
+        if max_padding is not None and entries > (1.0 + max_padding) * max(self.nnz, 1):
+            return self
+        sc = torch.empty(max(entries, 1), dtype=torch.int32, device=dev)
+        sv = torch.empty(max(entries, 1), dtype=torch.float64, device=dev)
+        _check(lib().cbg_sell_fill(C.byref(csr), _ptr(sp), _ptr(sc), _ptr(sv), _stream()),
+               "cbg_sell_fill")
+        self.sell_ptr, self.sell_col, self.sell_val = sp, sc[:entries], sv[:entries]
+        return self
+
+    def drop_sell(self):
+        """Forget the sliced-ELL copy (the CSR kernels run).  Returns self."""
+        self.sell_ptr = self.sell_col = self.sell_val = None
+        return self
+
+    @property
+    def sell_entries(self) -> int:
+        return 0 if self.sell_col is None else int(self.sell_col.numel())
 
     def check(self):
         """Raise ValueError unless the arrays match n and nnz (int32 indices,
-        fp64 values, contiguous, one GPU)."""
+        fp64 values, contiguous, one GPU), and the sliced-ELL arrays, if any,
+        match each other."""
         torch = _torch()
         if self.n < 0 or self.nnz < 0:
             raise ValueError(f"CSR: n = {self.n}, nnz = {self.nnz}")
         dev = self.val.device
-        arrays = ((self.row_ptr, "A.row_ptr", torch.int32, self.n + 1),
+        arrays = [(self.row_ptr, "A.row_ptr", torch.int32, self.n + 1),
                   (self.col_idx, "A.col_idx", torch.int32, self.nnz),
-                  (self.val, "A.val", torch.float64, self.nnz))
+                  (self.val, "A.val", torch.float64, self.nnz)]
+        sell = (self.sell_ptr, self.sell_col, self.sell_val)
+        if any(t is not None for t in sell):
+            if any(t is None for t in sell):
+                raise ValueError("A.sell_*: the sliced-ELL arrays are all given or none")
+            ent = self.sell_entries
+            if ent < self.nnz or ent % SELL_SLICE:
+                raise ValueError(f"A.sell_col: {ent} entries for nnz = {self.nnz}")
+            arrays += [(self.sell_ptr, "A.sell_ptr", torch.int64,
+                        (self.n + SELL_SLICE - 1) // SELL_SLICE + 1),
+                       (self.sell_col, "A.sell_col", torch.int32, ent),
+                       (self.sell_val, "A.sell_val", torch.float64, ent)]
         for gpu in (False, True):           # shapes first, then the device
             for t, nm, dt, cnt in arrays:
                 _need(t, nm, dt, cnt, dev, exact=True, gpu=gpu)
@@ -301,8 +365,12 @@ class DeviceCSR:
 
     def cstruct(self) -> CbgCsr:
         self.check()
+        if self.sell_col is None:
+            return CbgCsr(self.n, 0, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(),
+                          self.val.data_ptr(), None, None, None, 0)
         return CbgCsr(self.n, 0, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(),
-                      self.val.data_ptr())
+                      self.val.data_ptr(), self.sell_ptr.data_ptr(), self.sell_col.data_ptr(),
+                      self.sell_val.data_ptr(), self.sell_entries)
 
 
 @dataclasses.dataclass

@@ -611,6 +611,199 @@ __global__ __launch_bounds__(BLK) void k_spmv_rp(int n, int64_t ldy,
 }
 
 // ---------------------------------------------------------------------------
+// SpMV on the sliced-ELL copy of A (SELL-64; layout in include/cbgmres.h):
+// one wave per slice of 64 rows, lane = row, so the value and column loads
+// of one entry index are 512 and 256 contiguous bytes and, on a stencil
+// matrix, the gather of x at one stencil offset reads 64 consecutive
+// entries.  No LDS and no barrier inside the slice loop.  Each row is summed
+// in CSR order with separately rounded products and sums (floating-point
+// contraction off), the order of the row-sequential CSR sum, so y = A x is
+// that sum bit for bit; a padding entry adds 0 * x_row.  NT: stream the
+// values and columns past the caches (non-temporal loads), which keeps x
+// resident in L2 on long rows.  Modes as k_spmv's, without the sparse-P
+// ones (those read float values on the CSR pattern).
+// ---------------------------------------------------------------------------
+
+template <int MODE>
+__device__ __forceinline__ double sell_x(int c, const double *__restrict__ x,
+                                         const double *__restrict__ dinv, double tdiv, int fmt,
+                                         EncParam ep)
+{
+#pragma clang fp contract(off)
+    double xv = x[c];
+    if constexpr (sp_step(MODE))
+        xv = xv / tdiv;
+    if constexpr (sp_quant(MODE))
+        xv = quantize(fmt, xv, ep);
+    if constexpr ((MODE & 7) == SP_JACOBI)
+        xv = dinv[c] * xv;
+    return xv;
+}
+
+template <bool NT, typename T>
+__device__ __forceinline__ T sell_ld(const T *p)
+{
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+constexpr int SELL_UNR = 9;      // entries per row in flight (a third of a 27-point row)
+
+template <int MODE, bool NT>
+__global__ __launch_bounds__(BLK) void k_spmv_sell(
+    int n, int64_t ldy, int64_t nslice, const int64_t *__restrict__ sp,
+    const int32_t *__restrict__ sc, const double *__restrict__ sv, const double *__restrict__ x,
+    const double *__restrict__ dinv, const double *__restrict__ b, double *__restrict__ y,
+    RedArgs ra, int role, const DevState *st, uint8_t *__restrict__ Q,
+    const double *__restrict__ qscale, int fmt)
+{
+#pragma clang fp contract(off)
+    if (st && role != SR_FREE && st->done)
+        return;
+    double tdiv = 1.0;
+    EncParam ep{1.0, 0};
+    if constexpr (sp_step(MODE)) {
+        tdiv = st->t;
+        ep = param_from_scale(fmt, *qscale);
+    }
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t nsy = (ldy + 63) / 64;        // slices of rows to write (>= nslice)
+    double ssq = 0.0, mx = 0.0;
+    for (int64_t s = (int64_t)blockIdx.x * NWAVE + wv; s < nsy;
+         s += (int64_t)gridDim.x * NWAVE) {
+        const int64_t row = s * 64 + lane;
+        double acc = 0.0;
+        if (s < nslice) {
+            const int64_t o = sp[s];
+            const int w = (int)((sp[s + 1] - o) >> 6);
+            const int32_t *c = sc + o + lane;
+            const double *v = sv + o + lane;
+            // batches of SELL_UNR entries, every load of a batch in flight
+            // before the first product; a short last batch re-reads entry
+            // w - 1 for its missing slots and adds nothing for them
+            for (int k = 0; k < w; k += SELL_UNR) {
+                int32_t cc[SELL_UNR];
+                double vv[SELL_UNR];
+#pragma unroll
+                for (int u = 0; u < SELL_UNR; ++u) {
+                    const int64_t e = (int64_t)min(k + u, w - 1) * 64;
+                    cc[u] = sell_ld<NT>(c + e);
+                    vv[u] = sell_ld<NT>(v + e);
+                }
+#pragma unroll
+                for (int u = 0; u < SELL_UNR; ++u) {
+                    const double t = vv[u] * sell_x<MODE>(cc[u], x, dinv, tdiv, fmt, ep);
+                    if (k + u < w)
+                        acc = acc + t;
+                }
+            }
+        }
+        if (row < ldy) {
+            if constexpr (sp_step(MODE))
+                store_entry(fmt, Q, row, x[row] / tdiv, ep);   // steps 13-14 for this row
+            double yv;
+            if constexpr ((MODE & 7) == SP_RESID)
+                yv = row < n ? b[row] - acc : 0.0;
+            else
+                yv = row < n ? acc : 0.0;
+            y[row] = yv;
+            ssq += yv * yv;
+            mx = fmax(mx, fabs(yv));
+        }
+    }
+    if (role == SR_NONE)
+        return;
+    block_sum_max(ssq, mx);
+    if (threadIdx.x == 0) {
+        ra.part[blockIdx.x] = ssq;
+        ra.part[(size_t)ra.stride + blockIdx.x] = mx;
+    }
+}
+
+// Set-up of the sliced-ELL copy.  sp[s + 1] = 64 * (longest row of slice
+// s), sp[0] = 0; one wave per slice.
+__global__ __launch_bounds__(BLK) void k_sell_width(int n, const int32_t *__restrict__ rp,
+                                                    int64_t nslice, int64_t *__restrict__ sp)
+{
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    for (int64_t s = (int64_t)blockIdx.x * NWAVE + wv; s < nslice;
+         s += (int64_t)gridDim.x * NWAVE) {
+        const int64_t row = s * 64 + lane;
+        int len = row < n ? rp[row + 1] - rp[row] : 0;
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1)
+            len = max(len, __shfl_xor(len, d));
+        if (lane == 0)
+            sp[s + 1] = 64 * (int64_t)len;
+        if (s == 0 && lane == 0)
+            sp[0] = 0;
+    }
+}
+
+// In-place inclusive scan of sp[1 .. nslice], one block of 1024 threads,
+// 1024 entries per round with the running total carried between rounds.
+constexpr int SCAN_BLK = 1024;
+__global__ __launch_bounds__(SCAN_BLK) void k_sell_scan(int64_t nslice, int64_t *__restrict__ sp)
+{
+    __shared__ int64_t buf[2][SCAN_BLK];
+    __shared__ int64_t carry;
+    const int tid = threadIdx.x;
+    if (tid == 0)
+        carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nslice; base += SCAN_BLK) {
+        const int64_t i = base + tid;
+        int cur = 0;
+        buf[cur][tid] = i < nslice ? sp[1 + i] : 0;
+        __syncthreads();
+        for (int d = 1; d < SCAN_BLK; d <<= 1) {     // Hillis-Steele, double-buffered
+            const int64_t v = buf[cur][tid] + (tid >= d ? buf[cur][tid - d] : 0);
+            buf[cur ^ 1][tid] = v;
+            cur ^= 1;
+            __syncthreads();
+        }
+        const int64_t total = buf[cur][SCAN_BLK - 1];
+        if (i < nslice)
+            sp[1 + i] = carry + buf[cur][tid];
+        __syncthreads();                 // every thread has read carry
+        if (tid == 0)
+            carry += total;
+        __syncthreads();
+    }
+}
+
+// Fills the entries: one wave per slice, lane = row, entry k at
+// sp[s] + 64 k + lane.
+__global__ __launch_bounds__(BLK) void k_sell_fill(int n, const int32_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ ci,
+                                                   const double *__restrict__ val, int64_t nslice,
+                                                   const int64_t *__restrict__ sp,
+                                                   int32_t *__restrict__ sc,
+                                                   double *__restrict__ sv)
+{
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    for (int64_t s = (int64_t)blockIdx.x * NWAVE + wv; s < nslice;
+         s += (int64_t)gridDim.x * NWAVE) {
+        const int64_t row = s * 64 + lane;
+        const int p0 = row < n ? rp[row] : 0;
+        const int len = row < n ? rp[row + 1] - p0 : 0;
+        const int pad = (int)min(row, (int64_t)n - 1);
+        const int64_t o = sp[s];
+        const int w = (int)((sp[s + 1] - o) >> 6);
+        for (int k = 0; k < w; ++k) {
+            const int64_t e = o + (int64_t)k * 64 + lane;
+            sc[e] = k < len ? ci[p0 + k] : pad;
+            sv[e] = k < len ? val[p0 + k] : 0.0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Multi-dot through the accessor: h_k = sum_i dec(V_k)_i w_i, k < j.
 // Each block keeps a tile of w in registers and streams the stored vectors
 // KC at a time.  In full tiles every load of a batch is issued before any
@@ -2173,8 +2366,65 @@ static int spmv_rp_shape(const SpmvArgs &a, hipStream_t s)
     return g;
 }
 
+static int spmv_sell(const SpmvArgs &a, hipStream_t s)
+{
+    const int64_t nsy = (a.ldy + 63) / 64;
+    const int g = grid_for((nsy + NWAVE - 1) / NWAVE, 1);
+    RedArgs ra{a.ws.spmv, a.ws.stride};
+#define CBG_SELL_LAUNCH(M, NT)                                                                 \
+    if (a.ev0)                                                                                 \
+        hipExtLaunchKernelGGL(k_spmv_sell<M, NT>, dim3(g), dim3(BLK), 0, s, a.ev0, a.ev1, 0,   \
+                              a.n, a.ldy, a.nslice, a.sp, a.sc, a.sv, a.x, a.dinv, a.b, a.y,   \
+                              ra, a.role, a.st, (uint8_t *)a.Q, a.qscale, a.fmt);              \
+    else                                                                                       \
+        k_spmv_sell<M, NT><<<g, BLK, 0, s>>>(a.n, a.ldy, a.nslice, a.sp, a.sc, a.sv, a.x,      \
+                                             a.dinv, a.b, a.y, ra, a.role, a.st,               \
+                                             (uint8_t *)a.Q, a.qscale, a.fmt);
+#define CBG_SELL_CASE(M)                                                                       \
+    case M:                                                                                    \
+        if (a.sell_nt) {                                                                       \
+            CBG_SELL_LAUNCH(M, true)                                                           \
+        } else {                                                                               \
+            CBG_SELL_LAUNCH(M, false)                                                          \
+        }                                                                                      \
+        break;
+    switch (a.mode) {
+        CBG_SELL_CASE(SP_PLAIN)
+        CBG_SELL_CASE(SP_JACOBI)
+        CBG_SELL_CASE(SP_RESID)
+        CBG_SELL_CASE(SP_STEP_PLAIN)
+        CBG_SELL_CASE(SP_STEP_JACOBI)
+        CBG_SELL_CASE(SP_STEP_PLAIN_Q)
+        CBG_SELL_CASE(SP_STEP_JACOBI_Q)
+    }
+#undef CBG_SELL_CASE
+#undef CBG_SELL_LAUNCH
+    return g;
+}
+
+bool sell_takes(int mode)
+{
+    const int base = mode & 7;
+    return base == SP_PLAIN || base == SP_JACOBI || base == SP_RESID;
+}
+
+void launch_sell_ptr(int n, const int32_t *rp, int64_t nslice, int64_t *sp, hipStream_t s)
+{
+    k_sell_width<<<grid_for((nslice + NWAVE - 1) / NWAVE, 1), BLK, 0, s>>>(n, rp, nslice, sp);
+    k_sell_scan<<<1, SCAN_BLK, 0, s>>>(nslice, sp);
+}
+
+void launch_sell_fill(int n, const int32_t *rp, const int32_t *ci, const double *val,
+                      int64_t nslice, const int64_t *sp, int32_t *sc, double *sv, hipStream_t s)
+{
+    k_sell_fill<<<grid_for((nslice + NWAVE - 1) / NWAVE, 1), BLK, 0, s>>>(n, rp, ci, val, nslice,
+                                                                           sp, sc, sv);
+}
+
 int launch_spmv(const SpmvArgs &a, hipStream_t s)
 {
+    if (a.sp && sell_takes(a.mode))
+        return spmv_sell(a, s);
     switch (a.sg) {
     case SPMV_R256_C2K: return spmv_shape<256, 2048>(a, s);
     case SPMV_R64_C2K: return spmv_shape<64, 2048>(a, s);

@@ -32,6 +32,12 @@ struct SpmvArgs {
     const double *qscale; // step variants: that slot's scale
     int fmt;              // step variants: storage format
     hipEvent_t ev0, ev1;  // optional: recorded at the kernel's own start and end
+    // optional sliced-ELL copy of A (used when sp is set and the mode allows)
+    const int64_t *sp;
+    const int32_t *sc;
+    const double *sv;
+    int64_t nslice;
+    int sell_nt;          // stream values and columns past the caches (long rows)
 };
 
 struct OrthArgs {
@@ -71,6 +77,10 @@ int spmv_rows(int shape);
 int spmv_grid(int shape, int64_t ldy);
 int orth_grid(int fmt, int64_t n);
 int launch_spmv(const SpmvArgs &a, hipStream_t s);
+bool sell_takes(int mode);                 // modes the sliced-ELL kernel runs
+void launch_sell_ptr(int n, const int32_t *rp, int64_t nslice, int64_t *sp, hipStream_t s);
+void launch_sell_fill(int n, const int32_t *rp, const int32_t *ci, const double *val,
+                      int64_t nslice, const int64_t *sp, int32_t *sc, double *sv, hipStream_t s);
 void launch_multidot(const OrthArgs &a, hipStream_t s);
 void launch_update(const OrthArgs &a, hipStream_t s);
 // Fused update + re-dot with norms (w -= V coef; partials of V^T w, ||w||^2,

@@ -30,6 +30,33 @@ bool valid_format(int f) { return f >= CBG_FP64 && f <= CBG_FP16S; }
 // the preconditioners whose explicit-residual checks may drop them (M = I)
 bool droppable(int pc) { return pc == CBG_PC_SPARSE || pc == CBG_PC_STENCIL; }
 
+bool has_sell(const cbg_csr *A) { return A->sell_ptr && A->sell_col && A->sell_val; }
+
+// the sliced-ELL fields all set or all absent, and the entry count plausible
+bool sell_ok(const cbg_csr *A)
+{
+    const bool any = A->sell_ptr || A->sell_col || A->sell_val;
+    if (!any)
+        return true;
+    return has_sell(A) && A->sell_entries >= A->nnz && A->sell_entries % 64 == 0;
+}
+
+// A's arrays into an SpMV argument block, with the sliced-ELL copy when
+// present (rows longer than 12 entries on average stream it past the caches)
+void set_matrix(SpmvArgs &a, const cbg_csr *A)
+{
+    a.rp = A->row_ptr;
+    a.ci = A->col_idx;
+    a.val = A->val;
+    if (has_sell(A)) {
+        a.sp = A->sell_ptr;
+        a.sc = A->sell_col;
+        a.sv = A->sell_val;
+        a.nslice = ((int64_t)A->n + 63) / 64;
+        a.sell_nt = A->sell_entries > 12 * (int64_t)A->n;
+    }
+}
+
 int64_t basis_ld(int32_t n) { return ((int64_t)n + 255) / 256 * 256; }
 
 size_t red_bytes(int jmax)
@@ -137,9 +164,15 @@ double now_s()
 // Algorithmic HBM bytes (what each kernel must move at least).
 struct ByteModel {
     double n, nnz, bs;
-    // CSR (values, column indices, row pointers), the gathered input and the
-    // output vector
-    double spmv() const { return 12.0 * nnz + 4.0 * (n + 1) + 16.0 * n; }
+    double sell = 0.0;      // entries of the sliced-ELL copy the SpMV reads (0: CSR)
+    // CSR (values, column indices, row pointers), or the sliced-ELL copy
+    // (values, columns, slice offsets), the gathered input and the output
+    // vector
+    double spmv() const
+    {
+        return sell > 0.0 ? 12.0 * sell + 8.0 * (std::floor((n + 63.0) / 64.0) + 1.0) + 16.0 * n
+                          : 12.0 * nnz + 4.0 * (n + 1) + 16.0 * n;
+    }
     // the Arnoldi-step SpMV also stores the previous basis vector
     double spmv_step() const { return spmv() + n * bs; }
     double dot(int j) const { return j * n * bs + 8.0 * n; }
@@ -316,7 +349,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
         res->seconds = now_s() - t_start;
         return code;
     };
-    if (!A || !opt)
+    if (!A || !opt || !sell_ok(A))
         return fail(CBG_E_ARG);
     const int32_t n = A->n, m = opt->restart;
     const int fmt = opt->format, pc0 = opt->precond;
@@ -387,6 +420,8 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
     // steps whose update and re-dot share one basis pass
     auto fused = [&](int j) { return !gram && fuse && fused_takes(fmt, basis_ld(n), j); };
     ByteModel bm{(double)n, (double)A->nnz, (double)fmt_bytes(fmt)};
+    if (has_sell(A))
+        bm.sell = (double)A->sell_entries;
 
     std::vector<unsigned char> sa_buf(step_arrays_size());
     void *sa = sa_buf.data();
@@ -460,7 +495,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
         // ||r|| and max|r_i|; resets the cycle state.
         {
             SpmvArgs a{};
-            a.n = n; a.ldy = ld; a.rp = A->row_ptr; a.ci = A->col_idx; a.val = A->val;
+            a.n = n; a.ldy = ld; set_matrix(a, A);
             a.x = x; a.b = b; a.y = W.w0; a.ws = W.red; a.mode = 2 /*SP_RESID*/;
             a.role = 2 /*SR_FREE*/; a.sg = sg; a.st = W.st;
             const int g = launch_spmv(a, s);
@@ -624,7 +659,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                 launch_stencil(fmt, 0, cur, n, ld, opt->grid, opt->p_stencil, W.dinv, W.z, slot,
                                W.scales + (j - 1), W.st, s);
                 SpmvArgs b2{};
-                b2.n = n; b2.ldy = ld; b2.rp = A->row_ptr; b2.ci = A->col_idx; b2.val = A->val;
+                b2.n = n; b2.ldy = ld; set_matrix(b2, A);
                 b2.x = W.z; b2.y = nxt; b2.ws = W.red; b2.mode = 0 /*SP_PLAIN*/;
                 b2.role = 1 /*SR_STEP*/; b2.sg = sg; b2.st = W.st;
                 b2.ev0 = sev0; b2.ev1 = sev1;
@@ -634,7 +669,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                 launch_bj_apply(n, ld, bj_bs, W.bj_tags, W.bj64, W.bj32, W.bj16, cur, W.z, 0,
                                 W.st, slot, W.scales + (j - 1), fmt, vhat, s);
                 SpmvArgs b2{};
-                b2.n = n; b2.ldy = ld; b2.rp = A->row_ptr; b2.ci = A->col_idx; b2.val = A->val;
+                b2.n = n; b2.ldy = ld; set_matrix(b2, A);
                 b2.x = W.z; b2.y = nxt; b2.ws = W.red; b2.mode = 0 /*SP_PLAIN*/;
                 b2.role = 1 /*SR_STEP*/; b2.sg = sg; b2.st = W.st;
                 b2.ev0 = sev0; b2.ev1 = sev1;
@@ -653,14 +688,14 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                 }
                 launch_spmv(a, s);
                 SpmvArgs b2{};
-                b2.n = n; b2.ldy = ld; b2.rp = A->row_ptr; b2.ci = A->col_idx; b2.val = A->val;
+                b2.n = n; b2.ldy = ld; set_matrix(b2, A);
                 b2.x = W.z; b2.y = nxt; b2.ws = W.red; b2.mode = 0 /*SP_PLAIN*/;
                 b2.role = 1 /*SR_STEP*/; b2.sg = sg; b2.st = W.st;
                 b2.ev0 = sev0; b2.ev1 = sev1;
                 nb_spmv = launch_spmv(b2, s);
             } else {
                 SpmvArgs a{};
-                a.n = n; a.ldy = ld; a.rp = A->row_ptr; a.ci = A->col_idx; a.val = A->val;
+                a.n = n; a.ldy = ld; set_matrix(a, A);
                 a.dinv = W.dinv; a.y = nxt; a.ws = W.red; a.role = 1 /*SR_STEP*/;
                 a.sg = sg; a.st = W.st;
                 const int base = pc == CBG_PC_JACOBI ? 1 /*SP_JACOBI*/ : 0 /*SP_PLAIN*/;
@@ -853,7 +888,7 @@ int cbg_decode(int32_t format, const void *q, const double *scale, int32_t n, do
 int cbg_spmv(const cbg_csr *A, const double *x, double *y, double *norm2, void *ws,
              size_t ws_bytes, void *stream)
 {
-    if (!A || A->n < 0 || A->nnz < 0 ||
+    if (!A || A->n < 0 || A->nnz < 0 || !sell_ok(A) ||
         (A->n > 0 && (!A->row_ptr || !x || !y || (A->nnz > 0 && (!A->col_idx || !A->val)))))
         return CBG_E_ARG;
     if (norm2 && !kernel_ws_ok(ws, ws_bytes, 0))
@@ -865,7 +900,7 @@ int cbg_spmv(const cbg_csr *A, const double *x, double *y, double *norm2, void *
         return CBG_OK;
     }
     SpmvArgs a{};
-    a.n = A->n; a.ldy = A->n; a.rp = A->row_ptr; a.ci = A->col_idx; a.val = A->val; a.x = x;
+    a.n = A->n; a.ldy = A->n; set_matrix(a, A); a.x = x;
     a.y = y; a.mode = 0; a.sg = spmv_shape_of(A->n, A->nnz);
     a.role = norm2 ? 2 /*SR_FREE*/ : 0;
     if (norm2)
@@ -873,6 +908,42 @@ int cbg_spmv(const cbg_csr *A, const double *x, double *y, double *norm2, void *
     const int g = launch_spmv(a, s);
     if (norm2)
         launch_reduce(a.ws, RR_NORM2, 0, g, 0, nullptr, nullptr, norm2, 0, s);
+    HIP_TRY(hipGetLastError());
+    return CBG_OK;
+}
+
+int cbg_sell_ptr(const cbg_csr *A, int64_t *sell_ptr, int64_t *entries, void *stream)
+{
+    if (!A || A->n < 0 || A->nnz < 0 || !sell_ptr || !entries || ((uintptr_t)sell_ptr & 7) ||
+        (A->n > 0 && !A->row_ptr))
+        return CBG_E_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t nslice = ((int64_t)A->n + 63) / 64;
+    *entries = 0;
+    if (nslice == 0) {
+        HIP_TRY(hipMemsetAsync(sell_ptr, 0, sizeof(int64_t), s));
+        HIP_TRY(hipStreamSynchronize(s));
+        return CBG_OK;
+    }
+    launch_sell_ptr(A->n, A->row_ptr, nslice, sell_ptr, s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(entries, sell_ptr + nslice, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return CBG_OK;
+}
+
+int cbg_sell_fill(const cbg_csr *A, const int64_t *sell_ptr, int32_t *sell_col, double *sell_val,
+                  void *stream)
+{
+    if (!A || A->n < 0 || A->nnz < 0 || !sell_ptr ||
+        (A->n > 0 && (!A->row_ptr || !sell_col || !sell_val ||
+                      (A->nnz > 0 && (!A->col_idx || !A->val)))))
+        return CBG_E_ARG;
+    const int64_t nslice = ((int64_t)A->n + 63) / 64;
+    if (nslice == 0)
+        return CBG_OK;
+    launch_sell_fill(A->n, A->row_ptr, A->col_idx, A->val, nslice, sell_ptr, sell_col, sell_val,
+                     (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
     return CBG_OK;
 }

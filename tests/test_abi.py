@@ -122,6 +122,35 @@ def test_kernel_calls_reject_bad_arguments_on_host(L):
     assert L.cbg_spmv(C.byref(bad), vp(16), vp(32), None, None, 0, None) == B.E_ARG
 
 
+def test_sell_arguments_rejected_on_host(L):
+    """The sliced-ELL fields of cbg_csr are all set or all NULL, with an
+    entry count that is a multiple of 64 and at least nnz; the set-up calls
+    check their pointers.  All before any HIP call."""
+    from paper_2009_12101_amd import _binding as B
+    vp = C.c_void_p
+    ent = C.c_int64(-1)
+    A = B.CbgCsr(100, 0, 500, 16, 32, 48)
+    assert L.cbg_sell_ptr(C.byref(A), None, C.byref(ent), None) == B.E_ARG
+    assert L.cbg_sell_ptr(C.byref(A), vp(64), None, None) == B.E_ARG
+    assert L.cbg_sell_ptr(C.byref(A), vp(68), C.byref(ent), None) == B.E_ARG   # misaligned
+    assert L.cbg_sell_ptr(None, vp(64), C.byref(ent), None) == B.E_ARG
+    assert L.cbg_sell_fill(C.byref(A), None, vp(64), vp(128), None) == B.E_ARG
+    assert L.cbg_sell_fill(C.byref(A), vp(64), None, vp(128), None) == B.E_ARG
+    assert L.cbg_sell_fill(C.byref(A), vp(64), vp(64), None, None) == B.E_ARG
+    # partial or implausible sliced-ELL fields: refused by the SpMV and the solve
+    res = B.CbgResult()
+    opts = B.CbgOpts(restart=10, format=2, tol=1e-10, maxiter=100)
+    for fields in ((64, None, None, 512), (64, 80, 96, 100), (64, 80, 96, 448)):
+        Ab = B.CbgCsr(100, 0, 500, 16, 32, 48, *fields)
+        assert L.cbg_spmv(C.byref(Ab), vp(16), vp(32), None, None, 0, None) == B.E_ARG
+        assert L.cbgmres_solve(C.byref(Ab), vp(64), vp(128), C.byref(opts), None, 0, None,
+                               C.byref(res), None, 0) == B.E_ARG
+    # complete fields pass the check (and reach the workspace test)
+    Ag = B.CbgCsr(100, 0, 500, 16, 32, 48, 64, 80, 96, 512)
+    assert L.cbgmres_solve(C.byref(Ag), vp(64), vp(128), C.byref(opts), None, 0, None,
+                           C.byref(res), None, 0) == B.E_WORKSPACE
+
+
 def test_variant_names_map_to_flags():
     """Variant names mean what the oracle's names mean; an empty variant is
     the library default (the Gram-form re-dot with steps 5-10 in one

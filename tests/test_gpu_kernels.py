@@ -112,15 +112,21 @@ def _spmv_bound(A, x):
     return 4 * (np.diff(A.row_ptr).max() + 2) * U * mag
 
 
+@pytest.mark.parametrize("sell", [False, True], ids=["csr", "sell"])
 @pytest.mark.parametrize("name", ["poisson2d_64", "convdiff7_33", "lognormal27_21"])
-def test_spmv_parity(cbg, orc, dev, name):
+def test_spmv_parity(cbg, orc, dev, name, sell):
+    """CSR kernels: within the summation-order bound.  Sliced-ELL copy: the
+    oracle's row-sequential sum bit for bit."""
     from paper_2009_12101_amd import problems as P
     A, _, _ = P.workload(name)
     x = np.random.default_rng(1).standard_normal(A.n)
-    y, nrm = cbg.spmv(cbg.DeviceCSR.from_host(A, dev), torch.from_numpy(x).to(dev),
-                      want_norm=True)
+    D = cbg.DeviceCSR.from_host(A, dev, sell=sell)
+    assert (D.sell_col is not None) == sell
+    y, nrm = cbg.spmv(D, torch.from_numpy(x).to(dev), want_norm=True)
     y = y.cpu().numpy()
     yo = orc.spmv(A, x)
+    if sell:
+        assert np.array_equal(y.view(np.uint64), yo.view(np.uint64))
     assert np.all(np.abs(y - yo) <= _spmv_bound(A, x))
     assert abs(nrm.item() - np.sqrt(orc.dot(yo, yo))) <= 1e-13 * np.linalg.norm(yo)
 
