@@ -100,6 +100,11 @@ CONFIGS = {
 }
 
 
+# Arnoldi steps of the CPU oracle's sample per configuration (about 10-30 s
+# on a 16-thread host share; a whole solve where it needs fewer)
+CPU_STEPS = {"D1": 100000, "D2": 500, "D3": 150, "D4": 150, "D5": 90}
+
+
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -270,9 +275,9 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="D5", choices=sorted(CONFIGS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-steps", type=int, default=400,
+    ap.add_argument("--cpu-steps", type=int, default=None,
                     help="Arnoldi steps of the CPU oracle sample (a whole solve if it needs "
-                         "no more)")
+                         "no more; default sized for 10-30 s of host work per configuration)")
     ap.add_argument("--weights", default=None,
                     help="trained parameters (.npz of LearnedSPAI.save); trained here if absent")
     ap.add_argument("--train-count", type=int, default=256)
@@ -453,7 +458,8 @@ def main() -> int:
     cpu = None
     if not args.no_cpu:
         import oracle
-        steps = max(1, min(args.cpu_steps, r0.iterations + m))
+        cpu_steps = args.cpu_steps if args.cpu_steps is not None else CPU_STEPS[cfg.key]
+        steps = max(1, min(cpu_steps, r0.iterations + m))
         t = time.perf_counter()
         kw = {}
         sample = ""

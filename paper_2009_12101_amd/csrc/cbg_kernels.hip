@@ -2127,11 +2127,19 @@ __global__ __launch_bounds__(BLK) void k_step_normalize(const double *__restrict
 // the Jacobi pass's z bit for bit), and v_j = w / t is stored through the
 // accessor for rows [0, ld) as in k_step_normalize (z written for all ld
 // rows, 0 beyond n).  ST_PLAIN: z = M^-1 w and ST_ACC: z += M^-1 w (the
-// solution update), both for rows < n only.  A thread takes
-// two consecutive rows: one 4-byte load per slot for both rows' codes.
+// solution update), both for rows < n only.
+//
+// A block takes a tile of BLK consecutive rows, one row per thread.  The
+// tile's nine (dy, dz) neighbour lines of w, each BLK + 2 entries (dx = -1
+// .. +1), are staged in LDS first: nine coalesced loads per thread, issued
+// together with the row's 27 code loads, then one barrier.  The slot sums
+// then read LDS only, so a wave has all of its global loads in flight at
+// once instead of waiting on one plane of gathers after another.  Entries
+// outside [0, n) are staged as 0; only absent slots (weight 0) read them.
 enum { ST_STEP = 0, ST_PLAIN = 1, ST_ACC = 2 };
+constexpr int ST_LINE = BLK + 2;
 
-template <int F, int MODE>
+template <int F, int MODE, bool BUF>
 __global__ __launch_bounds__(BLK) void k_stencil(const double *__restrict__ w, int n, int64_t ld,
                                                  int nx, int ny, int nz,
                                                  const uint16_t *__restrict__ codes,
@@ -2148,64 +2156,97 @@ __global__ __launch_bounds__(BLK) void k_stencil(const double *__restrict__ w, i
         t = st->t;
         ep = param_from_scale(F, *scale_slot);
     }
-    const int64_t npair = ld / 2;                     // ld is a multiple of 16
+    __shared__ double lw[9][ST_LINE];
+    const int tid = threadIdx.x;
     const int64_t S = (int64_t)nx * ny;
-    for (int64_t q = blockIdx.x * (int64_t)BLK + threadIdx.x; q < npair;
-         q += (int64_t)gridDim.x * BLK) {
-        const int64_t i0 = 2 * q;
-        // per row, which of the three offsets along each axis exist; a slot
-        // whose grid point does not exist (or a row >= n) contributes
-        // nothing, and its gather reads an address clamped into [0, n) (no
-        // branch per slot)
-        bool live[2];
-        uint32_t mx[2], my[2], mz[2];
+    const int64_t ntiles = (ld + BLK - 1) / BLK;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t r0 = tile * BLK, i = r0 + tid;
+        const bool live = i < n;
+        // every load unconditional, so that all of them are in flight
+        // together; values read for rows >= n or outside the grid only meet
+        // weight 0
+        const int64_t ic = min(i, (int64_t)n - 1);
+        uint32_t cc[27];
+        double lv[9], lt[9];
+        if constexpr (BUF) {
+            // buffer loads: the codes' slot offset in a scalar register
+            // (one vector offset for all 27), and w's line entries outside
+            // [0, n) returned as 0 by the buffer's range check
+            const __amdgpu_buffer_rsrc_t rc =
+                __builtin_amdgcn_make_buffer_rsrc((void *)codes, 0, (int)(27 * ld * 2), BUF_RSRC_W3);
+            const __amdgpu_buffer_rsrc_t rw =
+                __builtin_amdgcn_make_buffer_rsrc((void *)w, 0, (int)((int64_t)n * 8), BUF_RSRC_W3);
+            const uint32_t vo = (uint32_t)ic * 2u;
 #pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            const int64_t i = i0 + r;
-            live[r] = i < n;
-            const uint32_t u = live[r] ? (uint32_t)i : 0u, row = u / (uint32_t)nx;
-            const int gx = (int)(u - row * (uint32_t)nx), gy = (int)(row % (uint32_t)ny),
-                      gz = (int)(row / (uint32_t)ny);
-            mx[r] = 2u | (gx > 0 ? 1u : 0u) | (gx < nx - 1 ? 4u : 0u);
-            my[r] = 2u | (gy > 0 ? 1u : 0u) | (gy < ny - 1 ? 4u : 0u);
-            mz[r] = 2u | (gz > 0 ? 1u : 0u) | (gz < nz - 1 ? 4u : 0u);
-        }
-        double s[2] = {0.0, 0.0};
+            for (int p = 0; p < 27; ++p)
+                cc[p] = __builtin_amdgcn_raw_buffer_load_b16(rc, vo, (int)(p * ld * 2), 0);
 #pragma unroll
-        for (int slot = 0; slot < 27; ++slot) {
-            const int dz = slot / 9 - 1, dy = (slot / 3) % 3 - 1, dx = slot % 3 - 1;
-            const uint32_t cc = *(const uint32_t *)(codes + slot * ld + i0);
-            const int64_t off = dz * S + dy * nx + dx;
-#pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                const bool in = live[r] && ((mx[r] >> (dx + 1)) & (my[r] >> (dy + 1)) &
-                                            (mz[r] >> (dz + 1)) & 1u);
-                const int64_t idx = min(max(i0 + r + off, (int64_t)0), (int64_t)n - 1);
-                const double c = (slot == 13 ? 1.0 : 0.0) + dec_f16((cc >> (16 * r)) & 0xFFFFu);
-                s[r] = fma(in ? c : 0.0, w[idx], s[r]);
+            for (int k = 0; k < 9; ++k) {
+                const int64_t e = r0 + (k / 3 - 1) * S + (k % 3 - 1) * (int64_t)nx - 1 + tid;
+                lv[k] = __builtin_bit_cast(
+                    double, __builtin_amdgcn_raw_buffer_load_b64(rw, (uint32_t)(e * 8), 0, 0));
             }
+            if (tid < ST_LINE - BLK) {              // the lines' last two entries
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    const int64_t e = r0 + (k / 3 - 1) * S + (k % 3 - 1) * (int64_t)nx - 1 + BLK + tid;
+                    lt[k] = __builtin_bit_cast(
+                        double, __builtin_amdgcn_raw_buffer_load_b64(rw, (uint32_t)(e * 8), 0, 0));
+                }
+            }
+        } else {
+            // indices clamped into the arrays
+#pragma unroll
+            for (int p = 0; p < 27; ++p)
+                cc[p] = codes[(int64_t)p * ld + ic];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const int64_t base = r0 + (k / 3 - 1) * S + (k % 3 - 1) * (int64_t)nx - 1;
+                lv[k] = w[min(max(base + tid, (int64_t)0), (int64_t)n - 1)];
+            }
+            if (tid < ST_LINE - BLK) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    const int64_t base = r0 + (k / 3 - 1) * S + (k % 3 - 1) * (int64_t)nx - 1;
+                    lt[k] = w[min(max(base + BLK + tid, (int64_t)0), (int64_t)n - 1)];
+                }
+            }
+        }
+        __syncthreads();                            // lw free from the previous tile
+#pragma unroll
+        for (int k = 0; k < 9; ++k)
+            lw[k][tid] = lv[k];
+        if (tid < ST_LINE - BLK) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k)
+                lw[k][BLK + tid] = lt[k];
+        }
+        // which of the three offsets along each axis exist for this row
+        const uint32_t u = live ? (uint32_t)i : 0u, row = u / (uint32_t)nx;
+        const int gx = (int)(u - row * (uint32_t)nx), gy = (int)(row % (uint32_t)ny),
+                  gz = (int)(row / (uint32_t)ny);
+        const uint32_t mx = 2u | (gx > 0 ? 1u : 0u) | (gx < nx - 1 ? 4u : 0u);
+        const uint32_t my = 2u | (gy > 0 ? 1u : 0u) | (gy < ny - 1 ? 4u : 0u);
+        const uint32_t mz = 2u | (gz > 0 ? 1u : 0u) | (gz < nz - 1 ? 4u : 0u);
+        __syncthreads();                            // the lines are staged
+        double s = 0.0;
+#pragma unroll
+        for (int p = 0; p < 27; ++p) {
+            const int dz = p / 9 - 1, dy = (p / 3) % 3 - 1, dx = p % 3 - 1;
+            const bool in = live && ((mx >> (dx + 1)) & (my >> (dy + 1)) & (mz >> (dz + 1)) & 1u);
+            const double c = (p == 13 ? 1.0 : 0.0) + dec_f16(cc[p]);
+            s = fma(in ? c : 0.0, lw[p / 3][tid + dx + 1], s);
         }
         if constexpr (MODE == ST_ACC) {
-#pragma unroll
-            for (int r = 0; r < 2; ++r)
-                if (live[r])
-                    z[i0 + r] = fma(dinv[i0 + r], s[r], z[i0 + r]);   // as x += dinv .* s
+            if (live)
+                z[i] = fma(dinv[i], s, z[i]);           // as x += dinv .* s
         } else if constexpr (MODE == ST_PLAIN) {
-#pragma unroll
-            for (int r = 0; r < 2; ++r)
-                if (live[r])
-                    z[i0 + r] = dinv[i0 + r] * s[r];
-        } else {
-            const f64x2 d = *(const f64x2 *)(dinv + i0);      // dinv holds 0 beyond n
-            f64x2 o;
-            o.x = live[0] ? d.x * (s[0] / t) : 0.0;
-            o.y = live[1] ? d.y * (s[1] / t) : 0.0;
-            *(f64x2 *)(z + i0) = o;
-            if constexpr (MODE == ST_STEP) {
-                const double a = live[0] ? w[i0] / t : 0.0;
-                const double b = live[1] ? w[i0 + 1] / t : 0.0;
-                store_pair<F>(Q, i0, a, b, ep);
-            }
+            if (live)
+                z[i] = dinv[i] * s;
+        } else if (i < ld) {
+            z[i] = live ? dinv[i] * (s / t) : 0.0;      // dinv holds 0 beyond n
+            store_entry(F, Q, i, live ? lw[4][tid + 1] / t : 0.0, ep);
         }
     }
 }
@@ -2662,18 +2703,30 @@ void launch_stencil(int fmt, int mode, const double *w, int n, int64_t ld, const
                     const uint16_t *codes, const double *dinv, double *z, void *Q,
                     const double *scale_slot, const DevState *st, hipStream_t s)
 {
-    const int g = grid_for((ld / 2 + BLK - 1) / BLK, 1);
-    if (mode == ST_STEP) {
-        CBG_FMT_SWITCH(fmt, (k_stencil<F, ST_STEP><<<g, BLK, 0, s>>>(
-                                w, n, ld, grid[0], grid[1], grid[2], codes, dinv, z,
-                                (uint8_t *)Q, scale_slot, st)))
-    } else if (mode == ST_PLAIN) {
-        k_stencil<F_FP64, ST_PLAIN><<<g, BLK, 0, s>>>(w, n, ld, grid[0], grid[1], grid[2], codes,
-                                                      dinv, z, nullptr, nullptr, nullptr);
-    } else {
-        k_stencil<F_FP64, ST_ACC><<<g, BLK, 0, s>>>(w, n, ld, grid[0], grid[1], grid[2], codes,
-                                                    dinv, z, nullptr, nullptr, nullptr);
+    const int g = grid_for((ld + BLK - 1) / BLK, 1);
+    // buffer loads while the codes' byte range and w's fit the 32-bit
+    // offsets of a buffer resource (ld below about 39.7 million)
+    const bool buf = 27 * ld * 2 <= (int64_t)INT32_MAX - 16;
+#define CBG_ST(B)                                                                              \
+    if (mode == ST_STEP) {                                                                     \
+        CBG_FMT_SWITCH(fmt, (k_stencil<F, ST_STEP, B><<<g, BLK, 0, s>>>(                       \
+                                w, n, ld, grid[0], grid[1], grid[2], codes, dinv, z,           \
+                                (uint8_t *)Q, scale_slot, st)))                                \
+    } else if (mode == ST_PLAIN) {                                                             \
+        k_stencil<F_FP64, ST_PLAIN, B><<<g, BLK, 0, s>>>(w, n, ld, grid[0], grid[1], grid[2],  \
+                                                         codes, dinv, z, nullptr, nullptr,     \
+                                                         nullptr);                             \
+    } else {                                                                                   \
+        k_stencil<F_FP64, ST_ACC, B><<<g, BLK, 0, s>>>(w, n, ld, grid[0], grid[1], grid[2],    \
+                                                       codes, dinv, z, nullptr, nullptr,       \
+                                                       nullptr);                               \
     }
+    if (buf) {
+        CBG_ST(true)
+    } else {
+        CBG_ST(false)
+    }
+#undef CBG_ST
 }
 
 void launch_decode(int fmt, const void *Q, int n, const double *scale, double *v, hipStream_t s)
