@@ -409,7 +409,9 @@ struct DevState {
     double t;           // h_{j+1,j}
     double wmax;        // ||w||_inf after the last orthogonalisation pass
     double last_rec;    // |g_{j+1}| / ||b||
-    double red[4];      // reduction outputs (sum, max, ...)
+    double carry;       // entry j-1 of the new Hessenberg column after the j-1 stored
+                        // rotations (formed by the one-pass update's column block)
+    double pad2[3];
 };
 
 }  // namespace cbg

@@ -108,39 +108,28 @@ struct StepArrays {
     double *G;         // (m+1) x (m+1), row-major: Gram matrix of the stored basis
 };
 
-// Fig. 1 steps 9-12 and the column-by-column Givens update of step 17, run
-// by every thread of a one-block kernel.  Reading of step 12 (the literal
-// test would end every re-orthogonalised cycle): breakdown iff
-// h_{j+1,j} = 0, or the second pass again lost more than a factor eta.
-// The new column (h, plus u after a re-orthogonalisation) meets the j-1
-// stored rotations: rotation i maps the carried entry x to -s_i x + c_i
-// h_{i+1} and writes H_i = c_i x + s_i h_{i+1}.  The carries are the prefix
-// compositions of these affine maps, formed by a block-wide scan (log2 j
-// rounds) instead of a serial chain of j-1 rotations; thread 0 then forms
-// the new rotation and updates g.
-__device__ void finish_step(DevState *st, const StepArrays &a, int j, bool reorth, double t2,
-                            double wmax2)
+// Step 16's first part: the j-1 stored rotations applied to the new column
+// c (c_k, k < j, in LDS).  Rotation i maps the carried entry x to
+// -s_i x + c_i c_{i+1} and writes H_i = c_i x + s_i c_{i+1}.  The carries are
+// the prefix compositions of these affine maps, formed by a block-wide
+// Hillis-Steele scan (log2 j rounds) instead of a serial chain of j-1
+// rotations.  Writes rows 0 .. j-2 of the column to Hc and returns the
+// carry (row j-1 before the new rotation) to every thread.  pa, pb: LDS
+// scratch of 2 x MAX_RESTART doubles each.  Block-uniform call.
+__device__ double rotate_column(const double *c, int j, const double *__restrict__ cs,
+                                const double *__restrict__ sn, double *__restrict__ Hc,
+                                double (*pa)[MAX_RESTART], double (*pb)[MAX_RESTART])
 {
-    __shared__ double lh[MAX_RESTART + 1], lc[MAX_RESTART], ls[MAX_RESTART];
-    __shared__ double pa[2][MAX_RESTART], pb[2][MAX_RESTART];
     const int tid = threadIdx.x, nth = blockDim.x;
     const int jc = j - 1;
-    for (int k = tid; k < j; k += nth)
-        lh[k] = reorth ? a.h[k] + a.u[k] : a.h[k];
-    for (int k = tid; k < jc; k += nth) {
-        lc[k] = a.cs[k];
-        ls[k] = a.sn[k];
-    }
-    __syncthreads();
-    // rotation i as the affine map x -> pa x + pb
     for (int i = tid; i < jc; i += nth) {
-        pa[0][i] = -ls[i];
-        pb[0][i] = lc[i] * lh[i + 1];
+        pa[0][i] = -sn[i];
+        pb[0][i] = cs[i] * c[i + 1];
     }
     __syncthreads();
     int cur = 0;
     for (int d = 1; d < jc; d <<= 1) {
-        // inclusive scan: map i composed after map i - d (Hillis-Steele)
+        // inclusive scan: map i composed after map i - d
         for (int i = tid; i < jc; i += nth) {
             double A = pa[cur][i], B = pb[cur][i];
             if (i >= d) {
@@ -153,14 +142,41 @@ __device__ void finish_step(DevState *st, const StepArrays &a, int j, bool reort
         __syncthreads();
         cur ^= 1;
     }
+    for (int i = tid; i < jc; i += nth) {
+        const double x = i == 0 ? c[0] : fma(pa[cur][i - 1], c[0], pb[cur][i - 1]);
+        Hc[i] = fma(cs[i], x, sn[i] * c[i + 1]);
+    }
+    const double carry = jc == 0 ? c[0] : fma(pa[cur][jc - 1], c[0], pb[cur][jc - 1]);
+    __syncthreads();
+    return carry;
+}
+
+// Fig. 1 steps 9-12 and step 16, run by every thread of a one-block kernel.
+// Reading of step 12 (the literal test would end every re-orthogonalised
+// cycle): breakdown iff h_{j+1,j} = 0, or the second pass again lost more
+// than a factor eta.  The new column (h, plus u after a
+// re-orthogonalisation) meets the j-1 stored rotations (rotate_column), or,
+// with `rotated`, that was done already by the one-pass update's column
+// block (rows 0 .. j-2 in H, the carry in the state); thread 0 then forms
+// the new rotation and updates g.
+__device__ void finish_step(DevState *st, const StepArrays &a, int j, bool reorth, double t2,
+                            double wmax2, bool rotated = false)
+{
+    __shared__ double lh[MAX_RESTART];
+    __shared__ double pa[2][MAX_RESTART], pb[2][MAX_RESTART];
+    const int tid = threadIdx.x;
+    const int jc = j - 1;
     const int m = st->m;
     double *Hc = a.H + (size_t)jc * (m + 1);
-    for (int i = tid; i < jc; i += nth) {
-        const double x = i == 0 ? lh[0] : fma(pa[cur][i - 1], lh[0], pb[cur][i - 1]);
-        Hc[i] = lc[i] * x + ls[i] * lh[i + 1];
+    double carry;
+    if (rotated) {
+        carry = st->carry;
+    } else {
+        for (int k = tid; k < j; k += blockDim.x)
+            lh[k] = reorth ? a.h[k] + a.u[k] : a.h[k];
+        __syncthreads();
+        carry = rotate_column(lh, j, a.cs, a.sn, Hc, pa, pb);
     }
-    const double carry = jc == 0 ? lh[0] : fma(pa[cur][jc - 1], lh[0], pb[cur][jc - 1]);
-    __syncthreads();
     if (tid != 0)
         return;
     double t = st->t;
@@ -1031,6 +1047,10 @@ enum { U_PLAIN = 0, U_STEP1 = 1, U_STEP2 = 2, U_SOLUTION = 3, U_COMBINE = 4, U_S
 // t / omega stays above 0.3, so the explicit form is a safeguard for
 // near-breakdowns (clustered spectra), not the common path.
 constexpr double HARD_RATIO = 1e-4;
+// Tile blocks of the second-pass kernel (U_HARD).  It is launched on every
+// step and returns at once unless the step is hard, so a small grid keeps
+// that launch cheap; a hard step's second pass streams the basis with it.
+constexpr int HARD_BLOCKS = 256;
 
 template <int F, int ROLE>
 __global__ __launch_bounds__(BLK) void k_update(const uint8_t *__restrict__ V, int64_t ld,
@@ -1040,7 +1060,8 @@ __global__ __launch_bounds__(BLK) void k_update(const uint8_t *__restrict__ V, i
                                                 const double *__restrict__ dinv, RedArgs ra,
                                                 const DevState *st,
                                                 double *__restrict__ uio, DevState *stw,
-                                                const double *__restrict__ G)
+                                                const double *__restrict__ G, StepArrays sa,
+                                                int nb_first)
 {
     int j = j_arg;
     if constexpr (ROLE == U_STEP1 || ROLE == U_STEP2 || ROLE == U_STEP1N || ROLE == U_CGS2 ||
@@ -1064,10 +1085,26 @@ __global__ __launch_bounds__(BLK) void k_update(const uint8_t *__restrict__ V, i
     // U_CGS2: Gram-form re-dot u = h - G h, then steps 5-10 in one update;
     // U_HARD: the explicit second pass of a hard step.  lp holds partial sums
     // of G h in the prologue and, on a hard step, the per-wave re-dot sums.
-    __shared__ double lc[(ROLE == U_CGS2 || ROLE == U_HARD) ? MAX_RESTART : 1];
-    __shared__ double lh[ROLE == U_CGS2 ? MAX_RESTART : 1];
-    __shared__ double lp[ROLE == U_CGS2 ? NWAVE * MAX_RESTART : 1];
+    // Both run one block more than the grid of tiles: that column block,
+    // once the step's final coefficients are known, applies the stored
+    // Givens rotations to the new Hessenberg column (rotate_column; rows
+    // 0 .. j-2 into H, the carry into the state) while the other blocks
+    // stream the basis, which leaves the closing fold only the new rotation.
+    constexpr bool ONEPASS = ROLE == U_CGS2 || ROLE == U_HARD;
+    __shared__ double lc[ONEPASS ? MAX_RESTART : 1];
+    __shared__ double lh[ONEPASS ? MAX_RESTART : 1];
+    __shared__ double lp[ONEPASS ? NWAVE * MAX_RESTART : 1];
     __shared__ double lr[2][NWAVE];
+    const int ntb = ONEPASS ? (int)gridDim.x - 1 : (int)gridDim.x;    // blocks with tiles
+    const bool colblk = ONEPASS && (int)blockIdx.x == ntb;
+    auto rotate = [&](const double *c) {
+        double *Hc = sa.H + (size_t)(j - 1) * ((size_t)st->m + 1);
+        double(*pa)[MAX_RESTART] = (double(*)[MAX_RESTART])lp;
+        double(*pb)[MAX_RESTART] = (double(*)[MAX_RESTART])(lp + 2 * MAX_RESTART);
+        const double carry = rotate_column(c, j, sa.cs, sa.sn, Hc, pa, pb);
+        if (tid == 0)
+            stw->carry = carry;
+    };
     bool hard = false;
     if constexpr (ROLE == U_CGS2) {
         // Every block forms the same u = h - G h (G symmetric: wave wv sums
@@ -1133,6 +1170,14 @@ __global__ __launch_bounds__(BLK) void k_update(const uint8_t *__restrict__ V, i
                 stw->t = t1;
             }
         }
+        if (colblk) {
+            // a hard step's column waits for its second pass (U_HARD)
+            if (!hard) {
+                __syncthreads();                // lc complete
+                rotate(lc);
+            }
+            return;
+        }
         if (hard) {
             // per-wave re-dot sums, accumulated over the block's tiles
             for (int k = tid; k < NWAVE * j; k += BLK)
@@ -1147,7 +1192,7 @@ __global__ __launch_bounds__(BLK) void k_update(const uint8_t *__restrict__ V, i
         // ||w1||^2, max|w1|), u and t1, decides step 7 against t1, and
         // updates w1 -= V u.  Block 0 publishes u, t1, max|w1| and the
         // decision; the norms go to rows j+2, j+3 for the closing fold.
-        const int nb = gridDim.x;            // the first pass ran on the same grid
+        const int nb = nb_first;             // the first pass's tile blocks
         for (int k = wv; k < j; k += NWAVE) {
             const double a = wave_fold(ra.part + (size_t)k * ra.stride, nb, false);
             if (lane == 0)
@@ -1170,11 +1215,19 @@ __global__ __launch_bounds__(BLK) void k_update(const uint8_t *__restrict__ V, i
                 stw->reorth = ro ? 1 : 0;
             }
         }
+        if (colblk) {
+            // the column: h + u when the second pass re-orthogonalises, else h
+            for (int k = tid; k < j; k += BLK)
+                lh[k] = ro ? coef[k] + lc[k] : coef[k];
+            __syncthreads();
+            rotate(lh);
+            return;
+        }
         if (!ro)
             return;
         coef = lc;
     }
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += ntb) {
         const bool full = (tile + 1) * TILE <= n;
         double s[CH * VW];
         int64_t i0[CH];
@@ -1884,11 +1937,11 @@ __global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth
         nb = nb_orth;
     } else if (role == RR_C2) {
         // the one-pass update's norms (rows 0, 1), or a hard step's second
-        // pass (rows j+2, j+3)
+        // pass (rows j+2, j+3, from its smaller grid)
         const int row = st->hard ? j + 2 : 0;
         s0 = ws.orth + (size_t)row * ws.stride;
         s1 = ws.orth + (size_t)(row + 1) * ws.stride;
-        nb = nb_orth;
+        nb = st->hard ? min(nb_orth, HARD_BLOCKS) : nb_orth;
     } else if (role == RR_T2 || role == RR_NORMS || role == RR_MGS_T || role == RR_UG) {
         s0 = ws.orth;
         s1 = ws.orth + ws.stride;
@@ -1984,8 +2037,9 @@ __global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth
         // norm against t1 (which the update stored), else the step's t.  A
         // hard step without re-orthogonalisation has its t and max|w| from
         // the second-pass kernel already.
+        // The column was rotated by the update's column block.
         if (st->reorth) {
-            finish_step(st, sa, j, true, sqrt(sv[0]), sv[1]);
+            finish_step(st, sa, j, true, sqrt(sv[0]), sv[1], true);
         } else {
             __syncthreads();
             if (tid == 0 && !st->hard) {
@@ -1993,7 +2047,7 @@ __global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth
                 st->wmax = sv[1];
             }
             __syncthreads();
-            finish_step(st, sa, j, false, 0.0, 0.0);
+            finish_step(st, sa, j, false, 0.0, 0.0, true);
         }
         break;
     }
@@ -2561,19 +2615,26 @@ void launch_multidot(const OrthArgs &a, hipStream_t s)
 
 void launch_update(const OrthArgs &a, hipStream_t s)
 {
-    int g = orth_grid(a.fmt, a.n);
+    // the one-pass roles run one block more: the column block
+    const bool onepass = a.role == U_CGS2 || a.role == U_HARD;
+    const int g0 = orth_grid(a.fmt, a.n);
+    const int g = (a.role == U_HARD ? min(g0, HARD_BLOCKS) : g0) + (onepass ? 1 : 0);
     RedArgs ra{a.ws.orth, a.ws.stride};
     const uint8_t *V = (const uint8_t *)a.V;
+    StepArrays sa{};
+    if (a.sa)
+        sa = *(const StepArrays *)a.sa;
 #define CBG_UPD(R)                                                                            \
     if (a.ev0) {                                                                              \
         CBG_FMT_SWITCH(a.fmt, (hipExtLaunchKernelGGL(k_update<F, R>, dim3(g), dim3(BLK), 0, s, \
                                                      a.ev0, a.ev1, 0, V, a.ld, a.scales, a.n, \
                                                      a.j, a.coef, a.wio, a.dinv, ra, a.st,    \
-                                                     a.u, a.stw, a.G)))                       \
+                                                     a.u, a.stw, a.G, sa, g0)))               \
     } else {                                                                                  \
         CBG_FMT_SWITCH(a.fmt, (k_update<F, R><<<g, BLK, 0, s>>>(V, a.ld, a.scales, a.n, a.j,   \
                                                                  a.coef, a.wio, a.dinv, ra,   \
-                                                                 a.st, a.u, a.stw, a.G)))     \
+                                                                 a.st, a.u, a.stw, a.G, sa,   \
+                                                                 g0)))                        \
     }
     switch (a.role) {
     case U_PLAIN: CBG_UPD(U_PLAIN) break;

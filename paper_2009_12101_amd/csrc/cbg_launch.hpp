@@ -53,6 +53,7 @@ struct OrthArgs {
     double *u;            // one-pass update: receives u (Gram form, or a hard step's explicit re-dot)
     DevState *stw;        // one-pass update: the step-7 decision and t1
     const double *G;      // one-pass update: the Gram matrix of the stored basis
+    const void *sa;       // one-pass update: the step arrays (H, cs, sn) of the column block
     const double *coef;   // update coefficients
     double *wio;          // update: the vector updated in place (or written)
     const double *dinv;

@@ -752,7 +752,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                 // u = h - G h and steps 5-10 in one update with h + u or h;
                 // a hard step's explicit second pass (nothing otherwise);
                 // the close
-                o.role = 6 /*U_CGS2*/; o.u = W.u; o.stw = W.st; o.G = W.G;
+                o.role = 6 /*U_CGS2*/; o.u = W.u; o.stw = W.st; o.G = W.G; o.sa = sa;
                 launch_update(o, s);
                 o.role = 7 /*U_HARD*/;
                 o.ev0 = o.ev1 = nullptr;        // the events belong to the update above
