@@ -162,39 +162,40 @@ def pmc_summary(fetch_csv: str, write_csv: str, cfg: Config) -> dict:
 
 
 def trace_summary(trace_csv: str, cfg: Config) -> dict:
-    """Per-j durations of the basis-streaming kernels and the step SpMV from
-    a rocprofv3 --kernel-trace CSV of bench runs of a configuration without
-    a preconditioner.  The solver launches each of them once per Arnoldi
-    step, j = 1..restart in every cycle (launches after a cycle ended return
-    at once), so dispatch k of a kernel in launch order belongs to step
-    j = k mod restart + 1.  Per kernel and j: the median duration over all
-    cycles and the algorithmic GB/s; per kernel the j-weighted rate over all
-    j and over j >= 20."""
+    """Per-j durations of the step kernels from a rocprofv3 --kernel-trace CSV
+    of bench runs of a configuration.  A cycle starts with the residual SpMV
+    (mode 2); inside it the solver launches each step kernel once per
+    Arnoldi step, j = 1, 2, ..., and after the cycle has ended up to two
+    chunks of launches that return at once.  The steps that did work are the
+    leading step-SpMV dispatches of the cycle longer than 10 us (an SpMV that
+    moves the matrix takes far longer, one that returns at once a few us),
+    and dispatch k of each step kernel in the cycle belongs to step j = k + 1.
+    Per kernel and j: the median duration over the cycles and the
+    algorithmic GB/s; per kernel the j-weighted rate over all j and over
+    j >= 20."""
     import csv
     import statistics
+    import numpy as np
     from paper_2009_12101_amd import problems as P
     A = build_system(cfg, P)[0]
-    n, nnz, bs, restart = A.n, A.nnz, FMT_BYTES[cfg.fmt], cfg.restart
+    n, nnz, bs = A.n, A.nnz, FMT_BYTES[cfg.fmt]
     fid = FMT_ID[cfg.fmt]
-    kernels = {
-        f"k_multidot<{fid}, true>": lambda j: j * n * bs + 8.0 * n + n * bs,
-        f"k_update<{fid}, 6>": lambda j: j * n * bs + 16.0 * n,
-    }
     rows = list(csv.DictReader(open(trace_csv)))
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    dur = lambda r: (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+
+    def spmv_mode(name):
+        targs = name.split("<", 1)[1].split(">", 1)[0].split(",")
+        return int(targs[0] if "k_spmv_sell" in name else targs[-1])
+
     spmv = {}
     for r in rows:
         if "k_spmv" in r["Kernel_Name"]:
             spmv[r["Kernel_Name"]] = spmv.get(r["Kernel_Name"], 0) + 1
     step_spmv = max(spmv, key=spmv.get)
-    targs = step_spmv.split("<", 1)[1].split(">", 1)[0].split(",")
-    sell = "k_spmv_sell" in step_spmv
-    # the mode is the first template argument of the sliced-ELL kernel, the
-    # last of the CSR ones
-    mode = int(targs[0] if sell else targs[-1])
+    mode = spmv_mode(step_spmv)
     gather = (mode & 8) != 0                     # an Arnoldi-step mode: stores v_j too
-    if sell:
-        import numpy as np
+    if "k_spmv_sell" in step_spmv:
         lens = np.zeros(-(-n // 64) * 64, dtype=np.int64)
         lens[:n] = np.diff(A.row_ptr)
         entries = 64 * int(lens.reshape(-1, 64).max(axis=1).sum())
@@ -202,24 +203,49 @@ def trace_summary(trace_csv: str, cfg: Config) -> dict:
     else:
         sp_bytes = 12.0 * nnz + 4.0 * (n + 1) + 16.0 * n
     sp_bytes += n * bs if gather else 0.0
-    kernels[step_spmv] = lambda j: sp_bytes
-    out = {"config": cfg.key, "format": cfg.fmt, "kernels": {}}
+    kernels = {
+        step_spmv: lambda j: sp_bytes,
+        f"k_multidot<{fid}, true>": lambda j: j * n * bs + 8.0 * n + n * bs,
+        f"k_update<{fid}, 6>": lambda j: j * n * bs + 16.0 * n,
+        # the stored form of the learned preconditioner with steps 13-14:
+        # 27 codes of 2 bytes, w, dinv and z of 8 bytes, the stored entry
+        f"k_stencil<{fid}, 0": lambda j: 54.0 * n + 24.0 * n + n * bs,
+    }
+    # cycles: from one residual SpMV to the next
+    cycles, cur = [], None
+    for r in rows:
+        name = r["Kernel_Name"]
+        if "k_spmv" in name and spmv_mode(name) == 2:
+            cur = []
+            cycles.append(cur)
+        elif cur is not None:
+            cur.append(r)
+    out = {"config": cfg.key, "format": cfg.fmt, "cycles": len(cycles), "kernels": {}}
     for key, model in kernels.items():
-        sel = [r for r in rows if key in r["Kernel_Name"]]
-        if not sel or len(sel) % restart:
-            raise SystemExit(f"{trace_csv}: {len(sel)} dispatches of {key}, not a multiple of "
-                             f"{restart}")
         per_j = {}
-        for k, r in enumerate(sel):
-            per_j.setdefault(k % restart + 1, []).append(
-                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9)
+        count = 0
+        for cyc in cycles:
+            nwork = 0
+            for r in cyc:
+                if r["Kernel_Name"] == step_spmv:
+                    if dur(r) <= 10e-6:
+                        break
+                    nwork += 1
+            sel = [r for r in cyc if key in r["Kernel_Name"]][:nwork]
+            count += len(sel)
+            for k, r in enumerate(sel):
+                per_j.setdefault(k + 1, []).append(dur(r))
+        if not per_j:
+            continue
         table = [{"j": j, "median_us": statistics.median(v) * 1e6,
                   "gbps": model(j) / statistics.median(v) / 1e9, "samples": len(v)}
                  for j, v in sorted(per_j.items())]
 
         def weighted(tab):
-            return sum(model(t["j"]) for t in tab) / sum(t["median_us"] * 1e-6 for t in tab) / 1e9
-        out["kernels"][key] = {"dispatches": len(sel), "j_weighted_gbps": weighted(table),
+            return (sum(model(t["j"]) for t in tab) /
+                    sum(t["median_us"] * 1e-6 for t in tab) / 1e9) if tab else None
+        out["kernels"][key] = {"dispatches_that_worked": count, "bytes_j1": model(1),
+                               "j_weighted_gbps": weighted(table),
                                "j_weighted_gbps_j_ge_20": weighted([t for t in table
                                                                     if t["j"] >= 20]),
                                "per_j": table}
