@@ -100,9 +100,10 @@ CONFIGS = {
 }
 
 
-# Arnoldi steps of the CPU oracle's sample per configuration (about 10-30 s
-# on a 16-thread host share; a whole solve where it needs fewer)
-CPU_STEPS = {"D1": 100000, "D2": 500, "D3": 150, "D4": 150, "D5": 90}
+# Arnoldi steps of the CPU oracle's sample per configuration: the whole
+# solve where it takes under about 40 s on a 16-thread host share (D2 19 s,
+# D5 38 s measured), else a stated number of steps scaled to the GPU's count
+CPU_STEPS = {"D1": 100000, "D2": 100000, "D3": 1000, "D4": 100000, "D5": 100000}
 
 
 def kernel_source_hash() -> str:
@@ -304,6 +305,8 @@ def main() -> int:
     ap.add_argument("--cpu-steps", type=int, default=None,
                     help="Arnoldi steps of the CPU oracle sample (a whole solve if it needs "
                          "no more; default sized for 10-30 s of host work per configuration)")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="host threads of the CPU oracle (0: all the process may use)")
     ap.add_argument("--weights", default=None,
                     help="trained parameters (.npz of LearnedSPAI.save); trained here if absent")
     ap.add_argument("--train-count", type=int, default=256)
@@ -484,6 +487,8 @@ def main() -> int:
     cpu = None
     if not args.no_cpu:
         import oracle
+        if args.cpu_threads > 0:
+            oracle.set_threads(args.cpu_threads)
         cpu_steps = args.cpu_steps if args.cpu_steps is not None else CPU_STEPS[cfg.key]
         steps = max(1, min(cpu_steps, r0.iterations + m))
         t = time.perf_counter()

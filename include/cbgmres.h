@@ -89,7 +89,15 @@ enum {
  * CSR order with separately rounded products and sums, so y = A x equals
  * the row-sequential CSR sum bit for bit (for finite x; a padding entry
  * multiplies x at the row's own index by 0).  The CSR arrays stay required:
- * the preconditioner set-ups and the sparse-P products read them. */
+ * the preconditioner set-ups and the sparse-P products read them.
+ *
+ * Diagonal-index columns (cbg_sell_diag): when A has at most
+ * CBG_SELL_MAX_DIAG distinct offsets col - row (banded and stencil
+ * matrices), sell_dix [dev] (sell_entries uint8) holds per entry the index
+ * of its offset in sell_diag [dev] (sell_ndiag int32, sorted ascending,
+ * 0 included), so a column is row + sell_diag[sell_dix[e]] (padding
+ * entries: offset 0) and the SpMV reads 9 instead of 12 bytes per entry.
+ * With sell_dix, sell_diag and sell_ndiag set, sell_col may be NULL. */
 typedef struct {
     int32_t n;
     int32_t reserved;
@@ -101,7 +109,13 @@ typedef struct {
     const int32_t *sell_col;
     const double *sell_val;
     int64_t sell_entries;
+    const uint8_t *sell_dix;
+    const int32_t *sell_diag;
+    int32_t sell_ndiag;
+    int32_t reserved2;
 } cbg_csr;
+
+#define CBG_SELL_MAX_DIAG 256
 
 #define CBG_SELL_SLICE 64
 
@@ -313,6 +327,18 @@ int cbg_sell_ptr(const cbg_csr *A, int64_t *sell_ptr, int64_t *entries, void *st
  * cbg_sell_ptr) from A's CSR arrays and sell_ptr. */
 int cbg_sell_fill(const cbg_csr *A, const int64_t *sell_ptr, int32_t *sell_col,
                   double *sell_val, void *stream);
+
+/* Diagonal-index columns of the sliced-ELL copy (see cbg_csr): from A's
+ * sell_ptr and sell_col, finds the distinct offsets col - row of the rows
+ * < n (padding counts as offset 0).  With at most CBG_SELL_MAX_DIAG of them,
+ * writes them sorted to sell_diag [dev] (CBG_SELL_MAX_DIAG int32), the
+ * per-entry indices to sell_dix [dev] (sell_entries uint8) and their count
+ * to *ndiag [host], and returns CBG_OK; with more, writes only *ndiag (the
+ * count, or more than CBG_SELL_MAX_DIAG when the search stopped early) and
+ * returns CBG_E_UNSUPPORTED.  ws: cbg_kernel_workspace_bytes(n, 0) bytes.
+ * Synchronises the stream. */
+int cbg_sell_diag(const cbg_csr *A, int32_t *sell_diag, uint8_t *sell_dix, int32_t *ndiag,
+                  void *ws, size_t ws_bytes, void *stream);
 
 /* y = A x (step 3); if norm2 [dev, nullable] is given, *norm2 = ||y||_2
  * (step 4).  x [dev] n doubles, y [dev] n doubles.  With A's sliced-ELL

@@ -60,7 +60,7 @@ def variant_flags(names) -> int:
 EXPORTS = ["cbg_strerror", "cbg_last_hip_error", "cbg_basis_ld", "cbg_workspace_bytes", "cbg_kernel_workspace_bytes",
            "cbg_workspace_basis", "cbgmres_solve", "cbg_encode", "cbg_decode", "cbg_spmv",
            "cbg_multidot", "cbg_multidot_noalloc", "cbg_update", "cbg_update_redot",
-           "cbg_sell_ptr", "cbg_sell_fill",
+           "cbg_sell_ptr", "cbg_sell_fill", "cbg_sell_diag",
            "cbg_block_jacobi_setup",
            "cbg_block_jacobi_apply", "cbg_spai_workspace_bytes", "cbg_spai_features", "cbg_mlp_forward",
            "cbg_spai_assemble", "cbg_learned_build", "cbg_learned_build_stencil",
@@ -75,7 +75,8 @@ class CbgCsr(C.Structure):
     _fields_ = [("n", C.c_int32), ("reserved", C.c_int32), ("nnz", C.c_int64),
                 ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("val", C.c_void_p),
                 ("sell_ptr", C.c_void_p), ("sell_col", C.c_void_p), ("sell_val", C.c_void_p),
-                ("sell_entries", C.c_int64)]
+                ("sell_entries", C.c_int64), ("sell_dix", C.c_void_p), ("sell_diag", C.c_void_p),
+                ("sell_ndiag", C.c_int32), ("reserved2", C.c_int32)]
 
 
 class CbgOpts(C.Structure):
@@ -142,6 +143,7 @@ def lib():
         L.cbg_spmv.argtypes = [C.POINTER(CbgCsr), vp, vp, vp, vp, sz, vp]
         L.cbg_sell_ptr.argtypes = [C.POINTER(CbgCsr), vp, C.POINTER(i64), vp]
         L.cbg_sell_fill.argtypes = [C.POINTER(CbgCsr), vp, vp, vp, vp]
+        L.cbg_sell_diag.argtypes = [C.POINTER(CbgCsr), vp, vp, C.POINTER(i32), vp, sz, vp]
         L.cbg_multidot.argtypes = [i32, vp, i64, vp, i32, i32, vp, vp, vp, sz, vp]
         L.cbg_multidot_noalloc.argtypes = [i32, vp, i64, vp, i32, i32, vp, vp, vp]
         L.cbg_update.argtypes = [i32, vp, i64, vp, i32, i32, vp, vp, vp, vp, sz, vp]
@@ -169,7 +171,7 @@ def lib():
         L.cbg_spai_round_weights.argtypes = [vp, vp, vp]
         L.cbg_adam_step.argtypes = [vp, vp, vp, vp, vp, i64, f64, f64, f64, f64, vp]
         for f in ("cbgmres_solve", "cbg_encode", "cbg_decode", "cbg_spmv", "cbg_multidot",
-                  "cbg_multidot_noalloc", "cbg_sell_ptr", "cbg_sell_fill",
+                  "cbg_multidot_noalloc", "cbg_sell_ptr", "cbg_sell_fill", "cbg_sell_diag",
                   "cbg_update", "cbg_update_redot", "cbg_block_jacobi_setup",
                   "cbg_block_jacobi_apply", "cbg_workspace_basis", "cbg_spai_features", "cbg_mlp_forward",
                   "cbg_spai_assemble", "cbg_learned_build", "cbg_learned_build_stencil",
@@ -275,6 +277,7 @@ def _check(rc: int, where: str):
 SELL_SLICE = 64
 # the sliced-ELL copy is kept when its padding is at most this fraction of nnz
 SELL_MAX_PADDING = 0.25
+SELL_MAX_DIAG = 256
 
 
 @dataclasses.dataclass
@@ -290,24 +293,31 @@ class DeviceCSR:
     sell_ptr: "object" = None
     sell_col: "object" = None
     sell_val: "object" = None
+    sell_dix: "object" = None
+    sell_diag: "object" = None
+    sell_ndiag: int = 0
 
     @classmethod
-    def from_host(cls, A, device="cuda", sell="auto"):
+    def from_host(cls, A, device="cuda", sell="auto", diag=True):
         """Copy a host CSR matrix to the GPU.  sell: "auto" builds the
         sliced-ELL copy unless its padding exceeds SELL_MAX_PADDING of nnz;
-        True builds it regardless; False keeps the CSR kernels."""
+        True builds it regardless; False keeps the CSR kernels.  diag: store
+        the copy's columns as diagonal indices when A has at most
+        SELL_MAX_DIAG distinct offsets col - row."""
         torch = _torch()
         rp = torch.from_numpy(np.ascontiguousarray(A.row_ptr, dtype=np.int32)).to(device)
         ci = torch.from_numpy(np.ascontiguousarray(A.col_idx, dtype=np.int32)).to(device)
         va = torch.from_numpy(np.ascontiguousarray(A.val, dtype=np.float64)).to(device)
         D = cls(int(A.n), int(A.nnz), rp, ci, va)
         if sell and D.n > 0 and (sell is True or D.val.device.type == "cuda"):
-            D.build_sell(max_padding=None if sell is True else SELL_MAX_PADDING)
+            D.build_sell(max_padding=None if sell is True else SELL_MAX_PADDING, diag=diag)
         return D
 
-    def build_sell(self, max_padding=None):
+    def build_sell(self, max_padding=None, diag=True, keep_col=False):
         """Build the sliced-ELL copy on the GPU (kept only if its padding is
-        at most max_padding of nnz, when given).  Returns self."""
+        at most max_padding of nnz, when given), with diagonal-index columns
+        when diag and A has few enough distinct offsets (then the int32
+        columns are dropped unless keep_col).  Returns self."""
         torch = _torch()
         self.drop_sell()
         dev = self.val.device
@@ -325,16 +335,32 @@ class DeviceCSR:
         _check(lib().cbg_sell_fill(C.byref(csr), _ptr(sp), _ptr(sc), _ptr(sv), _stream()),
                "cbg_sell_fill")
         self.sell_ptr, self.sell_col, self.sell_val = sp, sc[:entries], sv[:entries]
+        if diag:
+            dg = torch.empty(SELL_MAX_DIAG, dtype=torch.int32, device=dev)
+            dx = torch.empty(max(entries, 1), dtype=torch.uint8, device=dev)
+            nd = C.c_int32(0)
+            csr = self.cstruct()
+            ws = _kws(self.n, 0, dev)
+            rc = lib().cbg_sell_diag(C.byref(csr), _ptr(dg), _ptr(dx), C.byref(nd), _ptr(ws),
+                                     ws.numel(), _stream())
+            if rc == E_UNSUPPORTED:
+                return self                     # too many distinct offsets: int32 columns
+            _check(rc, "cbg_sell_diag")
+            self.sell_dix, self.sell_diag, self.sell_ndiag = dx[:entries], dg, int(nd.value)
+            if not keep_col:
+                self.sell_col = None
         return self
 
     def drop_sell(self):
         """Forget the sliced-ELL copy (the CSR kernels run).  Returns self."""
         self.sell_ptr = self.sell_col = self.sell_val = None
+        self.sell_dix = self.sell_diag = None
+        self.sell_ndiag = 0
         return self
 
     @property
     def sell_entries(self) -> int:
-        return 0 if self.sell_col is None else int(self.sell_col.numel())
+        return 0 if self.sell_val is None else int(self.sell_val.numel())
 
     def check(self):
         """Raise ValueError unless the arrays match n and nnz (int32 indices,
@@ -347,17 +373,27 @@ class DeviceCSR:
         arrays = [(self.row_ptr, "A.row_ptr", torch.int32, self.n + 1),
                   (self.col_idx, "A.col_idx", torch.int32, self.nnz),
                   (self.val, "A.val", torch.float64, self.nnz)]
-        sell = (self.sell_ptr, self.sell_col, self.sell_val)
+        dix = (self.sell_dix, self.sell_diag)
+        if any(t is not None for t in dix) and (any(t is None for t in dix) or
+                                                not 1 <= self.sell_ndiag <= SELL_MAX_DIAG):
+            raise ValueError("A.sell_dix / sell_diag / sell_ndiag: given together, "
+                             f"1 <= ndiag <= {SELL_MAX_DIAG}")
+        cols = self.sell_col if self.sell_col is not None else self.sell_dix
+        sell = (self.sell_ptr, cols, self.sell_val)
         if any(t is not None for t in sell):
             if any(t is None for t in sell):
                 raise ValueError("A.sell_*: the sliced-ELL arrays are all given or none")
             ent = self.sell_entries
             if ent < self.nnz or ent % SELL_SLICE:
-                raise ValueError(f"A.sell_col: {ent} entries for nnz = {self.nnz}")
+                raise ValueError(f"A.sell_val: {ent} entries for nnz = {self.nnz}")
             arrays += [(self.sell_ptr, "A.sell_ptr", torch.int64,
                         (self.n + SELL_SLICE - 1) // SELL_SLICE + 1),
-                       (self.sell_col, "A.sell_col", torch.int32, ent),
                        (self.sell_val, "A.sell_val", torch.float64, ent)]
+            if self.sell_col is not None:
+                arrays.append((self.sell_col, "A.sell_col", torch.int32, ent))
+            if self.sell_dix is not None:
+                arrays += [(self.sell_dix, "A.sell_dix", torch.uint8, ent),
+                           (self.sell_diag, "A.sell_diag", torch.int32, SELL_MAX_DIAG)]
         for gpu in (False, True):           # shapes first, then the device
             for t, nm, dt, cnt in arrays:
                 _need(t, nm, dt, cnt, dev, exact=True, gpu=gpu)
@@ -365,12 +401,14 @@ class DeviceCSR:
 
     def cstruct(self) -> CbgCsr:
         self.check()
-        if self.sell_col is None:
+        ptr = lambda t: None if t is None else t.data_ptr()
+        if self.sell_val is None:
             return CbgCsr(self.n, 0, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(),
-                          self.val.data_ptr(), None, None, None, 0)
+                          self.val.data_ptr(), None, None, None, 0, None, None, 0, 0)
         return CbgCsr(self.n, 0, self.nnz, self.row_ptr.data_ptr(), self.col_idx.data_ptr(),
-                      self.val.data_ptr(), self.sell_ptr.data_ptr(), self.sell_col.data_ptr(),
-                      self.sell_val.data_ptr(), self.sell_entries)
+                      self.val.data_ptr(), ptr(self.sell_ptr), ptr(self.sell_col),
+                      ptr(self.sell_val), self.sell_entries, ptr(self.sell_dix),
+                      ptr(self.sell_diag), self.sell_ndiag if self.sell_dix is not None else 0, 0)
 
 
 @dataclasses.dataclass

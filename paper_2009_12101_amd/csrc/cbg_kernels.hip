@@ -666,18 +666,27 @@ __device__ __forceinline__ T sell_ld(const T *p)
 }
 
 constexpr int SELL_UNR = 9;      // entries per row in flight (a third of a 27-point row)
+constexpr int SELL_MAX_DIAG = 256;  // distinct offsets col - row of the diagonal-index form
 
-template <int MODE, bool NT>
+template <int MODE, bool NT, bool DIX>
 __global__ __launch_bounds__(BLK) void k_spmv_sell(
     int n, int64_t ldy, int64_t nslice, const int64_t *__restrict__ sp,
-    const int32_t *__restrict__ sc, const double *__restrict__ sv, const double *__restrict__ x,
-    const double *__restrict__ dinv, const double *__restrict__ b, double *__restrict__ y,
-    RedArgs ra, int role, const DevState *st, uint8_t *__restrict__ Q,
+    const int32_t *__restrict__ sc, const uint8_t *__restrict__ sd,
+    const int32_t *__restrict__ sdiag, int ndiag, const double *__restrict__ sv,
+    const double *__restrict__ x, const double *__restrict__ dinv, const double *__restrict__ b,
+    double *__restrict__ y, RedArgs ra, int role, const DevState *st, uint8_t *__restrict__ Q,
     const double *__restrict__ qscale, int fmt)
 {
 #pragma clang fp contract(off)
     if (st && role != SR_FREE && st->done)
         return;
+    // DIX: columns as row + offset, the offset's index one byte per entry
+    __shared__ int32_t ldg[DIX ? SELL_MAX_DIAG : 1];
+    if constexpr (DIX) {
+        for (int k = threadIdx.x; k < ndiag; k += BLK)
+            ldg[k] = sdiag[k];
+        __syncthreads();
+    }
     double tdiv = 1.0;
     EncParam ep{1.0, 0};
     if constexpr (sp_step(MODE)) {
@@ -696,7 +705,9 @@ __global__ __launch_bounds__(BLK) void k_spmv_sell(
             const int64_t o = sp[s];
             const int w = (int)((sp[s + 1] - o) >> 6);
             const int32_t *c = sc + o + lane;
+            const uint8_t *cd = sd + o + lane;
             const double *v = sv + o + lane;
+            const int32_t rowc = (int32_t)min(row, (int64_t)n - 1);   // rows >= n: padding only
             // batches of SELL_UNR entries, every load of a batch in flight
             // before the first product; a short last batch re-reads entry
             // w - 1 for its missing slots and adds nothing for them
@@ -706,8 +717,16 @@ __global__ __launch_bounds__(BLK) void k_spmv_sell(
 #pragma unroll
                 for (int u = 0; u < SELL_UNR; ++u) {
                     const int64_t e = (int64_t)min(k + u, w - 1) * 64;
-                    cc[u] = sell_ld<NT>(c + e);
+                    if constexpr (DIX)
+                        cc[u] = sell_ld<NT>(cd + e);
+                    else
+                        cc[u] = sell_ld<NT>(c + e);
                     vv[u] = sell_ld<NT>(v + e);
+                }
+                if constexpr (DIX) {
+#pragma unroll
+                    for (int u = 0; u < SELL_UNR; ++u)
+                        cc[u] = rowc + ldg[cc[u]];
                 }
 #pragma unroll
                 for (int u = 0; u < SELL_UNR; ++u) {
@@ -817,6 +836,145 @@ __global__ __launch_bounds__(BLK) void k_sell_fill(int n, const int32_t *__restr
             sv[e] = k < len ? val[p0 + k] : 0.0;
         }
     }
+}
+
+// Diagonal-index form of the sliced-ELL columns.  The distinct offsets
+// col - row go into an open-addressing hash set (DIAG_HASH int32 slots,
+// empty = INT32_MIN, which no offset can equal), then one block collects
+// and sorts them, and a last pass writes each entry's index.  Set-up only:
+// the hash insertion uses atomics, the result does not depend on their
+// order (the offsets are sorted).
+constexpr int DIAG_HASH = 4096;
+constexpr int32_t DIAG_EMPTY = INT32_MIN;
+
+__device__ __forceinline__ int32_t entry_offset(const int32_t *__restrict__ sc, int64_t e,
+                                                int64_t row, int n)
+{
+    return row < n ? (int32_t)(sc[e] - row) : 0;        // rows >= n: padding, offset 0
+}
+
+// inserts v; returns false when the table is full
+__device__ bool diag_insert(int32_t *hash, int32_t v)
+{
+    uint32_t h = ((uint32_t)v * 2654435761u) & (DIAG_HASH - 1);   // Knuth's multiplicative hash
+    for (int probe = 0; probe < DIAG_HASH; ++probe) {
+        const int32_t cur = __hip_atomic_load(&hash[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (cur == v)
+            return true;
+        if (cur == DIAG_EMPTY) {
+            const int32_t old = atomicCAS(&hash[h], DIAG_EMPTY, v);
+            if (old == DIAG_EMPTY || old == v)
+                return true;
+        }
+        h = (h + 1) & (DIAG_HASH - 1);
+    }
+    return false;
+}
+
+__global__ __launch_bounds__(BLK) void k_diag_insert(int n, int64_t nslice,
+                                                     const int64_t *__restrict__ sp,
+                                                     const int32_t *__restrict__ sc,
+                                                     int32_t *hash, unsigned *full)
+{
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && !diag_insert(hash, 0))
+        atomicOr(full, 1u);
+    for (int64_t s = (int64_t)blockIdx.x * NWAVE + wv; s < nslice;
+         s += (int64_t)gridDim.x * NWAVE) {
+        const int64_t row = s * 64 + lane;
+        const int64_t o = sp[s];
+        const int w = (int)((sp[s + 1] - o) >> 6);
+        for (int k = 0; k < w; ++k) {
+            const int32_t off = entry_offset(sc, o + (int64_t)k * 64 + lane, row, n);
+            // one insertion per wave when all lanes share the offset
+            const int32_t first = __shfl(off, 0);
+            const bool same = __all(off == first);
+            if ((!same || lane == 0) && !diag_insert(hash, off))
+                atomicOr(full, 1u);
+            if (*(volatile unsigned *)full)
+                return;
+        }
+    }
+}
+
+// One block: the distinct offsets, sorted, into diag[0 .. count) when
+// count <= SELL_MAX_DIAG; count (or more than SELL_MAX_DIAG when the table
+// overflowed) into *count_out.
+__global__ __launch_bounds__(BLK) void k_diag_collect(const int32_t *__restrict__ hash,
+                                                      const unsigned *full, int32_t *diag,
+                                                      int32_t *count_out)
+{
+    __shared__ int32_t list[SELL_MAX_DIAG];
+    __shared__ int cnt;
+    if (threadIdx.x == 0)
+        cnt = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < DIAG_HASH; i += BLK) {
+        const int32_t v = hash[i];
+        if (v != DIAG_EMPTY) {
+            const int at = atomicAdd(&cnt, 1);
+            if (at < SELL_MAX_DIAG)
+                list[at] = v;
+        }
+    }
+    __syncthreads();
+    const int c = cnt;
+    if (*full || c > SELL_MAX_DIAG) {
+        if (threadIdx.x == 0)
+            *count_out = max(c, SELL_MAX_DIAG + 1);
+        return;
+    }
+    // rank sort of distinct values
+    for (int t = threadIdx.x; t < c; t += BLK) {
+        const int32_t v = list[t];
+        int rank = 0;
+        for (int u = 0; u < c; ++u)
+            rank += list[u] < v ? 1 : 0;
+        diag[rank] = v;
+    }
+    if (threadIdx.x == 0)
+        *count_out = c;
+}
+
+// Each entry's offset index, by binary search in the sorted table.
+__global__ __launch_bounds__(BLK) void k_diag_index(int n, int64_t nslice,
+                                                    const int64_t *__restrict__ sp,
+                                                    const int32_t *__restrict__ sc,
+                                                    const int32_t *__restrict__ diag, int ndiag,
+                                                    uint8_t *__restrict__ sd)
+{
+    __shared__ int32_t ld[SELL_MAX_DIAG];
+    for (int k = threadIdx.x; k < ndiag; k += BLK)
+        ld[k] = diag[k];
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    for (int64_t s = (int64_t)blockIdx.x * NWAVE + wv; s < nslice;
+         s += (int64_t)gridDim.x * NWAVE) {
+        const int64_t row = s * 64 + lane;
+        const int64_t o = sp[s];
+        const int w = (int)((sp[s + 1] - o) >> 6);
+        for (int k = 0; k < w; ++k) {
+            const int64_t e = o + (int64_t)k * 64 + lane;
+            const int32_t off = entry_offset(sc, e, row, n);
+            int lo = 0, hi = ndiag - 1;                 // off is in the table
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (ld[mid] < off)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            sd[e] = (uint8_t)lo;
+        }
+    }
+}
+
+__global__ void k_fill_i32(int32_t *p, int count, int32_t v)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+        p[i] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -2466,21 +2624,29 @@ static int spmv_sell(const SpmvArgs &a, hipStream_t s)
     const int64_t nsy = (a.ldy + 63) / 64;
     const int g = grid_for((nsy + NWAVE - 1) / NWAVE, 1);
     RedArgs ra{a.ws.spmv, a.ws.stride};
-#define CBG_SELL_LAUNCH(M, NT)                                                                 \
+#define CBG_SELL_LAUNCH(M, NT, DX)                                                             \
     if (a.ev0)                                                                                 \
-        hipExtLaunchKernelGGL(k_spmv_sell<M, NT>, dim3(g), dim3(BLK), 0, s, a.ev0, a.ev1, 0,   \
-                              a.n, a.ldy, a.nslice, a.sp, a.sc, a.sv, a.x, a.dinv, a.b, a.y,   \
-                              ra, a.role, a.st, (uint8_t *)a.Q, a.qscale, a.fmt);              \
+        hipExtLaunchKernelGGL(k_spmv_sell<M, NT, DX>, dim3(g), dim3(BLK), 0, s, a.ev0, a.ev1,  \
+                              0, a.n, a.ldy, a.nslice, a.sp, a.sc, a.sd, a.sdiag, a.ndiag,     \
+                              a.sv, a.x, a.dinv, a.b, a.y, ra, a.role, a.st, (uint8_t *)a.Q,   \
+                              a.qscale, a.fmt);                                                \
     else                                                                                       \
-        k_spmv_sell<M, NT><<<g, BLK, 0, s>>>(a.n, a.ldy, a.nslice, a.sp, a.sc, a.sv, a.x,      \
-                                             a.dinv, a.b, a.y, ra, a.role, a.st,               \
-                                             (uint8_t *)a.Q, a.qscale, a.fmt);
+        k_spmv_sell<M, NT, DX><<<g, BLK, 0, s>>>(a.n, a.ldy, a.nslice, a.sp, a.sc, a.sd,       \
+                                                 a.sdiag, a.ndiag, a.sv, a.x, a.dinv, a.b,     \
+                                                 a.y, ra, a.role, a.st, (uint8_t *)a.Q,        \
+                                                 a.qscale, a.fmt);
 #define CBG_SELL_CASE(M)                                                                       \
     case M:                                                                                    \
-        if (a.sell_nt) {                                                                       \
-            CBG_SELL_LAUNCH(M, true)                                                           \
+        if (a.sd) {                                                                            \
+            if (a.sell_nt) {                                                                   \
+                CBG_SELL_LAUNCH(M, true, true)                                                 \
+            } else {                                                                           \
+                CBG_SELL_LAUNCH(M, false, true)                                                \
+            }                                                                                  \
+        } else if (a.sell_nt) {                                                                \
+            CBG_SELL_LAUNCH(M, true, false)                                                    \
         } else {                                                                               \
-            CBG_SELL_LAUNCH(M, false)                                                          \
+            CBG_SELL_LAUNCH(M, false, false)                                                   \
         }                                                                                      \
         break;
     switch (a.mode) {
@@ -2507,6 +2673,28 @@ void launch_sell_ptr(int n, const int32_t *rp, int64_t nslice, int64_t *sp, hipS
 {
     k_sell_width<<<grid_for((nslice + NWAVE - 1) / NWAVE, 1), BLK, 0, s>>>(n, rp, nslice, sp);
     k_sell_scan<<<1, SCAN_BLK, 0, s>>>(nslice, sp);
+}
+
+int launch_sell_diag(int n, int64_t nslice, const int64_t *sp, const int32_t *sc, int32_t *diag,
+                     uint8_t *sd, void *ws, hipStream_t s, int32_t *count_host)
+{
+    // ws: the hash table, the overflow flag and the count
+    int32_t *hash = (int32_t *)ws;
+    unsigned *full = (unsigned *)(hash + DIAG_HASH);
+    int32_t *count = (int32_t *)(full + 1);
+    k_fill_i32<<<grid_for(DIAG_HASH + 2, 256), 256, 0, s>>>(hash, DIAG_HASH + 2, DIAG_EMPTY);
+    k_fill_i32<<<1, 64, 0, s>>>((int32_t *)full, 1, 0);
+    const int g = grid_for((nslice + NWAVE - 1) / NWAVE, 1);
+    k_diag_insert<<<g, BLK, 0, s>>>(n, nslice, sp, sc, hash, full);
+    k_diag_collect<<<1, BLK, 0, s>>>(hash, full, diag, count);
+    if (hipMemcpyAsync(count_host, count, sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return -1;
+    if (*count_host < 1 || *count_host > SELL_MAX_DIAG)
+        return 1;
+    k_diag_index<<<g, BLK, 0, s>>>(n, nslice, sp, sc, diag, *count_host, sd);
+    return 0;
 }
 
 void launch_sell_fill(int n, const int32_t *rp, const int32_t *ci, const double *val,

@@ -36,6 +36,9 @@ struct SpmvArgs {
     const int64_t *sp;
     const int32_t *sc;
     const double *sv;
+    const uint8_t *sd;    // diagonal-index columns (with sdiag, ndiag), or null
+    const int32_t *sdiag;
+    int ndiag;
     int64_t nslice;
     int sell_nt;          // stream values and columns past the caches (long rows)
 };
@@ -80,6 +83,10 @@ int orth_grid(int fmt, int64_t n);
 int launch_spmv(const SpmvArgs &a, hipStream_t s);
 bool sell_takes(int mode);                 // modes the sliced-ELL kernel runs
 void launch_sell_ptr(int n, const int32_t *rp, int64_t nslice, int64_t *sp, hipStream_t s);
+// 0: done; 1: more distinct offsets than the diagonal-index form holds
+// (*count_host tells how many); -1: HIP error.  Reads the count back.
+int launch_sell_diag(int n, int64_t nslice, const int64_t *sp, const int32_t *sc, int32_t *diag,
+                     uint8_t *sd, void *ws, hipStream_t s, int32_t *count_host);
 void launch_sell_fill(int n, const int32_t *rp, const int32_t *ci, const double *val,
                       int64_t nslice, const int64_t *sp, int32_t *sc, double *sv, hipStream_t s);
 void launch_multidot(const OrthArgs &a, hipStream_t s);

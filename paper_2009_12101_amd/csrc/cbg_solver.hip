@@ -30,14 +30,26 @@ bool valid_format(int f) { return f >= CBG_FP64 && f <= CBG_FP16S; }
 // the preconditioners whose explicit-residual checks may drop them (M = I)
 bool droppable(int pc) { return pc == CBG_PC_SPARSE || pc == CBG_PC_STENCIL; }
 
-bool has_sell(const cbg_csr *A) { return A->sell_ptr && A->sell_col && A->sell_val; }
+bool has_dix(const cbg_csr *A)
+{
+    return A->sell_dix && A->sell_diag && A->sell_ndiag >= 1 &&
+           A->sell_ndiag <= CBG_SELL_MAX_DIAG;
+}
 
-// the sliced-ELL fields all set or all absent, and the entry count plausible
+bool has_sell(const cbg_csr *A)
+{
+    return A->sell_ptr && A->sell_val && (A->sell_col || has_dix(A));
+}
+
+// the sliced-ELL fields all set or all absent (columns as indices or as
+// diagonal indices), and the entry count plausible
 bool sell_ok(const cbg_csr *A)
 {
-    const bool any = A->sell_ptr || A->sell_col || A->sell_val;
+    const bool any = A->sell_ptr || A->sell_col || A->sell_val || A->sell_dix || A->sell_diag;
     if (!any)
         return true;
+    if ((A->sell_dix || A->sell_diag) && !has_dix(A))
+        return false;
     return has_sell(A) && A->sell_entries >= A->nnz && A->sell_entries % 64 == 0;
 }
 
@@ -52,6 +64,11 @@ void set_matrix(SpmvArgs &a, const cbg_csr *A)
         a.sp = A->sell_ptr;
         a.sc = A->sell_col;
         a.sv = A->sell_val;
+        if (has_dix(A)) {
+            a.sd = A->sell_dix;
+            a.sdiag = A->sell_diag;
+            a.ndiag = A->sell_ndiag;
+        }
         a.nslice = ((int64_t)A->n + 63) / 64;
         a.sell_nt = A->sell_entries > 12 * (int64_t)A->n;
     }
@@ -165,12 +182,13 @@ double now_s()
 struct ByteModel {
     double n, nnz, bs;
     double sell = 0.0;      // entries of the sliced-ELL copy the SpMV reads (0: CSR)
+    double sell_eb = 12.0;  // bytes per entry: value and column (9 with diagonal indices)
     // CSR (values, column indices, row pointers), or the sliced-ELL copy
     // (values, columns, slice offsets), the gathered input and the output
     // vector
     double spmv() const
     {
-        return sell > 0.0 ? 12.0 * sell + 8.0 * (std::floor((n + 63.0) / 64.0) + 1.0) + 16.0 * n
+        return sell > 0.0 ? sell_eb * sell + 8.0 * (std::floor((n + 63.0) / 64.0) + 1.0) + 16.0 * n
                           : 12.0 * nnz + 4.0 * (n + 1) + 16.0 * n;
     }
     // the Arnoldi-step SpMV also stores the previous basis vector
@@ -420,8 +438,10 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
     // steps whose update and re-dot share one basis pass
     auto fused = [&](int j) { return !gram && fuse && fused_takes(fmt, basis_ld(n), j); };
     ByteModel bm{(double)n, (double)A->nnz, (double)fmt_bytes(fmt)};
-    if (has_sell(A))
+    if (has_sell(A)) {
         bm.sell = (double)A->sell_entries;
+        bm.sell_eb = has_dix(A) ? 9.0 : 12.0;
+    }
 
     std::vector<unsigned char> sa_buf(step_arrays_size());
     void *sa = sa_buf.data();
@@ -930,6 +950,28 @@ int cbg_sell_ptr(const cbg_csr *A, int64_t *sell_ptr, int64_t *entries, void *st
     HIP_TRY(hipMemcpyAsync(entries, sell_ptr + nslice, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return CBG_OK;
+}
+
+int cbg_sell_diag(const cbg_csr *A, int32_t *sell_diag, uint8_t *sell_dix, int32_t *ndiag,
+                  void *ws, size_t ws_bytes, void *stream)
+{
+    if (!A || A->n < 0 || !ndiag || !sell_diag || (A->n > 0 && (!A->sell_ptr || !A->sell_col ||
+                                                                !sell_dix)))
+        return CBG_E_ARG;
+    if (!kernel_ws_ok(ws, ws_bytes, 0))
+        return CBG_E_WORKSPACE;
+    *ndiag = 0;
+    const int64_t nslice = ((int64_t)A->n + 63) / 64;
+    if (nslice == 0)
+        return CBG_OK;
+    int32_t count = 0;
+    const int rc = launch_sell_diag(A->n, nslice, A->sell_ptr, A->sell_col, sell_diag, sell_dix,
+                                    ws, (hipStream_t)stream, &count);
+    HIP_TRY(hipGetLastError());
+    if (rc < 0)
+        return CBG_E_HIP;
+    *ndiag = count;
+    return rc == 0 ? CBG_OK : CBG_E_UNSUPPORTED;
 }
 
 int cbg_sell_fill(const cbg_csr *A, const int64_t *sell_ptr, int32_t *sell_col, double *sell_val,

@@ -149,6 +149,26 @@ def test_sell_arguments_rejected_on_host(L):
     Ag = B.CbgCsr(100, 0, 500, 16, 32, 48, 64, 80, 96, 512)
     assert L.cbgmres_solve(C.byref(Ag), vp(64), vp(128), C.byref(opts), None, 0, None,
                            C.byref(res), None, 0) == B.E_WORKSPACE
+    # diagonal-index columns: indices and table together, 1 <= ndiag <= 256;
+    # then the int32 columns may be absent
+    for dix in ((112, None, 27), (None, 128, 27), (112, 128, 0), (112, 128, 257)):
+        Ad = B.CbgCsr(100, 0, 500, 16, 32, 48, 64, 80, 96, 512, *dix)
+        assert L.cbgmres_solve(C.byref(Ad), vp(64), vp(128), C.byref(opts), None, 0, None,
+                               C.byref(res), None, 0) == B.E_ARG
+    Ad = B.CbgCsr(100, 0, 500, 16, 32, 48, 64, None, 96, 512, 112, 128, 27)
+    assert L.cbgmres_solve(C.byref(Ad), vp(64), vp(128), C.byref(opts), None, 0, None,
+                           C.byref(res), None, 0) == B.E_WORKSPACE
+    Ad = B.CbgCsr(100, 0, 500, 16, 32, 48, 64, None, 96, 512)     # no columns at all
+    assert L.cbg_spmv(C.byref(Ad), vp(16), vp(32), None, None, 0, None) == B.E_ARG
+    # cbg_sell_diag: pointers, then the workspace
+    nd = C.c_int32(-1)
+    assert L.cbg_sell_diag(C.byref(Ag), None, vp(64), C.byref(nd), vp(256), 1 << 20,
+                           None) == B.E_ARG
+    assert L.cbg_sell_diag(C.byref(Ag), vp(64), None, C.byref(nd), vp(256), 1 << 20,
+                           None) == B.E_ARG
+    assert L.cbg_sell_diag(C.byref(Ag), vp(64), vp(64), None, vp(256), 1 << 20, None) == B.E_ARG
+    assert L.cbg_sell_diag(C.byref(Ag), vp(64), vp(64), C.byref(nd), None, 0, None) == \
+        B.E_WORKSPACE
 
 
 def test_variant_names_map_to_flags():

@@ -121,7 +121,7 @@ def test_spmv_parity(cbg, orc, dev, name, sell):
     A, _, _ = P.workload(name)
     x = np.random.default_rng(1).standard_normal(A.n)
     D = cbg.DeviceCSR.from_host(A, dev, sell=sell)
-    assert (D.sell_col is not None) == sell
+    assert (D.sell_val is not None) == sell
     y, nrm = cbg.spmv(D, torch.from_numpy(x).to(dev), want_norm=True)
     y = y.cpu().numpy()
     yo = orc.spmv(A, x)

@@ -4,8 +4,11 @@
   layout in include/cbgmres.h defines (built here in numpy from that
   definition), on stencil matrices, on n not a multiple of 64 (ragged last
   slice), on irregular rows (empty rows, one long row, a diagonal-only
-  matrix) and on n = 1.
-* SpMV: y = A x on the copy equals the oracle's row-sequential CSR sum bit
+  matrix) and on n = 1; cbg_sell_diag gives the sorted distinct offsets
+  col - row (0 included) and each entry's index, or refuses a matrix with
+  more than 256 of them.
+* SpMV: y = A x on the copy (int32 columns, and diagonal indices where the
+  matrix allows them) equals the oracle's row-sequential CSR sum bit
   for bit (products and sums rounded separately, in CSR order; padding adds
   0 * x_row), on the same matrices and on the 27-point 160^3 system the
   benchmark solves (n = 4,096,000, the launch configuration of the solve).
@@ -102,18 +105,67 @@ CASES = cases()
 @pytest.mark.parametrize("name,A", CASES, ids=[c[0] for c in CASES])
 def test_sell_layout(cbg, dev, name, A):
     print(f"sell layout {name} n={A.n} nnz={A.nnz}", flush=True)
-    D = cbg.DeviceCSR.from_host(A, dev, sell=True)
+    D = cbg.DeviceCSR.from_host(A, dev, sell=True, diag=False)
     ptr, col, val = sell_reference(A)
     assert np.array_equal(D.sell_ptr.cpu().numpy(), ptr)
     assert D.sell_entries == ptr[-1]
     assert np.array_equal(D.sell_col.cpu().numpy(), col)
     assert np.array_equal(D.sell_val.cpu().numpy().view(np.uint64), val.view(np.uint64))
+    assert D.sell_dix is None
+
+
+def diag_reference(A, ptr, col):
+    """Per entry the offset col - row (0 for rows >= n), and the sorted
+    distinct offsets with 0 included."""
+    ns = len(ptr) - 1
+    off = np.empty(len(col), np.int64)
+    for s in range(ns):
+        w = (ptr[s + 1] - ptr[s]) // 64
+        rows = 64 * s + np.arange(64)
+        blk = col[ptr[s]:ptr[s + 1]].reshape(w, 64).astype(np.int64) - rows
+        blk[:, rows >= A.n] = 0
+        off[ptr[s]:ptr[s + 1]] = blk.reshape(-1)
+    return off, np.unique(np.concatenate([off, [0]]))
 
 
 @pytest.mark.parametrize("name,A", CASES, ids=[c[0] for c in CASES])
-def test_sell_spmv_bit_exact(cbg, orc, dev, name, A):
-    print(f"sell spmv {name} n={A.n}", flush=True)
-    D = cbg.DeviceCSR.from_host(A, dev, sell=True)
+def test_sell_diag_layout(cbg, dev, name, A):
+    print(f"sell diag layout {name} n={A.n}", flush=True)
+    D = cbg.DeviceCSR.from_host(A, dev, sell=True, diag=True)
+    ptr, col, _ = sell_reference(A)
+    off, uniq = diag_reference(A, ptr, col)
+    if len(uniq) > 256:
+        assert D.sell_dix is None and D.sell_col is not None      # refused: int32 columns
+        return
+    assert D.sell_ndiag == len(uniq)
+    assert np.array_equal(D.sell_diag.cpu().numpy()[:len(uniq)], uniq)
+    dix = D.sell_dix.cpu().numpy()
+    assert np.array_equal(uniq[dix], off)
+    assert D.sell_col is None                                     # dropped with the indices
+
+
+def test_sell_diag_refuses_many_offsets(cbg, dev):
+    """300 distinct offsets: cbg_sell_diag reports the count (at least 257)
+    and refuses; the copy keeps int32 columns and stays bit-exact."""
+    from paper_2009_12101_amd.problems import CSR
+    n = 600
+    rp, ci, va = [0], [], []
+    for i in range(n):
+        cols = sorted({i, (i + 1 + (i % 300)) % n})
+        ci += cols
+        va += [3.0 if c == i else -1.0 for c in cols]
+        rp.append(len(ci))
+    A = CSR(n, np.array(rp, np.int32), np.array(ci, np.int32), np.array(va))
+    D = cbg.DeviceCSR.from_host(A, dev, sell=True, diag=True)
+    assert D.sell_dix is None and D.sell_col is not None
+
+
+@pytest.mark.parametrize("diag", [False, True], ids=["col", "dix"])
+@pytest.mark.parametrize("name,A", CASES, ids=[c[0] for c in CASES])
+def test_sell_spmv_bit_exact(cbg, orc, dev, name, A, diag):
+    print(f"sell spmv {name} n={A.n} diag={diag}", flush=True)
+    D = cbg.DeviceCSR.from_host(A, dev, sell=True, diag=diag)
+    assert (D.sell_dix is not None) == (diag and name != "irregular_1000")
     for seed in (0, 1):
         x = np.random.default_rng(seed).standard_normal(A.n) * 10.0 ** np.random.default_rng(
             seed + 9).uniform(-3, 3, A.n)
@@ -136,7 +188,7 @@ def test_sell_auto_keeps_csr_when_padding_is_large(cbg, dev):
         rp.append(len(ci))
     A = CSR(n, np.array(rp, np.int32), np.array(ci, np.int32), np.array(va))
     assert A.nnz == 382
-    assert cbg.DeviceCSR.from_host(A, dev).sell_col is None
+    assert cbg.DeviceCSR.from_host(A, dev).sell_val is None
     D = cbg.DeviceCSR.from_host(A, dev, sell=True)
     assert D.sell_entries == 64 * n + 64 * 2
 
@@ -148,7 +200,8 @@ def test_sell_spmv_fullsize_160(cbg, orc, dev):
     A = P.lognormal27(160, 0)
     print(f"sell spmv 160^3 n={A.n} nnz={A.nnz}", flush=True)
     D = cbg.DeviceCSR.from_host(A, dev)
-    assert D.sell_col is not None and D.sell_entries < 1.01 * A.nnz
+    assert D.sell_dix is not None and D.sell_ndiag == 27
+    assert D.sell_entries < 1.01 * A.nnz
     x = P.rhs_uniform(A.n, 5)
     y = cbg.spmv(D, torch.from_numpy(x).to(dev)).cpu().numpy()
     yo = orc.spmv(A, x)
@@ -164,8 +217,8 @@ def test_solve_with_and_without_sell(cbg, orc, dev, name):
     o = orc.gmres(A, b, restart=30, fmt="fp64", tol=1e-10, maxiter=3000)
     bd = torch.from_numpy(b).to(dev)
     its = []
-    for sell in (True, False):
-        D = cbg.DeviceCSR.from_host(A, dev, sell=sell)
+    for sell, diag in ((True, True), (True, False), (False, False)):
+        D = cbg.DeviceCSR.from_host(A, dev, sell=sell, diag=diag)
         r = cbg.solve(D, bd, restart=30, fmt="fp64", tol=1e-10, maxiter=3000)
         assert r.status == 0
         x = r.x.cpu().numpy()
