@@ -124,7 +124,7 @@ def kernel_pattern(cfg: Config) -> str:
     """Substring of the roofline kernel's name in rocprofv3 outputs."""
     if cfg.kernel == "multidot":
         return f"k_multidot<{FMT_ID[cfg.fmt]}, true>"
-    return "k_spmv_sell<0, true>"   # the step SpMV on the sliced-ELL copy (27-point rows)
+    return "k_spmv_sell<0, true"    # the step SpMV on the sliced-ELL copy (27-point rows)
 
 
 def pmc_summary(fetch_csv: str, write_csv: str, cfg: Config) -> dict:
@@ -200,7 +200,9 @@ def trace_summary(trace_csv: str, cfg: Config) -> dict:
         lens = np.zeros(-(-n // 64) * 64, dtype=np.int64)
         lens[:n] = np.diff(A.row_ptr)
         entries = 64 * int(lens.reshape(-1, 64).max(axis=1).sum())
-        sp_bytes = 12.0 * entries + 8.0 * (len(lens) // 64 + 1) + 16.0 * n
+        targs = step_spmv.split("<", 1)[1].split(">", 1)[0].split(",")
+        per_entry = 9.0 if targs[2].strip() == "true" else 12.0    # diagonal indices or int32
+        sp_bytes = per_entry * entries + 8.0 * (len(lens) // 64 + 1) + 16.0 * n
     else:
         sp_bytes = 12.0 * nnz + 4.0 * (n + 1) + 16.0 * n
     sp_bytes += n * bs if gather else 0.0
