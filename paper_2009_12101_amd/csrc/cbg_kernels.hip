@@ -2380,7 +2380,10 @@ __global__ __launch_bounds__(BLK) void k_stencil(const double *__restrict__ w, i
         // weight 0
         const int64_t ic = min(i, (int64_t)n - 1);
         uint32_t cc[27];
-        double lv[9], lt[9];
+        // the nine lines, 9 x ST_LINE entries, in flat order: entry f of
+        // the staging goes to line f / ST_LINE, position f % ST_LINE
+        constexpr int NLD = (9 * ST_LINE + BLK - 1) / BLK;
+        double lv[NLD];
         if constexpr (BUF) {
             // buffer loads: the codes' slot offset in a scalar register
             // (one vector offset for all 27), and w's line entries outside
@@ -2394,18 +2397,12 @@ __global__ __launch_bounds__(BLK) void k_stencil(const double *__restrict__ w, i
             for (int p = 0; p < 27; ++p)
                 cc[p] = __builtin_amdgcn_raw_buffer_load_b16(rc, vo, (int)(p * ld * 2), 0);
 #pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                const int64_t e = r0 + (k / 3 - 1) * S + (k % 3 - 1) * (int64_t)nx - 1 + tid;
-                lv[k] = __builtin_bit_cast(
-                    double, __builtin_amdgcn_raw_buffer_load_b64(rw, (uint32_t)(e * 8), 0, 0));
-            }
-            if (tid < ST_LINE - BLK) {              // the lines' last two entries
-#pragma unroll
-                for (int k = 0; k < 9; ++k) {
-                    const int64_t e = r0 + (k / 3 - 1) * S + (k % 3 - 1) * (int64_t)nx - 1 + BLK + tid;
-                    lt[k] = __builtin_bit_cast(
-                        double, __builtin_amdgcn_raw_buffer_load_b64(rw, (uint32_t)(e * 8), 0, 0));
-                }
+            for (int q = 0; q < NLD; ++q) {
+                const int f = min(tid + q * BLK, 9 * ST_LINE - 1);
+                const int k = f / ST_LINE, e = f - k * ST_LINE;
+                const int64_t g = r0 + (k / 3 - 1) * S + (k % 3 - 1) * (int64_t)nx - 1 + e;
+                lv[q] = __builtin_bit_cast(
+                    double, __builtin_amdgcn_raw_buffer_load_b64(rw, (uint32_t)(g * 8), 0, 0));
             }
         } else {
             // indices clamped into the arrays
@@ -2413,26 +2410,19 @@ __global__ __launch_bounds__(BLK) void k_stencil(const double *__restrict__ w, i
             for (int p = 0; p < 27; ++p)
                 cc[p] = codes[(int64_t)p * ld + ic];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                const int64_t base = r0 + (k / 3 - 1) * S + (k % 3 - 1) * (int64_t)nx - 1;
-                lv[k] = w[min(max(base + tid, (int64_t)0), (int64_t)n - 1)];
-            }
-            if (tid < ST_LINE - BLK) {
-#pragma unroll
-                for (int k = 0; k < 9; ++k) {
-                    const int64_t base = r0 + (k / 3 - 1) * S + (k % 3 - 1) * (int64_t)nx - 1;
-                    lt[k] = w[min(max(base + BLK + tid, (int64_t)0), (int64_t)n - 1)];
-                }
+            for (int q = 0; q < NLD; ++q) {
+                const int f = min(tid + q * BLK, 9 * ST_LINE - 1);
+                const int k = f / ST_LINE, e = f - k * ST_LINE;
+                const int64_t g = r0 + (k / 3 - 1) * S + (k % 3 - 1) * (int64_t)nx - 1 + e;
+                lv[q] = w[min(max(g, (int64_t)0), (int64_t)n - 1)];
             }
         }
         __syncthreads();                            // lw free from the previous tile
 #pragma unroll
-        for (int k = 0; k < 9; ++k)
-            lw[k][tid] = lv[k];
-        if (tid < ST_LINE - BLK) {
-#pragma unroll
-            for (int k = 0; k < 9; ++k)
-                lw[k][BLK + tid] = lt[k];
+        for (int q = 0; q < NLD; ++q) {
+            const int f = tid + q * BLK;
+            if (f < 9 * ST_LINE)
+                (&lw[0][0])[f] = lv[q];
         }
         // which of the three offsets along each axis exist for this row
         const uint32_t u = live ? (uint32_t)i : 0u, row = u / (uint32_t)nx;
