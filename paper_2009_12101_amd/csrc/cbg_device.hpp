@@ -284,6 +284,28 @@ __device__ __forceinline__ double wave_max(double x)
     return x;
 }
 
+// Row i's diagonal entry (the last one in CSR order if stored twice, 0 if
+// none), read by a half-wave (32 lanes) on the row's entries l, l + 32, ...
+// and returned on every lane of it; `chunks` (the row's 32-entry chunks) is
+// uniform over the wave.
+__device__ __forceinline__ double hw_row_diag(int64_t i, int beg, int end, int chunks,
+                                              const int32_t *__restrict__ ci,
+                                              const double *__restrict__ val)
+{
+    const int lane = threadIdx.x & 31, half = threadIdx.x & 32;
+    double d = 0.0;
+    for (int q = 0; q < chunks; ++q) {
+        const int p = beg + q * 32 + lane;
+        const bool hit = p < end && ci[p] == i;
+        const double v = hit ? val[p] : 0.0;
+        const uint32_t mine = (uint32_t)(__ballot(hit) >> half);
+        const double last = __shfl(v, half + (mine ? 31 - __clz(mine) : 0));
+        if (mine)
+            d = last;
+    }
+    return d;
+}
+
 // The value of lane (l xor P>>10) for an immediate ds_swizzle bit-mask
 // pattern P (and-mask 31, or-mask 0, xor-mask P>>10: the partner within the
 // lane's 32-lane half, no address arithmetic).

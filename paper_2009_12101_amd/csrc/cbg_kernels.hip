@@ -244,22 +244,31 @@ __global__ void k_init_state(DevState *st, int n, int m, int fmt, double tol, do
     }
 }
 
-// dinv_i = 1 / a_ii (Jacobi); rows >= n get 0.  bad != 0 if a diagonal entry
-// is missing, zero or not finite.
-__global__ void k_jacobi_setup(int n, int64_t ld, const int32_t *__restrict__ rp,
-                               const int32_t *__restrict__ ci, const double *__restrict__ val,
-                               double *__restrict__ dinv, unsigned *bad)
+// dinv_i = 1 / a_ii (Jacobi), a_ii the row's last diagonal entry in CSR
+// order; rows in [n, ld) get 0.  bad != 0 if a diagonal entry is missing,
+// zero or not finite.  A half-wave per row reads its indices as one
+// contiguous run.
+__global__ __launch_bounds__(BLK) void k_jacobi_setup(int n, int64_t ld,
+                                                      const int32_t *__restrict__ rp,
+                                                      const int32_t *__restrict__ ci,
+                                                      const double *__restrict__ val,
+                                                      double *__restrict__ dinv, unsigned *bad)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < ld;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        if (i >= n) {
+    constexpr int RPB = BLK / 32;                   // rows per block
+    const int g = threadIdx.x >> 5, lane = threadIdx.x & 31;
+    for (int64_t base = (int64_t)blockIdx.x * RPB; base < ld; base += (int64_t)gridDim.x * RPB) {
+        const int64_t i = base + g;
+        const bool live = i < n;
+        const int beg = live ? rp[i] : 0, end = live ? rp[i + 1] : 0;
+        const int ch = (end - beg + 31) / 32;
+        const int chunks = max(ch, __shfl_xor(ch, 32));          // uniform over the wave
+        const double d = hw_row_diag(i, beg, end, chunks, ci, val);
+        if (lane != 0 || i >= ld)
+            continue;
+        if (!live) {
             dinv[i] = 0.0;
             continue;
         }
-        double d = 0.0;
-        for (int p = rp[i]; p < rp[i + 1]; ++p)
-            if (ci[p] == i)
-                d = val[p];
         if (d == 0.0 || !isfinite(d))
             atomicOr(bad, 1u);
         dinv[i] = 1.0 / d;
@@ -2991,7 +3000,9 @@ void launch_init_state(DevState *st, int n, int m, int fmt, double tol, double e
 void launch_jacobi_setup(int n, int64_t ld, const int32_t *rp, const int32_t *ci,
                          const double *val, double *dinv, unsigned *bad, hipStream_t s)
 {
-    k_jacobi_setup<<<grid_for(ld, BLK), BLK, 0, s>>>(n, ld, rp, ci, val, dinv, bad);
+    const int g = (int)std::min<int64_t>(std::max<int64_t>((ld + BLK / 32 - 1) / (BLK / 32), 1),
+                                         65536);
+    k_jacobi_setup<<<g, BLK, 0, s>>>(n, ld, rp, ci, val, dinv, bad);
 }
 
 __global__ void k_clear_flags(DevState *st, unsigned *bad)

@@ -125,26 +125,6 @@ __device__ __forceinline__ int block_chunks(int chunks)
     return r;
 }
 
-// Row i's diagonal entry (the last one in CSR order if stored twice, 0 if
-// none), on every lane of the half-wave; `chunks` is uniform over the wave.
-__device__ __forceinline__ double hw_row_diag(int64_t i, int beg, int end, int chunks,
-                                              const int32_t *__restrict__ ci,
-                                              const double *__restrict__ val)
-{
-    const int lane = threadIdx.x & 31, half = threadIdx.x & 32;
-    double d = 0.0;
-    for (int q = 0; q < chunks; ++q) {
-        const int p = beg + q * 32 + lane;
-        const bool hit = p < end && ci[p] == i;
-        const double v = hit ? val[p] : 0.0;
-        const uint32_t mine = (uint32_t)(__ballot(hit) >> half);
-        const double last = __shfl(v, half + (mine ? 31 - __clz(mine) : 0));
-        if (mine)
-            d = last;
-    }
-    return d;
-}
-
 // The diagonal of A (0 where a row stores none).
 __global__ __launch_bounds__(256) void k_diag(int n, const int32_t *__restrict__ rp,
                                               const int32_t *__restrict__ ci,
@@ -164,12 +144,21 @@ __global__ __launch_bounds__(256) void k_diag(int n, const int32_t *__restrict__
     }
 }
 
+// Orders a wave's LDS accesses across its lanes (its half-waves keep their
+// rows in LDS regions of their own, so no block barrier is needed).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Features of each row: f_p = fl32(a_{i,c(p)} / a_ii) and f_{32+p} =
 // fl32(a_{c(p),c(p)} / a_ii) on present slots, f_27 = fl32((a_ii -
 // sum_{c != i} |a_ic|) / a_ii) with the sum in CSR order, the rest 0; all
-// rounded to bf16.  The entries' terms go through LDS; one lane adds them
-// in CSR order.  (Columns are unique within a row, so each slot is written
-// at most once.)
+// rounded to bf16.  The entries' terms go through the half-wave's own LDS
+// region; one lane adds them in CSR order.  (Columns are unique within a
+// row, so each slot is written at most once.)
 __global__ __launch_bounds__(256) void k_features(int n, const int32_t *__restrict__ rp,
                                                   const int32_t *__restrict__ ci,
                                                   const double *__restrict__ val, int nx, int ny,
@@ -178,48 +167,44 @@ __global__ __launch_bounds__(256) void k_features(int n, const int32_t *__restri
                                                   unsigned *__restrict__ bad)
 {
     __shared__ double loff[HWR][32];
-    __shared__ uint16_t lf[HWR][NF];
+    __shared__ uint32_t lfw[HWR][NF / 2];
     const int g = threadIdx.x >> 5, lane = threadIdx.x & 31;
-    for (int64_t base = (int64_t)blockIdx.x * HWR; base < n; base += (int64_t)gridDim.x * HWR) {
-        const int64_t i = base + g;
-        const bool live = i < n;
-        const int beg = live ? rp[i] : 0, end = live ? rp[i + 1] : 0;
-        const double d = live ? diag[i] : 1.0;
-        const RowPos rpos = row_pos(live ? i : 0, nx, ny);
-        lf[g][2 * lane] = 0;
-        lf[g][2 * lane + 1] = 0;
-        const int chunks = block_chunks((end - beg + 31) / 32);
+    uint16_t *lf = (uint16_t *)lfw[g];
+    for (int64_t i = (int64_t)blockIdx.x * HWR + g; i < n; i += (int64_t)gridDim.x * HWR) {
+        const int beg = rp[i], end = rp[i + 1];
+        const double d = diag[i];
+        const RowPos rpos = row_pos(i, nx, ny);
+        lfw[g][lane] = 0u;
+        wave_sync();
         double off = 0.0;
-        for (int q = 0; q < chunks; ++q) {
-            const int p = beg + q * 32 + lane;
+        for (int p0 = beg; p0 < end; p0 += 32) {
+            const int p = p0 + lane;
             const bool in = p < end;
             const int64_t c = in ? ci[p] : -1;
             const double a = in ? val[p] : 0.0;
             loff[g][lane] = (in && c != i) ? fabs(a) : 0.0;
             const int s = in ? slot_at(rpos, i, c, nx, ny) : -1;
             if (s >= 0) {
-                lf[g][s] = bf16_of((float)(a / d));
-                lf[g][NBR + s] = bf16_of((float)(diag[c] / d));
+                lf[s] = bf16_of((float)(a / d));
+                lf[NBR + s] = bf16_of((float)(diag[c] / d));
             }
-            __syncthreads();
+            wave_sync();
             if (lane == 0) {
-                const int m = min(32, end - (beg + q * 32));
+                const int m = min(32, end - p0);
                 for (int k = 0; k < m; ++k)
                     off += loff[g][k];
             }
-            __syncthreads();
+            wave_sync();
         }
-        if (lane == 0 && live) {
+        if (lane == 0) {
             const double margin = (d - off) / d;
             if (!(d != 0.0) || !isfinite(margin))
                 *bad = 1u;
-            lf[g][27] = bf16_of((float)margin);
+            lf[27] = bf16_of((float)margin);
         }
-        __syncthreads();
-        if (live)
-            ((uint32_t *)(feat + i * NF))[lane] =
-                (uint32_t)lf[g][2 * lane] | ((uint32_t)lf[g][2 * lane + 1] << 16);
-        __syncthreads();
+        wave_sync();
+        ((uint32_t *)(feat + i * NF))[lane] = lfw[g][lane];
+        wave_sync();
     }
 }
 
@@ -398,37 +383,47 @@ __device__ __forceinline__ uint16_t f16_code(float f)
     return (uint16_t)(rne_code<10, -14, 15>(v) | (sign_of(v) << 15));
 }
 
-// The stored form of the learned preconditioner (CBG_PC_STENCIL): codes[p
-// ld + i] = f16(O_{i,p}) for the slots p row i stores, 0 for the other
-// slots and for rows [n, ld) (a half-wave per row; the row's 27 codes are
-// assembled in LDS, then written one per lane).
+// The stored form's codes: on the slots present in A's row the float16 code
+// of O[i][slot], 0 on the others and on rows in [n, ld); slot-major with row
+// stride ld.  A block takes PK_ROWS consecutive rows: each half-wave walks
+// PK_ROWS / 8 of them (one entry per lane) and puts the row's codes in LDS,
+// slot-major; the block then writes each slot's run of PK_ROWS codes with
+// one 4-byte store per two rows.
+constexpr int PK_ROWS = 128;
+constexpr int PK_LD = PK_ROWS + 2;      // LDS row stride: a half-wave's 27 slots in 27 banks
+
 __global__ __launch_bounds__(256) void k_stencil_pack(int n, int64_t ld,
                                                       const int32_t *__restrict__ rp,
                                                       const int32_t *__restrict__ ci, int nx,
                                                       int ny, const float *__restrict__ O,
                                                       uint16_t *__restrict__ codes)
 {
-    __shared__ uint16_t lc[HWR][NO];
+    __shared__ uint32_t lcw[NSLOT * PK_LD / 2];
+    uint16_t *lc = (uint16_t *)lcw;
     const int g = threadIdx.x >> 5, lane = threadIdx.x & 31;
-    for (int64_t base = (int64_t)blockIdx.x * HWR; base < ld; base += (int64_t)gridDim.x * HWR) {
-        const int64_t i = base + g;
-        const bool live = i < n;
-        const int beg = live ? rp[i] : 0, end = live ? rp[i + 1] : 0;
-        const int chunks = block_chunks((end - beg + 31) / 32);
-        const RowPos rpos = row_pos(live ? i : 0, nx, ny);
-        lc[g][lane] = 0;
+    for (int64_t base = (int64_t)blockIdx.x * PK_ROWS; base < ld;
+         base += (int64_t)gridDim.x * PK_ROWS) {
+        for (int e = threadIdx.x; e < NSLOT * PK_LD / 2; e += blockDim.x)
+            lcw[e] = 0u;
         __syncthreads();
-        for (int q = 0; q < chunks; ++q) {
-            const int p = beg + q * 32 + lane;
-            if (p < end) {
+        for (int r = g; r < PK_ROWS && base + r < n; r += HWR) {
+            const int64_t i = base + r;
+            const int beg = rp[i], end = rp[i + 1];
+            const RowPos rpos = row_pos(i, nx, ny);
+            for (int p = beg + lane; p < end; p += 32) {
                 const int sl = slot_at(rpos, i, ci[p], nx, ny);
                 if (sl >= 0)
-                    lc[g][sl] = f16_code(O[i * NO + sl]);
+                    lc[sl * PK_LD + r] = f16_code(O[i * NO + sl]);
             }
         }
         __syncthreads();
-        if (i < ld && lane < NSLOT)
-            codes[(int64_t)lane * ld + i] = lc[g][lane];
+        // ld is even and base a multiple of PK_ROWS: every pair starts 4-byte aligned
+        for (int e = threadIdx.x; e < NSLOT * (PK_ROWS / 2); e += blockDim.x) {
+            const int sl = e / (PK_ROWS / 2), r = 2 * (e - sl * (PK_ROWS / 2));
+            const int64_t i = base + r;
+            if (i < ld)
+                *(uint32_t *)(codes + (int64_t)sl * ld + i) = lcw[(sl * PK_LD + r) / 2];
+        }
         __syncthreads();
     }
 }
@@ -1132,7 +1127,8 @@ int cbg_learned_build_stencil(const cbg_csr *A, const int32_t grid[3], const uin
                        A->col_idx, A->val, grid[0], grid[1], (const double *)W.diag, W.feat,
                        W.bad);
     enqueue_forward(A->n, W.feat, weights, params, W.O, nullptr, nullptr, s);
-    hipLaunchKernelGGL(k_stencil_pack, dim3(group_grid(ld)), dim3(256), 0, s, A->n, ld,
+    const int gp = (int)std::min<int64_t>((ld + PK_ROWS - 1) / PK_ROWS, MAXB_ROW);
+    hipLaunchKernelGGL(k_stencil_pack, dim3(std::max(gp, 1)), dim3(256), 0, s, A->n, ld,
                        A->row_ptr, A->col_idx, grid[0], grid[1], (const float *)W.O, p_stencil);
     SP_TRY(hipGetLastError());
     unsigned bad = 0;
