@@ -2951,7 +2951,10 @@ void launch_stencil(int fmt, int mode, const double *w, int n, int64_t ld, const
                     const uint16_t *codes, const double *dinv, double *z, void *Q,
                     const double *scale_slot, const DevState *st, hipStream_t s)
 {
-    const int g = grid_for((ld + BLK - 1) / BLK, 1);
+    // one tile per block (no block partials here): a block's loads, barrier
+    // and sums are not serialised over several tiles, which measured about
+    // 10% faster at 160^3 than 4096 blocks looping over 16,000 tiles
+    const int g = (int)std::min<int64_t>(std::max<int64_t>((ld + BLK - 1) / BLK, 1), 65536);
     // buffer loads while the codes' byte range and w's fit the 32-bit
     // offsets of a buffer resource (ld below about 39.7 million)
     const bool buf = 27 * ld * 2 <= (int64_t)INT32_MAX - 16;

@@ -4,15 +4,21 @@ workloads that tests/test_gpu_configs.py (27-point lognormal diffusion) and
 tests/test_gpu_fullsize.py (7-point convection-diffusion) run for one
 restart cycle.
 
-For each case (system, grid N, restart m, storage format) the oracle (Fig. 1
-as written) runs one cycle on b ~ U[-1, 1] (seed 0) and on NPERT copies
+For each case (system, grid N, restart m, storage format, preconditioner)
+the oracle (Fig. 1 as written) runs one cycle on b ~ U[-1, 1] (seed 0) and
+on NPERT copies
 b_p = b (1 + 1e-15 z_p), z_p ~ N(0, 1) (numpy seed 1000 + p).  Two correct
 implementations of the same iteration differ by rounding only, like these
 runs, so the largest relative deviation max_p |r_p / r_0 - 1| of the
 end-of-cycle residual r is the scale of the GPU-vs-oracle band.  Only the
 oracle runs here.
 
-    python tests/golden/make_cycle_spread.py      # about 40 min on 8 cores
+    python tests/golden/make_cycle_spread.py      # about 50 min on 8 cores
+    python tests/golden/make_cycle_spread.py KEY ...   # only these cases
+
+The "stencil" case is the learned preconditioner's stored form with
+synthetic corrections: float16 codes of O = 0.05 z, z ~ N(0, 1) (numpy seed
+7, n x 32 fp32), on the slots each row stores (stencil_codes).
 """
 import json
 import os
@@ -28,43 +34,63 @@ sys.path.insert(0, ROOT)
 import oracle as orc                                   # noqa: E402
 from paper_2009_12101_amd import problems as P         # noqa: E402
 
-CASES = [("convdiff7", 128, 100, "fp16"),
-         ("lognormal27", 128, 100, "bf16"), ("lognormal27", 128, 100, "e4m3"),
-         ("lognormal27", 160, 200, "fp16"), ("lognormal27", 160, 200, "int16"),
-         ("lognormal27", 160, 200, "fp64")]
+CASES = [("convdiff7", 128, 100, "fp16", "none"),
+         ("lognormal27", 128, 100, "bf16", "none"), ("lognormal27", 128, 100, "e4m3", "none"),
+         ("lognormal27", 160, 200, "fp16", "none"), ("lognormal27", 160, 200, "int16", "none"),
+         ("lognormal27", 160, 200, "fp64", "none"),
+         ("lognormal27", 160, 200, "fp16", "stencil")]
 NPERT = 8
+
+
+def case_key(name, N, m, fmt, pc):
+    return f"{name}_{N}_{m}_{fmt}" + ("" if pc == "none" else f"_{pc}")
 
 
 def perturbed(b, p):
     return b * (1.0 + 1e-15 * np.random.default_rng(1000 + p).standard_normal(b.size))
 
 
-def main():
+def synthetic_stencil_codes(A):
+    """The stencil case's codes (27 x ld, ld = n rounded up to 256)."""
+    from oracle import spai as S
+    O = (0.05 * np.random.default_rng(7).standard_normal((A.n, 32))).astype(np.float32)
+    return S.stencil_codes(A, A.grid, O, A.n + (-A.n) % 256)
+
+
+def main(keys):
+    path = os.path.join(HERE, "cycle_spread.json")
     out = {"npert": NPERT, "perturbation": "b (1 + 1e-15 z), z ~ N(0,1), numpy seed 1000 + p",
            "threads": orc.get_threads(), "cases": {}}
+    if keys:
+        out["cases"] = json.load(open(path))["cases"]
     systems = {}
-    for name, N, m, fmt in CASES:
+    for name, N, m, fmt, pc in CASES:
+        key = case_key(name, N, m, fmt, pc)
+        if keys and key not in keys:
+            continue
         if (name, N) not in systems:
             systems.clear()
             A = P.lognormal27(N, 0) if name == "lognormal27" else P.convdiff7(N)
             systems[(name, N)] = (A, P.rhs_uniform(A.n, 0))
         A, b = systems[(name, N)]
+        kw = {}
+        if pc == "stencil":
+            kw = dict(precond="stencil", p_stencil=synthetic_stencil_codes(A), grid=A.grid)
         t0 = time.time()
         res = []
         for p in range(-1, NPERT):
             bp = b if p < 0 else perturbed(b, p)
-            r = orc.gmres(A, bp, restart=m, fmt=fmt, tol=1e-10, maxiter=m)
+            r = orc.gmres(A, bp, restart=m, fmt=fmt, tol=1e-10, maxiter=m, **kw)
             res.append(float(r["hist"][m - 1]))
         r0 = res[0]
         dev = [abs(r / r0 - 1.0) for r in res[1:]]
-        key = f"{name}_{N}_{m}_{fmt}"
         out["cases"][key] = {"end_of_cycle_residual": r0, "perturbed": res[1:],
                              "max_rel_deviation": max(dev)}
         print(f"{key}: r0 = {r0:.4e}, max deviation {max(dev):.3e} "
               f"({time.time() - t0:.0f} s)", flush=True)
-    with open(os.path.join(HERE, "cycle_spread.json"), "w") as f:
+    with open(path, "w") as f:
         json.dump(out, f, indent=1)
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1:])
