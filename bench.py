@@ -26,7 +26,9 @@ The comparison solves run after the timed region.
 Prints one JSON line.  `value` is the headline solve's time to solution
 (seconds, lower is better).  `roofline` covers the dominant kernel of the
 configuration, HIP events recorded at each launch's own start and end in
-the timed solves: the multi-dot h = V^T w with the Gram row on D1/D2 (bytes
+the timed solves, on every 8th Arnoldi step's launch (an event pair delays
+the launch it brackets by a few microseconds; `--events all` times every
+launch): the multi-dot h = V^T w with the Gram row on D1/D2 (bytes
 j n b_s + 8 n + n b_s per launch), the step SpMV with A on D3-D5, which
 reads the sliced-ELL copy of A (12 e + 8 (n/64 + 1) + 16 n: values and
 columns of the e stored entries, slice offsets, the gathered input and the
@@ -327,6 +329,9 @@ def main() -> int:
                     help="run a plain 256 MiB device copy first (counter calibration)")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the roofline kernel's traffic record from two counter runs")
+    ap.add_argument("--events", choices=["sampled", "all"], default="sampled",
+                    help="roofline kernel's launches timed with HIP events in the timed solves: "
+                         "every 8th Arnoldi step's (default) or all")
     ap.add_argument("--trace-summary", metavar="KERNEL_TRACE_CSV",
                     help="print per-j rates of the step kernels from a kernel trace and exit")
     args = ap.parse_args()
@@ -426,7 +431,8 @@ def main() -> int:
         return cbg.solve(Ad, bd, restart=m, fmt=fmt, tol=tol, maxiter=maxiter, precond=pc,
                          profile=profile, workspace=ws, hist=False, variant=variant)
 
-    prof_kind = "dot" if cfg.kernel == "multidot" else "spmv"
+    prof_kind = ("dot" if cfg.kernel == "multidot" else "spmv") + \
+        ("/sampled" if args.events == "sampled" else "")
     for _ in range(args.warmup):
         one(cfg.fmt, cfg.precond, prof_kind)
     torch.cuda.synchronize()
@@ -579,6 +585,9 @@ def main() -> int:
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                      "kernel": k_name, "launches": k_launch,
+                     "timed_launches": ("every 8th Arnoldi step's launch in the timed solves"
+                                        if args.events == "sampled" else
+                                        "every launch in the timed solves"),
                      "copy_gbps": copy_gbps, "frac_of_copy": achieved / copy_gbps,
                      "avg_launch_us": k_ms * 1e3 / max(k_launch, 1),
                      "algorithmic_bytes_per_launch": k_bytes / max(k_launch, 1),

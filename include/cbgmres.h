@@ -216,7 +216,14 @@ typedef struct {
 /* time the Arnoldi steps' SpMV with A (w = A M^-1 v, Fig. 1 step 3) with HIP
  * events at each launch's own start and end (cbg_result.prof_spmv_*) */
 #define CBG_FLAG_PROFILE_SPMV 1024
-#define CBG_FLAG_ALL 2047   /* any other bit is an argument error */
+/* with the PROFILE flags: time the launches of every 8th Arnoldi step only
+ * (steps counted over the whole solve, across cycles, the ones that found
+ * their cycle finished included).  An event pair delays the launch it
+ * brackets by a few microseconds; sampling cuts that cost eightfold, and
+ * the prof_* sums then cover the sampled launches. */
+#define CBG_FLAG_PROFILE_SAMPLED 2048
+#define CBG_PROFILE_STRIDE 8
+#define CBG_FLAG_ALL 4095   /* any other bit is an argument error */
 
 typedef struct {
     int64_t iterations;        /* Arnoldi steps (SpMVs with A inside cycles) */

@@ -14,7 +14,7 @@ from ._binding import (FORMATS, FORMAT_BYTES, PRECONDS, CbgError, DeviceCSR, Sol
                        csr_transpose_values, decode, encode,
                        kernel_workspace_bytes, learned_build, learned_build_stencil, lib,
                        mlp_backward, mlp_forward, stencil_apply,
-                       multidot, multidot_noalloc, NOALLOC_MAX_J, solve, spai_assemble, spai_features, spai_grad_o, spai_grad_p,
+                       multidot, multidot_noalloc, NOALLOC_MAX_J, PROFILE_STRIDE, solve, spai_assemble, spai_features, spai_grad_o, spai_grad_p,
                        spai_loss_grad, spai_pack, spai_round_weights, spai_workspace_bytes, spmv,
                        strerror, update, update_redot, workspace_basis, workspace_bytes)
 
@@ -23,6 +23,6 @@ __all__ = ["problems", "FORMATS", "FORMAT_BYTES", "PRECONDS", "CbgError", "Devic
            "csr_transpose_values", "decode", "encode",
            "kernel_workspace_bytes", "learned_build", "learned_build_stencil", "lib",
            "mlp_backward", "mlp_forward", "stencil_apply",
-           "multidot", "multidot_noalloc", "NOALLOC_MAX_J", "solve", "spai_assemble", "spai_features", "spai_grad_o", "spai_grad_p",
+           "multidot", "multidot_noalloc", "NOALLOC_MAX_J", "PROFILE_STRIDE", "solve", "spai_assemble", "spai_features", "spai_grad_o", "spai_grad_p",
            "spai_loss_grad", "spai_pack", "spai_round_weights", "spai_workspace_bytes", "spmv",
            "strerror", "update", "update_redot", "workspace_basis", "workspace_bytes"]

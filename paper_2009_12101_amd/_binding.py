@@ -33,6 +33,8 @@ FLAG_NORMALISE_GATHER = 128
 FLAG_EXPLICIT_REDOT = 256
 FLAG_TWO_PASS = 512
 FLAG_PROFILE_SPMV = 1024
+FLAG_PROFILE_SAMPLED = 2048
+PROFILE_STRIDE = 8
 # where steps 13-14 run: solve(..., normalise=...)
 NORMALISE = {"auto": 0, "pass": FLAG_NORMALISE_PASS, "gather": FLAG_NORMALISE_GATHER}
 # Arnoldi-step variants by name, the names the oracle uses: "gram" is the
@@ -449,7 +451,8 @@ def solve(A: DeviceCSR, b, x0=None, restart=100, fmt="fp64", tol=1e-10, maxiter=
     from learned_build_stencil) and grid (nx, ny, nz).
     profile: False, True (event-time every basis-streaming launch), "dot"
     (only the multi-dot launches), "spmv" (only the steps' SpMV with A) or
-    "all" (both kinds).  variant: names from VARIANTS (ablations
+    "all" (both kinds); a suffix "/sampled" (e.g. "spmv/sampled") times only
+    every PROFILE_STRIDE-th Arnoldi step's launches.  variant: names from VARIANTS (ablations
     of the Arnoldi step).  normalise: "auto", "pass" or "gather" (where
     v_j = w / t is formed; the same bits either way).  Raises CbgError on a
     negative status."""
@@ -477,9 +480,14 @@ def solve(A: DeviceCSR, b, x0=None, restart=100, fmt="fp64", tol=1e-10, maxiter=
         _need(workspace, "workspace", torch.uint8, 0, dev)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=b.device)
-    flags = {False: 0, True: FLAG_PROFILE, "dot": FLAG_PROFILE_DOT,
-             "spmv": FLAG_PROFILE_SPMV, "all": FLAG_PROFILE | FLAG_PROFILE_SPMV}[profile] \
+    kind, _, sampled = str(profile).partition("/")
+    flags = {"False": 0, "True": FLAG_PROFILE, "dot": FLAG_PROFILE_DOT,
+             "spmv": FLAG_PROFILE_SPMV, "all": FLAG_PROFILE | FLAG_PROFILE_SPMV}[kind] \
         | (0 if fuse else FLAG_NO_FUSE) | NORMALISE[normalise]
+    if sampled:
+        if sampled != "sampled" or kind == "False":
+            raise ValueError(f"profile: {profile!r}")
+        flags |= FLAG_PROFILE_SAMPLED
     flags |= variant_flags(variant)
     opts = CbgOpts(restart, FORMATS[fmt], tol, maxiter, eta, PRECONDS[precond],
                    int(bool(fallback)), None if p_val is None else p_val.data_ptr(),

@@ -411,6 +411,11 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
     const bool prof_all = (opt->flags & CBG_FLAG_PROFILE) != 0;
     const bool prof = prof_all || (opt->flags & CBG_FLAG_PROFILE_DOT) != 0;
     const bool prof_spmv = (opt->flags & CBG_FLAG_PROFILE_SPMV) != 0;
+    // the steps whose launches carry events: all, or every CBG_PROFILE_STRIDE-th
+    // step of the solve; ev_on[j] marks them in the current cycle
+    const int64_t prof_stride = (opt->flags & CBG_FLAG_PROFILE_SAMPLED) ? CBG_PROFILE_STRIDE : 1;
+    int64_t step_no = 0;
+    std::vector<char> ev_on((size_t)m + 1, 0);
     // launch slots k of a step: 0 multi-dot, 1 update (or fused update +
     // re-dot), 2 re-dot multi-dot, 3 re-orthogonalising update
     auto profiled = [&](int k) { return prof_all || k % 2 == 0; };
@@ -539,6 +544,8 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                 // every launch of the cycle is timed, including the ones that
                 // found the cycle finished (they move no bytes)
                 for (int j = 1; j <= jl; ++j) {
+                    if (!ev_on[j])
+                        continue;
                     const bool ro = j <= jeff && (cyc_flags[j - 1] & 1);
                     for (int k = 0; k < 4; ++k) {
                         if ((k == 2 && (fused(j) || gram)) || (k == 3 && onepass) ||
@@ -571,6 +578,8 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
                 const bool gather = !norm_pass && prev_pc != CBG_PC_STENCIL &&
                                     prev_pc != CBG_PC_SPARSE && prev_pc != CBG_PC_BLOCK_JACOBI;
                 for (int j = 1; j <= jl; ++j) {
+                    if (!ev_on[j])
+                        continue;
                     float ms;
                     HIP_TRY(hipEventElapsedTime(&ms, evs.at(j, 4, 0), evs.at(j, 4, 1)));
                     res->prof_spmv_ms += ms;
@@ -672,8 +681,9 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
             // vector j) fused with steps 3-4: w = A M^-1 v_j, omega
             void *slot = W.V + (size_t)(j - 1) * vbytes;
             int nb_spmv;
-            hipEvent_t sev0 = prof_spmv ? evs.at(j, 4, 0) : nullptr;
-            hipEvent_t sev1 = prof_spmv ? evs.at(j, 4, 1) : nullptr;
+            ev_on[j] = step_no++ % prof_stride == 0 ? 1 : 0;
+            hipEvent_t sev0 = prof_spmv && ev_on[j] ? evs.at(j, 4, 0) : nullptr;
+            hipEvent_t sev1 = prof_spmv && ev_on[j] ? evs.at(j, 4, 1) : nullptr;
             if (pc == CBG_PC_STENCIL) {
                 // v_j = w / t stored, z = M^-1 v_j in one pass; then w = A z
                 launch_stencil(fmt, 0, cur, n, ld, opt->grid, opt->p_stencil, W.dinv, W.z, slot,
@@ -755,7 +765,7 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
             o.fmt = fmt; o.V = W.V; o.ld = ld; o.scales = W.scales; o.n = n; o.j = j;
             o.w = nxt; o.wio = nxt; o.ws = W.red; o.st = W.st; o.gated = 1;
             auto timed = [&](int k) {
-                const bool on = prof && profiled(k);
+                const bool on = prof && profiled(k) && ev_on[j];
                 o.ev0 = on ? evs.at(j, k, 0) : nullptr;
                 o.ev1 = on ? evs.at(j, k, 1) : nullptr;
             };

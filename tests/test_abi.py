@@ -80,10 +80,11 @@ def test_solve_rejects_bad_arguments_on_host(L):
     assert call(ws=None) == B.E_WORKSPACE          # missing workspace
     assert call(ws=4096 + 8, wsb=1 << 40) == B.E_WORKSPACE   # misaligned workspace
     assert call(ws=4096, wsb=10) == B.E_WORKSPACE            # too small
-    # formats 0..7 (7: scaled float16), flag bits 1..1024, block-Jacobi sizes
+    # formats 0..7 (7: scaled float16), flag bits 1..2048, block-Jacobi sizes
     assert call(format=8) == B.E_ARG
     assert call(format=7) == B.E_WORKSPACE                    # valid: reaches the workspace check
-    assert call(flags=2048) == B.E_ARG
+    assert call(flags=4096) == B.E_ARG
+    assert call(flags=B.FLAG_PROFILE_SPMV | B.FLAG_PROFILE_SAMPLED) == B.E_WORKSPACE
     assert call(flags=B.FLAG_TWO_PASS | B.FLAG_EXPLICIT_REDOT) == B.E_ARG
     assert call(flags=B.FLAG_TWO_PASS | B.FLAG_MGS) == B.E_ARG
     assert call(flags=B.FLAG_TWO_PASS) == B.E_WORKSPACE

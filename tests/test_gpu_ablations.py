@@ -221,6 +221,31 @@ def test_onepass_gram_is_the_default_and_profiles(cbg, dev):
         cbg.solve(Ad, b, variant="onepass", **kw)
 
 
+def test_sampled_profiling(cbg, dev):
+    """profile "<kind>/sampled" times every PROFILE_STRIDE-th Arnoldi step's
+    launches (counted over the solve, no-op launches after a cycle's end
+    included) and leaves the solve itself unchanged."""
+    A = P.convdiff7(10)
+    Ad = cbg.DeviceCSR.from_host(A, dev)
+    b = torch.from_numpy(P.rhs_uniform(A.n, 1)).to(dev)
+    kw = dict(restart=20, fmt="fp16", tol=1e-10, maxiter=2000)
+    ra = cbg.solve(Ad, b, profile="all", **kw)
+    rs = cbg.solve(Ad, b, profile="all/sampled", **kw)
+    assert np.array_equal(ra.x.cpu().numpy(), rs.x.cpu().numpy())
+    # every step launch is timed without sampling, no-op ones included: the
+    # steps are enqueued in chunks of 16 behind a look-ahead read of the done
+    # flag, so at most two chunks per cycle find it set (how many depends on
+    # host timing)
+    st = cbg.PROFILE_STRIDE
+    assert ra.iterations <= ra.prof_spmv_launches <= ra.iterations + 32 * ra.restarts
+    assert -(-rs.iterations // st) <= rs.prof_spmv_launches
+    assert rs.prof_spmv_launches <= -(-(rs.iterations + 32 * rs.restarts) // st)
+    assert rs.prof_dot_launches == rs.prof_spmv_launches
+    assert 0 < rs.prof_spmv_bytes < ra.prof_spmv_bytes and rs.prof_spmv_ms > 0
+    with pytest.raises(ValueError):
+        cbg.solve(Ad, b, profile="spmv/every", **kw)
+
+
 def test_mgs_with_profiling_is_unsupported(cbg, dev):
     A = P.poisson2d(6)
     Ad = cbg.DeviceCSR.from_host(A, dev)
@@ -270,7 +295,7 @@ def test_unknown_flag_bits_are_argument_errors(cbg, dev):
     b = torch.ones(A.n, dtype=torch.float64, device=dev)
     x = torch.zeros_like(b)
     ws = torch.empty(B.workspace_bytes(A.n, 8, "fp64"), dtype=torch.uint8, device=dev)
-    opts = B.CbgOpts(8, 0, 1e-10, 10, 0.0, 0, 0, None, 2048, 0, 0, 0)
+    opts = B.CbgOpts(8, 0, 1e-10, 10, 0.0, 0, 0, None, 4096, 0, 0, 0)
     res = B.CbgResult()
     csr = Ad.cstruct()
     rc = B.lib().cbgmres_solve(C.byref(csr), B._ptr(b), B._ptr(x), C.byref(opts), B._ptr(ws),
