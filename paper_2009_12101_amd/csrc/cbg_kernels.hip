@@ -1219,6 +1219,53 @@ constexpr double HARD_RATIO = 1e-4;
 // that launch cheap; a hard step's second pass streams the basis with it.
 constexpr int HARD_BLOCKS = 256;
 
+// The one-pass update's G h for one wave: out[k] = sum over l in [l0, l1) of
+// G[l][k] h_l, for k = lane + 64 q < j (q < NK), each sum in increasing l
+// as one FMA chain.  The NK columns of a row are loaded together and UL
+// rows at a time (column indices clamped into [0, j); the extra sums are
+// not stored), so a wave keeps NK * UL loads of G in flight instead of
+// walking its columns one after another.
+template <int NK>
+__device__ __forceinline__ void gram_times_h(const double *__restrict__ G, size_t ldg,
+                                             const double *lh, int j, int l0, int l1, int lane,
+                                             double *out)
+{
+    constexpr int UL = NK == 1 ? 8 : NK == 2 ? 4 : NK == 3 ? 3 : 2;
+    int kc[NK];
+    double acc[NK];
+#pragma unroll
+    for (int q = 0; q < NK; ++q) {
+        kc[q] = min(lane + 64 * q, j - 1);
+        acc[q] = 0.0;
+    }
+    int l = l0;
+    for (; l + UL <= l1; l += UL) {
+        double g[UL][NK];
+#pragma unroll
+        for (int u = 0; u < UL; ++u)
+#pragma unroll
+            for (int q = 0; q < NK; ++q)
+                g[u][q] = G[(size_t)(l + u) * ldg + kc[q]];
+#pragma unroll
+        for (int u = 0; u < UL; ++u) {
+            const double hl = lh[l + u];
+#pragma unroll
+            for (int q = 0; q < NK; ++q)
+                acc[q] = fma(g[u][q], hl, acc[q]);
+        }
+    }
+    for (; l < l1; ++l) {
+        const double hl = lh[l];
+#pragma unroll
+        for (int q = 0; q < NK; ++q)
+            acc[q] = fma(G[(size_t)l * ldg + kc[q]], hl, acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < NK; ++q)
+        if (lane + 64 * q < j)
+            out[lane + 64 * q] = acc[q];
+}
+
 template <int F, int ROLE>
 __global__ __launch_bounds__(BLK) void k_update(const uint8_t *__restrict__ V, int64_t ld,
                                                 const double *__restrict__ scales, int n, int j_arg,
@@ -1287,12 +1334,15 @@ __global__ __launch_bounds__(BLK) void k_update(const uint8_t *__restrict__ V, i
         const size_t ldg = (size_t)st->m + 1;
         const int q = (j + NWAVE - 1) / NWAVE;
         const int l0 = min(wv * q, j), l1 = min(l0 + q, j);
-        for (int k = lane; k < j; k += 64) {
-            double acc = 0.0;
-#pragma unroll 4
-            for (int l = l0; l < l1; ++l)
-                acc = fma(G[(size_t)l * ldg + k], lh[l], acc);
-            lp[wv * MAX_RESTART + k] = acc;
+        switch ((j + 63) / 64) {
+        case 1: gram_times_h<1>(G, ldg, lh, j, l0, l1, lane, lp + wv * MAX_RESTART); break;
+        case 2: gram_times_h<2>(G, ldg, lh, j, l0, l1, lane, lp + wv * MAX_RESTART); break;
+        case 3: gram_times_h<3>(G, ldg, lh, j, l0, l1, lane, lp + wv * MAX_RESTART); break;
+        case 4: gram_times_h<4>(G, ldg, lh, j, l0, l1, lane, lp + wv * MAX_RESTART); break;
+        default:
+            for (int k0 = 0; k0 < j; k0 += 256)
+                gram_times_h<4>(G + k0, ldg, lh, j - k0, l0, l1, lane, lp + wv * MAX_RESTART + k0);
+            break;
         }
         __syncthreads();
         double phh = 0.0, phu = 0.0;
