@@ -162,6 +162,52 @@ def test_jacobi_parity(cbg, orc, dev):
     assert true_res(orc, A, b, r.x.cpu().numpy()) <= 1e-10
 
 
+def _long_row_matrix(n=3000, seed=11, drop_diag=None):
+    """Diagonally dominant rows of 0..11 off-diagonal entries, every 37th row
+    with up to 150 (several 32-entry chunks); every 53rd row stores its
+    diagonal twice (the last entry in CSR order is Jacobi's a_ii on both
+    sides, and the SpMV adds both).  drop_diag: a row left without one."""
+    from paper_2009_12101_amd import problems as P
+    rng = np.random.default_rng(seed)
+    rp, ci, va = [0], [], []
+    for i in range(n):
+        k = int(rng.integers(0, 150)) if i % 37 == 0 else int(rng.integers(0, 12))
+        c = np.unique(rng.integers(0, n, size=k))
+        c = c[c != i]
+        ent = [(int(x), -float(rng.random()) / (len(c) + 1)) for x in c]
+        if i != drop_diag:
+            ent.append((i, 2.0 + float(rng.random())))
+            if i % 53 == 0:
+                ent.append((i, 3.0 + float(rng.random())))
+        ent.sort(key=lambda e: e[0])                # stable: the repeats keep their order
+        ci += [e[0] for e in ent]
+        va += [e[1] for e in ent]
+        rp.append(len(ci))
+    return P.CSR(n, np.array(rp, np.int32), np.array(ci, np.int32), np.array(va),
+                 name="long_rows")
+
+
+def test_jacobi_setup_long_rows_and_repeated_diagonal(cbg, orc, dev):
+    """Jacobi's 1/a_ii, read by a half-wave per row over several chunks and
+    with a repeated diagonal entry: iteration-matched fp64 solves agree with
+    the oracle's within 1e-8 and their first recurrence residuals to 1e-12; a
+    missing diagonal is an argument error on both sides."""
+    A = _long_row_matrix()
+    assert np.diff(A.row_ptr).max() > 96
+    b = np.random.default_rng(12).uniform(-1, 1, A.n)
+    kw = dict(restart=20, fmt="fp64", tol=0.0, maxiter=12, precond="jacobi")
+    ref, r, Ad, bd = run_pair(cbg, orc, dev, A, b, **kw)
+    assert ref["status"] == r.status
+    assert np.allclose(r.hist[:3], ref["hist"][:3], rtol=1e-12, atol=0)
+    xo = ref["x"]
+    assert np.linalg.norm(r.x.cpu().numpy() - xo) <= 1e-8 * np.linalg.norm(xo)
+    Z = _long_row_matrix(drop_diag=1234)
+    assert orc.gmres(Z, b, **kw)["status"] == -1
+    with pytest.raises(cbg.CbgError) as e:
+        cbg.solve(cbg.DeviceCSR.from_host(Z, dev), bd, **kw)
+    assert e.value.status == -1
+
+
 def test_sparse_preconditioner_equal_to_jacobi(cbg, orc, dev):
     from paper_2009_12101_amd import problems as P
     A = P.lognormal27(10, 5)
