@@ -201,27 +201,33 @@ struct ByteModel {
 // basis-streaming launches (dot, update, re-dot, re-update) and of the SpMV
 // with A, recorded by hipExtLaunchKernelGGL at each kernel's own start and
 // end.
+// Event pairs for the timed launches of a cycle: five launch slots per step.
+// The events are created once per host thread and device, grown to the
+// longest cycle asked for, and kept until the process ends (creating m x 10
+// of them for every solve took about half a millisecond at m = 200).
 struct CycleEvents {
-    std::vector<hipEvent_t> ev;
-    int m = 0;
-    bool ok = false;
-    int create(int mm)
+    hipEvent_t *ev = nullptr;
+    int create(int m)
     {
-        m = mm;
-        ev.assign((size_t)m * 10, nullptr);
-        for (auto &e : ev)
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess)
+            return CBG_E_HIP;
+        static thread_local std::vector<std::vector<hipEvent_t>> pools;
+        if ((int)pools.size() <= dev)
+            pools.resize((size_t)dev + 1);
+        std::vector<hipEvent_t> &p = pools[(size_t)dev];
+        const size_t need = (size_t)m * 10;
+        p.reserve(need);
+        while (p.size() < need) {
+            hipEvent_t e = nullptr;
             if (hipEventCreate(&e) != hipSuccess)
                 return CBG_E_HIP;
-        ok = true;
+            p.push_back(e);
+        }
+        ev = p.data();
         return 0;
     }
-    hipEvent_t at(int j, int k, int edge) { return ev[((size_t)(j - 1) * 5 + k) * 2 + edge]; }
-    ~CycleEvents()
-    {
-        for (auto &e : ev)
-            if (e)
-                (void)hipEventDestroy(e);
-    }
+    hipEvent_t at(int j, int k, int edge) const { return ev[((size_t)(j - 1) * 5 + k) * 2 + edge]; }
 };
 
 // Steps of a cycle are enqueued in chunks; after each chunk the cycle's done
