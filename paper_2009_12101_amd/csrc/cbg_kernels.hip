@@ -275,6 +275,49 @@ __global__ __launch_bounds__(BLK) void k_jacobi_setup(int n, int64_t ld,
     }
 }
 
+constexpr int SELL_MAX_DIAG = 256;  // distinct offsets col - row of the diagonal-index form
+
+// The same from A's sliced-ELL copy with one-byte diagonal indices: a lane
+// per row (a wave per 64-row slice) walks the row's CSR-length prefix of the
+// copy's index bytes and reads the value of the last entry at offset 0 only.
+// Rows in [n, ld) get 0.
+__global__ __launch_bounds__(BLK) void k_jacobi_setup_sell(
+    int n, int64_t ld, const int32_t *__restrict__ rp, const int64_t *__restrict__ sp,
+    const uint8_t *__restrict__ sd, const double *__restrict__ sv,
+    const int32_t *__restrict__ sdiag, int ndiag, double *__restrict__ dinv, unsigned *bad)
+{
+    constexpr int B = 9;
+    __shared__ int32_t ldg[SELL_MAX_DIAG];
+    for (int t = threadIdx.x; t < ndiag; t += BLK)
+        ldg[t] = sdiag[t];
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * BLK + threadIdx.x; i < ld;
+         i += (int64_t)gridDim.x * BLK) {
+        if (i >= n) {
+            dinv[i] = 0.0;
+            continue;
+        }
+        const int64_t sl = i / 64, beg = sp[sl];
+        const int width = (int)((sp[sl + 1] - beg) / 64);
+        const int len = rp[i + 1] - rp[i];
+        int64_t hit = -1;
+        for (int k0 = 0; k0 < len; k0 += B) {
+            uint32_t dx[B];
+#pragma unroll
+            for (int u = 0; u < B; ++u)
+                dx[u] = sd[beg + (int64_t)min(k0 + u, width - 1) * 64 + (i & 63)];
+#pragma unroll
+            for (int u = 0; u < B; ++u)
+                if (k0 + u < len && ldg[dx[u]] == 0)
+                    hit = beg + (int64_t)(k0 + u) * 64 + (i & 63);
+        }
+        const double d = hit >= 0 ? sv[hit] : 0.0;
+        if (d == 0.0 || !isfinite(d))
+            atomicOr(bad, 1u);
+        dinv[i] = 1.0 / d;
+    }
+}
+
 // Block partials of ||x||_2^2 and ||x||_inf of a length-n vector (two
 // values, in the SpMV partial region).
 __global__ __launch_bounds__(BLK) void k_norm(const double *__restrict__ x, int64_t n, RedArgs ra)
@@ -675,7 +718,6 @@ __device__ __forceinline__ T sell_ld(const T *p)
 }
 
 constexpr int SELL_UNR = 9;      // entries per row in flight (a third of a 27-point row)
-constexpr int SELL_MAX_DIAG = 256;  // distinct offsets col - row of the diagonal-index form
 
 template <int MODE, bool NT, bool DIX>
 __global__ __launch_bounds__(BLK) void k_spmv_sell(
@@ -3050,12 +3092,18 @@ void launch_init_state(DevState *st, int n, int m, int fmt, double tol, double e
     k_init_state<<<1, 64, 0, s>>>(st, n, m, fmt, tol, eta, maxiter, reorth_all);
 }
 
-void launch_jacobi_setup(int n, int64_t ld, const int32_t *rp, const int32_t *ci,
-                         const double *val, double *dinv, unsigned *bad, hipStream_t s)
+void launch_jacobi_setup(const SpmvArgs &a, int64_t ld, double *dinv, unsigned *bad,
+                         hipStream_t s)
 {
+    if (a.sp && a.sd && a.sv) {
+        const int g = (int)std::min<int64_t>(std::max<int64_t>((ld + BLK - 1) / BLK, 1), 65536);
+        k_jacobi_setup_sell<<<g, BLK, 0, s>>>(a.n, ld, a.rp, a.sp, a.sd, a.sv, a.sdiag, a.ndiag,
+                                              dinv, bad);
+        return;
+    }
     const int g = (int)std::min<int64_t>(std::max<int64_t>((ld + BLK / 32 - 1) / (BLK / 32), 1),
                                          65536);
-    k_jacobi_setup<<<g, BLK, 0, s>>>(n, ld, rp, ci, val, dinv, bad);
+    k_jacobi_setup<<<g, BLK, 0, s>>>(a.n, ld, a.rp, a.ci, a.val, dinv, bad);
 }
 
 __global__ void k_clear_flags(DevState *st, unsigned *bad)

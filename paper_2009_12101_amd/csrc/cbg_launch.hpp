@@ -143,8 +143,10 @@ void launch_stencil(int fmt, int mode, const double *w, int n, int64_t ld, const
 int launch_norm(const double *x, int64_t n, const RedWs &ws, hipStream_t s);
 void launch_init_state(DevState *st, int n, int m, int fmt, double tol, double eta,
                        int64_t maxiter, int reorth_all, hipStream_t s);
-void launch_jacobi_setup(int n, int64_t ld, const int32_t *rp, const int32_t *ci,
-                         const double *val, double *dinv, unsigned *bad, hipStream_t s);
+// dinv = 1 / a_ii for rows < n, 0 for rows in [n, ld): from the sliced-ELL
+// copy with diagonal indices when `a` carries one (set_matrix), else from CSR
+void launch_jacobi_setup(const SpmvArgs &a, int64_t ld, double *dinv, unsigned *bad,
+                         hipStream_t s);
 void launch_clear_flags(DevState *st, unsigned *bad, hipStream_t s);
 void launch_fill_zero(double *p, int count, hipStream_t s);
 void launch_backsolve(const DevState *st, const void *sa, hipStream_t s);

@@ -468,8 +468,12 @@ int cbgmres_solve(const cbg_csr *A, const double *b, double *x, const cbg_opts *
         launch_reduce(W.red, RR_NB, 0, g, 0, W.st, sa, nullptr, fmt, s);
     }
     int pc = pc0;
-    if (pc == CBG_PC_JACOBI || pc == CBG_PC_STENCIL)
-        launch_jacobi_setup(n, ld, A->row_ptr, A->col_idx, A->val, W.dinv, W.bad, s);
+    if (pc == CBG_PC_JACOBI || pc == CBG_PC_STENCIL) {
+        SpmvArgs am{};
+        am.n = n;
+        set_matrix(am, A);
+        launch_jacobi_setup(am, ld, W.dinv, W.bad, s);
+    }
     const int bj_nblk = (n + bj_bs - 1) / bj_bs;
     std::vector<int8_t> bj_tags;
     if (pc == CBG_PC_BLOCK_JACOBI) {

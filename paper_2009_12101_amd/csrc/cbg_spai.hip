@@ -153,6 +153,43 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+constexpr int SL_B = 9;                 // entries per batch of the sliced-ELL row walks
+
+// The diagonal from A's sliced-ELL copy with one-byte diagonal indices: a
+// lane per row walks the row's CSR-length prefix of the index bytes and
+// reads the value of the last entry at offset 0 only (the last in CSR order,
+// as k_diag; 0 where a row stores none).
+__global__ __launch_bounds__(256) void k_diag_sell(int n, const int32_t *__restrict__ rp,
+                                                   const int64_t *__restrict__ sp,
+                                                   const uint8_t *__restrict__ sd,
+                                                   const double *__restrict__ sv,
+                                                   const int32_t *__restrict__ sdiag, int ndiag,
+                                                   double *__restrict__ diag)
+{
+    __shared__ int32_t ldg[CBG_SELL_MAX_DIAG];
+    for (int t = threadIdx.x; t < ndiag; t += blockDim.x)
+        ldg[t] = sdiag[t];
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t sl = i / 64, beg = sp[sl];
+        const int width = (int)((sp[sl + 1] - beg) / 64);
+        const int len = rp[i + 1] - rp[i];
+        int64_t hit = -1;
+        for (int k0 = 0; k0 < len; k0 += SL_B) {
+            uint32_t dx[SL_B];
+#pragma unroll
+            for (int u = 0; u < SL_B; ++u)
+                dx[u] = sd[beg + (int64_t)min(k0 + u, width - 1) * 64 + (i & 63)];
+#pragma unroll
+            for (int u = 0; u < SL_B; ++u)
+                if (k0 + u < len && ldg[dx[u]] == 0)
+                    hit = beg + (int64_t)(k0 + u) * 64 + (i & 63);
+        }
+        diag[i] = hit >= 0 ? sv[hit] : 0.0;
+    }
+}
+
 // Features of each row: f_p = fl32(a_{i,c(p)} / a_ii) and f_{32+p} =
 // fl32(a_{c(p),c(p)} / a_ii) on present slots, f_27 = fl32((a_ii -
 // sum_{c != i} |a_ic|) / a_ii) with the sum in CSR order, the rest 0; all
@@ -204,6 +241,86 @@ __global__ __launch_bounds__(256) void k_features(int n, const int32_t *__restri
         }
         wave_sync();
         ((uint32_t *)(feat + i * NF))[lane] = lfw[g][lane];
+        wave_sync();
+    }
+}
+
+// The same features from A's sliced-ELL copy with one-byte diagonal indices
+// (the same values and bits): one wave per 64-row slice, lane = row.  The
+// copy keeps each row's entries in CSR order, so the lane adds the
+// off-diagonal sum in that order; entries past the row's CSR length are
+// padding and skipped.  A batch's values and indices are loaded together
+// (indices clamped into the slice), then the neighbours' diagonals.  Each
+// lane assembles its row's 64 features in an LDS row of its own (odd word
+// stride: the 64 rows sit in distinct banks); the wave then writes two rows
+// per store.
+constexpr int FS_LD = NF / 2 + 1;       // LDS row stride in 32-bit words
+
+__global__ __launch_bounds__(256) void k_features_sell(
+    int n, int64_t nslice, const int32_t *__restrict__ rp, const int64_t *__restrict__ sp,
+    const uint8_t *__restrict__ sd, const double *__restrict__ sv,
+    const int32_t *__restrict__ sdiag, int ndiag, int nx, int ny,
+    const double *__restrict__ diag, uint16_t *__restrict__ feat, unsigned *__restrict__ bad)
+{
+    __shared__ int32_t ldg[CBG_SELL_MAX_DIAG];
+    __shared__ uint32_t lf[4][64 * FS_LD];
+    for (int t = threadIdx.x; t < ndiag; t += blockDim.x)
+        ldg[t] = sdiag[t];
+    __syncthreads();
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint32_t *my = lf[wv] + lane * FS_LD;
+    uint16_t *myh = (uint16_t *)my;
+    for (int64_t sl = (int64_t)blockIdx.x * 4 + wv; sl < nslice; sl += (int64_t)gridDim.x * 4) {
+        const int64_t i = sl * 64 + lane;
+        const bool live = i < n;
+        const int64_t ic = live ? i : (int64_t)n - 1;
+        for (int q = 0; q < NF / 2; ++q)
+            my[q] = 0u;
+        const int64_t beg = sp[sl];
+        const int width = (int)((sp[sl + 1] - beg) / 64);
+        const int len = live ? rp[i + 1] - rp[i] : 0;
+        const double d = diag[ic];
+        const RowPos rpos = row_pos(ic, nx, ny);
+        double off = 0.0;
+        for (int k0 = 0; k0 < width; k0 += SL_B) {
+            double a[SL_B];
+            int64_t c[SL_B];
+#pragma unroll
+            for (int u = 0; u < SL_B; ++u) {
+                const int64_t e = beg + (int64_t)min(k0 + u, width - 1) * 64 + lane;
+                a[u] = sv[e];
+                c[u] = ic + ldg[sd[e]];
+            }
+            double dc[SL_B];
+#pragma unroll
+            for (int u = 0; u < SL_B; ++u)
+                dc[u] = diag[min(max(c[u], (int64_t)0), (int64_t)n - 1)];
+#pragma unroll
+            for (int u = 0; u < SL_B; ++u) {
+                if (k0 + u >= len)
+                    continue;
+                if (c[u] != ic)
+                    off += fabs(a[u]);
+                const int s = slot_at(rpos, ic, c[u], nx, ny);
+                if (s >= 0) {
+                    myh[s] = bf16_of((float)(a[u] / d));
+                    myh[NBR + s] = bf16_of((float)(dc[u] / d));
+                }
+            }
+        }
+        if (live) {
+            const double margin = (d - off) / d;
+            if (!(d != 0.0) || !isfinite(margin))
+                *bad = 1u;
+            myh[27] = bf16_of((float)margin);
+        }
+        wave_sync();
+        for (int q = 0; q < 32; ++q) {
+            const int r = 2 * q + (lane >> 5);
+            const int64_t row = sl * 64 + r;
+            if (row < n)
+                ((uint32_t *)(feat + row * NF))[lane & 31] = lf[wv][r * FS_LD + (lane & 31)];
+        }
         wave_sync();
     }
 }
@@ -425,6 +542,61 @@ __global__ __launch_bounds__(256) void k_stencil_pack(int n, int64_t ld,
                 *(uint32_t *)(codes + (int64_t)sl * ld + i) = lcw[(sl * PK_LD + r) / 2];
         }
         __syncthreads();
+    }
+}
+
+// The stored form's codes from the sliced-ELL copy with diagonal indices
+// (the same codes): one wave per 64-row slice, lane = row, the row's slots
+// marked in an LDS block of the wave's own (slot-major, 64 rows), then each
+// slot's 64 codes written as one run.  Slices past the copy's (rows up to
+// ld) are written as 0.
+__global__ __launch_bounds__(256) void k_stencil_pack_sell(
+    int n, int64_t ld, int64_t nslice, const int32_t *__restrict__ rp,
+    const int64_t *__restrict__ sp, const uint8_t *__restrict__ sd,
+    const int32_t *__restrict__ sdiag, int ndiag, int nx, int ny, const float *__restrict__ O,
+    uint16_t *__restrict__ codes)
+{
+    __shared__ int32_t ldg[CBG_SELL_MAX_DIAG];
+    __shared__ uint16_t lc[4][NSLOT * 64];
+    for (int t = threadIdx.x; t < ndiag; t += blockDim.x)
+        ldg[t] = sdiag[t];
+    __syncthreads();
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint16_t *mine = lc[wv];
+    const int64_t nsl_ld = ld / 64;                      // ld is a multiple of 256
+    for (int64_t sl = (int64_t)blockIdx.x * 4 + wv; sl < nsl_ld; sl += (int64_t)gridDim.x * 4) {
+        for (int s = 0; s < NSLOT; ++s)
+            mine[s * 64 + lane] = 0;
+        wave_sync();
+        if (sl < nslice) {
+            const int64_t i = sl * 64 + lane;
+            const bool live = i < n;
+            const int64_t ic = live ? i : (int64_t)n - 1;
+            const int64_t beg = sp[sl];
+            const int width = (int)((sp[sl + 1] - beg) / 64);
+            const int len = live ? rp[i + 1] - rp[i] : 0;
+            const RowPos rpos = row_pos(ic, nx, ny);
+            for (int k0 = 0; k0 < width; k0 += SL_B) {
+                int sl_of[SL_B];
+                float o[SL_B];
+#pragma unroll
+                for (int u = 0; u < SL_B; ++u) {
+                    const int64_t e = beg + (int64_t)min(k0 + u, width - 1) * 64 + lane;
+                    sl_of[u] = slot_at(rpos, ic, ic + ldg[sd[e]], nx, ny);
+                }
+#pragma unroll
+                for (int u = 0; u < SL_B; ++u)
+                    o[u] = O[ic * NO + max(sl_of[u], 0)];
+#pragma unroll
+                for (int u = 0; u < SL_B; ++u)
+                    if (k0 + u < len && sl_of[u] >= 0)
+                        mine[sl_of[u] * 64 + lane] = f16_code(o[u]);
+            }
+        }
+        wave_sync();
+        for (int s = 0; s < NSLOT; ++s)
+            codes[(int64_t)s * ld + sl * 64 + lane] = mine[s * 64 + lane];
+        wave_sync();
     }
 }
 
@@ -930,6 +1102,14 @@ bool csr_ok(const cbg_csr *A)
            (A->n == 0 || (A->row_ptr && (A->nnz == 0 || (A->col_idx && A->val))));
 }
 
+// A carries a whole sliced-ELL copy with one-byte diagonal indices
+bool sell_dix_of(const cbg_csr *A)
+{
+    return A->sell_ptr && A->sell_val && A->sell_dix && A->sell_diag && A->sell_ndiag >= 1 &&
+           A->sell_ndiag <= CBG_SELL_MAX_DIAG && A->sell_entries >= A->nnz &&
+           A->sell_entries % 64 == 0;
+}
+
 bool grid_ok(const cbg_csr *A, const int32_t *grid)
 {
     return grid && grid[0] > 0 && grid[1] > 0 && grid[2] > 0 &&
@@ -939,6 +1119,41 @@ bool grid_ok(const cbg_csr *A, const int32_t *grid)
 int row_grid(int64_t rows) { return (int)std::min<int64_t>(std::max<int64_t>((rows + 255) / 256, 1), MAXB_ROW); }
 int group_grid(int64_t rows) { return (int)std::min<int64_t>(std::max<int64_t>((rows + 7) / 8, 1), MAXB_ROW); }
 int tile_grid(int64_t n, int cap) { return (int)std::min<int64_t>(std::max<int64_t>((n + 63) / 64, 1), cap); }
+
+int slice_grid(int64_t n)
+{
+    return (int)std::min<int64_t>(std::max<int64_t>(((n + 63) / 64 + 3) / 4, 1), 65536);
+}
+
+// The diagonal, from the sliced-ELL copy when A carries one
+void enqueue_diag(const cbg_csr *A, double *diag, hipStream_t s)
+{
+    if (sell_dix_of(A)) {
+        const int g = (int)std::min<int64_t>(std::max<int64_t>(((int64_t)A->n + 255) / 256, 1),
+                                             65536);
+        hipLaunchKernelGGL(k_diag_sell, dim3(g), dim3(256), 0, s, A->n, A->row_ptr,
+                           A->sell_ptr, A->sell_dix, A->sell_val, A->sell_diag, A->sell_ndiag,
+                           diag);
+    } else {
+        hipLaunchKernelGGL(k_diag, dim3(group_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
+                           A->col_idx, A->val, diag);
+    }
+}
+
+// The features, from the sliced-ELL copy when A carries one
+void enqueue_features(const cbg_csr *A, const int32_t grid[3], const double *diag, uint16_t *feat,
+                      unsigned *bad, hipStream_t s)
+{
+    if (sell_dix_of(A)) {
+        hipLaunchKernelGGL(k_features_sell, dim3(slice_grid(A->n)), dim3(256), 0, s, A->n,
+                           (int64_t)(A->n + 63) / 64, A->row_ptr, A->sell_ptr, A->sell_dix,
+                           A->sell_val, A->sell_diag, A->sell_ndiag, grid[0], grid[1], diag,
+                           feat, bad);
+    } else {
+        hipLaunchKernelGGL(k_features, dim3(group_grid(A->n)), dim3(256), 0, s, A->n,
+                           A->row_ptr, A->col_idx, A->val, grid[0], grid[1], diag, feat, bad);
+    }
+}
 
 size_t ws_need(int64_t n, int64_t nnz, int64_t K)
 {
@@ -1037,11 +1252,8 @@ int cbg_spai_features(const cbg_csr *A, const int32_t grid[3], uint16_t *feat, v
     hipStream_t s = (hipStream_t)stream;
     SpaiWs W = carve_spai(ws, A->n, A->nnz, 0, nullptr);
     SP_TRY(hipMemsetAsync(W.bad, 0, sizeof(unsigned), s));
-    hipLaunchKernelGGL(k_diag, dim3(group_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
-                       A->col_idx, A->val, W.diag);
-    hipLaunchKernelGGL(k_features, dim3(group_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
-                       A->col_idx, A->val, grid[0], grid[1], (const double *)W.diag, feat,
-                       W.bad);
+    enqueue_diag(A, W.diag, s);
+    enqueue_features(A, grid, (const double *)W.diag, feat, W.bad, s);
     SP_TRY(hipGetLastError());
     unsigned bad = 0;
     if ((e = read_flag(W.bad, s, &bad)))
@@ -1090,11 +1302,8 @@ int cbg_learned_build(const cbg_csr *A, const int32_t grid[3], const uint16_t *w
     hipStream_t s = (hipStream_t)stream;
     SpaiWs W = carve_spai(ws, A->n, A->nnz, 0, nullptr);
     SP_TRY(hipMemsetAsync(W.bad, 0, sizeof(unsigned), s));
-    hipLaunchKernelGGL(k_diag, dim3(group_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
-                       A->col_idx, A->val, W.diag);
-    hipLaunchKernelGGL(k_features, dim3(group_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
-                       A->col_idx, A->val, grid[0], grid[1], (const double *)W.diag, W.feat,
-                       W.bad);
+    enqueue_diag(A, W.diag, s);
+    enqueue_features(A, grid, (const double *)W.diag, W.feat, W.bad, s);
     enqueue_forward(A->n, W.feat, weights, params, W.O, nullptr, nullptr, s);
     hipLaunchKernelGGL(k_assemble, dim3(group_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
                        A->col_idx, A->val, grid[0], grid[1], (const float *)W.O, p_val);
@@ -1121,15 +1330,20 @@ int cbg_learned_build_stencil(const cbg_csr *A, const int32_t grid[3], const uin
     SpaiWs W = carve_spai(ws, A->n, A->nnz, 0, nullptr);
     const int64_t ld = cbg_basis_ld(A->n);
     SP_TRY(hipMemsetAsync(W.bad, 0, sizeof(unsigned), s));
-    hipLaunchKernelGGL(k_diag, dim3(group_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
-                       A->col_idx, A->val, W.diag);
-    hipLaunchKernelGGL(k_features, dim3(group_grid(A->n)), dim3(256), 0, s, A->n, A->row_ptr,
-                       A->col_idx, A->val, grid[0], grid[1], (const double *)W.diag, W.feat,
-                       W.bad);
+    enqueue_diag(A, W.diag, s);
+    enqueue_features(A, grid, (const double *)W.diag, W.feat, W.bad, s);
     enqueue_forward(A->n, W.feat, weights, params, W.O, nullptr, nullptr, s);
-    const int gp = (int)std::min<int64_t>((ld + PK_ROWS - 1) / PK_ROWS, MAXB_ROW);
-    hipLaunchKernelGGL(k_stencil_pack, dim3(std::max(gp, 1)), dim3(256), 0, s, A->n, ld,
-                       A->row_ptr, A->col_idx, grid[0], grid[1], (const float *)W.O, p_stencil);
+    if (sell_dix_of(A)) {
+        hipLaunchKernelGGL(k_stencil_pack_sell, dim3(slice_grid(ld)), dim3(256), 0, s, A->n, ld,
+                           (int64_t)(A->n + 63) / 64, A->row_ptr, A->sell_ptr, A->sell_dix,
+                           A->sell_diag, A->sell_ndiag, grid[0], grid[1], (const float *)W.O,
+                           p_stencil);
+    } else {
+        const int gp = (int)std::min<int64_t>((ld + PK_ROWS - 1) / PK_ROWS, MAXB_ROW);
+        hipLaunchKernelGGL(k_stencil_pack, dim3(std::max(gp, 1)), dim3(256), 0, s, A->n, ld,
+                           A->row_ptr, A->col_idx, grid[0], grid[1], (const float *)W.O,
+                           p_stencil);
+    }
     SP_TRY(hipGetLastError());
     unsigned bad = 0;
     if ((e = read_flag(W.bad, s, &bad)))
@@ -1152,7 +1366,19 @@ int cbg_stencil_apply(const cbg_csr *A, const int32_t grid[3], const uint16_t *p
     SpaiWs W = carve_spai(ws, A->n, A->nnz, 0, nullptr);
     const int64_t ld = cbg_basis_ld(A->n);
     SP_TRY(hipMemsetAsync(W.bad, 0, sizeof(unsigned), s));
-    launch_jacobi_setup(A->n, ld, A->row_ptr, A->col_idx, A->val, W.dinv, W.bad, s);
+    SpmvArgs am{};
+    am.n = A->n;
+    am.rp = A->row_ptr;
+    am.ci = A->col_idx;
+    am.val = A->val;
+    if (sell_dix_of(A)) {
+        am.sp = A->sell_ptr;
+        am.sv = A->sell_val;
+        am.sd = A->sell_dix;
+        am.sdiag = A->sell_diag;
+        am.ndiag = A->sell_ndiag;
+    }
+    launch_jacobi_setup(am, ld, W.dinv, W.bad, s);
     launch_stencil(F_FP64, 1, v, A->n, ld, grid, p_stencil, W.dinv, z, nullptr, nullptr, nullptr,
                    s);
     SP_TRY(hipGetLastError());

@@ -208,6 +208,57 @@ def test_jacobi_setup_long_rows_and_repeated_diagonal(cbg, orc, dev):
     assert e.value.status == -1
 
 
+def _banded_with_holes(drop_diag=None):
+    """27-point lognormal 11^3 with a seeded fifth of its off-diagonal entries
+    removed (rows of different lengths inside a slice: the sliced-ELL copy
+    pads) and the diagonal stored twice in every 53rd row (the last entry in
+    CSR order is a_ii); drop_diag: a row left without one."""
+    from paper_2009_12101_amd import problems as P
+    A = P.lognormal27(11, 4)
+    rng = np.random.default_rng(5)
+    rp, ci, va = [0], [], []
+    for i in range(A.n):
+        lo, hi = A.row_ptr[i], A.row_ptr[i + 1]
+        for p in range(lo, hi):
+            c = int(A.col_idx[p])
+            if c == i:
+                if i == drop_diag:
+                    continue
+                ci.append(c)
+                va.append(float(A.val[p]))
+                if i % 53 == 0:
+                    ci.append(c)
+                    va.append(0.5 * float(A.val[p]))
+            elif rng.random() >= 0.2:
+                ci.append(c)
+                va.append(float(A.val[p]))
+        rp.append(len(ci))
+    return P.CSR(A.n, np.array(rp, np.int32), np.array(ci, np.int32), np.array(va),
+                 grid=A.grid, name="lognormal27_11_holes")
+
+
+def test_jacobi_setup_from_the_sliced_ell_copy(cbg, orc, dev):
+    """The same set-up read from the sliced-ELL copy with diagonal indices
+    (a lane per row over the row's CSR-length prefix of the padded slice):
+    iteration-matched fp64 solves against the oracle's, and a missing
+    diagonal is an argument error."""
+    A = _banded_with_holes()
+    b = np.random.default_rng(13).uniform(-1, 1, A.n)
+    Ad = cbg.DeviceCSR.from_host(A, dev, sell=True)
+    assert Ad.sell_dix is not None
+    kw = dict(restart=20, fmt="fp64", tol=0.0, maxiter=12, precond="jacobi")
+    ref = orc.gmres(A, b, variant=FIG1, **kw)
+    r = cbg.solve(Ad, torch.from_numpy(b).to(dev), **kw)
+    assert np.allclose(r.hist[:3], ref["hist"][:3], rtol=1e-12, atol=0)
+    xo = ref["x"]
+    assert np.linalg.norm(r.x.cpu().numpy() - xo) <= 1e-8 * np.linalg.norm(xo)
+    Z = _banded_with_holes(drop_diag=100)
+    assert orc.gmres(Z, b, **kw)["status"] == -1
+    with pytest.raises(cbg.CbgError) as e:
+        cbg.solve(cbg.DeviceCSR.from_host(Z, dev, sell=True), torch.from_numpy(b).to(dev), **kw)
+    assert e.value.status == -1
+
+
 def test_sparse_preconditioner_equal_to_jacobi(cbg, orc, dev):
     from paper_2009_12101_amd import problems as P
     A = P.lognormal27(10, 5)

@@ -109,10 +109,39 @@ def unit_vectors(n, K, seed):
     return V / np.linalg.norm(V, axis=1, keepdims=True)
 
 
-@pytest.mark.parametrize("name", list(SYSTEMS))
-def test_features_bit_exact(cbg, S, dev, name):
-    A = SYSTEMS[name]()
-    Ad = cbg.DeviceCSR.from_host(A, dev)
+def with_holes(A, frac=0.2, seed=3):
+    """A with a seeded fraction of its off-diagonal entries removed: rows of
+    different lengths inside one 64-row slice, so the sliced-ELL copy pads."""
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr))
+    keep = (A.col_idx == rows) | (np.random.default_rng(seed).random(A.nnz) >= frac)
+    rp = np.concatenate([[0], np.cumsum(np.bincount(rows[keep], minlength=A.n))]).astype(np.int32)
+    return P.CSR(A.n, rp, A.col_idx[keep].copy(), A.val[keep].copy(), grid=A.grid,
+                 name=A.name + "_holes")
+
+
+# the feature and code kernels read A's sliced-ELL copy when it has one (one
+# lane per row), else the CSR arrays (a half-wave per row): both, on the
+# stencil systems and on one with holes in its pattern
+BUILD_CASES = [(name, st) for name in list(SYSTEMS) + ["lognormal27_11_holes"]
+               for st in ("sell", "csr")]
+
+
+def build_system(name):
+    if name == "lognormal27_11_holes":
+        return with_holes(P.lognormal27(11, 5))
+    return SYSTEMS[name]()
+
+
+def device_csr(cbg, A, dev, storage):
+    Ad = cbg.DeviceCSR.from_host(A, dev, sell=storage == "sell")
+    assert (Ad.sell_dix is not None) == (storage == "sell")
+    return Ad
+
+
+@pytest.mark.parametrize("name,storage", BUILD_CASES)
+def test_features_bit_exact(cbg, S, dev, name, storage):
+    A = build_system(name)
+    Ad = device_csr(cbg, A, dev, storage)
     feat = cbg.spai_features(Ad, A.grid)
     torch.cuda.synchronize()
     assert np.array_equal(from_bf16(feat), S.features(A, A.grid))
@@ -387,15 +416,15 @@ def _stencil_ref(A, grid, codes, v):
     return dinv * s, 64 * 2.0 ** -53 * np.abs(dinv) * sa
 
 
-@pytest.mark.parametrize("name", list(SYSTEMS))
-def test_stencil_codes_bit_exact(cbg, S, dev, name):
+@pytest.mark.parametrize("name,storage", BUILD_CASES)
+def test_stencil_codes_bit_exact(cbg, S, dev, name, storage):
     """The stored form: float16 of the network output on the slots each row
     stores, 0 elsewhere, slot-major at stride basis_ld(n) -- against the
     oracle's codes of the same (GPU) network output."""
-    A = SYSTEMS[name]()
+    A = build_system(name)
     prm = random_params(S, 11, scale3=0.2)
     params, weights = to_device(prm, dev)
-    Ad = cbg.DeviceCSR.from_host(A, dev)
+    Ad = device_csr(cbg, A, dev, storage)
     codes = cbg.learned_build_stencil(Ad, A.grid, weights, params)
     O = cbg.mlp_forward(cbg.spai_features(Ad, A.grid), weights, params)
     torch.cuda.synchronize()
