@@ -69,11 +69,12 @@ __device__ __forceinline__ double dec_f16(uint32_t c)
     return (double)(float)h;
 }
 __device__ __forceinline__ double dec_bf16(uint32_t c) { return (double)__uint_as_float(c << 16); }
+// e4m3 (OCP E4M3FN) code -> value: gfx950's fp8 conversion, exact for every
+// finite code (each is a float); S.1111.111 is NaN, which the encoder never
+// writes.
 __device__ __forceinline__ double dec_e4m3(uint32_t c)
 {
-    uint32_t e = (c >> 3) & 15u, m = c & 7u;
-    float f = e ? __uint_as_float(((e + 120u) << 23) | (m << 20)) : (float)m * 0x1p-9f;
-    return (c & 0x80u) ? -(double)f : (double)f;
+    return (double)__builtin_amdgcn_cvt_f32_fp8((int)c, 0);
 }
 
 // Encoding parameters of one stored vector, derived from its scale.
@@ -201,12 +202,18 @@ template <> struct Fmt<F_E4M3> {
     static constexpr bool SCALED = true;
     __device__ static void dec(u32x4 q, double s, double *d)
     {
+        // two codes per conversion (bytes 0-1, then 2-3, of each word);
+        // s = 2^k, so the products are exact
         uint32_t w[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-                d[4 * i + b] = dec_e4m3((w[i] >> (8 * b)) & 0xFFu) * s;   // s = 2^k: exact
+        for (int i = 0; i < 4; ++i) {
+            const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[i], false);
+            const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[i], true);
+            d[4 * i + 0] = (double)lo[0] * s;
+            d[4 * i + 1] = (double)lo[1] * s;
+            d[4 * i + 2] = (double)hi[0] * s;
+            d[4 * i + 3] = (double)hi[1] * s;
+        }
     }
     __device__ static uint32_t code(double v, EncParam p)
     {

@@ -94,6 +94,21 @@ def test_e4m3_all_codes_and_ties(cbg, orc, dev):
     assert np.array_equal(gpu_codes(q, "e4m3"), qo)
 
 
+def test_e4m3_decode_every_code(cbg, orc, dev):
+    """All 256 codes through the kernel-level decode against the oracle's
+    table: equal values, and NaN exactly where the OCP E4M3FN format puts
+    it (S.1111.111), at two scales."""
+    codes = np.arange(256, dtype=np.uint8)
+    for scale in (1.0, 2.0 ** -9):
+        sc = torch.tensor([scale], dtype=torch.float64, device=dev)
+        got = cbg.decode("e4m3", torch.from_numpy(codes).to(dev), sc).cpu().numpy()
+        want = orc.decode("e4m3", codes, scale)
+        assert np.array_equal(np.isnan(got), np.isnan(want))
+        assert np.isnan(got).sum() == 2
+        ok = ~np.isnan(want)
+        assert np.array_equal(got[ok].view(np.uint64), want[ok].view(np.uint64))
+
+
 @pytest.mark.parametrize("fmt", ["int16", "int32"])
 def test_fixed_point_ties(cbg, orc, dev, fmt):
     M = 32767 if fmt == "int16" else 2147483647
