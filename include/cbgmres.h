@@ -457,7 +457,11 @@ size_t cbg_spai_workspace_bytes(int32_t n, int64_t nnz, int32_t K);
 
 /* Features of every row (see above).  grid [host] {nx, ny, nz}; feat [dev]
  * n x 64 bf16.  Synchronises with the stream; returns CBG_E_NONFINITE if a
- * row has a zero (or missing) diagonal or a non-finite feature. */
+ * row has a zero (or missing) diagonal or a non-finite feature.  This call,
+ * cbg_learned_build, cbg_learned_build_stencil and cbg_stencil_apply read
+ * A's sliced-ELL copy when A carries one with diagonal indices (sell_ptr,
+ * sell_val, sell_dix, sell_diag), else the CSR arrays; the results are the
+ * same bit for bit. */
 int cbg_spai_features(const cbg_csr *A, const int32_t grid[3], uint16_t *feat, void *ws,
                       size_t ws_bytes, void *stream);
 
