@@ -16,6 +16,7 @@ constexpr int BLK = 256;                 // threads per block (4 wave64)
 constexpr int NWAVE = BLK / 64;
 constexpr int MAX_RESTART = 512;
 constexpr int MAX_GRID = 4096;           // upper bound on blocks of reducing kernels
+constexpr int SPMV_MAX_GRID = 8192;      // the sliced-ELL SpMV's bound (its partials have rows of their own)
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));

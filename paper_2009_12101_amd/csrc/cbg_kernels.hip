@@ -2188,7 +2188,7 @@ __global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth
     int nb;
     if (role == RR_H || role == RR_HG) {
         s0 = ws.spmv;                                   // omega^2
-        s1 = ws.spmv + ws.stride;
+        s1 = ws.spmv + ws.sstride;
         nb = nb_spmv;
     } else if (role == RR_U) {
         s0 = ws.orth + (size_t)j * ws.stride;           // ||w||^2, max|w_i|
@@ -2207,7 +2207,7 @@ __global__ __launch_bounds__(RBLK) void k_reduce(RedWs ws, int role, int nb_orth
         nb = nb_orth;
     } else {
         s0 = ws.spmv;
-        s1 = ws.spmv + ws.stride;
+        s1 = ws.spmv + ws.sstride;
         nb = nb_spmv;
     }
     {
@@ -2647,7 +2647,7 @@ template <int RPB, int CAP>
 static int spmv_shape(const SpmvArgs &a, hipStream_t s)
 {
     int g = grid_for((a.ldy + RPB - 1) / RPB, 1);
-    RedArgs ra{a.ws.spmv, a.ws.stride};
+    RedArgs ra{a.ws.spmv, a.ws.sstride};
 #define CBG_SPMV_CASE(M)                                                                      \
     case M:                                                                                   \
         if (a.ev0)                                                                            \
@@ -2680,7 +2680,7 @@ template <int RPB, int CAP>
 static int spmv_rp_shape(const SpmvArgs &a, hipStream_t s)
 {
     int g = grid_for((a.ldy + RPB - 1) / RPB, 1);
-    RedArgs ra{a.ws.spmv, a.ws.stride};
+    RedArgs ra{a.ws.spmv, a.ws.sstride};
 #define CBG_SPMV_CASE(M)                                                                      \
     case M:                                                                                   \
         if (a.ev0)                                                                            \
@@ -2712,9 +2712,14 @@ static int spmv_rp_shape(const SpmvArgs &a, hipStream_t s)
 
 static int spmv_sell(const SpmvArgs &a, hipStream_t s)
 {
+    // long rows (more than 12 per row): up to SPMV_MAX_GRID blocks, which
+    // measured 2% faster on the 27-point rows at 160^3; short rows keep
+    // MAX_GRID (8192 blocks were 3% slower on the 7-point rows at 128^3,
+    // the fold of their partials included)
     const int64_t nsy = (a.ldy + 63) / 64;
-    const int g = grid_for((nsy + NWAVE - 1) / NWAVE, 1);
-    RedArgs ra{a.ws.spmv, a.ws.stride};
+    const int g = (int)std::min<int64_t>(std::max<int64_t>((nsy + NWAVE - 1) / NWAVE, 1),
+                                         a.sell_nt ? SPMV_MAX_GRID : MAX_GRID);
+    RedArgs ra{a.ws.spmv, a.ws.sstride};
 #define CBG_SELL_LAUNCH(M, NT, DX)                                                             \
     if (a.ev0)                                                                                 \
         hipExtLaunchKernelGGL(k_spmv_sell<M, NT, DX>, dim3(g), dim3(BLK), 0, s, a.ev0, a.ev1,  \
@@ -3082,7 +3087,7 @@ void launch_decode(int fmt, const void *Q, int n, const double *scale, double *v
 int launch_norm(const double *x, int64_t n, const RedWs &ws, hipStream_t s)
 {
     int g = grid_for(n, BLK * 4);
-    k_norm<<<g, BLK, 0, s>>>(x, n, RedArgs{ws.spmv, ws.stride});
+    k_norm<<<g, BLK, 0, s>>>(x, n, RedArgs{ws.spmv, ws.sstride});
     return g;
 }
 

@@ -11,8 +11,9 @@ struct DevState;
 // Block-partial scratch carved from a workspace (value-major, see RedArgs).
 struct RedWs {
     double *orth;     // multi-dot / update partials: (max j + 2) rows of `stride`
-    double *spmv;     // SpMV / norm partials: 2 rows of `stride`
-    int stride;       // >= the grid of every producer
+    double *spmv;     // SpMV / norm partials: 2 rows of `sstride`
+    int stride;       // >= the grid of every producer of `orth`
+    int sstride;      // >= the grid of every producer of `spmv`
 };
 
 struct SpmvArgs {

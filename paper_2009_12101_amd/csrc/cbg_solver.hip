@@ -79,7 +79,7 @@ int64_t basis_ld(int32_t n) { return ((int64_t)n + 255) / 256 * 256; }
 size_t red_bytes(int jmax)
 {
     return align_up((size_t)(jmax + 2) * MAX_GRID * sizeof(double)) +
-           align_up((size_t)2 * MAX_GRID * sizeof(double));
+           align_up((size_t)2 * SPMV_MAX_GRID * sizeof(double));
 }
 
 // Carves a workspace front to back; records the total size.
@@ -99,8 +99,9 @@ RedWs carve_red(Carver &c, int jmax, int rows = 0)
 {
     RedWs r;
     r.stride = MAX_GRID;
+    r.sstride = SPMV_MAX_GRID;
     r.orth = c.take<double>((size_t)(rows > 0 ? rows : jmax + 2) * MAX_GRID);
-    r.spmv = c.take<double>((size_t)2 * MAX_GRID);
+    r.spmv = c.take<double>((size_t)2 * SPMV_MAX_GRID);
     return r;
 }
 
@@ -1110,6 +1111,7 @@ int cbg_multidot_noalloc(int32_t format, const void *V, int64_t ld, const double
     o.ws.orth = base;          // rows 0 .. j-1: the block partials of h
     o.ws.spmv = base + (size_t)(j + 2) * MAX_GRID;
     o.ws.stride = MAX_GRID;
+    o.ws.sstride = MAX_GRID;            // no SpMV here
     launch_multidot(o, s);
     launch_reduce(o.ws, RR_VALUES, orth_grid(format, n), 0, j, nullptr, nullptr, h, format, s);
     HIP_TRY(hipGetLastError());
