@@ -17,7 +17,9 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# CBG_ORACLE_LIB names another build of oracle.c to load in place of the
+# in-tree one (the mutation test loads copies with planted mistakes this way).
+LIB_PATH = os.environ.get("CBG_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 SRC = os.path.join(_HERE, "oracle.c")
 
 FORMATS = {"fp64": 0, "fp32": 1, "fp16": 2, "bf16": 3, "e4m3": 4, "int32": 5, "int16": 6,

@@ -160,6 +160,10 @@ def test_e4m3_decode_table_matches_torch(orc):
     assert np.array_equal(np.isnan(mine), np.isnan(tvals))
     assert np.array_equal(mine[~both_nan], tvals[~both_nan])
     assert mine[0x7E] == 448.0 and mine[0x01] == 2.0 ** -9 and mine[0x38] == 1.0
+    # a stored vector's value is its scale times the code's value (Section 4)
+    for k in (-13, 5):
+        scaled = orc.decode("e4m3", codes.astype(np.uint8), 2.0 ** k)
+        assert np.array_equal(scaled[~both_nan], tvals[~both_nan] * 2.0 ** k)
 
 
 def test_e4m3_scale_and_brute_force(orc):
