@@ -132,6 +132,69 @@ MUTANTS = [
      "(size_t)(i - i0) * bs;", "(size_t)(i - i0);"),
 ]
 
+# The learned preconditioner's oracle (oracle/spai.py, an extension of the
+# paper: features, network, loss and gradients, Adam), checked the same way
+# against tests/test_oracle_spai.py: (name, what the mistake is, text in
+# spai.py, text it is replaced with).
+SPAI_SRC = os.path.join(ROOT, "oracle", "spai.py")
+SPAI_MUTANTS = [
+    ("slot_axes_swapped", "slots run x-major instead of z-major",
+     "(dz + 1) * 9 + (dy + 1) * 3 + (dx + 1)", "(dx + 1) * 9 + (dy + 1) * 3 + (dz + 1)"),
+    ("row_y_unwrapped", "a row's y coordinate is not taken modulo ny",
+     "xr, yr, zr = rows % nx, (rows // nx) % ny,", "xr, yr, zr = rows % nx, (rows // nx),"),
+    ("coef_by_column_diagonal", "a coefficient feature divides by the column's a_jj",
+     "fl32(A.val[good] / d[rows[good]])", "fl32(A.val[good] / d[A.col_idx[good]])"),
+    ("neighbour_ratio_inverted", "the neighbour-diagonal feature is inverted",
+     "fl32(d[A.col_idx[good]] / d[rows[good]])", "fl32(d[rows[good]] / d[A.col_idx[good]])"),
+    ("dominance_sign", "the dominance feature adds the off-diagonal sum",
+     "F[:, 27] = fl32((d - s) / d)", "F[:, 27] = fl32((d + s) / d)"),
+    ("no_first_relu", "the first hidden layer has no ReLU",
+     "H1 = r(np.maximum(F @ W1 + b1, 0.0))", "H1 = r(F @ W1 + b1)"),
+    ("drops_b2", "the second layer drops its bias",
+     "H2 = r(np.maximum(H1 @ W2 + b2, 0.0))", "H2 = r(np.maximum(H1 @ W2, 0.0))"),
+    ("p_minus_o", "P takes delta - O",
+     "val = (delta + np.where(slots >= 0, o, 0.0)) / d[rows]",
+     "val = (delta - np.where(slots >= 0, o, 0.0)) / d[rows]"),
+    ("p_times_aii", "P multiplies by a_ii",
+     "val = (delta + np.where(slots >= 0, o, 0.0)) / d[rows]",
+     "val = (delta + np.where(slots >= 0, o, 0.0)) * d[rows]"),
+    ("codes_by_column", "a stored code goes to the column's row",
+     "codes[slots[good], rows[good]] = o16", "codes[slots[good], A.col_idx[good]] = o16"),
+    ("loss_scale", "the loss divides by K n instead of K",
+     "L = float(np.sum(R * R)) / K", "L = float(np.sum(R * R)) / (K * A.n)"),
+    ("grad_factor", "dL/dP loses the factor 2",
+     "G = (2.0 / K) * (At @ R)", "G = (1.0 / K) * (At @ R)"),
+    ("grad_p_transposed", "dP pairs G's column with v's row",
+     'np.einsum("ek,ek->e", G[rows], V.T[A.col_idx])',
+     'np.einsum("ek,ek->e", G[A.col_idx], V.T[rows])'),
+    ("grad_o_times_aii", "dL/dO multiplies by a_ii",
+     "dO[rows[good], slots[good]] = dP[good] / d[rows[good]]",
+     "dO[rows[good], slots[good]] = dP[good] * d[rows[good]]"),
+    ("dw2_wrong_layer", "dW2 takes H2 in place of H1",
+     "dW2 = H1.T @ dH2", "dW2 = H2.T @ dH2"),
+    ("relu_mask_wrong_layer", "dH2 is masked by H1's ReLU",
+     "dH2 = r((dO @ W3.T) * (H2 > 0))", "dH2 = r((dO @ W3.T) * (H1 > 0))"),
+    ("w2_not_transposed", "dH1 multiplies by W2 instead of its transpose",
+     "dH1 = r((dH2 @ W2.T) * (H1 > 0))", "dH1 = r((dH2 @ W2) * (H1 > 0))"),
+    ("adam_no_bias_correction", "Adam drops the first moment's bias correction",
+     "mh = m / (1 - beta1 ** t)", "mh = m"),
+    ("adam_no_sqrt", "Adam divides by v instead of sqrt(v)",
+     "lr * mh / (np.sqrt(vh) + eps)", "lr * mh / (vh + eps)"),
+]
+
+_SPAI_CHILD = """
+import importlib.util, sys
+sys.path.insert(0, sys.argv[1])
+import oracle
+spec = importlib.util.spec_from_file_location("oracle.spai", sys.argv[2])
+mod = importlib.util.module_from_spec(spec)
+sys.modules["oracle.spai"] = mod
+spec.loader.exec_module(mod)
+oracle.spai = mod
+import pytest
+sys.exit(pytest.main(["-x", "-q", "-p", "no:cacheprovider", sys.argv[3]]))
+"""
+
 
 def _build(src_text, out):
     c = out + ".c"
@@ -186,5 +249,47 @@ def test_every_planted_mistake_fails_a_pin(tmp_path):
         results = dict(ex.map(one, jobs))
     rc, msg = results.pop("unmodified")
     assert rc == 0, f"the unmodified oracle fails its pins: {msg}"
+    survivors = {n: msg for n, (rc, msg) in results.items() if rc == 0}
+    assert not survivors, f"planted mistakes no pin catches: {survivors}"
+
+
+def _run_spai_pins(path, timeout=240):
+    env = dict(os.environ, OMP_NUM_THREADS="2", OMP_WAIT_POLICY="PASSIVE")
+    cmd = [sys.executable, "-c", _SPAI_CHILD, ROOT, path,
+           os.path.join(ROOT, "tests", "test_oracle_spai.py")]
+    try:
+        r = subprocess.run(cmd, cwd=ROOT, env=env, capture_output=True, text=True,
+                           timeout=timeout)
+    except subprocess.TimeoutExpired:
+        return None, "timed out"
+    lines = [ln for ln in r.stdout.splitlines() if ln.startswith("FAILED") or "rror" in ln]
+    return r.returncode, (lines[0] if lines else r.stdout.strip().splitlines()[-1:])
+
+
+def test_spai_mutant_table_applies_once():
+    src = open(SPAI_SRC).read()
+    names = [m[0] for m in SPAI_MUTANTS]
+    assert len(set(names)) == len(names)
+    for name, _, old, new in SPAI_MUTANTS:
+        assert src.count(old) == 1, name
+        assert old != new, name
+
+
+@pytest.mark.slow
+def test_every_planted_mistake_in_the_network_oracle_fails_a_pin(tmp_path):
+    src = open(SPAI_SRC).read()
+    jobs = [("unmodified", src)] + [(n, src.replace(old, new)) for n, _, old, new in SPAI_MUTANTS]
+
+    def one(job):
+        name, text = job
+        path = str(tmp_path / f"spai_{name}.py")
+        with open(path, "w") as f:
+            f.write(text)
+        return name, _run_spai_pins(path)
+
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        results = dict(ex.map(one, jobs))
+    rc, msg = results.pop("unmodified")
+    assert rc == 0, f"the unmodified network oracle fails its pins: {msg}"
     survivors = {n: msg for n, (rc, msg) in results.items() if rc == 0}
     assert not survivors, f"planted mistakes no pin catches: {survivors}"

@@ -61,6 +61,26 @@ def test_features_of_constant_coefficient_stencil(S):
     assert F[0, 27] == S.bf16(np.array([b((26.01 - 7.0) / 26.01)]))[0]
 
 
+@pytest.mark.parametrize("axis", ["x", "z"])
+def test_features_of_a_chain_with_varying_diagonal(S, axis):
+    # three unknowns in a line along x (slots 12, 14) or z (slots 4, 22),
+    # diagonal 2, 4, 8 and -1 between neighbours; every feature is a ratio of
+    # small powers of two, exact in bfloat16
+    from _helpers import csr_from_dense
+    M = np.diag([2.0, 4.0, 8.0]) - np.eye(3, k=1) - np.eye(3, k=-1)
+    A = csr_from_dense(M)
+    grid = (3, 1, 1) if axis == "x" else (1, 1, 3)
+    lo, hi = (12, 14) if axis == "x" else (4, 22)
+    F = S.features(A, grid)
+    expect = np.zeros((3, 64))
+    expect[:, 13] = expect[:, 32 + 13] = 1.0
+    expect[0, hi], expect[0, 32 + hi], expect[0, 27] = -0.5, 2.0, 0.5
+    expect[1, lo], expect[1, hi], expect[1, 27] = -0.25, -0.25, 0.5
+    expect[1, 32 + lo], expect[1, 32 + hi] = 0.5, 2.0
+    expect[2, lo], expect[2, 32 + lo], expect[2, 27] = -0.125, 0.5, 0.875
+    assert np.array_equal(F, expect)
+
+
 def test_identity_network_returns_relu_of_features(S):
     A = P.lognormal27(4, 3)
     F = S.features(A, A.grid)
