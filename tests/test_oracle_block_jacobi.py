@@ -77,6 +77,17 @@ def test_precision_rule_on_blocks_of_known_condition(orc):
     assert np.all(prec == 64)
 
 
+def test_precision_rule_takes_the_one_norm_condition_number(orc):
+    # U = I + 2 (e_1 e_2^T + e_1 e_3^T + e_1 e_4^T) and its inverse I - 2(...)
+    # have column sums at most 3 and row sums up to 7: kappa_1 = 9 (fp16) while
+    # kappa_inf = 49 (fp32); U^T swaps the two
+    U = np.eye(4)
+    U[0, 1:] = 2.0
+    A = csr_from_dense(blockdiag([U, U.T.copy()]))
+    _, prec = orc.block_jacobi(A, bs=4, prec_min=16)
+    assert list(prec) == [16, 32]
+
+
 def test_stored_values_are_single_roundings(orc):
     A = P.lognormal27(6, 2)
     v64, p64 = orc.block_jacobi(A, bs=4, prec_min=64)

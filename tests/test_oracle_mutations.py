@@ -128,6 +128,16 @@ MUTANTS = [
      "const double f = D[i * bs + c];", "const double f = D[c * bs + i];"),
     ("bj_fp16_unit", "block_jacobi", "block-Jacobi's fp16 rule uses fp32's unit roundoff",
      "kappa * ldexp(1.0, -11) <= 0.01", "kappa * ldexp(1.0, -24) <= 0.01"),
+    ("norm1_by_rows", "block_jacobi", "kappa_1 sums rows instead of columns",
+     "s = s + fabs(M[i * bs + k]);", "s = s + fabs(M[k * bs + i]);"),
+    ("stagnation_late", "solver", "the stagnation fallback waits for a third flat cycle",
+     "if (stagnant >= 2) {", "if (stagnant >= 3) {"),
+    ("eta_half", "solver", "the re-orthogonalisation threshold is 1/2, not 1/sqrt(2)",
+     "#define ETA_DEFAULT 0.70710678118654752440", "#define ETA_DEFAULT 0.5"),
+    ("breakdown_only_exact", "solver", "step 12 ends a cycle only on an exact zero",
+     "brk = (t2 == 0.0) || (t2 < eta * t);", "brk = (t2 == 0.0);"),
+    ("spmv_vhat_first_column", "ablations", "the stored-vector SpMV reads the first column",
+     "orc_decode(fmt, n, Q[jc], sc[jc], v);", "orc_decode(fmt, n, Q[0], sc[0], v);"),
     ("bj_block_row", "block_jacobi", "block-Jacobi applies row i of the block with the wrong stride",
      "(size_t)(i - i0) * bs;", "(size_t)(i - i0);"),
 ]
