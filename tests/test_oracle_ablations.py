@@ -336,6 +336,30 @@ def test_onepass_textbook_breakdowns(orc, fmt):
         assert r1["breakdowns"] >= 1
 
 
+def test_onepass_sees_the_exhausted_krylov_space(orc):
+    """A = Q diag(d) Q^T with k distinct eigenvalues (random orthogonal Q):
+    the Krylov space has dimension k, so w of step k lies in span(V_k) and
+    h_{k+1,k} = 0 in exact arithmetic; after rounding, the one-pass form's
+    floored t1 must still report the breakdown at step k, with x the
+    solution.  (Fig. 1's two-pass form, read as in step 12, goes on with a
+    rounding-level vector here; its stop test ends it at step k instead.)"""
+    for seed in range(24):
+        rng = np.random.default_rng(seed)
+        n, k = 24, 3 + seed % 4
+        Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        d = np.repeat(np.arange(1.0, k + 1), -(-n // k))[:n]
+        M = Q @ np.diag(d) @ Q.T
+        b = rng.standard_normal(n)
+        A = csr_from_dense(M)
+        r = orc.gmres(A, b, restart=20, fmt="fp64", tol=1e-30, maxiter=k,
+                      variant=("gram", "onepass"))
+        assert (r["iterations"], r["breakdowns"]) == (k, 1), seed
+        xs = np.linalg.solve(M, b)
+        assert np.linalg.norm(r["x"] - xs) <= 1e-10 * np.linalg.norm(xs), seed
+        r0 = orc.gmres(A, b, restart=20, fmt="fp64", tol=1e-12, maxiter=40)
+        assert r0["status"] == 0 and r0["iterations"] == k, seed
+
+
 def test_onepass_needs_the_gram_form(orc):
     A = P.poisson2d(4)
     assert orc.gmres(A, np.ones(A.n), restart=5, variant="onepass")["status"] == -1

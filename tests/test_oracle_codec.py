@@ -182,6 +182,15 @@ def test_e4m3_scale_and_brute_force(orc):
         assert np.array_equal(q.astype(np.uint32), ref)
 
 
+def test_e4m3_scale_when_the_top_entry_is_exactly_448(orc):
+    # max|v| * 2^-k must lie in (224, 448]: at exactly 448 the scale stays
+    for top, k in ((1.75, -8), (448.0 * 2.0 ** 5, 5)):
+        v = np.array([top, 0.5 * top, -0.25 * top, 0.0])
+        q, sc = orc.encode("e4m3", v)
+        assert sc == 2.0 ** k
+        assert list(q) == [0x7E, 0x76, 0xEE, 0x00]      # 448, 224, -112, 0
+
+
 def test_e4m3_matches_torch_on_f32_exact(orc):
     import torch
     rng = np.random.default_rng(5)

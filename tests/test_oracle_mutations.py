@@ -138,6 +138,22 @@ MUTANTS = [
      "brk = (t2 == 0.0) || (t2 < eta * t);", "brk = (t2 == 0.0);"),
     ("spmv_vhat_first_column", "ablations", "the stored-vector SpMV reads the first column",
      "orc_decode(fmt, n, Q[jc], sc[jc], v);", "orc_decode(fmt, n, Q[0], sc[0], v);"),
+    ("onepass_criterion_inverted", "ablations", "the one-pass step re-orthogonalises when t1 is large",
+     "const int ro = always_reorth || t1 < eta * omega;",
+     "const int ro = always_reorth || t1 > eta * omega;"),
+    ("onepass_no_floor", "ablations", "the one-pass norm has no rounding floor",
+     "const double floor2 = 4.0 * (j + 1) * 0x1p-53 * omega * omega;",
+     "const double floor2 = 0.0;"),
+    ("sparse_pc_row_operand", "solver", "the sparse P multiplies by v at the row",
+     "s += (double)val[p] * x[ci[p]];", "s += (double)val[p] * x[i];"),
+    ("bj_apply_operand", "block_jacobi", "block-Jacobi pairs the block row with the block's first v",
+     "s = s + row[l] * v[i0 + l];", "s = s + row[l] * v[i0];"),
+    ("gj_smallest_pivot", "block_jacobi", "Gauss-Jordan pivots on the smallest entry",
+     "if (fabs(D[i * bs + c]) > best) {", "if (fabs(D[i * bs + c]) < best) {"),
+    ("e4m3_scale_edge", "codec", "e4m3's scale steps up when the top entry is exactly 448",
+     "if (ldexp(vinf, -k) > 448.0)", "if (ldexp(vinf, -k) >= 448.0)"),
+    ("fp16s_scale_edge", "ablations", "scaled float16 steps up when the top entry is exactly 65504",
+     "if (ldexp(vinf, -k) > 65504.0)", "if (ldexp(vinf, -k) >= 65504.0)"),
     ("bj_block_row", "block_jacobi", "block-Jacobi applies row i of the block with the wrong stride",
      "(size_t)(i - i0) * bs;", "(size_t)(i - i0);"),
 ]
