@@ -126,3 +126,26 @@ def test_stencil_steps_take_the_one_pass_form(cbg, orc, dev):
     r = cbg.solve(cbg.DeviceCSR.from_host(A, dev), torch.from_numpy(b).to(dev), restart=30,
                   fmt="fp16", tol=1e-10, maxiter=2000)
     assert r.status == 0 and r.explicit_steps == 0
+
+
+def test_exhausted_krylov_space_ends_at_k_steps(cbg, orc, dev):
+    """A = Q diag(d) Q^T with k distinct eigenvalues and random orthogonal Q:
+    the Krylov space has dimension k, so the solve ends at step k with x the
+    solution, as the oracle's Fig. 1 form does; step k is hard (t / omega at
+    rounding level) and takes the explicit form."""
+    for seed in range(12):
+        rng = np.random.default_rng(seed)
+        n, k = 24, 3 + seed % 4
+        Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+        d = np.repeat(np.arange(1.0, k + 1), -(-n // k))[:n]
+        M = Q @ np.diag(d) @ Q.T
+        b = rng.standard_normal(n)
+        A = csr_from_dense(M, f"kdistinct_{seed}")
+        ref = orc.gmres(A, b, restart=20, fmt="fp64", tol=1e-12, maxiter=40, variant=FIG1)
+        r = cbg.solve(cbg.DeviceCSR.from_host(A, dev), torch.from_numpy(b).to(dev), restart=20,
+                      fmt="fp64", tol=1e-12, maxiter=40)
+        assert ref["status"] == 0 and ref["iterations"] == k, seed
+        assert r.status == 0 and r.iterations == k, (seed, r.iterations)
+        assert r.explicit_steps >= 1, seed
+        xs = np.linalg.solve(M, b)
+        assert np.linalg.norm(r.x.cpu().numpy() - xs) <= 1e-10 * np.linalg.norm(xs), seed
