@@ -154,6 +154,17 @@ MUTANTS = [
      "if (ldexp(vinf, -k) > 448.0)", "if (ldexp(vinf, -k) >= 448.0)"),
     ("fp16s_scale_edge", "ablations", "scaled float16 steps up when the top entry is exactly 65504",
      "if (ldexp(vinf, -k) > 65504.0)", "if (ldexp(vinf, -k) >= 65504.0)"),
+    ("mgs_adds", "ablations", "the MGS pass adds h_k v_k",
+     "w[i] = w[i] - hk * buf[i];", "w[i] = w[i] + hk * buf[i];"),
+    ("history_lags", "solver", "the residual history records the previous step's estimate",
+     "hist[it - 1] = last_rec;", "hist[it - 1] = fabs(g[jc]) / nb;"),
+    ("cycle_length_short", "solver", "a cycle's length is reported one short",
+     "cycle_len[cycle] = meff;", "cycle_len[cycle] = meff - 1;"),
+    ("cycle_residual_unscaled", "solver", "the restart residual is reported without 1/||b||",
+     "cycle_res[cycle] = rho / nb;", "cycle_res[cycle] = rho;"),
+    ("true_residual_unscaled", "solver", "the true residual is reported without 1/||b||",
+     "res->true_rel_res = sqrt(orc_dot(n, r, r)) / nb;",
+     "res->true_rel_res = sqrt(orc_dot(n, r, r));"),
     ("bj_block_row", "block_jacobi", "block-Jacobi applies row i of the block with the wrong stride",
      "(size_t)(i - i0) * bs;", "(size_t)(i - i0);"),
 ]

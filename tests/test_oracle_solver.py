@@ -109,6 +109,20 @@ def test_full_gmres_converges_at_m_equal_n(orc):
         assert r["true_rel_res"] <= 1e-12
 
 
+def test_reported_residuals_are_relative_to_b(orc):
+    # step 1's explicit residual of every cycle is reported over ||b||: 1 for
+    # x0 = 0, and at the end the true residual of the returned x
+    A = P.convdiff7(6)
+    b = 40.0 * P.rhs_uniform(A.n, 2)
+    r = orc.gmres(A, b, restart=10, fmt="fp16", tol=1e-9, maxiter=500)
+    cr = np.asarray(r["cycle_res"])
+    assert r["status"] == 0 and cr[0] == 1.0
+    assert cr[-1] == r["true_rel_res"] <= 1e-9
+    D = sp.csr_matrix((A.val, A.col_idx, A.row_ptr), shape=(A.n, A.n))
+    assert r["true_rel_res"] == pytest.approx(
+        np.linalg.norm(b - D @ r["x"]) / np.linalg.norm(b), rel=1e-6)
+
+
 def test_identity_breaks_down_after_one_step(orc):
     A = csr_from_dense(np.eye(50))
     b = P.rhs_uniform(50, 2)
