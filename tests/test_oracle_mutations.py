@@ -213,6 +213,15 @@ SPAI_MUTANTS = [
      "dH2 = r((dO @ W3.T) * (H2 > 0))", "dH2 = r((dO @ W3.T) * (H1 > 0))"),
     ("w2_not_transposed", "dH1 multiplies by W2 instead of its transpose",
      "dH1 = r((dH2 @ W2.T) * (H1 > 0))", "dH1 = r((dH2 @ W2) * (H1 > 0))"),
+    ("adam_second_moment_linear", "Adam's second moment accumulates g, not g^2",
+     "v[...] = fl32(beta2 * v + (1 - beta2) * g * g)", "v[...] = fl32(beta2 * v + (1 - beta2) * g)"),
+    ("weights_not_bf16", "the weights the network sees are not rounded to bfloat16",
+     '(bf16(v) if k.startswith("W") else v)', "v"),
+    ("dominance_signed", "the dominance feature sums signed off-diagonals",
+     "off = np.where(A.col_idx == rows, 0.0, np.abs(A.val))",
+     "off = np.where(A.col_idx == rows, 0.0, A.val)"),
+    ("drops_b3", "the output layer drops its bias",
+     "O = H2 @ W3 + b3", "O = H2 @ W3"),
     ("adam_no_bias_correction", "Adam drops the first moment's bias correction",
      "mh = m / (1 - beta1 ** t)", "mh = m"),
     ("adam_no_sqrt", "Adam divides by v instead of sqrt(v)",

@@ -153,10 +153,18 @@ def test_adam_first_step_is_lr_sign(S):
     prm = dict(W1=np.zeros((64, 64)), b1=np.zeros(64), W2=np.zeros((64, 64)), b2=np.zeros(64),
                W3=np.zeros((64, 32)), b3=np.zeros(32))
     g = {k: rng.standard_normal(v.shape) for k, v in prm.items()}
-    S.adam_step(prm, g, {}, 1, lr=1e-3)
+    view = S.adam_step(prm, g, {}, 1, lr=1e-3)
     for k in prm:
         expect = -1e-3 * g[k].astype(np.float32) / (np.abs(g[k].astype(np.float32)) + 1e-8)
         assert np.allclose(prm[k], expect, rtol=1e-6, atol=0)
+        # the network reads bfloat16 weights (torch's round-to-nearest-even
+        # cast of the fp32 masters) and fp32 biases
+        if k.startswith("W"):
+            import torch
+            bf = torch.from_numpy(prm[k].astype(np.float32)).to(torch.bfloat16).double().numpy()
+            assert np.array_equal(view[k], bf)
+        else:
+            assert np.array_equal(view[k], prm[k])
 
 
 # ---------------------------------------------------------------- stored form
