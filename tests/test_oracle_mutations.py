@@ -119,6 +119,11 @@ MUTANTS = [
     # preconditioners
     ("jacobi_multiplies_by_aii", "solver", "Jacobi multiplies by a_ii",
      "z[i] = M->dinv[i] * v[i];", "z[i] = v[i] / M->dinv[i];"),
+    ("stencil_without_dinv", "spai", "the stored form leaves out diag(1/a_ii)",
+     "z[i] = M->dinv[i] * s;", "z[i] = s;"),
+    ("fallback_keeps_nonfinite_x", "solver", "the non-finite fallback keeps the broken iterate",
+     "memcpy(x, xprev, (size_t)n * sizeof(double));\n                M.kind = ORC_PC_NONE;",
+     "M.kind = ORC_PC_NONE;"),
     ("stencil_slot_order", "spai", "the stencil's slots run x-major instead of z-major",
      "const int p = 9 * (dz + 1) + 3 * (dy + 1) + (dx + 1);",
      "const int p = 9 * (dx + 1) + 3 * (dy + 1) + (dz + 1);"),
